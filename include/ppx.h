@@ -1,0 +1,194 @@
+/*
+ * ppx.h -- C ABI of libppx.so: batched power-of-two parallel-prefix
+ * operations (complex FFT, inclusive scan, tridiagonal solve) for AMD MI355X
+ * (gfx950), and the tuners that choose their launch parameters.
+ *
+ * Source of the operations: arXiv:2310.16214, Sec. III (definitions of the
+ * tridiagonal system, the scan operator and the Stockham complex FFT), Sec.
+ * IV-A (the tunable tuple (S,P,L), radix r, and batched execution of G
+ * problems of size N = r^n per invocation), Sec. IV-B and Table
+ * "parameters-TL" (the performance-parameter space and the Bayesian search),
+ * Sec. VI (data resident on the GPU; the Phi metric).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Problems are stored row-major, [batch][n], contiguous, problem stride n.
+ *   Device pointers must be 16-byte aligned.  The caller owns every buffer;
+ *   the compute entry points allocate nothing.
+ * - n must be a power of two in [PPX_MIN_N, PPX_MAX_N]; batch >= 1.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Compute calls are asynchronous and stream-ordered.
+ * - `cfg` may be NULL: the library then uses the configuration recorded by
+ *   tune() for (op, dtype, n) if there is one, else the analytical model's
+ *   choice.  An explicit cfg is validated (ppx_config_valid) and rejected
+ *   with PPX_ECONFIG if it does not describe a valid launch.
+ * - Every call returns PPX_OK (0) or a negative PPX_E* code; a message is
+ *   then available from ppx_last_error() (thread-local).  Argument checks run
+ *   before any HIP runtime call, so they need no GPU.
+ */
+#ifndef PPX_H
+#define PPX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define PPX_OK 0
+#define PPX_EINVAL (-1)   /* null/misaligned pointer, bad n, batch, dtype, op */
+#define PPX_ECONFIG (-2)  /* explicit configuration is not a valid launch */
+#define PPX_EDEVICE (-3)  /* current device is not gfx950 / no device */
+#define PPX_EHIP (-4)     /* a HIP runtime call or kernel launch failed */
+#define PPX_ENOMEM (-5)   /* allocation failed (tune, server, graph only) */
+#define PPX_ETIMEOUT (-6) /* a timed candidate exceeded its deadline */
+
+/* ---- data types ---- */
+#define PPX_I32 0
+#define PPX_F32 1
+#define PPX_F64 2
+#define PPX_C64 3 /* interleaved complex float (re, im) */
+
+/* ---- operations ---- */
+#define PPX_OP_FFT 0
+#define PPX_OP_SCAN 1
+#define PPX_OP_TRIDIAG 2
+
+/* ---- algorithm selectors (ppx_config.algo) ---- */
+#define PPX_FFT_LDS 0       /* exchange complex values through LDS */
+#define PPX_FFT_LDS_SPLIT 1 /* real parts, then imaginary parts, through a
+                               half-size LDS buffer (Sec. V-C) */
+#define PPX_SCAN_KS 0       /* Kogge-Stone lane network (DPP row shifts) */
+#define PPX_SCAN_LF 1       /* Ladner-Fischer lane network (swizzle bcasts) */
+#define PPX_TRI_CR 0        /* cyclic reduction (Sec. III) */
+#define PPX_TRI_PCR 1       /* parallel cyclic reduction (Sec. III) */
+
+/* ---- tuning methods ---- */
+#define PPX_TUNE_EXHAUSTIVE 0 /* time every valid configuration (Sec. VI) */
+#define PPX_TUNE_ANALYTICAL 1 /* occupancy guideline, no timing (Sec. IV-A) */
+#define PPX_TUNE_LEARNED 2    /* Bayesian optimisation, GP + EI (Sec. IV-B) */
+
+#define PPX_MIN_N 16
+#define PPX_MAX_N 16384
+
+/*
+ * Launch parameters of one batched call (Sec. IV-A's (S,P,L) and radix r,
+ * plus G_b, the problems solved by one workgroup).
+ *   radix               r: FFT butterfly radix in {2,4,8,16}; 2 for scan and
+ *                       tridiagonal.  When log2(n) is not a multiple of
+ *                       log2(r) the first FFT stage uses the lower radix
+ *                       2^(log2 n mod log2 r).
+ *   elems_per_thread    P = n * G_b / L; 0 means "derive from L and G_b".
+ *   threads_per_block   L in {64,128,256,512,1024}.
+ *   problems_per_block  G_b in {1,2,4,...}; G_b * n = P * L.
+ *   lds_elems           S, elements held in LDS per workgroup; 0 on input
+ *                       means "derive"; ppx_resolve_config reports the value.
+ *   algo                PPX_FFT_*, PPX_SCAN_* or PPX_TRI_*.
+ */
+typedef struct ppx_config {
+    int32_t radix;
+    int32_t elems_per_thread;
+    int32_t threads_per_block;
+    int32_t problems_per_block;
+    int32_t lds_elems;
+    int32_t algo;
+} ppx_config;
+
+/*
+ * fft_batched -- Sec. III (Stockham complex FFT), Sec. IV-A (batched).
+ * For every problem b < batch:
+ *   out[b][k] = sum_{j<n} in[b][j] * exp(direction * 2*pi*i * j*k / n)
+ * direction = -1 (forward) or +1 (inverse); neither is normalised.  Output is
+ * in natural order.  in/out: device pointers to batch*n interleaved complex
+ * floats (PPX_C64).  in == out (in place) is allowed; partial overlap is not.
+ */
+int fft_batched(const void *in, void *out, int64_t n, int64_t batch,
+                int direction, const ppx_config *cfg, void *stream);
+
+/*
+ * scan_batched -- Sec. III ("Scan Operator"): inclusive sum scan,
+ *   out[b][i] = sum_{j<=i} in[b][j]
+ * dtype PPX_I32 (wraps modulo 2^32, bit-exact) or PPX_F32.  in == out is
+ * allowed; partial overlap is not.
+ */
+int scan_batched(const void *in, void *out, int64_t n, int64_t batch,
+                 int dtype, const ppx_config *cfg, void *stream);
+
+/*
+ * tridiag_batched -- Sec. III (tridiagonal system solvers, CR and PCR):
+ * solves a_i x_{i-1} + b_i x_i + c_i x_{i+1} = d_i, i < n, for each system.
+ * a, b, c, d, x: device arrays [batch][n] of dtype PPX_F32 or PPX_F64 (four
+ * separate coefficient arrays).  a[.][0] and c[.][n-1] multiply absent
+ * unknowns: their stored values, even NaN, do not affect x.  x may equal d
+ * (the solve then overwrites the right-hand side); no other aliasing.
+ * No pivoting: systems are assumed diagonally dominant.
+ */
+int tridiag_batched(const void *a, const void *b, const void *c, const void *d,
+                    void *x, int64_t n, int64_t batch, int dtype,
+                    const ppx_config *cfg, void *stream);
+
+/*
+ * tune -- Sec. IV (analytical and learned tuning) and Sec. VI (exhaustive
+ * search as the reference).  Chooses a configuration for (op, dtype, n) at
+ * the given batch on the current device and records it in the tune cache,
+ * where later calls with cfg == NULL find it.
+ *   method     PPX_TUNE_EXHAUSTIVE | PPX_TUNE_ANALYTICAL | PPX_TUNE_LEARNED
+ *   max_evals  cap on timed candidates (<= 0: no cap); ignored for
+ *              ANALYTICAL, which times nothing.
+ *   best       receives the chosen configuration (required).
+ *   best_us    receives its median time in microseconds (NULL allowed; for
+ *              ANALYTICAL the chosen config is timed once for reporting).
+ *   evals_used receives the number of timed candidates (NULL allowed).
+ * Synchronous.  Allocates and frees its own scratch buffers (inputs are
+ * seeded synthetic data).  For op == PPX_OP_FFT, dtype must be PPX_C64.
+ * The cache file is $PPX_TUNE_CACHE if set, else none (in-memory only).
+ */
+int tune(int op, int dtype, int64_t n, int64_t batch, int method, int max_evals,
+         ppx_config *best, double *best_us, int *evals_used);
+
+/* ---------------------------------------------------------------------- */
+/* Helpers                                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Thread-local message describing the last error ("" if none). */
+const char *ppx_last_error(void);
+
+/*
+ * ppx_config_valid -- the validity predicate of the search space (Sec. V:
+ * the constraints on S, P, L, r and shuffle, restated for gfx950).
+ * Returns PPX_OK if cfg describes a launch the library can run for
+ * (op, dtype, n), PPX_ECONFIG otherwise (reason in ppx_last_error()).
+ * Static check: needs no GPU.
+ */
+int ppx_config_valid(int op, int dtype, int64_t n, const ppx_config *cfg);
+
+/*
+ * ppx_default_config -- the plain per-problem configuration used as the
+ * "default" in tuned-vs-default comparisons: one problem per workgroup,
+ * radix 2, L = min(n/2, 1024) (FFT) or the smallest L giving P <= 32.
+ */
+int ppx_default_config(int op, int dtype, int64_t n, ppx_config *out);
+
+/*
+ * ppx_resolve_config -- what a call with cfg == NULL will use for
+ * (op, dtype, n): the tuned entry if one is cached, else the analytical
+ * choice.  Needs no GPU when the analytical choice comes from the static
+ * resource table.
+ */
+int ppx_resolve_config(int op, int dtype, int64_t n, int64_t batch,
+                       ppx_config *out);
+
+/*
+ * ppx_enumerate_configs -- writes up to `cap` valid configurations for
+ * (op, dtype, n) into out[] and returns how many exist (so a call with
+ * cap = 0 sizes the array).  Static; needs no GPU.
+ */
+int ppx_enumerate_configs(int op, int dtype, int64_t n, ppx_config *out,
+                          int cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPX_H */

@@ -1,0 +1,210 @@
+// Exported C entry points of libppx.so: argument validation (before any HIP
+// runtime call), configuration resolution and kernel dispatch, plus the
+// per-device state (limits, twiddle table) and thread-local error messages.
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ppx_internal.h"
+
+namespace ppx {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string t_err;
+
+int fail(int code, const std::string &msg) {
+    t_err = msg;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return PPX_OK;
+    t_err = std::string(what) + ": " + hipGetErrorString(e);
+    return PPX_EHIP;
+}
+
+// ------------------------------------------------------------ device state
+namespace {
+std::mutex g_dev_mu;
+std::vector<DeviceInfo *> g_devices;  // indexed by device ordinal; never freed
+bool g_any_device = false;
+int64_t g_lds_limit = kStaticLdsPerBlock;
+}  // namespace
+
+int current_device_or_zero() {
+    if (!g_any_device) return 0;
+    int d = 0;
+    return hipGetDevice(&d) == hipSuccess ? d : 0;
+}
+
+int64_t lds_limit() { return g_lds_limit; }
+
+const DeviceInfo *device_info() {
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        fail(PPX_EDEVICE, std::string("no HIP device available: ") + hipGetErrorString(e));
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (dev < (int)g_devices.size() && g_devices[dev]) return g_devices[dev];
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        fail(PPX_EDEVICE, "hipGetDeviceProperties failed");
+        return nullptr;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        fail(PPX_EDEVICE, std::string("libppx is built for gfx950; device is ") + prop.gcnArchName);
+        return nullptr;
+    }
+    auto *di = new DeviceInfo();
+    di->device = dev;
+    di->cus = prop.multiProcessorCount;
+    di->lds_per_block = (int64_t)prop.sharedMemPerBlock;
+    di->lds_per_cu = (int64_t)prop.maxSharedMemoryPerMultiProcessor;
+    di->max_threads_per_cu = prop.maxThreadsPerMultiProcessor;
+    di->clock_khz = prop.clockRate;
+    di->l2_bytes = prop.l2CacheSize;
+    di->arch = prop.gcnArchName;
+    // Twiddle table for the largest supported FFT; every smaller size
+    // indexes it with a stride.
+    std::vector<float> tw(2 * (size_t(1) << kFftLog2NMax));
+    fft_host_twiddles(tw.data());
+    void *dtw = nullptr;
+    if (hipMalloc(&dtw, tw.size() * sizeof(float)) != hipSuccess ||
+        hipMemcpy(dtw, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        fail(PPX_ENOMEM, "could not create the FFT twiddle table");
+        delete di;
+        return nullptr;
+    }
+    di->twiddles = dtw;
+    if ((int)g_devices.size() <= dev) g_devices.resize(dev + 1, nullptr);
+    g_devices[dev] = di;
+    g_any_device = true;
+    g_lds_limit = di->lds_per_block;
+    return di;
+}
+
+// ----------------------------------------------------------- validation
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+static bool overlap_partial(const void *a, const void *b, int64_t bytes) {
+    const auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    if (x == y) return false;
+    return x < y + (uintptr_t)bytes && y < x + (uintptr_t)bytes;
+}
+
+static int check_shape(int64_t n, int64_t batch, int64_t elem_bytes) {
+    if (!is_pow2(n) || n < PPX_MIN_N || n > PPX_MAX_N)
+        return fail(PPX_EINVAL, "n must be a power of two in [16, 16384]");
+    if (batch < 1) return fail(PPX_EINVAL, "batch must be >= 1");
+    if (batch > (int64_t(1) << 40) / n || batch * n > INT64_MAX / elem_bytes)
+        return fail(PPX_EINVAL, "batch * n is too large");
+    return PPX_OK;
+}
+
+static int resolve(int op, int dtype, int64_t n, int64_t batch, const ppx_config *cfg,
+                   ppx_config &c) {
+    if (cfg) {
+        c = *cfg;
+        complete_config(op, dtype, n, c);
+        return validate_config(op, dtype, n, c);
+    }
+    if (cached_config(op, dtype, n, c)) return PPX_OK;
+    return analytical_config(op, dtype, n, batch, c);
+}
+
+}  // namespace ppx
+
+using namespace ppx;
+
+extern "C" {
+
+const char *ppx_last_error(void) { return t_err.c_str(); }
+
+int fft_batched(const void *in, void *out, int64_t n, int64_t batch, int direction,
+                const ppx_config *cfg, void *stream) {
+    t_err.clear();
+    if (!in || !out) return fail(PPX_EINVAL, "null pointer");
+    if (!aligned16(in) || !aligned16(out)) return fail(PPX_EINVAL, "pointers must be 16-byte aligned");
+    if (direction != -1 && direction != 1) return fail(PPX_EINVAL, "direction must be -1 or +1");
+    int rc = check_shape(n, batch, 8);
+    if (rc) return rc;
+    if (overlap_partial(in, out, batch * n * 8)) return fail(PPX_EINVAL, "in and out overlap partially");
+    ppx_config c;
+    if ((rc = resolve(PPX_OP_FFT, PPX_C64, n, batch, cfg, c))) return rc;
+    if ((batch + c.problems_per_block - 1) / c.problems_per_block > INT32_MAX)
+        return fail(PPX_EINVAL, "too many workgroups");
+    return launch_fft(in, out, ilog2(n), batch, c, direction == 1, static_cast<hipStream_t>(stream));
+}
+
+int scan_batched(const void *in, void *out, int64_t n, int64_t batch, int dtype,
+                 const ppx_config *cfg, void *stream) {
+    t_err.clear();
+    if (!in || !out) return fail(PPX_EINVAL, "null pointer");
+    if (!aligned16(in) || !aligned16(out)) return fail(PPX_EINVAL, "pointers must be 16-byte aligned");
+    if (dtype != PPX_I32 && dtype != PPX_F32) return fail(PPX_EINVAL, "scan dtype must be PPX_I32 or PPX_F32");
+    int rc = check_shape(n, batch, 4);
+    if (rc) return rc;
+    if (overlap_partial(in, out, batch * n * 4)) return fail(PPX_EINVAL, "in and out overlap partially");
+    ppx_config c;
+    if ((rc = resolve(PPX_OP_SCAN, dtype, n, batch, cfg, c))) return rc;
+    if ((batch + c.problems_per_block - 1) / c.problems_per_block > INT32_MAX)
+        return fail(PPX_EINVAL, "too many workgroups");
+    if (!device_info()) return PPX_EDEVICE;
+    return launch_scan(in, out, ilog2(n), batch, dtype, c, static_cast<hipStream_t>(stream));
+}
+
+int tridiag_batched(const void *a, const void *b, const void *c, const void *d, void *x,
+                    int64_t n, int64_t batch, int dtype, const ppx_config *cfg, void *stream) {
+    t_err.clear();
+    if (!a || !b || !c || !d || !x) return fail(PPX_EINVAL, "null pointer");
+    if (!aligned16(a) || !aligned16(b) || !aligned16(c) || !aligned16(d) || !aligned16(x))
+        return fail(PPX_EINVAL, "pointers must be 16-byte aligned");
+    if (dtype != PPX_F32 && dtype != PPX_F64)
+        return fail(PPX_EINVAL, "tridiagonal dtype must be PPX_F32 or PPX_F64");
+    const int64_t es = dtype == PPX_F64 ? 8 : 4;
+    int rc = check_shape(n, batch, es);
+    if (rc) return rc;
+    const int64_t bytes = batch * n * es;
+    const void *abc[3] = {a, b, c};
+    for (const void *p : abc)
+        if (p == (const void *)x || overlap_partial(p, x, bytes))
+            return fail(PPX_EINVAL, "x may alias d only");
+    if (overlap_partial(d, x, bytes)) return fail(PPX_EINVAL, "x and d overlap partially");
+    ppx_config cc;
+    if ((rc = resolve(PPX_OP_TRIDIAG, dtype, n, batch, cfg, cc))) return rc;
+    if ((batch + cc.problems_per_block - 1) / cc.problems_per_block > INT32_MAX)
+        return fail(PPX_EINVAL, "too many workgroups");
+    return launch_tridiag(a, b, c, d, x, ilog2(n), batch, dtype, cc, static_cast<hipStream_t>(stream));
+}
+
+int ppx_config_valid(int op, int dtype, int64_t n, const ppx_config *cfg) {
+    t_err.clear();
+    if (!cfg) return fail(PPX_EINVAL, "null config");
+    ppx_config c = *cfg;
+    complete_config(op, dtype, n, c);
+    return validate_config(op, dtype, n, c);
+}
+
+int ppx_default_config(int op, int dtype, int64_t n, ppx_config *out) {
+    t_err.clear();
+    if (!out) return fail(PPX_EINVAL, "null output");
+    return default_config(op, dtype, n, *out);
+}
+
+int ppx_resolve_config(int op, int dtype, int64_t n, int64_t batch, ppx_config *out) {
+    t_err.clear();
+    if (!out) return fail(PPX_EINVAL, "null output");
+    if (batch < 1) return fail(PPX_EINVAL, "batch must be >= 1");
+    return resolve(op, dtype, n, batch, nullptr, *out);
+}
+
+int ppx_enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap) {
+    t_err.clear();
+    return enumerate_configs(op, dtype, n, out, cap);
+}
+
+}  // extern "C"

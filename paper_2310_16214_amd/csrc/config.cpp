@@ -1,0 +1,170 @@
+// Launch-parameter space of the batched kernels: validity predicate,
+// derived fields, enumeration, the plain "default" configuration and the
+// tuned-configuration cache.
+//
+// The space is the paper's (Sec. IV-A, Sec. V and Table "parameters-TL"):
+// radix r, elements per thread P, threads per block L and -- made explicit
+// here -- problems per block G_b, tied by P * L = G_b * N.  The paper's
+// "shuffle" switch has no separate field: on gfx950 the lane networks of the
+// scan always run in registers, and the LDS use of each kernel follows from
+// (N, G_b, algo).
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "ppx_internal.h"
+
+namespace ppx {
+
+static bool is_valid_dtype(int op, int dtype) {
+    switch (op) {
+        case PPX_OP_FFT: return dtype == PPX_C64;
+        case PPX_OP_SCAN: return dtype == PPX_I32 || dtype == PPX_F32;
+        case PPX_OP_TRIDIAG: return dtype == PPX_F32 || dtype == PPX_F64;
+        default: return false;
+    }
+}
+
+static int64_t lds_needed(int op, int dtype, int64_t n, const ppx_config &c) {
+    switch (op) {
+        case PPX_OP_FFT: return fft_lds_bytes((int)n, c.problems_per_block, c.algo);
+        case PPX_OP_SCAN: return scan_lds_bytes((int)n, c.problems_per_block, c.elems_per_thread, dtype);
+        default: return tridiag_lds_bytes((int)n, c.problems_per_block, dtype, c.algo);
+    }
+}
+
+// Elements held in LDS per workgroup (the paper's S).
+static int lds_elems(int op, int64_t n, const ppx_config &c) {
+    switch (op) {
+        case PPX_OP_FFT: return (int)(c.problems_per_block * n);
+        case PPX_OP_SCAN: {
+            const int64_t T = n / c.elems_per_thread;  // threads per problem
+            return T > kWave ? c.threads_per_block / kWave : 0;
+        }
+        default: return (int)((c.algo == PPX_TRI_PCR ? 2 : 1) * c.problems_per_block * n);
+    }
+}
+
+void complete_config(int op, int, int64_t n, ppx_config &c) {
+    if (c.radix == 0) c.radix = 2;
+    if (c.elems_per_thread == 0 && c.threads_per_block > 0 && c.problems_per_block > 0)
+        c.elems_per_thread = (int)(n * c.problems_per_block / c.threads_per_block);
+    if (c.lds_elems == 0 && c.elems_per_thread > 0) c.lds_elems = lds_elems(op, n, c);
+}
+
+int validate_config(int op, int dtype, int64_t n, const ppx_config &c) {
+    if (!is_valid_dtype(op, dtype)) return fail(PPX_EINVAL, "unsupported op / dtype");
+    if (!is_pow2(n) || n < PPX_MIN_N || n > PPX_MAX_N) return fail(PPX_EINVAL, "n must be a power of two in [16, 16384]");
+    const int L = c.threads_per_block, G = c.problems_per_block;
+    if (!is_pow2(L) || L > kMaxThreadsPerBlock)
+        return fail(PPX_ECONFIG, "threads_per_block must be a power of two <= 1024");
+    if (!is_pow2(G) || G > kMaxProblemsPerBlock)
+        return fail(PPX_ECONFIG, "problems_per_block must be a power of two <= 64");
+    if (n * G % L != 0) return fail(PPX_ECONFIG, "threads_per_block must divide problems_per_block * n");
+    const int64_t P = n * G / L;
+    if (c.elems_per_thread != 0 && c.elems_per_thread != P)
+        return fail(PPX_ECONFIG, "elems_per_thread must equal n * problems_per_block / threads_per_block");
+    if (!is_pow2(P) || P < 2 || P > kMaxElemsPerThread)
+        return fail(PPX_ECONFIG, "elements per thread must be a power of two in [2, 32]");
+    if (P > n) return fail(PPX_ECONFIG, "a thread cannot hold elements of two problems (P > n)");
+    ppx_config full = c;
+    full.elems_per_thread = (int)P;
+    switch (op) {
+        case PPX_OP_FFT:
+            if (c.radix != 2 && c.radix != 4 && c.radix != 8 && c.radix != 16)
+                return fail(PPX_ECONFIG, "FFT radix must be 2, 4, 8 or 16");
+            if (c.radix > P) return fail(PPX_ECONFIG, "FFT radix must not exceed elements per thread");
+            if (L > fft_max_threads((int)P))
+                return fail(PPX_ECONFIG, "FFT with 32 elements per thread allows at most 512 threads");
+            if (c.algo != PPX_FFT_LDS && c.algo != PPX_FFT_LDS_SPLIT)
+                return fail(PPX_ECONFIG, "FFT algo must be PPX_FFT_LDS or PPX_FFT_LDS_SPLIT");
+            break;
+        case PPX_OP_SCAN:
+            if (c.radix != 0 && c.radix != 2) return fail(PPX_ECONFIG, "scan radix must be 2");
+            if (c.algo != PPX_SCAN_KS && c.algo != PPX_SCAN_LF)
+                return fail(PPX_ECONFIG, "scan algo must be PPX_SCAN_KS or PPX_SCAN_LF");
+            break;
+        case PPX_OP_TRIDIAG:
+            if (c.radix != 0 && c.radix != 2) return fail(PPX_ECONFIG, "tridiagonal radix must be 2");
+            if (c.algo != PPX_TRI_CR && c.algo != PPX_TRI_PCR)
+                return fail(PPX_ECONFIG, "tridiagonal algo must be PPX_TRI_CR or PPX_TRI_PCR");
+            break;
+        default:
+            return fail(PPX_EINVAL, "unknown op");
+    }
+    if (lds_needed(op, dtype, n, full) > lds_limit())
+        return fail(PPX_ECONFIG, "configuration needs more LDS than a workgroup can allocate");
+    if (c.lds_elems != 0 && c.lds_elems != lds_elems(op, n, full))
+        return fail(PPX_ECONFIG, "lds_elems does not match the configuration (pass 0 to derive)");
+    return PPX_OK;
+}
+
+int default_config(int op, int dtype, int64_t n, ppx_config &c) {
+    if (!is_valid_dtype(op, dtype)) return fail(PPX_EINVAL, "unsupported op / dtype");
+    if (!is_pow2(n) || n < PPX_MIN_N || n > PPX_MAX_N) return fail(PPX_EINVAL, "n must be a power of two in [16, 16384]");
+    std::memset(&c, 0, sizeof c);
+    c.radix = 2;
+    c.problems_per_block = 1;
+    c.threads_per_block = (int)(n / 2 < kMaxThreadsPerBlock ? n / 2 : kMaxThreadsPerBlock);
+    c.algo = 0;
+    if (op == PPX_OP_FFT && fft_lds_bytes((int)n, 1, PPX_FFT_LDS) > lds_limit()) c.algo = PPX_FFT_LDS_SPLIT;
+    complete_config(op, dtype, n, c);
+    return validate_config(op, dtype, n, c);
+}
+
+// The search space enumerated by the tuners: r in {2,4,8,16} (FFT only),
+// L in {64,...,1024}, G_b in {1,...,16}, and the algorithm variants of each
+// operation; invalid points are dropped.
+int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap) {
+    if (!is_valid_dtype(op, dtype)) return fail(PPX_EINVAL, "unsupported op / dtype");
+    if (!is_pow2(n) || n < PPX_MIN_N || n > PPX_MAX_N) return fail(PPX_EINVAL, "n must be a power of two in [16, 16384]");
+    static const int radices_fft[] = {2, 4, 8, 16};
+    static const int radix_two[] = {2};
+    const int *radices = op == PPX_OP_FFT ? radices_fft : radix_two;
+    const int nr = op == PPX_OP_FFT ? 4 : 1;
+    const int nalgo = 2;
+    int count = 0;
+    for (int ri = 0; ri < nr; ++ri)
+        for (int L = 64; L <= 1024; L *= 2)
+            for (int G = 1; G <= 16; G *= 2)
+                for (int a = 0; a < nalgo; ++a) {
+                    ppx_config c{};
+                    c.radix = radices[ri];
+                    c.threads_per_block = L;
+                    c.problems_per_block = G;
+                    c.algo = a;
+                    complete_config(op, dtype, n, c);
+                    if (validate_config(op, dtype, n, c) != PPX_OK) continue;
+                    // FFT: the split exchange only when it is needed or saves LDS
+                    // (a single-stage transform uses no LDS at all).
+                    if (op == PPX_OP_FFT && a == PPX_FFT_LDS_SPLIT && n <= c.radix) continue;
+                    if (count < cap && out) out[count] = c;
+                    ++count;
+                }
+    fail(PPX_OK, "");
+    return count;
+}
+
+// ---- tuned-configuration cache (in memory; tune.cpp persists it) ----
+namespace {
+std::mutex g_cache_mu;
+std::map<std::tuple<int, int, int, int64_t>, ppx_config> g_cache;  // (device, op, dtype, n)
+}  // namespace
+
+bool cached_config(int op, int dtype, int64_t n, ppx_config &c) {
+    const int dev = current_device_or_zero();
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find({dev, op, dtype, n});
+    if (it == g_cache.end()) return false;
+    c = it->second;
+    return true;
+}
+
+void store_cached_config(int op, int dtype, int64_t n, const ppx_config &c) {
+    const int dev = current_device_or_zero();
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache[{dev, op, dtype, n}] = c;
+}
+
+}  // namespace ppx

@@ -1,0 +1,143 @@
+// Device-side building blocks for the gfx950 kernels: complex arithmetic,
+// radix-R DFTs held in registers, and wave64 lane networks for scans.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ppx {
+
+// ------------------------------------------------------------------ complex
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// cos and sin of 2*pi*e/16 for the odd sixteenths (the even ones are handled
+// by exact special cases below).
+__host__ __device__ constexpr float cos16(int e) {
+    return e == 1 ? 0.92387953251128674f : e == 3 ? 0.38268343236508978f
+         : e == 5 ? -0.38268343236508978f : e == 7 ? -0.92387953251128674f : 0.0f;
+}
+__host__ __device__ constexpr float sin16(int e) {
+    return (e == 1 || e == 7) ? 0.38268343236508978f
+         : (e == 3 || e == 5) ? 0.92387953251128674f : 0.0f;
+}
+constexpr float kHalfSqrt2 = 0.70710678118654752f;
+
+// x * exp(-2*pi*i*m/M) for M a power of two <= 16 and m < M/2, with the
+// multiplications by 1, -i and (+-1 - i)/sqrt(2) done exactly as adds/swaps.
+template <int M, int m>
+__host__ __device__ __forceinline__ float2 twiddle_const(float2 x) {
+    constexpr int e = m * (16 / M);  // angle in sixteenths of a turn, 0..7
+    if constexpr (e == 0) {
+        return x;
+    } else if constexpr (e == 4) {
+        return make_float2(x.y, -x.x);
+    } else if constexpr (e == 2) {
+        return make_float2(kHalfSqrt2 * (x.x + x.y), kHalfSqrt2 * (x.y - x.x));
+    } else if constexpr (e == 6) {
+        return make_float2(kHalfSqrt2 * (x.y - x.x), -kHalfSqrt2 * (x.x + x.y));
+    } else {
+        constexpr float c = cos16(e), s = sin16(e);
+        return make_float2(x.x * c + x.y * s, x.y * c - x.x * s);
+    }
+}
+
+// In-register forward DFT of length M (power of two <= 16), natural order in
+// and out: u[k] <- sum_j u[j] exp(-2 pi i j k / M).  Radix-2 decimation in
+// time, fully unrolled; the even/odd split is pure register renaming.
+template <int M, int k>
+__host__ __device__ __forceinline__ void dft_combine(float2 (&u)[M], const float2 (&e)[M / 2],
+                                            const float2 (&o)[M / 2]) {
+    if constexpr (k < M / 2) {
+        const float2 t = twiddle_const<M, k>(o[k]);
+        u[k] = cadd(e[k], t);
+        u[k + M / 2] = csub(e[k], t);
+        dft_combine<M, k + 1>(u, e, o);
+    }
+}
+
+template <int M>
+struct RegDFT {
+    __host__ __device__ __forceinline__ static void run(float2 (&u)[M]) {
+        float2 e[M / 2], o[M / 2];
+#pragma unroll
+        for (int j = 0; j < M / 2; ++j) {
+            e[j] = u[2 * j];
+            o[j] = u[2 * j + 1];
+        }
+        RegDFT<M / 2>::run(e);
+        RegDFT<M / 2>::run(o);
+        dft_combine<M, 0>(u, e, o);
+    }
+};
+template <>
+struct RegDFT<1> {
+    __host__ __device__ __forceinline__ static void run(float2 (&)[1]) {}
+};
+
+// ------------------------------------------------------------ lane networks
+// DPP controls (GFX9 encoding).
+constexpr int kDppRowShr = 0x110;     // + shift (1..15), within 16-lane rows
+constexpr int kDppRowBcast15 = 0x142; // lane 15 of each row -> next row
+constexpr int kDppRowBcast31 = 0x143; // lane 31 -> rows 2 and 3
+
+template <typename T>
+__device__ __forceinline__ int as_int(T v) { return __builtin_bit_cast(int, v); }
+template <typename T>
+__device__ __forceinline__ T from_int(int v) { return __builtin_bit_cast(T, v); }
+
+// Value of lane (lane - D) within the same 16-lane row, 0 where that lane is
+// outside the row.
+template <int D, typename T>
+__device__ __forceinline__ T dpp_row_shr(T v) {
+    return from_int<T>(__builtin_amdgcn_update_dpp(0, as_int(v), kDppRowShr + D, 0xf, 0xf, false));
+}
+
+// Inclusive scan over aligned segments of SEG lanes (SEG power of two <= 64),
+// Kogge-Stone shape: shifts 1, 2, 4, 8 inside rows, then the row broadcasts.
+// Must be called with all 64 lanes active.
+template <typename T>
+__device__ __forceinline__ T lanes_scan_ks(T x, int seg, int lane) {
+    const int ls = lane & (seg - 1);
+    if (seg > 1) { T y = dpp_row_shr<1>(x); if (ls >= 1) x += y; }
+    if (seg > 2) { T y = dpp_row_shr<2>(x); if (ls >= 2) x += y; }
+    if (seg > 4) { T y = dpp_row_shr<4>(x); if (ls >= 4) x += y; }
+    if (seg > 8) { T y = dpp_row_shr<8>(x); if (ls >= 8) x += y; }
+    if (seg > 16) {
+        // rows 1 and 3 receive the last lane of rows 0 and 2
+        x += from_int<T>(__builtin_amdgcn_update_dpp(0, as_int(x), kDppRowBcast15, 0xa, 0xf, false));
+    }
+    if (seg > 32) {
+        // rows 2 and 3 receive lane 31
+        x += from_int<T>(__builtin_amdgcn_update_dpp(0, as_int(x), kDppRowBcast31, 0xc, 0xf, false));
+    }
+    return x;
+}
+
+// ds_swizzle in bit-mask mode within 32-lane halves: source lane =
+// (lane & AND) | OR.
+template <int AND, int OR, typename T>
+__device__ __forceinline__ T swz(T v) {
+    return from_int<T>(__builtin_amdgcn_ds_swizzle(as_int(v), (AND & 31) | ((OR & 31) << 5)));
+}
+
+// Inclusive scan over aligned segments of SEG lanes, Ladner-Fischer shape
+// (minimum depth: at step d every lane of the upper half of each 2d-block
+// adds the last value of the lower half, fetched by a swizzle broadcast).
+template <typename T>
+__device__ __forceinline__ T lanes_scan_lf(T x, int seg, int lane) {
+    if (seg > 1) { T y = swz<0x1e, 0x00>(x); if (lane & 1) x += y; }
+    if (seg > 2) { T y = swz<0x1c, 0x01>(x); if (lane & 2) x += y; }
+    if (seg > 4) { T y = swz<0x18, 0x03>(x); if (lane & 4) x += y; }
+    if (seg > 8) { T y = swz<0x10, 0x07>(x); if (lane & 8) x += y; }
+    if (seg > 16) { T y = swz<0x00, 0x0f>(x); if (lane & 16) x += y; }
+    if (seg > 32) {
+        T y = from_int<T>(__builtin_amdgcn_readlane(as_int(x), 31));
+        if (lane & 32) x += y;
+    }
+    return x;
+}
+
+}  // namespace ppx

@@ -1,0 +1,95 @@
+// Internal declarations shared by the translation units of libppx.so.
+// Host-side only: kernels live in fft.hip, scan.hip, tridiag.hip, fused.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/ppx.h"
+
+namespace ppx {
+
+// ---- error reporting (thread-local message behind ppx_last_error) ----
+int fail(int code, const std::string &msg);
+int fail_hip(hipError_t e, const char *what);
+
+// ---- static description of the target (gfx950) used by the validity
+// predicate when no GPU is present.  The runtime limits read from the device
+// replace these at first use on a GPU (see device_info()). ----
+constexpr int kWave = 64;
+constexpr int kMaxThreadsPerBlock = 1024;
+constexpr int kMinThreadsPerBlock = 64;
+constexpr int kMaxProblemsPerBlock = 64;
+constexpr int kMaxElemsPerThread = 32;
+constexpr int64_t kStaticLdsPerBlock = 160 * 1024;  // gfx950 LDS per CU
+
+struct DeviceInfo {
+    int device = -1;
+    int cus = 0;
+    int64_t lds_per_block = kStaticLdsPerBlock;
+    int64_t lds_per_cu = kStaticLdsPerBlock;
+    int max_threads_per_cu = 2048;
+    int clock_khz = 0;
+    int64_t l2_bytes = 0;
+    std::string arch;
+    const void *twiddles = nullptr;  // device table w[m] = exp(-2 pi i m/NMAX)
+};
+
+// Returns the cached info for the current device, initialising it (and the
+// twiddle table) on first use.  nullptr + ppx error on failure.
+const DeviceInfo *device_info();
+// LDS bytes per workgroup usable by a validity check: the device's value if
+// a device has been initialised in this process, else the static figure.
+int64_t lds_limit();
+// hipGetDevice() if this process has initialised a device through
+// device_info(), else 0 without touching the HIP runtime.
+int current_device_or_zero();
+
+// ---- shape helpers ----
+inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+inline int ilog2(int64_t v) {
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+
+// ---- LDS footprint of each kernel family (bytes per workgroup) ----
+int64_t fft_lds_bytes(int n, int gb, int algo);
+int64_t scan_lds_bytes(int n, int gb, int P, int dtype);
+int64_t tridiag_lds_bytes(int n, int gb, int dtype, int algo);
+
+// ---- kernel launchers (validated arguments only) ----
+constexpr int kFftLog2NMax = 14;
+// Workgroup-size bound of the FFT kernel holding P complex values per thread:
+// at P = 32 the 64 data registers plus twiddles need more than the 128 VGPRs
+// a 1024-thread workgroup leaves per lane, so those kernels cap L at 512.
+constexpr int fft_max_threads(int P) { return P >= 32 ? 512 : 1024; }
+int launch_fft(const void *in, void *out, int log2n, int64_t batch,
+               const ppx_config &c, bool inverse, hipStream_t s);
+int launch_scan(const void *in, void *out, int log2n, int64_t batch, int dtype,
+                const ppx_config &c, hipStream_t s);
+int launch_tridiag(const void *a, const void *b, const void *c, const void *d,
+                   void *x, int log2n, int64_t batch, int dtype,
+                   const ppx_config &cfg, hipStream_t s);
+
+// Device function pointers for occupancy queries (nullptr if no such kernel).
+const void *fft_kernel(int radix, int P, int algo);
+const void *scan_kernel(int dtype, int P, int algo);
+const void *tridiag_kernel(int dtype, int algo);
+
+// Builds the forward twiddle table for NMAX = 2^kFftLog2NMax in host memory
+// (float pairs from double-precision sincos).
+void fft_host_twiddles(float *out2);
+
+// ---- configuration logic (config.cpp) ----
+int validate_config(int op, int dtype, int64_t n, const ppx_config &c);
+void complete_config(int op, int dtype, int64_t n, ppx_config &c);
+int default_config(int op, int dtype, int64_t n, ppx_config &c);
+int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap);
+int analytical_config(int op, int dtype, int64_t n, int64_t batch, ppx_config &c);
+bool cached_config(int op, int dtype, int64_t n, ppx_config &c);
+void store_cached_config(int op, int dtype, int64_t n, const ppx_config &c);
+
+}  // namespace ppx

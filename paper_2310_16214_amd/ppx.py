@@ -1,0 +1,195 @@
+"""ctypes binding of libppx.so (declared in include/ppx.h).
+
+Argument marshalling only: every operation runs in the library's HIP
+kernels.  Buffers may be passed as torch tensors (their ``data_ptr()`` is
+used) or as raw integer device addresses.  When ``stream`` is None and a
+torch tensor is given, torch's current HIP stream is used so that the call is
+ordered with the caller's torch work.  A missing library raises at first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import threading
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libppx.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "ppx.h")
+
+# ---- constants mirrored from include/ppx.h ----
+OK, EINVAL, ECONFIG, EDEVICE, EHIP, ENOMEM, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+I32, F32, F64, C64 = 0, 1, 2, 3
+OP_FFT, OP_SCAN, OP_TRIDIAG = 0, 1, 2
+FFT_LDS, FFT_LDS_SPLIT = 0, 1
+SCAN_KS, SCAN_LF = 0, 1
+TRI_CR, TRI_PCR = 0, 1
+TUNE_EXHAUSTIVE, TUNE_ANALYTICAL, TUNE_LEARNED = 0, 1, 2
+MIN_N, MAX_N = 16, 16384
+
+
+class PpxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ppx error {code}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    """ppx_config: (radix r, P, L, G_b, S, algo)."""
+    _fields_ = [("radix", ctypes.c_int32),
+                ("elems_per_thread", ctypes.c_int32),
+                ("threads_per_block", ctypes.c_int32),
+                ("problems_per_block", ctypes.c_int32),
+                ("lds_elems", ctypes.c_int32),
+                ("algo", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.radix, self.elems_per_thread, self.threads_per_block,
+                self.problems_per_block, self.lds_elems, self.algo)
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+    def __repr__(self):
+        return "Config(r=%d, P=%d, L=%d, G_b=%d, S=%d, algo=%d)" % self.as_tuple()
+
+
+def make_config(radix=2, threads_per_block=64, problems_per_block=1, algo=0,
+                elems_per_thread=0, lds_elems=0) -> Config:
+    return Config(radix, elems_per_thread, threads_per_block, problems_per_block,
+                  lds_elems, algo)
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def header_functions():
+    """Names of the functions declared in include/ppx.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)
+
+
+def lib():
+    """Load libppx.so (raises if it has not been built).
+
+    torch bundles its own HIP runtime under the same soname as ROCm's
+    (libamdhip64.so.7).  Importing torch first makes the dynamic linker bind
+    libppx.so to that already-loaded runtime, so the process holds a single
+    HIP runtime and torch's device pointers and streams are valid here.
+    """
+    global _lib
+    with _lock:
+        if _lib is None:
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    f"{LIB_PATH} is missing: build it with "
+                    "`python -m paper_2310_16214_amd.build` (no CPU fallback exists)")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+            cfgp = ctypes.POINTER(Config)
+            L.fft_batched.argtypes = [vp, vp, i64, i64, ci, cfgp, vp]
+            L.scan_batched.argtypes = [vp, vp, i64, i64, ci, cfgp, vp]
+            L.tridiag_batched.argtypes = [vp, vp, vp, vp, vp, i64, i64, ci, cfgp, vp]
+            L.tune.argtypes = [ci, ci, i64, i64, ci, ci, cfgp,
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ci)]
+            L.ppx_last_error.restype = ctypes.c_char_p
+            L.ppx_last_error.argtypes = []
+            L.ppx_config_valid.argtypes = [ci, ci, i64, cfgp]
+            L.ppx_default_config.argtypes = [ci, ci, i64, cfgp]
+            L.ppx_resolve_config.argtypes = [ci, ci, i64, i64, cfgp]
+            L.ppx_enumerate_configs.argtypes = [ci, ci, i64, cfgp, ci]
+            for name in ("fft_batched", "scan_batched", "tridiag_batched", "tune",
+                         "ppx_config_valid", "ppx_default_config", "ppx_resolve_config",
+                         "ppx_enumerate_configs"):
+                getattr(L, name).restype = ci
+            _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().ppx_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise PpxError(rc, last_error())
+    return rc
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    return int(x)
+
+
+def _stream(stream, *tensors):
+    if stream is not None:
+        return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    for t in tensors:
+        if hasattr(t, "is_cuda") and t.is_cuda:
+            import torch
+            return torch.cuda.current_stream(t.device).cuda_stream
+    return None
+
+
+def _cfgp(cfg):
+    return ctypes.byref(cfg) if cfg is not None else None
+
+
+def fft_batched(inp, out, n, batch, direction=-1, cfg=None, stream=None):
+    """Batched complex FFT (see include/ppx.h)."""
+    _check(lib().fft_batched(_ptr(inp), _ptr(out), n, batch, direction, _cfgp(cfg),
+                             _stream(stream, inp, out)))
+
+
+def scan_batched(inp, out, n, batch, dtype, cfg=None, stream=None):
+    """Batched inclusive sum scan, dtype I32 or F32."""
+    _check(lib().scan_batched(_ptr(inp), _ptr(out), n, batch, dtype, _cfgp(cfg),
+                              _stream(stream, inp, out)))
+
+
+def tridiag_batched(a, b, c, d, x, n, batch, dtype, cfg=None, stream=None):
+    """Batched tridiagonal solve, dtype F32 or F64."""
+    _check(lib().tridiag_batched(_ptr(a), _ptr(b), _ptr(c), _ptr(d), _ptr(x), n, batch,
+                                 dtype, _cfgp(cfg), _stream(stream, a, b, c, d, x)))
+
+
+def tune(op, dtype, n, batch, method, max_evals=0):
+    """Returns (Config, best_us, evals_used)."""
+    best = Config()
+    us = ctypes.c_double(0.0)
+    ev = ctypes.c_int(0)
+    _check(lib().tune(op, dtype, n, batch, method, max_evals, ctypes.byref(best),
+                      ctypes.byref(us), ctypes.byref(ev)))
+    return best, us.value, ev.value
+
+
+def config_valid(op, dtype, n, cfg) -> bool:
+    return lib().ppx_config_valid(op, dtype, n, ctypes.byref(cfg)) == OK
+
+
+def default_config(op, dtype, n) -> Config:
+    c = Config()
+    _check(lib().ppx_default_config(op, dtype, n, ctypes.byref(c)))
+    return c
+
+
+def resolve_config(op, dtype, n, batch) -> Config:
+    c = Config()
+    _check(lib().ppx_resolve_config(op, dtype, n, batch, ctypes.byref(c)))
+    return c
+
+
+def enumerate_configs(op, dtype, n):
+    cnt = _check(lib().ppx_enumerate_configs(op, dtype, n, None, 0))
+    arr = (Config * max(cnt, 1))()
+    _check(lib().ppx_enumerate_configs(op, dtype, n, arr, cnt))
+    return [arr[i] for i in range(cnt)]

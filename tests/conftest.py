@@ -26,4 +26,6 @@ def cuda():
     if not gpu_available():
         pytest.skip("no GPU visible")
     import torch
-    return torch.device("cuda:0")
+    dev = torch.device("cuda:0")
+    torch.zeros(1, device=dev)  # create the context before libppx.so is used
+    return dev
