@@ -41,6 +41,14 @@ int current_device_or_zero() {
 
 int64_t lds_limit() { return g_lds_limit; }
 
+const DeviceInfo *device_info_if_ready() {
+    if (!g_any_device) return nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    return dev < (int)g_devices.size() ? g_devices[dev] : nullptr;
+}
+
 const DeviceInfo *device_info() {
     int dev = 0;
     const hipError_t e = hipGetDevice(&dev);

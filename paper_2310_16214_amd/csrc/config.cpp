@@ -9,9 +9,6 @@
 // scan always run in registers, and the LDS use of each kernel follows from
 // (N, G_b, algo).
 #include <cstring>
-#include <map>
-#include <mutex>
-#include <tuple>
 
 #include "ppx_internal.h"
 
@@ -144,27 +141,6 @@ int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap) {
                 }
     fail(PPX_OK, "");
     return count;
-}
-
-// ---- tuned-configuration cache (in memory; tune.cpp persists it) ----
-namespace {
-std::mutex g_cache_mu;
-std::map<std::tuple<int, int, int, int64_t>, ppx_config> g_cache;  // (device, op, dtype, n)
-}  // namespace
-
-bool cached_config(int op, int dtype, int64_t n, ppx_config &c) {
-    const int dev = current_device_or_zero();
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    auto it = g_cache.find({dev, op, dtype, n});
-    if (it == g_cache.end()) return false;
-    c = it->second;
-    return true;
-}
-
-void store_cached_config(int op, int dtype, int64_t n, const ppx_config &c) {
-    const int dev = current_device_or_zero();
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    g_cache[{dev, op, dtype, n}] = c;
 }
 
 }  // namespace ppx

@@ -40,6 +40,9 @@ struct DeviceInfo {
 // Returns the cached info for the current device, initialising it (and the
 // twiddle table) on first use.  nullptr + ppx error on failure.
 const DeviceInfo *device_info();
+// The current device's info if it has already been initialised, else nullptr
+// (never touches the HIP runtime before a device has been initialised).
+const DeviceInfo *device_info_if_ready();
 // LDS bytes per workgroup usable by a validity check: the device's value if
 // a device has been initialised in this process, else the static figure.
 int64_t lds_limit();
@@ -89,6 +92,7 @@ void complete_config(int op, int dtype, int64_t n, ppx_config &c);
 int default_config(int op, int dtype, int64_t n, ppx_config &c);
 int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap);
 int analytical_config(int op, int dtype, int64_t n, int64_t batch, ppx_config &c);
+// tune cache (tune.cpp): entry recorded for (op, dtype, n, any algorithm)
 bool cached_config(int op, int dtype, int64_t n, ppx_config &c);
 void store_cached_config(int op, int dtype, int64_t n, const ppx_config &c);
 

@@ -1,38 +1,948 @@
-// Tuners over the launch-parameter space (Sec. IV of arXiv:2310.16214).
-#include <cstring>
+// Tuners over the launch-parameter space (Sec. IV of arXiv:2310.16214):
+// exhaustive search, the analytical occupancy guideline (Sec. IV-A) and
+// Bayesian optimisation with a Gaussian-process surrogate and Expected
+// Improvement (Sec. IV-B), plus the GPU timing harness they share and the
+// tune cache that makes a tuned configuration the default for later calls.
+#include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <random>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ppx_tune.h"
 #include "ppx_internal.h"
 
 namespace ppx {
 
-int analytical_config(int op, int dtype, int64_t n, int64_t, ppx_config &c) {
-    // Provisional rule until the occupancy-model engine lands: the largest
-    // radix with P = radix, and a workgroup of about 256 threads.
-    std::memset(&c, 0, sizeof c);
-    const int R = op == PPX_OP_FFT ? (n >= 16 ? 16 : (int)n) : 2;
-    int P = op == PPX_OP_FFT ? R : 4;
-    for (int L = 256; L >= 64; L /= 2) {
-        for (int G = 1; G <= 16; G *= 2) {
-            if (n * G != (int64_t)P * L) continue;
-            c.radix = R;
-            c.threads_per_block = L;
-            c.problems_per_block = G;
-            c.algo = 0;
-            complete_config(op, dtype, n, c);
-            if (validate_config(op, dtype, n, c) == PPX_OK) return PPX_OK;
-            if (op == PPX_OP_FFT) {
-                c.algo = PPX_FFT_LDS_SPLIT;
-                c.lds_elems = 0;
-                complete_config(op, dtype, n, c);
-                if (validate_config(op, dtype, n, c) == PPX_OK) return PPX_OK;
+// ============================================================ occupancy
+static int64_t roundup(int64_t v, int64_t g) { return g > 0 ? (v + g - 1) / g * g : v; }
+
+static int occupancy_blocks(const ppx_device_model &m, const ppx_resource &r, int *waves) {
+    if (waves) *waves = 0;
+    if (r.threads <= 0 || m.wave_size <= 0) return 0;
+    if (r.lds_bytes > m.lds_per_block) return 0;
+    const int64_t wpb = (r.threads + m.wave_size - 1) / m.wave_size;
+    if (wpb > m.max_waves_per_cu) return 0;
+    int64_t b = std::min<int64_t>(m.max_blocks_per_cu, m.max_waves_per_cu / wpb);
+    if (r.regs_per_thread > 0) {
+        const int64_t per_wave = roundup((int64_t)r.regs_per_thread * m.wave_size, m.reg_granule);
+        if (per_wave > m.regs_per_partition) return 0;
+        const int64_t waves_per_part = m.regs_per_partition / per_wave;
+        b = std::min<int64_t>(b, m.partitions * waves_per_part / wpb);
+    }
+    if (r.lds_bytes > 0) b = std::min<int64_t>(b, m.lds_per_cu / roundup(r.lds_bytes, m.lds_granule));
+    if (b < 0) b = 0;
+    if (waves) *waves = (int)(b * wpb);
+    return (int)b;
+}
+
+static ppx_device_model gfx950_model() {
+    ppx_device_model m{};
+    m.wave_size = 64;
+    m.partitions = 4;
+    m.regs_per_partition = 512 * 64;
+    m.reg_granule = 8 * 64;
+    m.max_waves_per_cu = 32;
+    m.max_blocks_per_cu = 32;
+    m.lds_per_cu = 160 * 1024;
+    m.lds_per_block = 160 * 1024;
+    m.lds_granule = 512;
+    m.num_cus = 256;
+    if (const DeviceInfo *di = device_info_if_ready()) {
+        m.lds_per_block = (int32_t)di->lds_per_block;
+        m.lds_per_cu = (int32_t)di->lds_per_cu;
+        m.max_waves_per_cu = di->max_threads_per_cu / m.wave_size;
+        m.num_cus = di->cus;
+    }
+    return m;
+}
+
+// ============================================================ guideline
+struct CandEval {
+    int idx;
+    int blocks, waves;
+    double occ;  // warp occupancy W_SM / W^max
+    bool s1;     // W_SM = W^max and B_a = B^max
+    int radix, P, lds;
+};
+
+static int analytical_pick_impl(const ppx_device_model &m, const ppx_config *c,
+                                const ppx_resource *res, int n, int64_t batch, int flags) {
+    std::vector<CandEval> ev;
+    for (int i = 0; i < n; ++i) {
+        int w = 0;
+        const int b = occupancy_blocks(m, res[i], &w);
+        if (b <= 0) continue;
+        CandEval e{i, b, w, 0.0, false, c[i].radix, c[i].elems_per_thread, res[i].lds_bytes};
+        e.occ = (double)w / m.max_waves_per_cu;
+        e.s1 = (w == m.max_waves_per_cu && b == m.max_blocks_per_cu);
+        ev.push_back(e);
+    }
+    if (ev.empty()) return -1;
+    if (flags & PPX_ANALYTICAL_GRID_FILL) {
+        std::vector<CandEval> fill;
+        for (const auto &e : ev) {
+            const int64_t gb = c[e.idx].problems_per_block > 0 ? c[e.idx].problems_per_block : 1;
+            const int64_t grid = (batch + gb - 1) / gb;
+            if (grid >= (int64_t)e.blocks * m.num_cus) fill.push_back(e);
+        }
+        if (!fill.empty()) ev.swap(fill);
+    }
+    // the occupancy window of steps 1-2: [60%, 100%] of W^max in the paper;
+    // [50%, 100%] (four waves per SIMD) with the gfx950 term
+    const double lo = (flags & PPX_ANALYTICAL_WINDOW_50) ? 0.5 : 0.6;
+    std::vector<CandEval> window;
+    for (const auto &e : ev)
+        if (e.occ >= lo - 1e-12) window.push_back(e);
+    auto better_window = [](const CandEval &a, const CandEval &b) {
+        // step 4: larger radix first; then steps 1-2: full occupancy with all
+        // blocks, more active blocks, higher occupancy; then larger P, less LDS
+        if (a.radix != b.radix) return a.radix > b.radix;
+        if (a.s1 != b.s1) return a.s1;
+        if (a.blocks != b.blocks) return a.blocks > b.blocks;
+        if (a.occ != b.occ) return a.occ > b.occ;
+        if (a.P != b.P) return a.P > b.P;
+        if (a.lds != b.lds) return a.lds < b.lds;
+        return a.idx < b.idx;
+    };
+    auto better_fallback = [](const CandEval &a, const CandEval &b) {
+        // step 3: highest occupancy, ties to larger P (then radix, less LDS)
+        if (a.occ != b.occ) return a.occ > b.occ;
+        if (a.P != b.P) return a.P > b.P;
+        if (a.radix != b.radix) return a.radix > b.radix;
+        if (a.lds != b.lds) return a.lds < b.lds;
+        return a.idx < b.idx;
+    };
+    if (!window.empty()) return std::min_element(window.begin(), window.end(), better_window)->idx;
+    return std::min_element(ev.begin(), ev.end(), better_fallback)->idx;
+}
+
+// ============================================================ GP + EI
+// Matern-5/2 ARD kernel.
+static double matern52(const double *a, const double *b, int d, const double *ls, double sf2) {
+    double r2 = 0;
+    for (int k = 0; k < d; ++k) {
+        const double t = (a[k] - b[k]) / ls[k];
+        r2 += t * t;
+    }
+    const double s = std::sqrt(5.0 * r2);
+    return sf2 * (1.0 + s + s * s / 3.0) * std::exp(-s);
+}
+
+// In-place Cholesky of an n x n SPD matrix (lower). false if not SPD.
+static bool cholesky(std::vector<double> &A, int n) {
+    for (int j = 0; j < n; ++j) {
+        double s = A[j * n + j];
+        for (int k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
+        if (!(s > 0)) return false;
+        const double l = std::sqrt(s);
+        A[j * n + j] = l;
+        for (int i = j + 1; i < n; ++i) {
+            double t = A[i * n + j];
+            for (int k = 0; k < j; ++k) t -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = t / l;
+        }
+    }
+    return true;
+}
+
+static void chol_solve_lower(const std::vector<double> &L, int n, std::vector<double> &b) {
+    for (int i = 0; i < n; ++i) {
+        double t = b[i];
+        for (int k = 0; k < i; ++k) t -= L[i * n + k] * b[k];
+        b[i] = t / L[i * n + i];
+    }
+}
+
+static void chol_solve_upper(const std::vector<double> &L, int n, std::vector<double> &b) {
+    for (int i = n - 1; i >= 0; --i) {
+        double t = b[i];
+        for (int k = i + 1; k < n; ++k) t -= L[k * n + i] * b[k];
+        b[i] = t / L[i * n + i];
+    }
+}
+
+struct GP {
+    int n = 0, d = 0;
+    std::vector<double> X, L, alpha, ls;
+    double sf2 = 1, noise = 1e-4;
+
+    bool fit_fixed(const std::vector<double> &Xin, const std::vector<double> &y, int n_, int d_,
+                   const double *ls_, double sf2_, double noise_, double *logml) {
+        n = n_;
+        d = d_;
+        X = Xin;
+        ls.assign(ls_, ls_ + d);
+        sf2 = sf2_;
+        noise = noise_;
+        L.assign((size_t)n * n, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double k = matern52(&X[i * d], &X[j * d], d, ls.data(), sf2);
+                if (i == j) k += noise;
+                L[i * n + j] = k;
+                L[j * n + i] = k;
+            }
+        if (!cholesky(L, n)) return false;
+        alpha = y;
+        chol_solve_lower(L, n, alpha);
+        double quad = 0;
+        for (double v : alpha) quad += v * v;
+        chol_solve_upper(L, n, alpha);
+        if (logml) {
+            double ld = 0;
+            for (int i = 0; i < n; ++i) ld += std::log(L[i * n + i]);
+            *logml = -0.5 * quad - ld - 0.5 * n * std::log(2 * M_PI);
+        }
+        return true;
+    }
+
+    void predict(const double *xq, double *mu, double *var) const {
+        std::vector<double> k(n);
+        for (int i = 0; i < n; ++i) k[i] = matern52(xq, &X[i * d], d, ls.data(), sf2);
+        double m = 0;
+        for (int i = 0; i < n; ++i) m += k[i] * alpha[i];
+        std::vector<double> v = k;
+        chol_solve_lower(L, n, v);
+        double q = 0;
+        for (double t : v) q += t * t;
+        *mu = m;
+        *var = std::max(sf2 - q, 1e-12);
+    }
+};
+
+// Nelder-Mead on f over R^dim (minimisation).
+template <typename F>
+static std::vector<double> nelder_mead(F f, std::vector<double> x0, double step, int iters) {
+    const int dim = (int)x0.size();
+    std::vector<std::vector<double>> s(dim + 1, x0);
+    std::vector<double> fv(dim + 1);
+    for (int i = 0; i < dim; ++i) s[i + 1][i] += step;
+    for (int i = 0; i <= dim; ++i) fv[i] = f(s[i]);
+    for (int it = 0; it < iters; ++it) {
+        std::vector<int> ord(dim + 1);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::sort(ord.begin(), ord.end(), [&](int a, int b) { return fv[a] < fv[b]; });
+        std::vector<std::vector<double>> s2(dim + 1);
+        std::vector<double> f2(dim + 1);
+        for (int i = 0; i <= dim; ++i) {
+            s2[i] = s[ord[i]];
+            f2[i] = fv[ord[i]];
+        }
+        s.swap(s2);
+        fv.swap(f2);
+        if (std::fabs(fv[dim] - fv[0]) < 1e-9) break;
+        std::vector<double> cen(dim, 0.0);
+        for (int i = 0; i < dim; ++i)
+            for (int k = 0; k < dim; ++k) cen[k] += s[i][k] / dim;
+        auto lerp = [&](double t) {
+            std::vector<double> p(dim);
+            for (int k = 0; k < dim; ++k) p[k] = cen[k] + t * (s[dim][k] - cen[k]);
+            return p;
+        };
+        std::vector<double> xr = lerp(-1.0);
+        double fr = f(xr);
+        if (fr < fv[0]) {
+            std::vector<double> xe = lerp(-2.0);
+            double fe = f(xe);
+            if (fe < fr) { s[dim] = xe; fv[dim] = fe; } else { s[dim] = xr; fv[dim] = fr; }
+        } else if (fr < fv[dim - 1]) {
+            s[dim] = xr;
+            fv[dim] = fr;
+        } else {
+            std::vector<double> xc = lerp(fr < fv[dim] ? -0.5 : 0.5);
+            double fc = f(xc);
+            if (fc < std::min(fr, fv[dim])) {
+                s[dim] = xc;
+                fv[dim] = fc;
+            } else {
+                for (int i = 1; i <= dim; ++i) {
+                    for (int k = 0; k < dim; ++k) s[i][k] = s[0][k] + 0.5 * (s[i][k] - s[0][k]);
+                    fv[i] = f(s[i]);
+                }
             }
         }
     }
-    return default_config(op, dtype, n, c);
+    int best = (int)(std::min_element(fv.begin(), fv.end()) - fv.begin());
+    return s[best];
+}
+
+// Fits hyperparameters by maximum marginal likelihood; y already standardised.
+static bool fit_gp(GP &gp, const std::vector<double> &X, const std::vector<double> &y, int n, int d) {
+    // theta = (log ls[0..d), log sf2, log noise), clamped to sane boxes
+    auto unpack = [&](const std::vector<double> &t, std::vector<double> &ls, double &sf2, double &nz) {
+        ls.resize(d);
+        for (int k = 0; k < d; ++k) ls[k] = std::exp(std::min(std::max(t[k], std::log(0.05)), std::log(20.0)));
+        sf2 = std::exp(std::min(std::max(t[d], std::log(0.05)), std::log(20.0)));
+        nz = std::exp(std::min(std::max(t[d + 1], std::log(1e-6)), std::log(1.0)));
+    };
+    auto nll = [&](const std::vector<double> &t) {
+        std::vector<double> ls;
+        double sf2, nz;
+        unpack(t, ls, sf2, nz);
+        GP g;
+        double lml;
+        if (!g.fit_fixed(X, y, n, d, ls.data(), sf2, nz, &lml)) return 1e30;
+        return -lml;
+    };
+    std::vector<double> best;
+    double bestv = 1e300;
+    for (double l0 : {std::log(0.25), std::log(1.0), std::log(3.0)}) {
+        std::vector<double> t0(d + 2, l0);
+        t0[d] = 0.0;
+        t0[d + 1] = std::log(1e-2);
+        std::vector<double> t = nelder_mead(nll, t0, 0.7, 300);
+        const double v = nll(t);
+        if (v < bestv) {
+            bestv = v;
+            best = t;
+        }
+    }
+    std::vector<double> ls;
+    double sf2, nz;
+    unpack(best, ls, sf2, nz);
+    return gp.fit_fixed(X, y, n, d, ls.data(), sf2, nz, nullptr);
+}
+
+static double norm_pdf(double z) { return std::exp(-0.5 * z * z) / std::sqrt(2 * M_PI); }
+static double norm_cdf(double z) { return 0.5 * std::erfc(-z / std::sqrt(2.0)); }
+
+static double expected_improvement(double mu, double sigma, double best) {
+    if (!(sigma > 0)) return std::max(best - mu, 0.0);
+    const double z = (best - mu) / sigma;
+    return (best - mu) * norm_cdf(z) + sigma * norm_pdf(z);
+}
+
+static void features(const ppx_config *c, int n, std::vector<double> &F, int &d) {
+    d = 4;
+    F.assign((size_t)n * d, 0.0);
+    for (int i = 0; i < n; ++i) {
+        F[i * d + 0] = std::log2((double)std::max(1, c[i].radix));
+        F[i * d + 1] = std::log2((double)std::max(1, c[i].threads_per_block));
+        F[i * d + 2] = std::log2((double)std::max(1, c[i].problems_per_block));
+        F[i * d + 3] = (double)c[i].algo;
+    }
+    for (int k = 0; k < d; ++k) {
+        double lo = 1e300, hi = -1e300;
+        for (int i = 0; i < n; ++i) {
+            lo = std::min(lo, F[i * d + k]);
+            hi = std::max(hi, F[i * d + k]);
+        }
+        for (int i = 0; i < n; ++i) F[i * d + k] = hi > lo ? (F[i * d + k] - lo) / (hi - lo) : 0.0;
+    }
+}
+
+static int bo_search_impl(const ppx_config *c, int n, ppx_eval_fn fn, void *user, int max_evals,
+                          int n_init, int patience, double min_rel, uint64_t seed, int *order,
+                          double *values, int *evals_used, int *best_index) {
+    if (n <= 0) return fail(PPX_EINVAL, "empty candidate list");
+    if (n_init <= 0) n_init = std::max(3, (int)std::ceil(0.05 * n));
+    if (patience <= 0) patience = 5;
+    if (max_evals <= 0 || max_evals > n) max_evals = n;
+    n_init = std::min(n_init, max_evals);
+    std::vector<double> F;
+    int d;
+    features(c, n, F, d);
+    std::vector<char> done(n, 0);
+    std::vector<int> ord;
+    std::vector<double> val;  // recorded cost (penalised on failure)
+    std::vector<char> failed;
+    double worst = 0, best = 1e300;
+    int best_i = -1, last_improve = 0;
+    auto evaluate = [&](int i) {
+        const double v = fn(&c[i], user);
+        done[i] = 1;
+        ord.push_back(i);
+        const bool bad = !(v >= 0) || !std::isfinite(v);
+        failed.push_back(bad);
+        val.push_back(bad ? -1.0 : v);
+        if (!bad) worst = std::max(worst, v);
+        // re-penalise every failure at 10x the worst valid cost so far
+        for (size_t k = 0; k < val.size(); ++k)
+            if (failed[k]) val[k] = worst > 0 ? 10.0 * worst : 1e9;
+        if (!bad && v < best * (1.0 - min_rel)) last_improve = (int)ord.size();
+        if (!bad && v < best) {
+            best = v;
+            best_i = i;
+        }
+    };
+    std::mt19937_64 rng(seed);
+    std::vector<int> perm(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::shuffle(perm.begin(), perm.end(), rng);
+    for (int k = 0; k < n_init; ++k) evaluate(perm[k]);
+    last_improve = std::max(last_improve, n_init);
+    while ((int)ord.size() < max_evals) {
+        if ((int)ord.size() - last_improve >= patience) break;
+        const int m = (int)ord.size();
+        std::vector<double> X((size_t)m * d), y(m);
+        for (int k = 0; k < m; ++k) {
+            std::copy(&F[ord[k] * d], &F[ord[k] * d] + d, &X[k * d]);
+            y[k] = std::log(std::max(val[k], 1e-30));
+        }
+        const double mean = std::accumulate(y.begin(), y.end(), 0.0) / m;
+        double sd = 0;
+        for (double v : y) sd += (v - mean) * (v - mean);
+        sd = m > 1 ? std::sqrt(sd / (m - 1)) : 1.0;
+        if (!(sd > 1e-12)) sd = 1.0;
+        for (double &v : y) v = (v - mean) / sd;
+        GP gp;
+        const bool ok = fit_gp(gp, X, y, m, d);
+        double ybest = 1e300;
+        for (double v : y) ybest = std::min(ybest, v);
+        int pick = -1;
+        double pv = -1;
+        for (int i = 0; i < n; ++i) {
+            if (done[i]) continue;
+            double ei;
+            if (ok) {
+                double mu, var;
+                gp.predict(&F[i * d], &mu, &var);
+                ei = expected_improvement(mu, std::sqrt(var), ybest);
+            } else {
+                ei = 0.0;
+            }
+            if (ei > pv) {
+                pv = ei;
+                pick = i;
+            }
+        }
+        if (pick < 0) break;
+        evaluate(pick);
+    }
+    for (size_t k = 0; k < ord.size(); ++k) {
+        if (order) order[k] = ord[k];
+        if (values) values[k] = val[k];
+    }
+    if (evals_used) *evals_used = (int)ord.size();
+    if (best_index) *best_index = best_i;
+    return best_i >= 0 ? PPX_OK : fail(PPX_ETIMEOUT, "every evaluated candidate failed");
+}
+
+// ============================================================ tune cache
+namespace {
+std::mutex g_cache_mu;
+struct CacheEntry {
+    ppx_config cfg;
+    double us;
+    int method;
+};
+std::map<std::tuple<int, int, int64_t, int>, CacheEntry> g_cache;  // (op, dtype, n, algo filter)
+}  // namespace
+
+bool cached_config(int op, int dtype, int64_t n, ppx_config &c) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find({op, dtype, n, -1});
+    if (it == g_cache.end()) return false;
+    c = it->second.cfg;
+    return true;
+}
+
+static void cache_put(int op, int dtype, int64_t n, int algo, const ppx_config &c, double us,
+                      int method) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache[{op, dtype, n, algo}] = CacheEntry{c, us, method};
+}
+
+void store_cached_config(int op, int dtype, int64_t n, const ppx_config &c) {
+    cache_put(op, dtype, n, -1, c, 0.0, -1);
+}
+
+// ============================================================ resources
+// VGPR counts reported by the compiler for this build's kernels, used only
+// when no device is present to ask (CPU-side resolution of a NULL config).
+static int static_vgprs(int op, int dtype, int P, int algo) {
+    if (op == PPX_OP_FFT) return P <= 2 ? 16 : P <= 4 ? 29 : P <= 8 ? 55 : P <= 16 ? 107 : 200;
+    if (op == PPX_OP_SCAN) return P <= 2 ? 10 : P <= 4 ? 12 : P <= 8 ? 16 : P <= 16 ? 24 : 40;
+    return dtype == PPX_F64 ? (algo == PPX_TRI_PCR ? 44 : 40) : (algo == PPX_TRI_PCR ? 32 : 28);
+}
+
+static const void *kernel_for(int op, int dtype, const ppx_config &c) {
+    switch (op) {
+        case PPX_OP_FFT: return fft_kernel(c.radix, c.elems_per_thread, c.algo);
+        case PPX_OP_SCAN: return scan_kernel(dtype, c.elems_per_thread, c.algo);
+        default: return tridiag_kernel(dtype, c.algo);
+    }
+}
+
+static int64_t dyn_lds(int op, int dtype, int64_t n, const ppx_config &c) {
+    switch (op) {
+        case PPX_OP_FFT: return fft_lds_bytes((int)n, c.problems_per_block, c.algo);
+        case PPX_OP_SCAN: return scan_lds_bytes((int)n, c.problems_per_block, c.elems_per_thread, dtype);
+        default: return tridiag_lds_bytes((int)n, c.problems_per_block, dtype, c.algo);
+    }
+}
+
+static int elem_bytes(int op, int dtype) {
+    if (op == PPX_OP_FFT) return 8;
+    if (op == PPX_OP_SCAN) return 4;
+    return dtype == PPX_F64 ? 32 : 16;  // four coefficients per equation
+}
+
+static int resources(int op, int dtype, int64_t n, const ppx_config &c, bool have_device,
+                     ppx_resource &r) {
+    r.threads = c.threads_per_block;
+    r.lds_bytes = (int32_t)dyn_lds(op, dtype, n, c);
+    r.regs_per_thread = static_vgprs(op, dtype, c.elems_per_thread, c.algo);
+    if (have_device) {
+        const void *k = kernel_for(op, dtype, c);
+        hipFuncAttributes a;
+        if (!k || hipFuncGetAttributes(&a, k) != hipSuccess) return fail(PPX_EHIP, "hipFuncGetAttributes failed");
+        r.regs_per_thread = a.numRegs;
+        r.lds_bytes += (int32_t)a.sharedSizeBytes;
+    }
+    (void)elem_bytes;
+    return PPX_OK;
+}
+
+// Premise (i) of the analytical model (coalesced global accesses) restated
+// for these kernels on gfx950: the scan kernel gives each lane P contiguous
+// elements, so a load instruction is contiguous across the wave only when
+// those P elements are one 16-byte vector (P <= 4).  The FFT and tridiagonal
+// kernels read consecutive elements with consecutive lanes for every P.
+static bool coalesced(int op, const ppx_config &c) {
+    return op != PPX_OP_SCAN || c.elems_per_thread * 4 <= 16;
+}
+
+// Flags of the gfx950 analytical model: the paper's guideline plus our grid
+// fill term and a 50% occupancy window.
+constexpr int kGfx950Flags = PPX_ANALYTICAL_GRID_FILL | PPX_ANALYTICAL_WINDOW_50;
+
+static std::vector<ppx_config> analytical_candidates(int op, const std::vector<ppx_config> &all) {
+    std::vector<ppx_config> out;
+    for (const auto &c : all)
+        if (coalesced(op, c)) out.push_back(c);
+    return out.empty() ? all : out;
+}
+
+// ============================================================ analytical config
+int analytical_config(int op, int dtype, int64_t n, int64_t batch, ppx_config &c) {
+    static std::mutex memo_mu;
+    static std::map<std::tuple<int, int, int64_t, int64_t, bool>, ppx_config> memo;
+    const bool have_device = device_info() != nullptr;
+    const auto key = std::make_tuple(op, dtype, n, batch, have_device);
+    {
+        std::lock_guard<std::mutex> lk(memo_mu);
+        auto it = memo.find(key);
+        if (it != memo.end()) {
+            c = it->second;
+            return PPX_OK;
+        }
+    }
+    const int total = enumerate_configs(op, dtype, n, nullptr, 0);
+    if (total <= 0) return default_config(op, dtype, n, c);
+    std::vector<ppx_config> all(total);
+    enumerate_configs(op, dtype, n, all.data(), total);
+    std::vector<ppx_config> cands = analytical_candidates(op, all);
+    const int cnt = (int)cands.size();
+    std::vector<ppx_resource> res(cnt);
+    for (int i = 0; i < cnt; ++i)
+        if (resources(op, dtype, n, cands[i], have_device, res[i]) != PPX_OK) return PPX_EHIP;
+    ppx_device_model m = gfx950_model();
+    const int pick = analytical_pick_impl(m, cands.data(), res.data(), cnt, batch, kGfx950Flags);
+    if (pick < 0) return default_config(op, dtype, n, c);
+    c = cands[pick];
+    std::lock_guard<std::mutex> lk(memo_mu);
+    memo[key] = c;
+    fail(PPX_OK, "");
+    return PPX_OK;
+}
+
+// ============================================================ GPU timing
+namespace {
+uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+double unif(uint64_t &s) { return (splitmix(s) >> 11) * (1.0 / 9007199254740992.0); }
+
+// Device buffers for one (op, dtype, n, batch), replicated into enough sets
+// that consecutive timed launches never reuse cached data.
+struct Bench {
+    int op, dtype;
+    int64_t n, batch;
+    std::vector<std::vector<void *>> sets;  // per set: in.. out
+    hipStream_t stream = nullptr;
+    std::vector<hipEvent_t> ev;
+
+    ~Bench() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (auto &s : sets)
+            for (void *p : s)
+                if (p) (void)hipFree(p);
+        for (auto e : ev) (void)hipEventDestroy(e);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    int init(int reps) {
+        const int64_t cnt = n * batch;
+        std::vector<size_t> bytes;
+        int nin;
+        if (op == PPX_OP_FFT) {
+            bytes = {size_t(cnt) * 8, size_t(cnt) * 8};
+            nin = 1;
+        } else if (op == PPX_OP_SCAN) {
+            bytes = {size_t(cnt) * 4, size_t(cnt) * 4};
+            nin = 1;
+        } else {
+            const size_t es = dtype == PPX_F64 ? 8 : 4;
+            bytes.assign(5, size_t(cnt) * es);
+            nin = 4;
+        }
+        size_t set_bytes = 0;
+        for (size_t b : bytes) set_bytes += b;
+        const size_t target = size_t(1) << 30;  // rotate through >= 1 GiB
+        int nsets = (int)std::min<size_t>(16, std::max<size_t>(2, (target + set_bytes - 1) / set_bytes));
+        // host copy of one input set (seeded synthetic values)
+        std::vector<std::vector<char>> host(nin);
+        uint64_t s = 0x5eed;
+        for (int k = 0; k < nin; ++k) host[k].resize(bytes[k]);
+        if (op == PPX_OP_FFT) {
+            float *f = reinterpret_cast<float *>(host[0].data());
+            for (int64_t i = 0; i < 2 * cnt; ++i) f[i] = (float)(2 * unif(s) - 1);
+        } else if (op == PPX_OP_SCAN) {
+            if (dtype == PPX_I32) {
+                int *v = reinterpret_cast<int *>(host[0].data());
+                for (int64_t i = 0; i < cnt; ++i) v[i] = (int)(splitmix(s) % 201) - 100;
+            } else {
+                float *v = reinterpret_cast<float *>(host[0].data());
+                for (int64_t i = 0; i < cnt; ++i) v[i] = (float)unif(s);
+            }
+        } else {
+            for (int64_t i = 0; i < cnt; ++i) {
+                const double a = 2 * unif(s) - 1, c = 2 * unif(s) - 1;
+                const double b = std::fabs(a) + std::fabs(c) + 1 + unif(s), d = 2 * unif(s) - 1;
+                const double v[4] = {a, b, c, d};
+                for (int k = 0; k < 4; ++k) {
+                    if (dtype == PPX_F64) reinterpret_cast<double *>(host[k].data())[i] = v[k];
+                    else reinterpret_cast<float *>(host[k].data())[i] = (float)v[k];
+                }
+            }
+        }
+        sets.assign(nsets, std::vector<void *>(bytes.size(), nullptr));
+        for (int si = 0; si < nsets; ++si)
+            for (size_t k = 0; k < bytes.size(); ++k) {
+                if (hipMalloc(&sets[si][k], bytes[k]) != hipSuccess) return fail(PPX_ENOMEM, "tune: out of device memory");
+                if ((int)k < nin) {
+                    if (hipMemcpy(sets[si][k], host[k].data(), bytes[k], hipMemcpyHostToDevice) != hipSuccess)
+                        return fail(PPX_EHIP, "tune: upload failed");
+                } else if (hipMemset(sets[si][k], 0, bytes[k]) != hipSuccess) {
+                    return fail(PPX_EHIP, "tune: memset failed");
+                }
+            }
+        if (hipStreamCreate(&stream) != hipSuccess) return fail(PPX_EHIP, "tune: stream creation failed");
+        ev.resize(2 * (size_t)reps);
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(PPX_EHIP, "tune: event creation failed");
+        return PPX_OK;
+    }
+
+    int launch(const ppx_config &c, int set) {
+        auto &b = sets[set % sets.size()];
+        const int ln = ilog2(n);
+        if (op == PPX_OP_FFT) return launch_fft(b[0], b[1], ln, batch, c, false, stream);
+        if (op == PPX_OP_SCAN) return launch_scan(b[0], b[1], ln, batch, dtype, c, stream);
+        return launch_tridiag(b[0], b[1], b[2], b[3], b[4], ln, batch, dtype, c, stream);
+    }
+
+    // Median microseconds over `reps` launches (after 3 warm-ups); negative
+    // on a launch failure or when the deadline passes.
+    double time(const ppx_config &c, int reps, double deadline_s) {
+        for (int w = 0; w < 3; ++w)
+            if (launch(c, w) != PPX_OK) return -1.0;
+        for (int r = 0; r < reps; ++r) {
+            (void)hipEventRecord(ev[2 * r], stream);
+            if (launch(c, r + 3) != PPX_OK) {
+                (void)hipStreamSynchronize(stream);
+                return -1.0;
+            }
+            (void)hipEventRecord(ev[2 * r + 1], stream);
+        }
+        const auto t0 = std::chrono::steady_clock::now();
+        while (hipEventQuery(ev[2 * reps - 1]) == hipErrorNotReady) {
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
+            const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (el > deadline_s) {
+                (void)hipStreamSynchronize(stream);  // drain before reuse
+                fail(PPX_ETIMEOUT, "candidate exceeded its deadline");
+                return -2.0;
+            }
+        }
+        std::vector<double> t(reps);
+        for (int r = 0; r < reps; ++r) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]) != hipSuccess) return -1.0;
+            t[r] = ms * 1e3;
+        }
+        std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
+        return t[reps / 2];
+    }
+};
+
+struct EvalCtx {
+    Bench *b;
+    int reps;
+    std::vector<std::pair<ppx_config, double>> *trace;
+};
+
+double eval_gpu(const ppx_config *c, void *user) {
+    auto *ctx = static_cast<EvalCtx *>(user);
+    const double us = ctx->b->time(*c, ctx->reps, 60.0);
+    if (ctx->trace) ctx->trace->push_back({*c, us});
+    return us;
+}
+}  // namespace
+
+static int tune_impl(int op, int dtype, int64_t n, int64_t batch, int method, int max_evals,
+                     int algo, int reps, ppx_tune_report *rep) {
+    if (!rep) return fail(PPX_EINVAL, "null report");
+    if (method < PPX_TUNE_EXHAUSTIVE || method > PPX_TUNE_LEARNED) return fail(PPX_EINVAL, "unknown tuning method");
+    if (batch < 1) return fail(PPX_EINVAL, "batch must be >= 1");
+    if (reps <= 0) reps = 100;
+    const int total = enumerate_configs(op, dtype, n, nullptr, 0);
+    if (total < 0) return total;
+    std::vector<ppx_config> all(total);
+    enumerate_configs(op, dtype, n, all.data(), total);
+    std::vector<ppx_config> cands;
+    for (const auto &c : all)
+        if (algo < 0 || c.algo == algo) cands.push_back(c);
+    if (cands.empty()) return fail(PPX_ECONFIG, "no valid configuration to tune");
+    if (!device_info()) return PPX_EDEVICE;
+    Bench bench;
+    bench.op = op;
+    bench.dtype = dtype;
+    bench.n = n;
+    bench.batch = batch;
+    int rc = bench.init(reps);
+    if (rc) return rc;
+    std::vector<std::pair<ppx_config, double>> trace;
+    EvalCtx ctx{&bench, reps, &trace};
+    const int nc = (int)cands.size();
+    int best = -1;
+    if (method == PPX_TUNE_EXHAUSTIVE) {
+        double bv = 1e300;
+        const int lim = max_evals > 0 ? std::min(max_evals, nc) : nc;
+        for (int i = 0; i < lim; ++i) {
+            const double v = eval_gpu(&cands[i], &ctx);
+            if (v >= 0 && v < bv) {
+                bv = v;
+                best = i;
+            }
+        }
+    } else if (method == PPX_TUNE_ANALYTICAL) {
+        const std::vector<ppx_config> sub = analytical_candidates(op, cands);
+        std::vector<ppx_resource> res(sub.size());
+        for (size_t i = 0; i < sub.size(); ++i)
+            if ((rc = resources(op, dtype, n, sub[i], true, res[i]))) return rc;
+        const int k = analytical_pick_impl(gfx950_model(), sub.data(), res.data(), (int)sub.size(),
+                                           batch, kGfx950Flags);
+        for (int i = 0; k >= 0 && i < nc; ++i)
+            if (std::memcmp(&cands[i], &sub[k], sizeof(ppx_config)) == 0) best = i;
+        if (best >= 0) eval_gpu(&cands[best], &ctx);  // timed once, for the report
+    } else {
+        std::vector<int> order(nc);
+        std::vector<double> vals(nc);
+        int used = 0;
+        rc = bo_search_impl(cands.data(), nc, eval_gpu, &ctx, max_evals, 0, 5, 0.01, 0x2310'16214ULL,
+                            order.data(), vals.data(), &used, &best);
+        if (rc) return rc;
+    }
+    if (best < 0) return fail(PPX_ETIMEOUT, "no candidate ran successfully");
+    double best_us = -1;
+    for (auto it = trace.rbegin(); it != trace.rend(); ++it)
+        if (std::memcmp(&it->first, &cands[best], sizeof(ppx_config)) == 0) {
+            best_us = it->second;
+            break;
+        }
+    rep->best = cands[best];
+    rep->best_us = best_us;
+    rep->evals_used = method == PPX_TUNE_ANALYTICAL ? 0 : (int)trace.size();
+    rep->ncands = nc;
+    if (rep->trace_cfg && rep->trace_us)
+        for (int i = 0; i < (int)trace.size() && i < rep->trace_cap; ++i) {
+            rep->trace_cfg[i] = trace[i].first;
+            rep->trace_us[i] = trace[i].second;
+        }
+    cache_put(op, dtype, n, algo, cands[best], best_us, method);
+    fail(PPX_OK, "");
+    return PPX_OK;
 }
 
 }  // namespace ppx
 
-extern "C" int tune(int, int, int64_t, int64_t, int, int, ppx_config *, double *, int *) {
-    return ppx::fail(PPX_EINVAL, "tune: not available in this build");
+using namespace ppx;
+
+extern "C" {
+
+int ppx_occupancy(const ppx_device_model *m, const ppx_resource *r, int32_t *blocks, int32_t *waves) {
+    if (!m || !r) return fail(PPX_EINVAL, "null argument");
+    int w = 0;
+    const int b = occupancy_blocks(*m, *r, &w);
+    if (blocks) *blocks = b;
+    if (waves) *waves = w;
+    return b > 0 ? PPX_OK : fail(PPX_ECONFIG, "the block cannot be resident");
 }
+
+int ppx_device_model_gfx950(ppx_device_model *out) {
+    if (!out) return fail(PPX_EINVAL, "null output");
+    *out = gfx950_model();
+    return PPX_OK;
+}
+
+int ppx_analytical_pick(const ppx_device_model *m, const ppx_config *cands, const ppx_resource *res,
+                        int ncands, int64_t batch, int flags, int *chosen) {
+    if (!m || !cands || !res || !chosen || ncands <= 0) return fail(PPX_EINVAL, "bad argument");
+    const int k = analytical_pick_impl(*m, cands, res, ncands, batch, flags);
+    *chosen = k;
+    return k >= 0 ? PPX_OK : fail(PPX_ECONFIG, "no candidate can be resident");
+}
+
+int ppx_bo_search(const ppx_config *cands, int ncands, ppx_eval_fn fn, void *user, int max_evals,
+                  int n_init, int patience, double min_rel_improvement, uint64_t seed,
+                  int *order_out, double *values_out, int *evals_used, int *best_index) {
+    if (!cands || !fn) return fail(PPX_EINVAL, "bad argument");
+    return bo_search_impl(cands, ncands, fn, user, max_evals, n_init, patience, min_rel_improvement,
+                          seed, order_out, values_out, evals_used, best_index);
+}
+
+int ppx_gp_posterior(const double *X, const double *y, int n, int d, const double *ls,
+                     double sigma_f2, double noise2, const double *Xq, int m, double *mean,
+                     double *var) {
+    if (!X || !y || !ls || !Xq || !mean || !var || n <= 0 || d <= 0 || m < 0)
+        return fail(PPX_EINVAL, "bad argument");
+    GP gp;
+    std::vector<double> Xv(X, X + (size_t)n * d), yv(y, y + n);
+    if (!gp.fit_fixed(Xv, yv, n, d, ls, sigma_f2, noise2, nullptr))
+        return fail(PPX_EINVAL, "kernel matrix is not positive definite");
+    for (int i = 0; i < m; ++i) gp.predict(Xq + (size_t)i * d, &mean[i], &var[i]);
+    return PPX_OK;
+}
+
+double ppx_expected_improvement(double mu, double sigma, double best) {
+    return expected_improvement(mu, sigma, best);
+}
+
+int ppx_tune_ex(int op, int dtype, int64_t n, int64_t batch, int method, int max_evals, int algo,
+                int reps, ppx_tune_report *report) {
+    return tune_impl(op, dtype, n, batch, method, max_evals, algo, reps, report);
+}
+
+int tune(int op, int dtype, int64_t n, int64_t batch, int method, int max_evals, ppx_config *best,
+         double *best_us, int *evals_used) {
+    if (!best) return fail(PPX_EINVAL, "null output");
+    ppx_tune_report rep{};
+    const int rc = tune_impl(op, dtype, n, batch, method, max_evals, -1, 0, &rep);
+    if (rc) return rc;
+    *best = rep.best;
+    if (best_us) *best_us = rep.best_us;
+    if (evals_used) *evals_used = rep.evals_used;
+    if (const char *path = std::getenv("PPX_TUNE_CACHE")) ppx_tune_cache_save(path);
+    return PPX_OK;
+}
+
+int ppx_time_config(int op, int dtype, int64_t n, int64_t batch, const ppx_config *cfg, int reps,
+                    double *median_us) {
+    if (!cfg || !median_us) return fail(PPX_EINVAL, "null argument");
+    ppx_config c = *cfg;
+    complete_config(op, dtype, n, c);
+    int rc = validate_config(op, dtype, n, c);
+    if (rc) return rc;
+    if (batch < 1) return fail(PPX_EINVAL, "batch must be >= 1");
+    if (!device_info()) return PPX_EDEVICE;
+    if (reps <= 0) reps = 100;
+    Bench bench;
+    bench.op = op;
+    bench.dtype = dtype;
+    bench.n = n;
+    bench.batch = batch;
+    if ((rc = bench.init(reps))) return rc;
+    const double us = bench.time(c, reps, 60.0);
+    if (us < 0) return us < -1.5 ? PPX_ETIMEOUT : fail(PPX_EHIP, "timed launch failed");
+    *median_us = us;
+    return PPX_OK;
+}
+
+int ppx_kernel_resources(int op, int dtype, int64_t n, const ppx_config *cfg, ppx_resource *out) {
+    if (!cfg || !out) return fail(PPX_EINVAL, "null argument");
+    ppx_config c = *cfg;
+    complete_config(op, dtype, n, c);
+    int rc = validate_config(op, dtype, n, c);
+    if (rc) return rc;
+    if (!device_info()) return PPX_EDEVICE;
+    return resources(op, dtype, n, c, true, *out);
+}
+
+int ppx_tune_cache_load(const char *path) {
+    if (!path) return fail(PPX_EINVAL, "null path");
+    std::ifstream f(path);
+    if (!f) return fail(PPX_EINVAL, std::string("cannot open ") + path);
+    std::string line;
+    int count = 0;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream is(line);
+        std::string arch;
+        int op, dtype, algo, method;
+        int64_t n;
+        ppx_config c{};
+        double us;
+        if (!(is >> arch >> op >> dtype >> n >> algo >> c.radix >> c.elems_per_thread >>
+              c.threads_per_block >> c.problems_per_block >> c.lds_elems >> c.algo >> us >> method))
+            return fail(PPX_EINVAL, "malformed tune cache line: " + line);
+        if (arch != "gfx950") continue;
+        ppx_config v = c;
+        complete_config(op, dtype, n, v);
+        if (validate_config(op, dtype, n, v) != PPX_OK) continue;  // stale entry
+        cache_put(op, dtype, n, algo, v, us, method);
+        ++count;
+    }
+    fail(PPX_OK, "");
+    return count;
+}
+
+int ppx_tune_cache_save(const char *path) {
+    if (!path) return fail(PPX_EINVAL, "null path");
+    std::ofstream f(path);
+    if (!f) return fail(PPX_EINVAL, std::string("cannot write ") + path);
+    f << "# arch op dtype n algo_filter radix P L G_b S algo us method\n";
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (const auto &kv : g_cache) {
+        const auto &c = kv.second.cfg;
+        f << "gfx950 " << std::get<0>(kv.first) << ' ' << std::get<1>(kv.first) << ' '
+          << std::get<2>(kv.first) << ' ' << std::get<3>(kv.first) << ' ' << c.radix << ' '
+          << c.elems_per_thread << ' ' << c.threads_per_block << ' ' << c.problems_per_block << ' '
+          << c.lds_elems << ' ' << c.algo << ' ' << kv.second.us << ' ' << kv.second.method << '\n';
+    }
+    return f ? PPX_OK : fail(PPX_EINVAL, "write failed");
+}
+
+int ppx_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache.clear();
+    return PPX_OK;
+}
+
+int ppx_tuned_config(int op, int dtype, int64_t n, int algo, ppx_config *out) {
+    if (!out) return fail(PPX_EINVAL, "null output");
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find({op, dtype, n, algo});
+    if (it == g_cache.end()) return fail(PPX_EINVAL, "no tuned entry");
+    *out = it->second.cfg;
+    return PPX_OK;
+}
+
+}  // extern "C"

@@ -16,6 +16,7 @@ import threading
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libppx.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "ppx.h")
+HEADERS = [HEADER, os.path.join(os.path.dirname(_PKG), "include", "ppx_tune.h")]
 
 # ---- constants mirrored from include/ppx.h ----
 OK, EINVAL, ECONFIG, EDEVICE, EHIP, ENOMEM, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
@@ -64,11 +65,15 @@ _lib = None
 _lock = threading.Lock()
 
 
-def header_functions():
-    """Names of the functions declared in include/ppx.h."""
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)
+def header_functions(paths=None):
+    """Names of the functions declared in the include/*.h headers."""
+    names = []
+    for path in paths or HEADERS:
+        txt = open(path).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        txt = re.sub(r"typedef[^;]*;", "", txt, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)
+    return names
 
 
 def lib():
@@ -193,3 +198,181 @@ def enumerate_configs(op, dtype, n):
     arr = (Config * max(cnt, 1))()
     _check(lib().ppx_enumerate_configs(op, dtype, n, arr, cnt))
     return [arr[i] for i in range(cnt)]
+
+
+# ---------------------------------------------------------------- tuning engine
+# (declared in include/ppx_tune.h)
+
+class DeviceModel(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in (
+        "wave_size", "partitions", "regs_per_partition", "reg_granule", "max_waves_per_cu",
+        "max_blocks_per_cu", "lds_per_cu", "lds_per_block", "lds_granule", "num_cus")]
+
+
+class Resource(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("regs_per_thread", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("best", Config), ("best_us", ctypes.c_double), ("evals_used", ctypes.c_int32),
+                ("ncands", ctypes.c_int32), ("trace_cfg", ctypes.POINTER(Config)),
+                ("trace_us", ctypes.POINTER(ctypes.c_double)), ("trace_cap", ctypes.c_int32)]
+
+
+EVAL_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(Config), ctypes.c_void_p)
+ANALYTICAL_GRID_FILL, ANALYTICAL_WINDOW_50 = 1, 4
+
+_tune_sigs = {
+    "ppx_occupancy": ([ctypes.POINTER(DeviceModel), ctypes.POINTER(Resource),
+                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "ppx_device_model_gfx950": ([ctypes.POINTER(DeviceModel)], ctypes.c_int),
+    "ppx_analytical_pick": ([ctypes.POINTER(DeviceModel), ctypes.POINTER(Config),
+                             ctypes.POINTER(Resource), ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                             ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "ppx_bo_search": ([ctypes.POINTER(Config), ctypes.c_int, EVAL_FN, ctypes.c_void_p, ctypes.c_int,
+                       ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
+                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "ppx_gp_posterior": ([ctypes.POINTER(ctypes.c_double)] * 2 + [ctypes.c_int] * 2 +
+                         [ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double,
+                          ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                         ctypes.c_int),
+    "ppx_expected_improvement": ([ctypes.c_double] * 3, ctypes.c_double),
+    "ppx_tune_ex": ([ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(TuneReport)],
+                    ctypes.c_int),
+    "ppx_time_config": ([ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                         ctypes.POINTER(Config), ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
+                        ctypes.c_int),
+    "ppx_kernel_resources": ([ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(Config),
+                              ctypes.POINTER(Resource)], ctypes.c_int),
+    "ppx_tune_cache_load": ([ctypes.c_char_p], ctypes.c_int),
+    "ppx_tune_cache_save": ([ctypes.c_char_p], ctypes.c_int),
+    "ppx_tune_cache_clear": ([], ctypes.c_int),
+    "ppx_tuned_config": ([ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                          ctypes.POINTER(Config)], ctypes.c_int),
+}
+
+
+def _tl(name):
+    f = getattr(lib(), name)
+    if not getattr(f, "_ppx_typed", False):
+        f.argtypes, f.restype = _tune_sigs[name]
+        f._ppx_typed = True
+    return f
+
+
+def occupancy(model, res):
+    b, w = ctypes.c_int32(0), ctypes.c_int32(0)
+    _tl("ppx_occupancy")(ctypes.byref(model), ctypes.byref(res), ctypes.byref(b), ctypes.byref(w))
+    return b.value, w.value
+
+
+def device_model_gfx950():
+    m = DeviceModel()
+    _check(_tl("ppx_device_model_gfx950")(ctypes.byref(m)))
+    return m
+
+
+def analytical_pick(model, cands, resources, batch, flags=0):
+    n = len(cands)
+    ca = (Config * n)(*cands)
+    ra = (Resource * n)(*resources)
+    k = ctypes.c_int(-1)
+    _check(_tl("ppx_analytical_pick")(ctypes.byref(model), ca, ra, n, batch, flags, ctypes.byref(k)))
+    return k.value
+
+
+def bo_search(cands, evaluate, max_evals=0, n_init=0, patience=0, min_rel=0.01, seed=0):
+    """Bayesian search with a Python evaluator evaluate(Config) -> cost (<0 = failed).
+    Returns (best_index, order, values)."""
+    n = len(cands)
+    ca = (Config * n)(*cands)
+    order = (ctypes.c_int * n)()
+    vals = (ctypes.c_double * n)()
+    used, best = ctypes.c_int(0), ctypes.c_int(-1)
+    errors = []
+
+    def _cb(cp, _user):
+        try:
+            return float(evaluate(cp.contents))
+        except Exception as e:  # a failing evaluator is a failed run
+            errors.append(e)
+            return -1.0
+    cb = EVAL_FN(_cb)
+    _check(_tl("ppx_bo_search")(ca, n, cb, None, max_evals, n_init, patience, min_rel, seed,
+                                order, vals, ctypes.byref(used), ctypes.byref(best)))
+    k = used.value
+    return best.value, list(order[:k]), list(vals[:k])
+
+
+def gp_posterior(X, y, lengthscales, sigma_f2, noise2, Xq):
+    import numpy as np
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Xq = np.ascontiguousarray(Xq, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    ls = np.ascontiguousarray(lengthscales, dtype=np.float64)
+    n, d = X.shape
+    m = Xq.shape[0]
+    mu = np.empty(m)
+    var = np.empty(m)
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    _check(_tl("ppx_gp_posterior")(dp(X), dp(y), n, d, dp(ls), sigma_f2, noise2, dp(Xq), m,
+                                   dp(mu), dp(var)))
+    return mu, var
+
+
+def expected_improvement(mu, sigma, best):
+    return _tl("ppx_expected_improvement")(mu, sigma, best)
+
+
+def tune_ex(op, dtype, n, batch, method, max_evals=0, algo=-1, reps=0, trace_cap=256):
+    rep = TuneReport()
+    tc = (Config * trace_cap)()
+    tu = (ctypes.c_double * trace_cap)()
+    rep.trace_cfg = tc
+    rep.trace_us = tu
+    rep.trace_cap = trace_cap
+    _check(_tl("ppx_tune_ex")(op, dtype, n, batch, method, max_evals, algo, reps, ctypes.byref(rep)))
+    k = min(rep.evals_used if method != TUNE_ANALYTICAL else 1, trace_cap)
+    return rep, [(tc[i], tu[i]) for i in range(k)]
+
+
+def time_config(op, dtype, n, batch, cfg, reps=0):
+    us = ctypes.c_double(0)
+    _check(_tl("ppx_time_config")(op, dtype, n, batch, ctypes.byref(cfg), reps, ctypes.byref(us)))
+    return us.value
+
+
+def kernel_resources(op, dtype, n, cfg):
+    r = Resource()
+    _check(_tl("ppx_kernel_resources")(op, dtype, n, ctypes.byref(cfg), ctypes.byref(r)))
+    return r
+
+
+def load_tune_cache(path):
+    return _check(_tl("ppx_tune_cache_load")(os.fsencode(path)))
+
+
+def save_tune_cache(path):
+    _check(_tl("ppx_tune_cache_save")(os.fsencode(path)))
+
+
+def clear_tune_cache():
+    _tl("ppx_tune_cache_clear")()
+
+
+def tuned_config(op, dtype, n, algo=-1):
+    c = Config()
+    if _tl("ppx_tuned_config")(op, dtype, n, algo, ctypes.byref(c)) != OK:
+        return None
+    return c
+
+
+def phi(efficiencies):
+    """Harmonic mean of per-size efficiencies (Sec. VI's performance-portability
+    metric): |C| / sum 1/e_i."""
+    e = [float(v) for v in efficiencies]
+    return len(e) / sum(1.0 / v for v in e)
