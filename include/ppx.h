@@ -147,6 +147,47 @@ int tridiag_batched(const void *a, const void *b, const void *c, const void *d,
 int tune(int op, int dtype, int64_t n, int64_t batch, int method, int max_evals,
          ppx_config *best, double *best_us, int *evals_used);
 
+/*
+ * One job of a mixed launch: a whole batched call of any operation.
+ *   op, dtype, n, batch   as in the single calls
+ *   direction             FFT only: -1 forward, +1 inverse
+ *   algo                  tridiagonal only: PPX_TRI_CR or PPX_TRI_PCR
+ *   in                    FFT / scan input; tridiagonal: a
+ *   b, c, d               tridiagonal only (NULL otherwise)
+ *   out                   FFT / scan output; tridiagonal: x
+ * Device pointers, 16-byte aligned, caller-owned; aliasing as in the single
+ * calls.  Tridiagonal systems must fit one fused tile's 128 KiB of LDS
+ * (float32 CR: n <= 8192; PCR or float64: n <= 4096; float64 PCR: n <= 2048).
+ */
+typedef struct ppx_job {
+    int32_t op;
+    int32_t dtype;
+    int32_t direction;
+    int32_t algo;
+    int64_t n;
+    int64_t batch;
+    const void *in;
+    const void *b;
+    const void *c;
+    const void *d;
+    void *out;
+} ppx_job;
+
+/*
+ * launch_mixed -- Sec. IV-A's batched invocation extended to a batch of
+ * uneven jobs (different operations, sizes and batch counts) in ONE
+ * persistent launch.  Every job is cut into tiles whose shape depends only on
+ * (op, dtype, n, algo), so each job's output is bit-identical whatever else
+ * shares the launch.  Asynchronous and stream-ordered; allocates nothing
+ * (device tables are created on a device's first mixed launch).  At most
+ * 16384 jobs and 262144 tiles per launch (PPX_EINVAL beyond).  Each job's
+ * result equals the single call's within that call's tolerance.
+ */
+int launch_mixed(const ppx_job *jobs, int njobs, void *stream);
+
+/* Problems per tile the mixed launch uses for a job of (op, dtype, n, algo). */
+int ppx_mixed_tile_problems(int op, int dtype, int64_t n, int algo);
+
 /* ---------------------------------------------------------------------- */
 /* Helpers                                                                 */
 /* ---------------------------------------------------------------------- */

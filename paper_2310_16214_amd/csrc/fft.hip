@@ -1,183 +1,7 @@
-// Batched complex FFT, Stockham autosort formulation (Sec. III of
-// arXiv:2310.16214; radix r tunable, Sec. IV-A/V-C), for gfx950.
-//
-// A workgroup of L threads transforms G_b problems of size n; each problem is
-// owned by T = n/P consecutive threads and thread `tid` of a problem always
-// holds the P elements X[tid + j*T], j < P.  Stage s (radix RS, span Ns =
-// product of the earlier radices) performs, for every butterfly t < n/RS with
-// k = t mod Ns:
-//     u_q = X[t + q*n/RS] * w_{Ns*RS}^{q*k},  u = DFT_RS(u),
-//     Y[(t div Ns)*Ns*RS + k + q*Ns] = u_q,   q < RS,
-// so each thread does P/RS butterflies per stage, and its inputs are exactly
-// the P values it holds.  When log2 n is not a multiple of log2 r the first
-// stage uses radix 2^(log2 n mod log2 r) (mixed radix).  The first stage reads
-// global memory directly (consecutive threads read consecutive elements), the
-// last writes global memory directly (likewise coalesced), and the stages in
-// between exchange through LDS: either complex values, or -- to halve the LDS
-// footprint (Sec. V-C) -- the real parts and then the imaginary parts through
-// one float buffer.  Twiddles come from one table of w_NMAX^m held in global
-// memory (cache resident), computed on the host in double precision.
-#include <hip/hip_runtime.h>
-
-#include "device.h"
-#include "ppx_internal.h"
+// Host launcher of the kernels in fft_device.h.
+#include "fft_device.h"
 
 namespace ppx {
-
-constexpr int kNMax = 1 << kFftLog2NMax;
-
-// LDS index swizzles that keep the strided Stockham writes free of bank
-// conflicts without padding (the footprint stays n elements per problem).
-__device__ __forceinline__ int swz_c(int p) { return p ^ ((p >> 4) & 15); }  // float2 words
-__device__ __forceinline__ int swz_f(int p) { return p ^ ((p >> 5) & 31); }  // float words
-
-// The first stage (span 1) has no twiddles; it is a separate instantiation
-// (FIRST) rather than a runtime branch, so no control-flow join surrounds the
-// twiddle products.  (gfx950 code generation with packed-FP32 selection off
-// dropped the join copies of such a branch in the radix-4 kernel, feeding
-// untwiddled imaginary parts to the butterfly.)
-template <int RS, int P, bool FIRST>
-__device__ __forceinline__ void stage_butterflies(float2 (&v)[P], int tid, int T, int lns,
-                                                  const float2 *__restrict__ tw) {
-    constexpr int NB = P / RS;
-    constexpr int LRS = RS == 2 ? 1 : RS == 4 ? 2 : RS == 8 ? 3 : 4;
-    const int twshift = kFftLog2NMax - (lns + LRS);
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        float2 u[RS];
-#pragma unroll
-        for (int q = 0; q < RS; ++q) u[q] = v[i + q * NB];
-        if constexpr (!FIRST) {
-            const int k = (tid + i * T) & ((1 << lns) - 1);
-#pragma unroll
-            for (int q = 1; q < RS; ++q) u[q] = cmul(u[q], tw[(q * k) << twshift]);
-        }
-        RegDFT<RS>::run(u);
-#pragma unroll
-        for (int q = 0; q < RS; ++q) v[i + q * NB] = u[q];
-    }
-}
-
-// Output position (within the problem) of slot (i, q) after a stage.
-template <int RS>
-__device__ __forceinline__ int stage_out_pos(int t, int lns, int q) {
-    constexpr int LRS = RS == 2 ? 1 : RS == 4 ? 2 : RS == 8 ? 3 : 4;
-    const int k = t & ((1 << lns) - 1);
-    return ((t >> lns) << (lns + LRS)) + k + (q << lns);
-}
-
-template <int RS, int P, bool SPLIT>
-__device__ __forceinline__ void stage_exchange(float2 (&v)[P], void *lds_problem, int tid, int T,
-                                               int lns) {
-    constexpr int NB = P / RS;
-    if constexpr (!SPLIT) {
-        float2 *buf = static_cast<float2 *>(lds_problem);
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-            for (int q = 0; q < RS; ++q)
-                buf[swz_c(stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB];
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < P; ++j) v[j] = buf[swz_c(tid + j * T)];
-        __syncthreads();
-    } else {
-        float *buf = static_cast<float *>(lds_problem);
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-            for (int q = 0; q < RS; ++q)
-                buf[swz_f(stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB].x;
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < P; ++j) v[j].x = buf[swz_f(tid + j * T)];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-            for (int q = 0; q < RS; ++q)
-                buf[swz_f(stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB].y;
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < P; ++j) v[j].y = buf[swz_f(tid + j * T)];
-        __syncthreads();
-    }
-}
-
-template <int RS, int P>
-__device__ __forceinline__ void stage_store(const float2 (&v)[P], float2 *dst, int tid, int T,
-                                            int lns, float sgn) {
-    constexpr int NB = P / RS;
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int q = 0; q < RS; ++q) {
-            const float2 o = v[i + q * NB];
-            dst[stage_out_pos<RS>(tid + i * T, lns, q)] = make_float2(o.x, sgn * o.y);
-        }
-}
-
-// One stage of radix RS followed by either the LDS exchange or, for the last
-// stage, the global store.
-template <int RS, int P, bool SPLIT, bool FIRST>
-__device__ __forceinline__ void run_stage(float2 (&v)[P], void *lds_problem, float2 *dst, int tid,
-                                          int T, int &lns, int log2n, bool active, float sgn,
-                                          const float2 *__restrict__ tw) {
-    constexpr int LRS = RS == 2 ? 1 : RS == 4 ? 2 : RS == 8 ? 3 : 4;
-    stage_butterflies<RS, P, FIRST>(v, tid, T, lns, tw);
-    if (lns + LRS == log2n) {
-        if (active) stage_store<RS, P>(v, dst, tid, T, lns, sgn);
-    } else {
-        stage_exchange<RS, P, SPLIT>(v, lds_problem, tid, T, lns);
-    }
-    lns += LRS;
-}
-
-template <int R, int P, bool SPLIT>
-__global__ __launch_bounds__(fft_max_threads(P)) void k_fft(const float2 *in, float2 *out,
-                                              const float2 *__restrict__ tw, int log2n,
-                                              long long batch, int gb, float sgn) {
-    extern __shared__ float4 lds_raw[];
-    constexpr int LR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
-    const int n = 1 << log2n;
-    const int lT = log2n - (P == 2 ? 1 : P == 4 ? 2 : P == 8 ? 3 : P == 16 ? 4 : 5);
-    const int T = 1 << lT;
-    const int lp = threadIdx.x >> lT;
-    const int tid = threadIdx.x & (T - 1);
-    const long long prob = (long long)blockIdx.x * gb + lp;
-    const bool active = prob < batch;
-    const float2 *src = in + prob * n;
-    float2 *dst = out + prob * n;
-    void *lds_problem = SPLIT ? (void *)(reinterpret_cast<float *>(lds_raw) + (size_t)lp * n)
-                              : (void *)(reinterpret_cast<float2 *>(lds_raw) + (size_t)lp * n);
-
-    float2 v[P];
-    if (active) {
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const float2 x = src[tid + j * T];
-            v[j] = make_float2(x.x, sgn * x.y);
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < P; ++j) v[j] = make_float2(0.f, 0.f);
-    }
-
-    // first stage: radix 2^(log2 n mod log2 R) when R does not divide log2 n
-    int lns = 0;
-    const int rem = log2n % LR;
-    if (rem == 0) {
-        run_stage<R, P, SPLIT, true>(v, lds_problem, dst, tid, T, lns, log2n, active, sgn, tw);
-    } else if (rem == 1) {
-        run_stage<2, P, SPLIT, true>(v, lds_problem, dst, tid, T, lns, log2n, active, sgn, tw);
-    } else if constexpr (R >= 8) {
-        if (rem == 2) run_stage<4, P, SPLIT, true>(v, lds_problem, dst, tid, T, lns, log2n, active, sgn, tw);
-        if constexpr (R >= 16)
-            if (rem == 3) run_stage<8, P, SPLIT, true>(v, lds_problem, dst, tid, T, lns, log2n, active, sgn, tw);
-    }
-    while (lns < log2n)
-        run_stage<R, P, SPLIT, false>(v, lds_problem, dst, tid, T, lns, log2n, active, sgn, tw);
-}
 
 // ------------------------------------------------------------------- host
 

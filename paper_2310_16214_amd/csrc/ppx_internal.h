@@ -86,6 +86,13 @@ const void *tridiag_kernel(int dtype, int algo);
 // (float pairs from double-precision sincos).
 void fft_host_twiddles(float *out2);
 
+// ---- mixed launch (fused.hip) ----
+int check_job(const ppx_job &j);
+int64_t fused_tile_problems(int op, int dtype, int64_t n, int algo);
+int64_t mixed_tile_count(const ppx_job *jobs, int njobs);
+// launch_mixed with an optional extra event recorded after the launch.
+int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEvent_t done_event);
+
 // ---- configuration logic (config.cpp) ----
 int validate_config(int op, int dtype, int64_t n, const ppx_config &c);
 void complete_config(int op, int dtype, int64_t n, ppx_config &c);

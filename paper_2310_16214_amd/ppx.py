@@ -376,3 +376,43 @@ def phi(efficiencies):
     metric): |C| / sum 1/e_i."""
     e = [float(v) for v in efficiencies]
     return len(e) / sum(1.0 / v for v in e)
+
+
+# ---------------------------------------------------------------- mixed launch
+
+class Job(ctypes.Structure):
+    """ppx_job: one whole batched call inside a mixed launch."""
+    _fields_ = [("op", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("direction", ctypes.c_int32), ("algo", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("batch", ctypes.c_int64),
+                ("in_", ctypes.c_void_p), ("b", ctypes.c_void_p), ("c", ctypes.c_void_p),
+                ("d", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+def make_job(op, dtype, n, batch, inp, out, direction=-1, algo=0, b=None, c=None, d=None):
+    return Job(op, dtype, direction, algo, n, batch, _ptr(inp), _ptr(b), _ptr(c), _ptr(d),
+               _ptr(out))
+
+
+def launch_mixed(jobs, stream=None):
+    """One persistent fused launch over a list of Job (see include/ppx.h)."""
+    L = lib()
+    f = L.launch_mixed
+    if not getattr(f, "_ppx_typed", False):
+        f.argtypes = [ctypes.POINTER(Job), ctypes.c_int, ctypes.c_void_p]
+        f.restype = ctypes.c_int
+        f._ppx_typed = True
+    arr = (Job * len(jobs))(*jobs)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    elif hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    _check(f(arr, len(jobs), stream))
+
+
+def mixed_tile_problems(op, dtype, n, algo=0):
+    f = lib().ppx_mixed_tile_problems
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
+    f.restype = ctypes.c_int
+    return f(op, dtype, n, algo)
