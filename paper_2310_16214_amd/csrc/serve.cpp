@@ -1,0 +1,380 @@
+// Continuous-batching request loop (include/ppx_serve.h): FIFO admission by
+// HBM budget, one mixed persistent launch per progress step over everything
+// admitted since the last launch, several launches in flight on separate
+// streams, completion by events.  The per-request mode is the baseline.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ppx_serve.h"
+#include "../../include/ppx_tune.h"
+#include "ppx_internal.h"
+
+namespace ppx {
+namespace {
+
+int64_t elem_bytes(int dtype) { return dtype == PPX_C64 || dtype == PPX_F64 ? 8 : 4; }
+
+int64_t job_in_bytes(const ppx_job &j) {
+    return (j.op == PPX_OP_TRIDIAG ? 4 : 1) * j.n * j.batch * elem_bytes(j.dtype);
+}
+int64_t job_out_bytes(const ppx_job &j) { return j.n * j.batch * elem_bytes(j.dtype); }
+
+// First-fit allocator over [0, size) with coalescing of free neighbours.
+class Arena {
+  public:
+    void reset(int64_t size) {
+        free_.clear();
+        if (size > 0) free_[0] = size;
+    }
+    int64_t alloc(int64_t bytes) {
+        bytes = (bytes + 255) & ~int64_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= bytes) {
+                const int64_t off = it->first, rest = it->second - bytes;
+                free_.erase(it);
+                if (rest > 0) free_[off + bytes] = rest;
+                return off;
+            }
+        return -1;
+    }
+    void release(int64_t off, int64_t bytes) {
+        bytes = (bytes + 255) & ~int64_t(255);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<int64_t, int64_t> free_;
+};
+
+struct Job {
+    int64_t id;
+    ppx_job job;
+    double arrival_us = 0, admit_us = 0, complete_us = 0;
+    int64_t footprint = 0, arena_off = -1;
+    bool completed = false;
+};
+
+struct Launch {
+    std::vector<int64_t> ids;
+    hipEvent_t done = nullptr;
+    int stream = 0;
+};
+
+}  // namespace
+}  // namespace ppx
+
+struct ppx_server {
+    int flags = 0, max_inflight = 1;
+    int64_t budget = 0, used = 0, peak = 0;
+    char *arena_base = nullptr;
+    ppx::Arena arena;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> free_events;
+    std::deque<int64_t> pending;
+    std::unordered_map<int64_t, ppx::Job> jobs;
+    std::deque<ppx::Launch> inflight;
+    std::deque<int64_t> completed;
+    int64_t next_id = 1, submitted = 0, admitted = 0, ncompleted = 0, released = 0, launches = 0;
+    int max_inflight_seen = 0, rr = 0;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    bool null_device() const { return flags & PPX_SERVE_NULL_DEVICE; }
+    bool per_request() const { return flags & PPX_SERVE_PER_REQUEST; }
+    double now_us() const {
+        return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace ppx {
+namespace {
+
+hipEvent_t take_event(ppx_server *s) {
+    if (s->null_device()) return nullptr;
+    if (!s->free_events.empty()) {
+        hipEvent_t e = s->free_events.back();
+        s->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+int launch_single(const ppx_job &j, hipStream_t st) {
+    switch (j.op) {
+        case PPX_OP_FFT: return fft_batched(j.in, j.out, j.n, j.batch, j.direction, nullptr, st);
+        case PPX_OP_SCAN: return scan_batched(j.in, j.out, j.n, j.batch, j.dtype, nullptr, st);
+        default: {
+            ppx_config c{};
+            if (ppx_resolve_config(PPX_OP_TRIDIAG, j.dtype, j.n, j.batch, &c) != PPX_OK) return PPX_EINVAL;
+            if (c.algo != j.algo) {
+                // the tuned entry of the requested algorithm, else the plain default
+                if (ppx_tuned_config(PPX_OP_TRIDIAG, j.dtype, j.n, j.algo, &c) != PPX_OK) {
+                    if (default_config(PPX_OP_TRIDIAG, j.dtype, j.n, c) != PPX_OK) return PPX_EINVAL;
+                    c.algo = j.algo;
+                    c.lds_elems = 0;
+                }
+            }
+            return tridiag_batched(j.in, j.b, j.c, j.d, j.out, j.n, j.batch, j.dtype, &c, st);
+        }
+    }
+}
+
+// Retires launches whose completion event has fired (all of them, in the
+// null-device mode).
+void retire(ppx_server *s) {
+    const double t = s->now_us();
+    for (auto it = s->inflight.begin(); it != s->inflight.end();) {
+        bool done = s->null_device() || hipEventQuery(it->done) == hipSuccess;
+        if (!done) {
+            ++it;
+            continue;
+        }
+        for (int64_t id : it->ids) {
+            Job &j = s->jobs[id];
+            j.completed = true;
+            j.complete_us = t;
+            s->completed.push_back(id);
+            ++s->ncompleted;
+        }
+        if (it->done) s->free_events.push_back(it->done);
+        it = s->inflight.erase(it);
+    }
+}
+
+// Admits pending jobs in arrival order while they fit; stops at the first
+// that does not (no overtaking), so a large job is delayed, never starved.
+std::vector<int64_t> admit(ppx_server *s, int64_t tile_cap, int job_cap) {
+    std::vector<int64_t> out;
+    int64_t tiles = 0;
+    const double t = s->now_us();
+    while (!s->pending.empty() && (int)out.size() < job_cap) {
+        Job &j = s->jobs[s->pending.front()];
+        if (s->used + j.footprint > s->budget) break;
+        const int64_t jt = mixed_tile_count(&j.job, 1);
+        if (!out.empty() && tiles + jt > tile_cap) break;
+        if (!j.job.out) {
+            const int64_t off = s->arena.alloc(job_out_bytes(j.job));
+            if (off < 0) break;  // fragmented: wait for releases
+            j.arena_off = off;
+            j.job.out = s->null_device() ? reinterpret_cast<void *>(0x100000 + off)
+                                         : static_cast<void *>(s->arena_base + off);
+        }
+        s->used += j.footprint;
+        s->peak = std::max(s->peak, s->used);
+        j.admit_us = t;
+        tiles += jt;
+        out.push_back(j.id);
+        s->pending.pop_front();
+        ++s->admitted;
+    }
+    return out;
+}
+
+int progress(ppx_server *s, int *launched) {
+    if (launched) *launched = 0;
+    retire(s);
+    while ((int)s->inflight.size() < s->max_inflight && !s->pending.empty()) {
+        const bool single = s->per_request();
+        std::vector<int64_t> ids = admit(s, int64_t(1) << 18, single ? 1 : (1 << 14));
+        if (ids.empty()) break;
+        Launch l;
+        l.ids = ids;
+        l.stream = s->rr++ % (int)std::max<size_t>(1, s->streams.size());
+        if (!s->null_device()) {
+            l.done = take_event(s);
+            if (!l.done) return fail(PPX_EHIP, "event creation failed");
+            hipStream_t st = s->streams[l.stream];
+            int rc;
+            if (single) {
+                rc = launch_single(s->jobs[ids[0]].job, st);
+                if (rc == PPX_OK) rc = fail_hip(hipEventRecord(l.done, st), "event record");
+            } else {
+                std::vector<ppx_job> batch;
+                batch.reserve(ids.size());
+                for (int64_t id : ids) batch.push_back(s->jobs[id].job);
+                rc = launch_mixed_impl(batch.data(), (int)batch.size(), st, l.done);
+            }
+            if (rc != PPX_OK) return rc;
+        }
+        s->inflight.push_back(l);
+        ++s->launches;
+        s->max_inflight_seen = std::max(s->max_inflight_seen, (int)s->inflight.size());
+        if (launched) *launched += (int)ids.size();
+    }
+    return PPX_OK;
+}
+
+}  // namespace
+}  // namespace ppx
+
+using namespace ppx;
+
+extern "C" {
+
+int ppx_server_create(int64_t budget, int max_inflight, int flags, ppx_server **out) {
+    if (!out) return fail(PPX_EINVAL, "null output");
+    *out = nullptr;
+    if (budget < 1) return fail(PPX_EINVAL, "budget must be positive");
+    if (max_inflight < 1 || max_inflight > 4) return fail(PPX_EINVAL, "max_inflight must be in 1..4");
+    auto *s = new ppx_server();
+    s->flags = flags;
+    s->max_inflight = max_inflight;
+    s->budget = budget;
+    s->arena.reset(budget);
+    if (!s->null_device()) {
+        if (!device_info()) {
+            delete s;
+            return PPX_EDEVICE;
+        }
+        if (hipMalloc(reinterpret_cast<void **>(&s->arena_base), budget) != hipSuccess) {
+            delete s;
+            return fail(PPX_ENOMEM, "could not allocate the server's HBM arena");
+        }
+        s->streams.resize(max_inflight);
+        for (auto &st : s->streams)
+            if (hipStreamCreate(&st) != hipSuccess) {
+                ppx_server_destroy(s);
+                return fail(PPX_EHIP, "stream creation failed");
+            }
+    }
+    *out = s;
+    return PPX_OK;
+}
+
+int ppx_server_destroy(ppx_server *s) {
+    if (!s) return PPX_OK;
+    if (!s->null_device()) {
+        for (auto st : s->streams)
+            if (st) (void)hipStreamSynchronize(st);
+        for (auto &l : s->inflight)
+            if (l.done) (void)hipEventDestroy(l.done);
+        for (auto e : s->free_events) (void)hipEventDestroy(e);
+        for (auto st : s->streams)
+            if (st) (void)hipStreamDestroy(st);
+        if (s->arena_base) (void)hipFree(s->arena_base);
+    }
+    delete s;
+    return PPX_OK;
+}
+
+int ppx_server_submit(ppx_server *s, const ppx_job *job, int64_t *id) {
+    if (!s || !job) return fail(PPX_EINVAL, "null argument");
+    ppx_job j = *job;
+    // validate as the mixed launch would, with a placeholder output if the
+    // server is to allocate it
+    ppx_job probe = j;
+    if (!probe.out) probe.out = reinterpret_cast<void *>(256);
+    if (int rc = check_job(probe)) return rc;
+    const int64_t fp = job_in_bytes(j) + job_out_bytes(j);
+    if (fp > s->budget) return fail(PPX_ENOMEM, "job footprint exceeds the server's HBM budget");
+    Job rec;
+    rec.id = s->next_id++;
+    rec.job = j;
+    rec.footprint = fp;
+    rec.arrival_us = s->now_us();
+    s->jobs[rec.id] = rec;
+    s->pending.push_back(rec.id);
+    ++s->submitted;
+    if (id) *id = rec.id;
+    return PPX_OK;
+}
+
+int ppx_server_progress(ppx_server *s, int *launched) {
+    if (!s) return fail(PPX_EINVAL, "null server");
+    return progress(s, launched);
+}
+
+int ppx_server_poll(ppx_server *s, ppx_completion *out, int cap, int *count) {
+    if (!s) return fail(PPX_EINVAL, "null server");
+    int k = 0;
+    while (!s->completed.empty() && k < cap && out) {
+        const Job &j = s->jobs[s->completed.front()];
+        out[k++] = ppx_completion{j.id, j.job.out, j.arrival_us, j.admit_us, j.complete_us};
+        s->completed.pop_front();
+    }
+    if (count) *count = k;
+    return PPX_OK;
+}
+
+int ppx_server_release(ppx_server *s, int64_t id) {
+    if (!s) return fail(PPX_EINVAL, "null server");
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) return fail(PPX_EINVAL, "unknown job id");
+    if (!it->second.completed) return fail(PPX_EINVAL, "job has not completed");
+    s->used -= it->second.footprint;
+    if (it->second.arena_off >= 0) s->arena.release(it->second.arena_off, job_out_bytes(it->second.job));
+    s->jobs.erase(it);
+    ++s->released;
+    return PPX_OK;
+}
+
+int ppx_server_read(ppx_server *s, int64_t id, void *host_dst, int64_t bytes) {
+    if (!s || !host_dst) return fail(PPX_EINVAL, "null argument");
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end() || !it->second.completed) return fail(PPX_EINVAL, "no completed job with that id");
+    if (bytes < 0 || bytes > job_out_bytes(it->second.job)) return fail(PPX_EINVAL, "bad byte count");
+    if (s->null_device()) return fail(PPX_EDEVICE, "null-device server holds no data");
+    return fail_hip(hipMemcpy(host_dst, it->second.job.out, bytes, hipMemcpyDeviceToHost), "read");
+}
+
+int ppx_server_stats_get(ppx_server *s, ppx_server_stats *o) {
+    if (!s || !o) return fail(PPX_EINVAL, "null argument");
+    *o = ppx_server_stats{s->submitted, s->admitted, s->ncompleted, s->released, s->launches,
+                          s->budget, s->used, s->peak, s->max_inflight_seen, (int32_t)s->pending.size()};
+    return PPX_OK;
+}
+
+int ppx_serve_replay(ppx_server *s, const ppx_request *reqs, int n, int auto_release,
+                     ppx_completion *out) {
+    if (!s || (!reqs && n > 0) || !out) return fail(PPX_EINVAL, "null argument");
+    for (int i = 0; i + 1 < n; ++i)
+        if (reqs[i + 1].arrival_us < reqs[i].arrival_us) return fail(PPX_EINVAL, "arrivals must be sorted");
+    std::unordered_map<int64_t, int> slot;
+    const double start = s->now_us();
+    int next = 0, done = 0;
+    std::vector<ppx_completion> buf(256);
+    while (done < n) {
+        bool busy = false;
+        const double t = s->now_us() - start;
+        while (next < n && reqs[next].arrival_us <= t) {
+            int64_t id;
+            if (int rc = ppx_server_submit(s, &reqs[next].job, &id)) return rc;
+            s->jobs[id].arrival_us = start + reqs[next].arrival_us;  // queueing counts
+            slot[id] = next++;
+            busy = true;
+        }
+        int launched = 0;
+        if (int rc = progress(s, &launched)) return rc;
+        int got = 0;
+        ppx_server_poll(s, buf.data(), (int)buf.size(), &got);
+        for (int k = 0; k < got; ++k) {
+            out[slot[buf[k].id]] = buf[k];
+            ++done;
+            if (auto_release) ppx_server_release(s, buf[k].id);
+        }
+        if (!busy && launched == 0 && got == 0) std::this_thread::sleep_for(std::chrono::microseconds(5));
+    }
+    return PPX_OK;
+}
+
+}  // extern "C"

@@ -16,7 +16,8 @@ import threading
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libppx.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "ppx.h")
-HEADERS = [HEADER, os.path.join(os.path.dirname(_PKG), "include", "ppx_tune.h")]
+HEADERS = [HEADER] + [os.path.join(os.path.dirname(_PKG), "include", h)
+                      for h in ("ppx_tune.h", "ppx_serve.h")]
 
 # ---- constants mirrored from include/ppx.h ----
 OK, EINVAL, ECONFIG, EDEVICE, EHIP, ENOMEM, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
@@ -416,3 +417,104 @@ def mixed_tile_problems(op, dtype, n, algo=0):
     f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
     f.restype = ctypes.c_int
     return f(op, dtype, n, algo)
+
+
+# ---------------------------------------------------------------- serving
+# (declared in include/ppx_serve.h)
+
+SERVE_FUSED, SERVE_PER_REQUEST, SERVE_NULL_DEVICE = 0, 1, 2
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("out", ctypes.c_void_p), ("arrival_us", ctypes.c_double),
+                ("admit_us", ctypes.c_double), ("complete_us", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("submitted", "admitted", "completed", "released",
+                                              "launches", "budget_bytes", "used_bytes",
+                                              "peak_used_bytes")] + \
+               [("max_inflight_seen", ctypes.c_int32), ("pending", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("job", Job), ("arrival_us", ctypes.c_double)]
+
+
+def _sl(name, argtypes):
+    f = getattr(lib(), name)
+    if not getattr(f, "_ppx_typed", False):
+        f.argtypes = argtypes
+        f.restype = ctypes.c_int
+        f._ppx_typed = True
+    return f
+
+
+class Server:
+    """Continuous-batching request loop (include/ppx_serve.h)."""
+
+    def __init__(self, budget_bytes, max_inflight=2, flags=SERVE_FUSED):
+        self._h = ctypes.c_void_p()
+        _check(_sl("ppx_server_create", [ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_void_p)])(
+            budget_bytes, max_inflight, flags, ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _sl("ppx_server_destroy", [ctypes.c_void_p])(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, job):
+        i = ctypes.c_int64(0)
+        _check(_sl("ppx_server_submit", [ctypes.c_void_p, ctypes.POINTER(Job),
+                                         ctypes.POINTER(ctypes.c_int64)])(
+            self._h, ctypes.byref(job), ctypes.byref(i)))
+        return i.value
+
+    def progress(self):
+        k = ctypes.c_int(0)
+        _check(_sl("ppx_server_progress", [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)])(
+            self._h, ctypes.byref(k)))
+        return k.value
+
+    def poll(self, cap=1024):
+        arr = (Completion * cap)()
+        k = ctypes.c_int(0)
+        _check(_sl("ppx_server_poll", [ctypes.c_void_p, ctypes.POINTER(Completion), ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int)])(
+            self._h, arr, cap, ctypes.byref(k)))
+        return [arr[i] for i in range(k.value)]
+
+    def release(self, job_id):
+        _check(_sl("ppx_server_release", [ctypes.c_void_p, ctypes.c_int64])(self._h, job_id))
+
+    def read(self, job_id, host_array):
+        import numpy as np
+        assert isinstance(host_array, np.ndarray) and host_array.flags.c_contiguous
+        _check(_sl("ppx_server_read", [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_int64])(
+            self._h, job_id, host_array.ctypes.data, host_array.nbytes))
+        return host_array
+
+    def stats(self):
+        st = ServerStats()
+        _check(_sl("ppx_server_stats_get", [ctypes.c_void_p, ctypes.POINTER(ServerStats)])(
+            self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def replay(self, requests, auto_release=True):
+        """requests: list of (Job, arrival_us) sorted by arrival; returns a list
+        of Completion in request order."""
+        n = len(requests)
+        arr = (Request * n)(*[Request(j, t) for j, t in requests])
+        out = (Completion * n)()
+        _check(_sl("ppx_serve_replay", [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.c_int,
+                                        ctypes.c_int, ctypes.POINTER(Completion)])(
+            self._h, arr, n, 1 if auto_release else 0, out))
+        return [out[i] for i in range(n)]

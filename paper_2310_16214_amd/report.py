@@ -1,0 +1,61 @@
+"""Markdown summaries of the tuning study (tune_sweep JSON) and of the serving
+benchmark (serve_bench JSON).
+
+    python -m paper_2310_16214_amd.report tuning tuning_fft_scan_tridiag.json
+    python -m paper_2310_16214_amd.report serving serve.json
+"""
+from __future__ import annotations
+
+import json
+import sys
+
+DT = {0: "int32", 1: "f32", 2: "f64", 3: "c64"}
+ALGO = {-1: "", 0: " CR", 1: " PCR"}
+
+
+def cfg_str(c):
+    return f"r{c['radix']} P{c['elems_per_thread']} L{c['threads_per_block']} G{c['problems_per_block']}" \
+           + (f" a{c['algo']}" if c['algo'] else "")
+
+
+def tuning(path):
+    d = json.load(open(path))
+    out = ["| op | N | exhaustive best | us | GElem/s | analytical (e) | learned (e, evals/space) | default us | tuned/default | batched/plain |",
+           "|---|---|---|---|---|---|---|---|---|---|"]
+    for r in d["records"]:
+        name = r["op"] + " " + DT[r["dtype"]] + ALGO[r["algo"]]
+        out.append(f"| {name} | {r['n']} | {cfg_str(r['exhaustive']['cfg'])} | {r['exhaustive']['us']:.1f} | "
+                   f"{r['gelem_s']:.0f} | {cfg_str(r['analytical']['cfg'])} ({r['e_analytical']:.2f}) | "
+                   f"{cfg_str(r['learned']['cfg'])} ({r['e_learned']:.2f}, {r['learned']['evals']}/{r['exhaustive']['space']}) | "
+                   f"{r['default']['us']:.1f} | {r['tuned_vs_default']:.2f} | {r.get('batched_vs_plain', float('nan')):.0f} |")
+    out += ["", "| group | sizes | Phi analytical | Phi learned | mean learned evals | geo-mean tuned/default |",
+            "|---|---|---|---|---|---|"]
+    for s in d["summary"]:
+        import math
+        g = math.exp(sum(math.log(v) for v in s["tuned_vs_default"]) / len(s["tuned_vs_default"]))
+        out.append(f"| {s['op']} {DT[s['dtype']]}{ALGO[s['algo']]} | {s['sizes'][0]}..{s['sizes'][-1]} | "
+                   f"{s['phi_analytical']:.3f} | {s['phi_learned']:.3f} | "
+                   f"{sum(s['evals_learned']) / len(s['evals_learned']):.1f} | {g:.2f} |")
+    print("\n".join(out))
+
+
+def serving(path):
+    d = json.load(open(path))
+    out = [f"jobs per trace: {d['njobs']}; budget {d['budget_bytes'] / 2**30:.1f} GiB; "
+           f"max launches in flight {d['max_inflight']}; mix: {d['mix']}", "",
+           "| load (of fused saturation) | mode | p50 ms | p99 ms | GElem/s | % HBM peak | launches |",
+           "|---|---|---|---|---|---|---|"]
+    for m, r in d["saturation"].items():
+        out.append(f"| burst (saturation) | {m} | {r['p50_ms']:.2f} | {r['p99_ms']:.2f} | {r['gelem_s']:.1f} | "
+                   f"{100 * r['hbm_frac']:.1f} | {r['launches']} |")
+    for r in d["points"]:
+        out.append(f"| {r['load']:.2f} ({r['offered_jobs_per_s']:.0f} jobs/s) | {r['mode']} | {r['p50_ms']:.2f} | "
+                   f"{r['p99_ms']:.2f} | {r['gelem_s']:.1f} | {100 * r['hbm_frac']:.1f} | {r['launches']} |")
+    b = d["backpressure_half_budget"]
+    out.append(f"| {b['load']:.2f}, half budget | fused | {b['p50_ms']:.2f} | {b['p99_ms']:.2f} | "
+               f"{b['gelem_s']:.1f} | {100 * b['hbm_frac']:.1f} | {b['launches']} |")
+    print("\n".join(out))
+
+
+if __name__ == "__main__":
+    {"tuning": tuning, "serving": serving}[sys.argv[1]](sys.argv[2])

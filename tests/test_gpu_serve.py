@@ -1,0 +1,83 @@
+"""GPU tests of the request loop: every job served in the mix equals the same
+job launched alone (bitwise), sampled jobs match the oracle, and the
+per-request baseline serves the same trace within tolerance."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_16214_amd import ppx
+from paper_2310_16214_amd.serve_bench import Pools, make_trace
+from tests.gpu_util import banner, fft_tol, scan_f32_bound
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_trace(pools, njobs, seed):
+    trace = make_trace(njobs, 200000.0, seed, pools)
+    # keep it quick: cap the batch counts
+    out = []
+    for job, t, m in trace:
+        job.batch = min(job.batch, 64)
+        m["batch"] = job.batch
+        m["elems"] = job.n * job.batch
+        m["bytes"] = {"fft": 16, "scan": 8, "tridiag": 20}[m["op"]] * m["elems"]
+        out.append((job, t, m))
+    return out
+
+
+def _host_out(meta):
+    return np.empty((meta["batch"], meta["n"]),
+                    dtype=np.complex64 if meta["op"] == "fft" else np.float32)
+
+
+def _oracle_check(pools, meta, y):
+    n, batch, off = meta["n"], meta["batch"], meta["offset"]
+    if meta["op"] == "fft":
+        x = pools.fft[off:off + n * batch].cpu().numpy().reshape(batch, n)
+        assert oracle.rel_l2(y, oracle.dft(x)).max() <= fft_tol(n)
+    elif meta["op"] == "scan":
+        x = pools.scan[off:off + n * batch].cpu().numpy().reshape(batch, n)
+        assert np.all(np.abs(y.astype(np.float64) - oracle.scan(x)) <= scan_f32_bound(x))
+    else:
+        coeffs = [v[off:off + n * batch].cpu().numpy().reshape(batch, n) for v in pools.tri]
+        assert oracle.tridiag_residual(*coeffs, y).max() <= 1e-4
+
+
+@pytest.mark.parametrize("mode", [ppx.SERVE_FUSED, ppx.SERVE_PER_REQUEST])
+def test_served_jobs_match_alone_and_oracle(cuda, mode):
+    import torch
+    pools = Pools(cuda, seed=4)
+    trace = _small_trace(pools, 40, seed=9)
+    banner(f"serve mode={mode} jobs={len(trace)}")
+    srv = ppx.Server(1 << 30, max_inflight=2, flags=mode)
+    comps = srv.replay([(j, t) for j, t, _ in trace], auto_release=False)
+    outs = []
+    for c, (_, _, m) in zip(comps, trace):
+        outs.append(srv.read(c.id, _host_out(m)))
+    srv.close()
+    for k, ((job, _, m), y) in enumerate(zip(trace, outs)):
+        if mode == ppx.SERVE_FUSED:
+            # the same job alone in its own mixed launch: identical bits
+            alone = torch.empty(m["batch"] * m["n"] * (2 if m["op"] == "fft" else 1),
+                                dtype=torch.float32, device=cuda)
+            j2 = ppx.Job.from_buffer_copy(job)
+            j2.out = alone.data_ptr()
+            ppx.launch_mixed([j2])
+            torch.cuda.synchronize()
+            a = alone.cpu().numpy().view(y.dtype).reshape(y.shape)
+            assert np.array_equal(a, y), (k, m)
+        if k % 4 == 0:
+            _oracle_check(pools, m, y)
+
+
+def test_backpressure_with_a_tight_budget(cuda):
+    pools = Pools(cuda, seed=5)
+    trace = _small_trace(pools, 30, seed=2)
+    biggest = max(m["bytes"] for _, _, m in trace) + 4096
+    banner("serve tight budget")
+    srv = ppx.Server(biggest, max_inflight=2, flags=ppx.SERVE_FUSED)
+    comps = srv.replay([(j, t) for j, t, _ in trace], auto_release=True)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(trace) and st["peak_used_bytes"] <= biggest
+    assert all(c.complete_us >= c.admit_us >= c.arrival_us for c in comps)
