@@ -43,6 +43,9 @@ def parse():
     p.add_argument("--tune-cache", default=os.path.join(
         ROOT, "paper_2310_16214_amd", "tuned", "mi355x.txt"))
     p.add_argument("--detail", default="", help="write per-call records (JSONL) here")
+    p.add_argument("--copy-ref", action="store_true",
+                   help="first run a plain 256 MiB device-to-device copy (twice): the known-size "
+                        "reference that scales hardware traffic counters")
     return p.parse_args()
 
 
@@ -164,6 +167,13 @@ def main():
     if os.path.exists(args.tune_cache):
         ppx.load_tune_cache(args.tune_cache)
     ops = set(args.ops.split(","))
+    if args.copy_ref:
+        src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     calls = build_workload(ops, dev)
     torch.cuda.synchronize()
 

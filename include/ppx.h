@@ -61,8 +61,11 @@ extern "C" {
                                half-size LDS buffer (Sec. V-C) */
 #define PPX_SCAN_KS 0       /* Kogge-Stone lane network (DPP row shifts) */
 #define PPX_SCAN_LF 1       /* Ladner-Fischer lane network (swizzle bcasts) */
-#define PPX_TRI_CR 0        /* cyclic reduction (Sec. III) */
-#define PPX_TRI_PCR 1       /* parallel cyclic reduction (Sec. III) */
+#define PPX_TRI_CR 0        /* cyclic reduction (Sec. III), LDS exchange */
+#define PPX_TRI_PCR 1       /* parallel cyclic reduction (Sec. III), LDS exchange */
+#define PPX_TRI_CR_SHFL 2   /* CR inside a wave: registers + lane shuffles, no
+                               LDS (S = 0); valid when n / P <= 64, P <= 16 */
+#define PPX_TRI_PCR_SHFL 3  /* PCR inside a wave (S = 0); n / P <= 64, P <= 8 */
 
 /* ---- tuning methods ---- */
 #define PPX_TUNE_EXHAUSTIVE 0 /* time every valid configuration (Sec. VI) */
@@ -122,7 +125,10 @@ int scan_batched(const void *in, void *out, int64_t n, int64_t batch,
  * separate coefficient arrays).  a[.][0] and c[.][n-1] multiply absent
  * unknowns: their stored values, even NaN, do not affect x.  x may equal d
  * (the solve then overwrites the right-hand side); no other aliasing.
- * No pivoting: systems are assumed diagonally dominant.
+ * No pivoting: systems are assumed diagonally dominant.  cfg->algo picks CR
+ * or PCR and the exchange (LDS, or lane shuffles when a system fits a wave:
+ * the paper's "shuffle" option); the wave variants use a refined hardware
+ * reciprocal instead of IEEE division.
  */
 int tridiag_batched(const void *a, const void *b, const void *c, const void *d,
                     void *x, int64_t n, int64_t batch, int dtype,

@@ -139,7 +139,8 @@ typedef struct ppx_tune_report {
 /*
  * ppx_tune_ex -- tune() with an algorithm filter and a full report.  algo =
  * -1 searches every algorithm of the op; otherwise only that one (the cache
- * entry is then keyed by it).  reps = timed launches per candidate (<= 0:
+ * entry is then keyed by it); for the tridiagonal solvers the filter selects
+ * a family, PPX_TRI_CR (CR through LDS or shuffles) or PPX_TRI_PCR.  reps = timed launches per candidate (<= 0:
  * 100, the paper's count), each on a different buffer set so that no rep
  * reads data a previous rep left in the 256 MB Infinity Cache.  Synchronous;
  * needs a GPU.  Records the winner in the tune cache.

@@ -39,7 +39,9 @@ static int lds_elems(int op, int64_t n, const ppx_config &c) {
             const int64_t T = n / c.elems_per_thread;  // threads per problem
             return T > kWave ? c.threads_per_block / kWave : 0;
         }
-        default: return (int)((c.algo == PPX_TRI_PCR ? 2 : 1) * c.problems_per_block * n);
+        default:
+            if (c.algo == PPX_TRI_CR_SHFL || c.algo == PPX_TRI_PCR_SHFL) return 0;
+            return (int)((c.algo == PPX_TRI_PCR ? 2 : 1) * c.problems_per_block * n);
     }
 }
 
@@ -84,8 +86,13 @@ int validate_config(int op, int dtype, int64_t n, const ppx_config &c) {
             break;
         case PPX_OP_TRIDIAG:
             if (c.radix != 0 && c.radix != 2) return fail(PPX_ECONFIG, "tridiagonal radix must be 2");
-            if (c.algo != PPX_TRI_CR && c.algo != PPX_TRI_PCR)
-                return fail(PPX_ECONFIG, "tridiagonal algo must be PPX_TRI_CR or PPX_TRI_PCR");
+            if (c.algo < PPX_TRI_CR || c.algo > PPX_TRI_PCR_SHFL)
+                return fail(PPX_ECONFIG, "tridiagonal algo must be PPX_TRI_CR, _PCR, _CR_SHFL or _PCR_SHFL");
+            if (c.algo >= PPX_TRI_CR_SHFL) {
+                if (n / P > kWave) return fail(PPX_ECONFIG, "shuffle variant needs n / P <= 64 (a system within a wave)");
+                if (P > tri_wave_max_p(c.algo)) return fail(PPX_ECONFIG, "shuffle variant: too many elements per thread");
+                if (L > kTriWaveMaxThreads) return fail(PPX_ECONFIG, "shuffle variant allows at most 256 threads");
+            }
             break;
         default:
             return fail(PPX_EINVAL, "unknown op");
@@ -120,7 +127,7 @@ int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap) {
     static const int radix_two[] = {2};
     const int *radices = op == PPX_OP_FFT ? radices_fft : radix_two;
     const int nr = op == PPX_OP_FFT ? 4 : 1;
-    const int nalgo = 2;
+    const int nalgo = op == PPX_OP_TRIDIAG ? 4 : 2;
     int count = 0;
     for (int ri = 0; ri < nr; ++ri)
         for (int L = 64; L <= 1024; L *= 2)

@@ -29,9 +29,38 @@ namespace ppx {
 constexpr int kNMax = 1 << kFftLog2NMax;
 
 // LDS index swizzles that keep the strided Stockham writes free of bank
-// conflicts without padding (the footprint stays n elements per problem).
+// conflicts without padding.  They act on the workgroup-flat index (problem
+// offset included), so the problems sharing a workgroup land on different
+// banks too; each keeps an index inside its aligned 256 (float2) or 1024
+// (float) block, hence inside its problem for n >= that block and inside the
+// workgroup's buffer always.
 __device__ __forceinline__ int swz_c(int p) { return p ^ ((p >> 4) & 15); }  // float2 words
 __device__ __forceinline__ int swz_f(int p) { return p ^ ((p >> 5) & 31); }  // float words
+
+// Twiddles w[q] = w_{Ns*RS}^{q*k}, q = 1..RS-1, from the table of w_NMAX^m:
+// w^k, w^{4k} and w^{8k} are read (as the radix needs them) and the other
+// powers are products of at most three of them, so a butterfly issues at most
+// three table loads instead of RS - 1.
+template <int RS>
+__device__ __forceinline__ void stage_twiddles(float2 (&w)[RS], const float2 *__restrict__ tw, int k,
+                                               int shift) {
+    w[1] = tw[k << shift];
+    if constexpr (RS >= 4) {
+        w[2] = cmul(w[1], w[1]);
+        w[3] = cmul(w[2], w[1]);
+    }
+    if constexpr (RS >= 8) {
+        w[4] = tw[(4 * k) << shift];
+        w[5] = cmul(w[4], w[1]);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
+    }
+    if constexpr (RS >= 16) {
+        w[8] = tw[(8 * k) << shift];
+#pragma unroll
+        for (int q = 9; q < 16; ++q) w[q] = cmul(w[8], w[q - 8]);
+    }
+}
 
 // The first stage (span 1) has no twiddles; it is a separate instantiation
 // (FIRST) rather than a runtime branch, so no control-flow join surrounds the
@@ -51,8 +80,10 @@ __device__ __forceinline__ void stage_butterflies(float2 (&v)[P], int tid, int T
         for (int q = 0; q < RS; ++q) u[q] = v[i + q * NB];
         if constexpr (!FIRST) {
             const int k = (tid + i * T) & ((1 << lns) - 1);
+            float2 w[RS];
+            stage_twiddles<RS>(w, tw, k, twshift);
 #pragma unroll
-            for (int q = 1; q < RS; ++q) u[q] = cmul(u[q], tw[(q * k) << twshift]);
+            for (int q = 1; q < RS; ++q) u[q] = cmul(u[q], w[q]);
         }
         RegDFT<RS>::run(u);
 #pragma unroll
@@ -68,40 +99,41 @@ __device__ __forceinline__ int stage_out_pos(int t, int lns, int q) {
     return ((t >> lns) << (lns + LRS)) + k + (q << lns);
 }
 
+// `lds` is the workgroup's buffer and `poff` the problem's offset in it.
 template <int RS, int P, bool SPLIT>
-__device__ __forceinline__ void stage_exchange(float2 (&v)[P], void *lds_problem, int tid, int T,
+__device__ __forceinline__ void stage_exchange(float2 (&v)[P], void *lds, int poff, int tid, int T,
                                                int lns) {
     constexpr int NB = P / RS;
     if constexpr (!SPLIT) {
-        float2 *buf = static_cast<float2 *>(lds_problem);
+        float2 *buf = static_cast<float2 *>(lds);
 #pragma unroll
         for (int i = 0; i < NB; ++i)
 #pragma unroll
             for (int q = 0; q < RS; ++q)
-                buf[swz_c(stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB];
+                buf[swz_c(poff + stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB];
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < P; ++j) v[j] = buf[swz_c(tid + j * T)];
+        for (int j = 0; j < P; ++j) v[j] = buf[swz_c(poff + tid + j * T)];
         __syncthreads();
     } else {
-        float *buf = static_cast<float *>(lds_problem);
+        float *buf = static_cast<float *>(lds);
 #pragma unroll
         for (int i = 0; i < NB; ++i)
 #pragma unroll
             for (int q = 0; q < RS; ++q)
-                buf[swz_f(stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB].x;
+                buf[swz_f(poff + stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB].x;
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < P; ++j) v[j].x = buf[swz_f(tid + j * T)];
+        for (int j = 0; j < P; ++j) v[j].x = buf[swz_f(poff + tid + j * T)];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NB; ++i)
 #pragma unroll
             for (int q = 0; q < RS; ++q)
-                buf[swz_f(stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB].y;
+                buf[swz_f(poff + stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB].y;
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < P; ++j) v[j].y = buf[swz_f(tid + j * T)];
+        for (int j = 0; j < P; ++j) v[j].y = buf[swz_f(poff + tid + j * T)];
         __syncthreads();
     }
 }
@@ -122,7 +154,7 @@ __device__ __forceinline__ void stage_store(const float2 (&v)[P], float2 *dst, i
 // One stage of radix RS followed by either the LDS exchange or, for the last
 // stage, the global store.
 template <int RS, int P, bool SPLIT, bool FIRST>
-__device__ __forceinline__ void run_stage(float2 (&v)[P], void *lds_problem, float2 *dst, int tid,
+__device__ __forceinline__ void run_stage(float2 (&v)[P], void *lds, int poff, float2 *dst, int tid,
                                           int T, int &lns, int log2n, bool active, float sgn,
                                           const float2 *__restrict__ tw) {
     constexpr int LRS = RS == 2 ? 1 : RS == 4 ? 2 : RS == 8 ? 3 : 4;
@@ -130,7 +162,7 @@ __device__ __forceinline__ void run_stage(float2 (&v)[P], void *lds_problem, flo
     if (lns + LRS == log2n) {
         if (active) stage_store<RS, P>(v, dst, tid, T, lns, sgn);
     } else {
-        stage_exchange<RS, P, SPLIT>(v, lds_problem, tid, T, lns);
+        stage_exchange<RS, P, SPLIT>(v, lds, poff, tid, T, lns);
     }
     lns += LRS;
 }
@@ -153,8 +185,7 @@ __device__ __forceinline__ void fft_block(const float2 *in, float2 *out, const f
     const bool active = lp < nprob;
     const float2 *src = in + prob * n;
     float2 *dst = out + prob * n;
-    void *lds_problem = SPLIT ? (void *)(reinterpret_cast<float *>(lds_raw) + (size_t)lp * n)
-                              : (void *)(reinterpret_cast<float2 *>(lds_raw) + (size_t)lp * n);
+    const int poff = lp * n;  // the problem's offset in the workgroup's LDS buffer
 
     float2 v[P];
     if (active) {
@@ -172,16 +203,16 @@ __device__ __forceinline__ void fft_block(const float2 *in, float2 *out, const f
     int lns = 0;
     const int rem = log2n % LR;
     if (rem == 0) {
-        run_stage<R, P, SPLIT, true>(v, lds_problem, dst, tid, T, lns, log2n, active, sgn, tw);
+        run_stage<R, P, SPLIT, true>(v, lds_raw, poff, dst, tid, T, lns, log2n, active, sgn, tw);
     } else if (rem == 1) {
-        run_stage<2, P, SPLIT, true>(v, lds_problem, dst, tid, T, lns, log2n, active, sgn, tw);
+        run_stage<2, P, SPLIT, true>(v, lds_raw, poff, dst, tid, T, lns, log2n, active, sgn, tw);
     } else if constexpr (R >= 8) {
-        if (rem == 2) run_stage<4, P, SPLIT, true>(v, lds_problem, dst, tid, T, lns, log2n, active, sgn, tw);
+        if (rem == 2) run_stage<4, P, SPLIT, true>(v, lds_raw, poff, dst, tid, T, lns, log2n, active, sgn, tw);
         if constexpr (R >= 16)
-            if (rem == 3) run_stage<8, P, SPLIT, true>(v, lds_problem, dst, tid, T, lns, log2n, active, sgn, tw);
+            if (rem == 3) run_stage<8, P, SPLIT, true>(v, lds_raw, poff, dst, tid, T, lns, log2n, active, sgn, tw);
     }
     while (lns < log2n)
-        run_stage<R, P, SPLIT, false>(v, lds_problem, dst, tid, T, lns, log2n, active, sgn, tw);
+        run_stage<R, P, SPLIT, false>(v, lds_raw, poff, dst, tid, T, lns, log2n, active, sgn, tw);
 }
 
 template <int R, int P, bool SPLIT>

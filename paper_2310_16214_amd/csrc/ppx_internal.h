@@ -69,6 +69,10 @@ constexpr int kFftLog2NMax = 14;
 // at P = 32 the 64 data registers plus twiddles need more than the 128 VGPRs
 // a 1024-thread workgroup leaves per lane, so those kernels cap L at 512.
 constexpr int fft_max_threads(int P) { return P >= 32 ? 512 : 1024; }
+// Limits of the in-wave tridiagonal kernels (registers hold P equations of
+// four coefficients; PCR needs twice that again for the neighbours).
+constexpr int kTriWaveMaxThreads = 256;
+constexpr int tri_wave_max_p(int algo) { return algo == PPX_TRI_PCR_SHFL ? 8 : 16; }
 int launch_fft(const void *in, void *out, int log2n, int64_t batch,
                const ppx_config &c, bool inverse, hipStream_t s);
 int launch_scan(const void *in, void *out, int log2n, int64_t batch, int dtype,
@@ -80,7 +84,7 @@ int launch_tridiag(const void *a, const void *b, const void *c, const void *d,
 // Device function pointers for occupancy queries (nullptr if no such kernel).
 const void *fft_kernel(int radix, int P, int algo);
 const void *scan_kernel(int dtype, int P, int algo);
-const void *tridiag_kernel(int dtype, int algo);
+const void *tridiag_kernel(int dtype, int algo, int P);
 
 // Builds the forward twiddle table for NMAX = 2^kFftLog2NMax in host memory
 // (float pairs from double-precision sincos).

@@ -1,19 +1,38 @@
 // Host launcher of the kernels in tridiag_device.h.
 #include "tridiag_device.h"
+#include "tridiag_wave_device.h"
 
 namespace ppx {
 
 // ------------------------------------------------------------------- host
 
 int64_t tridiag_lds_bytes(int n, int gb, int dtype, int algo) {
+    if (algo == PPX_TRI_CR_SHFL || algo == PPX_TRI_PCR_SHFL) return 0;
     const int64_t es = dtype == PPX_F64 ? 8 : 4;
     return (algo == PPX_TRI_PCR ? 8 : 4) * es * (int64_t)gb * n;
+}
+
+template <typename T, int A>
+static const void *wave_kernel_p(int P) {
+    switch (P) {
+        case 2: return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 2>);
+        case 4: return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 4>);
+        case 8: return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 8>);
+        case 16:
+            if constexpr (A == PPX_TRI_CR_SHFL) return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 16>);
+            return nullptr;
+        default: return nullptr;
+    }
 }
 
 template <typename T>
 using TriKernel = void (*)(const T *, const T *, const T *, const T *, T *, int, long long, int);
 
-const void *tridiag_kernel(int dtype, int algo) {
+const void *tridiag_kernel(int dtype, int algo, int P) {
+    if (algo == PPX_TRI_CR_SHFL)
+        return dtype == PPX_F64 ? wave_kernel_p<double, PPX_TRI_CR_SHFL>(P) : dtype == PPX_F32 ? wave_kernel_p<float, PPX_TRI_CR_SHFL>(P) : nullptr;
+    if (algo == PPX_TRI_PCR_SHFL)
+        return dtype == PPX_F64 ? wave_kernel_p<double, PPX_TRI_PCR_SHFL>(P) : dtype == PPX_F32 ? wave_kernel_p<float, PPX_TRI_PCR_SHFL>(P) : nullptr;
     if (dtype == PPX_F32) {
         if (algo == PPX_TRI_CR) return reinterpret_cast<const void *>(&k_tridiag<float, PPX_TRI_CR>);
         if (algo == PPX_TRI_PCR) return reinterpret_cast<const void *>(&k_tridiag<float, PPX_TRI_PCR>);
@@ -41,7 +60,7 @@ int launch_tridiag(const void *a, const void *b, const void *c, const void *d, v
                    int64_t batch, int dtype, const ppx_config &cfg, hipStream_t s) {
     const DeviceInfo *di = device_info();
     if (!di) return PPX_EDEVICE;
-    const void *k = tridiag_kernel(dtype, cfg.algo);
+    const void *k = tridiag_kernel(dtype, cfg.algo, cfg.elems_per_thread);
     if (!k) return fail(PPX_ECONFIG, "no tridiagonal kernel for this dtype / algo");
     const int64_t lds = tridiag_lds_bytes(1 << log2n, cfg.problems_per_block, dtype, cfg.algo);
     if (lds > di->lds_per_block)

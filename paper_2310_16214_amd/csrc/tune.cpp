@@ -466,6 +466,8 @@ void store_cached_config(int op, int dtype, int64_t n, const ppx_config &c) {
 static int static_vgprs(int op, int dtype, int P, int algo) {
     if (op == PPX_OP_FFT) return P <= 2 ? 16 : P <= 4 ? 29 : P <= 8 ? 55 : P <= 16 ? 107 : 200;
     if (op == PPX_OP_SCAN) return P <= 2 ? 10 : P <= 4 ? 12 : P <= 8 ? 16 : P <= 16 ? 24 : 40;
+    if (algo == PPX_TRI_CR_SHFL || algo == PPX_TRI_PCR_SHFL)
+        return (dtype == PPX_F64 ? 2 : 1) * (algo == PPX_TRI_PCR_SHFL ? 12 : 5) * P + 16;
     return dtype == PPX_F64 ? (algo == PPX_TRI_PCR ? 44 : 40) : (algo == PPX_TRI_PCR ? 32 : 28);
 }
 
@@ -473,7 +475,7 @@ static const void *kernel_for(int op, int dtype, const ppx_config &c) {
     switch (op) {
         case PPX_OP_FFT: return fft_kernel(c.radix, c.elems_per_thread, c.algo);
         case PPX_OP_SCAN: return scan_kernel(dtype, c.elems_per_thread, c.algo);
-        default: return tridiag_kernel(dtype, c.algo);
+        default: return tridiag_kernel(dtype, c.algo, c.elems_per_thread);
     }
 }
 
@@ -719,7 +721,8 @@ static int tune_impl(int op, int dtype, int64_t n, int64_t batch, int method, in
     enumerate_configs(op, dtype, n, all.data(), total);
     std::vector<ppx_config> cands;
     for (const auto &c : all)
-        if (algo < 0 || c.algo == algo) cands.push_back(c);
+        if (algo < 0 || (op == PPX_OP_TRIDIAG ? (c.algo & 1) == (algo & 1) : c.algo == algo))
+            cands.push_back(c);
     if (cands.empty()) return fail(PPX_ECONFIG, "no valid configuration to tune");
     if (!device_info()) return PPX_EDEVICE;
     Bench bench;

@@ -45,11 +45,11 @@ def test_every_config(cuda, n, dtype):
           f"|x-oracle| {fe:.2e}, |x-x_true| {np.max(np.abs(x - xt)):.2e}")
 
 
-@pytest.mark.parametrize("algo", [ppx.TRI_CR, ppx.TRI_PCR])
+@pytest.mark.parametrize("algo", [ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL])
 def test_boundary_coefficients_are_ignored(cuda, algo):
     n, batch = 256, 8
     a, b, c, d, _ = inputs.tridiag_input(n, batch, np.float32, seed=2)
-    cfg = ppx.make_config(2, 128, 1, algo)
+    cfg = ppx.make_config(2, 128, 4, algo)  # P = 8: n / P = 32 lanes per system
     x_clean = _solve([to_dev(v, cuda) for v in (a, b, c, d)], n, batch, np.float32, cfg)
     a2, c2 = a.copy(), c.copy()
     a2[:, 0] = np.nan
@@ -71,7 +71,7 @@ def test_x_may_alias_d(cuda):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("n", [32, 1024])
-@pytest.mark.parametrize("algo", [ppx.TRI_CR, ppx.TRI_PCR])
+@pytest.mark.parametrize("algo", [ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL])
 def test_full_size(cuda, n, dtype, algo):
     """Benchmark sweep size: 2^22 unknowns per call; every system checked."""
     batch = (1 << 22) // n
@@ -81,7 +81,10 @@ def test_full_size(cuda, n, dtype, algo):
     cfg.algo = algo
     cfg.lds_elems = 0
     if not ppx.config_valid(ppx.OP_TRIDIAG, CODE[dtype], n, cfg):
-        cfg = ppx.make_config(2, max(64, n // 2), 1, algo)
+        valid = [c for c in ppx.enumerate_configs(ppx.OP_TRIDIAG, CODE[dtype], n) if c.algo == algo]
+        if not valid:
+            pytest.skip("no configuration of this variant exists at this size (n / P > 64)")
+        cfg = valid[0]
     banner(f"tridiag full n={n} {np.dtype(dtype).name} {cfg}")
     x = _solve(dev, n, batch, dtype, cfg)
     r = oracle.tridiag_residual(a, b, c, d, x)
