@@ -89,9 +89,7 @@ def build_workload(ops, dev):
                     # call of the same step has just touched
                     ad, bd, cd, dd = (torch.from_numpy(v).to(dev) for v in (a, b, c, d))
                     xo = torch.empty_like(dd)
-                    cfg = ppx.resolve_config(ppx.OP_TRIDIAG, code, n, batch)
-                    if cfg.algo != algo:
-                        cfg = _with_algo(ppx, code, n, batch, algo)
+                    cfg = _with_algo(ppx, code, n, batch, algo)
                     es = np.dtype(dt).itemsize
                     calls.append(dict(op="tridiag_" + name, dtype=np.dtype(dt).name, n=n,
                                       batch=batch, bpe=5 * es, cfg=cfg,
@@ -101,19 +99,38 @@ def build_workload(ops, dev):
 
 
 def _with_algo(ppx, code, n, batch, algo):
-    """Best configuration of the requested tridiagonal algorithm."""
+    """Tuned configuration of the requested tridiagonal family (CR or PCR, with
+    either exchange), else the resolved one if it is of that family, else the
+    first valid one of the family."""
     cfg = ppx.tuned_config(ppx.OP_TRIDIAG, code, n, algo)
     if cfg is not None:
         return cfg
     c = ppx.resolve_config(ppx.OP_TRIDIAG, code, n, batch)
-    c.algo = algo
-    c.lds_elems = 0
-    if ppx.config_valid(ppx.OP_TRIDIAG, code, n, c):
+    if (c.algo & 1) == algo:
         return c
     for cc in ppx.enumerate_configs(ppx.OP_TRIDIAG, code, n):
-        if cc.algo == algo:
+        if (cc.algo & 1) == algo:
             return cc
     raise RuntimeError("no valid tridiagonal configuration")
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bench_step.json")
+
+
+def measured_traffic(dom):
+    """HBM bytes per launch of the dominant call from the committed counter
+    record (FETCH_SIZE and WRITE_SIZE scaled by a known-size copy), or None if
+    there is no record for that call or its kernel sources changed since."""
+    from paper_2310_16214_amd import traffic
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        lines = f.read().splitlines()
+    for r in json.loads(lines[1])["calls"]:
+        if r["call"] == f"{dom['op']} n={dom['n']} {dom['dtype']}" and r["cfg"] == dom["cfg"] \
+                and r["sources_sha256"] == traffic.sources_sha(dom["op"]):
+            return round(r["traffic_bytes"])
+    return None
 
 
 def cpu_baseline(calls_meta, nthreads, budget_s=20.0):
@@ -204,12 +221,13 @@ def main():
         ts = np.array([events[s][i][0].elapsed_time(events[s][i][1]) for s in range(args.steps)])
         us = float(np.mean(ts)) * 1e3
         byt = c["bpe"] * c["n"] * c["batch"]
-        per.append(dict(op=c["op"], dtype=c["dtype"], n=c["n"], batch=c["batch"],
+        per.append(dict(op=c["op"], dtype=c["dtype"], n=c["n"], batch=c["batch"], bpe=c["bpe"],
                         cfg=c["cfg"].as_dict(), us=us, us_median=float(np.median(ts)) * 1e3,
                         gelem_s=c["n"] * c["batch"] / us / 1e3, gb_s=byt / us / 1e3,
                         hbm_frac=byt / us / 1e3 / HBM_PEAK_GBS))
     dom = max(per, key=lambda r: r["us"])
     bytes_step = sum(c["bpe"] * c["n"] * c["batch"] for c in calls)
+    traffic = measured_traffic(dom)
 
     out = {
         "metric": "GElem/s + % HBM peak, tuned vs default & batched vs plain; p50/p99 latency",
@@ -231,7 +249,7 @@ def main():
                    "algorithmic_bytes_per_step": bytes_step,
                    "hbm_frac_step": round(bytes_step / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "roofline": {"bound": "hbm", "achieved": round(dom["gb_s"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(dom["hbm_frac"], 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(dom["hbm_frac"], 4), "traffic": traffic,
                      "kernel": f"{dom['op']} n={dom['n']} {dom['dtype']}",
                      "kernel_us": round(dom["us"], 2)},
     }

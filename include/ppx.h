@@ -65,7 +65,8 @@ extern "C" {
 #define PPX_TRI_PCR 1       /* parallel cyclic reduction (Sec. III), LDS exchange */
 #define PPX_TRI_CR_SHFL 2   /* CR inside a wave: registers + lane shuffles, no
                                LDS (S = 0); valid when n / P <= 64, P <= 16 */
-#define PPX_TRI_PCR_SHFL 3  /* PCR inside a wave (S = 0); n / P <= 64, P <= 8 */
+#define PPX_TRI_PCR_SHFL 3  /* PCR inside a wave (S = 0); n / P <= 64, P <= 16
+                               (float32) or 8 (float64) */
 
 /* ---- tuning methods ---- */
 #define PPX_TUNE_EXHAUSTIVE 0 /* time every valid configuration (Sec. VI) */

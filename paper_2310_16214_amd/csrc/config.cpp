@@ -90,7 +90,7 @@ int validate_config(int op, int dtype, int64_t n, const ppx_config &c) {
                 return fail(PPX_ECONFIG, "tridiagonal algo must be PPX_TRI_CR, _PCR, _CR_SHFL or _PCR_SHFL");
             if (c.algo >= PPX_TRI_CR_SHFL) {
                 if (n / P > kWave) return fail(PPX_ECONFIG, "shuffle variant needs n / P <= 64 (a system within a wave)");
-                if (P > tri_wave_max_p(c.algo)) return fail(PPX_ECONFIG, "shuffle variant: too many elements per thread");
+                if (P > tri_wave_max_p(c.algo, dtype)) return fail(PPX_ECONFIG, "shuffle variant: too many elements per thread");
                 if (L > kTriWaveMaxThreads) return fail(PPX_ECONFIG, "shuffle variant allows at most 256 threads");
             }
             break;

@@ -72,7 +72,9 @@ constexpr int fft_max_threads(int P) { return P >= 32 ? 512 : 1024; }
 // Limits of the in-wave tridiagonal kernels (registers hold P equations of
 // four coefficients; PCR needs twice that again for the neighbours).
 constexpr int kTriWaveMaxThreads = 256;
-constexpr int tri_wave_max_p(int algo) { return algo == PPX_TRI_PCR_SHFL ? 8 : 16; }
+constexpr int tri_wave_max_p(int algo, int dtype) {
+    return algo == PPX_TRI_PCR_SHFL && dtype == PPX_F64 ? 8 : 16;
+}
 int launch_fft(const void *in, void *out, int log2n, int64_t batch,
                const ppx_config &c, bool inverse, hipStream_t s);
 int launch_scan(const void *in, void *out, int log2n, int64_t batch, int dtype,

@@ -2,6 +2,8 @@
 #include "tridiag_device.h"
 #include "tridiag_wave_device.h"
 
+#include <type_traits>
+
 namespace ppx {
 
 // ------------------------------------------------------------------- host
@@ -19,7 +21,8 @@ static const void *wave_kernel_p(int P) {
         case 4: return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 4>);
         case 8: return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 8>);
         case 16:
-            if constexpr (A == PPX_TRI_CR_SHFL) return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 16>);
+            if constexpr (A == PPX_TRI_CR_SHFL || std::is_same<T, float>::value)
+                return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 16>);
             return nullptr;
         default: return nullptr;
     }

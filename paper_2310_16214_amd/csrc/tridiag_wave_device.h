@@ -194,66 +194,95 @@ __device__ __forceinline__ void wave_cr(T (&a)[P], T (&b)[P], T (&c)[P], T (&d)[
     (void)log2n;
 }
 
+// PCR update of one equation from its left (l*) and right (r*) neighbours;
+// has_l / has_r false mean identity neighbours.
+template <typename T>
+__device__ __forceinline__ void pcr_update(T &a, T &b, T &c, T &d, T la, T lb, T lc, T ld, T ra, T rb,
+                                           T rc, T rd, bool has_l, bool has_r) {
+    T na = T(0), nc = T(0), nb = b, nd = d;
+    if (has_l) {
+        const T k1 = a * rcp(lb);
+        na = -la * k1;
+        nb -= lc * k1;
+        nd -= ld * k1;
+    }
+    if (has_r) {
+        const T k2 = c * rcp(rb);
+        nc = -rc * k2;
+        nb -= ra * k2;
+        nd -= rd * k2;
+    }
+    a = na;
+    b = nb;
+    c = nc;
+    d = nd;
+}
+
+// PCR steps with stride S < P, unrolled: the left neighbours of equations
+// r < S are equations P - S + r of the previous lane, the right neighbours of
+// r >= P - S equations r + S - P of the next lane (8 S shuffles per step).
+template <typename T, int P, int S>
+__device__ __forceinline__ void pcr_inlane_steps(T (&a)[P], T (&b)[P], T (&c)[P], T (&d)[P], int t,
+                                                 int n) {
+    if constexpr (S < P) {
+        if (S >= n) return;
+        T ua[S], ub[S], uc[S], ud[S], wa[S], wb[S], wc[S], wd[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            ua[k] = shfl_up(a[P - S + k], 1);
+            ub[k] = shfl_up(b[P - S + k], 1);
+            uc[k] = shfl_up(c[P - S + k], 1);
+            ud[k] = shfl_up(d[P - S + k], 1);
+            wa[k] = shfl_down(a[k], 1);
+            wb[k] = shfl_down(b[k], 1);
+            wc[k] = shfl_down(c[k], 1);
+            wd[k] = shfl_down(d[k], 1);
+        }
+        T na[P], nb[P], nc[P], nd[P];
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const int i = t * P + r;
+            na[r] = a[r];
+            nb[r] = b[r];
+            nc[r] = c[r];
+            nd[r] = d[r];
+            const T la = r >= S ? a[r - S] : ua[r % S], lb = r >= S ? b[r - S] : ub[r % S];
+            const T lc = r >= S ? c[r - S] : uc[r % S], ld = r >= S ? d[r - S] : ud[r % S];
+            const T ra = r + S < P ? a[(r + S) % P] : wa[(r + S) % S];
+            const T rb = r + S < P ? b[(r + S) % P] : wb[(r + S) % S];
+            const T rc = r + S < P ? c[(r + S) % P] : wc[(r + S) % S];
+            const T rd = r + S < P ? d[(r + S) % P] : wd[(r + S) % S];
+            pcr_update(na[r], nb[r], nc[r], nd[r], la, lb, lc, ld, ra, rb, rc, rd, i - S >= 0, i + S < n);
+        }
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            a[r] = na[r];
+            b[r] = nb[r];
+            c[r] = nc[r];
+            d[r] = nd[r];
+        }
+        pcr_inlane_steps<T, P, 2 * S>(a, b, c, d, t, n);
+    }
+}
+
 // PCR on the registers of one lane group.
 template <typename T, int P>
 __device__ __forceinline__ void wave_pcr(T (&a)[P], T (&b)[P], T (&c)[P], T (&d)[P], int t, int lps,
                                          int log2n) {
     const int n = P * lps;
-    for (int s = 1; s < n; s *= 2) {
-        T la[P], lb[P], lc[P], ld[P], ra[P], rb[P], rc[P], rd[P];
-        if (s < P) {
-#pragma unroll
-            for (int r = 0; r < P; ++r) {
-                // left neighbour: local r - s, else equation P - s + r of lane t - 1
-                const int ql = (r - s + P) % P, qr = (r + s) % P;
-                const T ua = shfl_up(a[ql], 1), ub = shfl_up(b[ql], 1);
-                const T uc = shfl_up(c[ql], 1), ud = shfl_up(d[ql], 1);
-                const T wa = shfl_down(a[qr], 1), wb = shfl_down(b[qr], 1);
-                const T wc = shfl_down(c[qr], 1), wd = shfl_down(d[qr], 1);
-                const bool ll = r >= s, rl = r + s < P;
-                la[r] = ll ? a[ql] : ua;
-                lb[r] = ll ? b[ql] : ub;
-                lc[r] = ll ? c[ql] : uc;
-                ld[r] = ll ? d[ql] : ud;
-                ra[r] = rl ? a[qr] : wa;
-                rb[r] = rl ? b[qr] : wb;
-                rc[r] = rl ? c[qr] : wc;
-                rd[r] = rl ? d[qr] : wd;
-            }
-        } else {
-            const int dl = s / P;
-#pragma unroll
-            for (int r = 0; r < P; ++r) {
-                la[r] = shfl_up(a[r], dl);
-                lb[r] = shfl_up(b[r], dl);
-                lc[r] = shfl_up(c[r], dl);
-                ld[r] = shfl_up(d[r], dl);
-                ra[r] = shfl_down(a[r], dl);
-                rb[r] = shfl_down(b[r], dl);
-                rc[r] = shfl_down(c[r], dl);
-                rd[r] = shfl_down(d[r], dl);
-            }
-        }
+    pcr_inlane_steps<T, P, 1>(a, b, c, d, t, n);
+    // strides s >= P: the neighbours are the same registers of the lanes s/P
+    // away; each equation only needs its own old values and the shuffled
+    // ones, so the update is in place (all lanes step through r together)
+    for (int s = P; s < n; s *= 2) {
+        const int dl = s / P;
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-            const int i = t * P + r;
-            T na_ = T(0), nc_ = T(0), nb_ = b[r], nd_ = d[r];
-            if (i - s >= 0) {
-                const T k1 = a[r] * rcp(lb[r]);
-                na_ = -la[r] * k1;
-                nb_ -= lc[r] * k1;
-                nd_ -= ld[r] * k1;
-            }
-            if (i + s < n) {
-                const T k2 = c[r] * rcp(rb[r]);
-                nc_ = -rc[r] * k2;
-                nb_ -= ra[r] * k2;
-                nd_ -= rd[r] * k2;
-            }
-            a[r] = na_;
-            b[r] = nb_;
-            c[r] = nc_;
-            d[r] = nd_;
+            const T la = shfl_up(a[r], dl), lb = shfl_up(b[r], dl);
+            const T lc = shfl_up(c[r], dl), ld = shfl_up(d[r], dl);
+            const T ra = shfl_down(a[r], dl), rb = shfl_down(b[r], dl);
+            const T rc = shfl_down(c[r], dl), rd = shfl_down(d[r], dl);
+            pcr_update(a[r], b[r], c[r], d[r], la, lb, lc, ld, ra, rb, rc, rd, t - dl >= 0, t + dl < lps);
         }
     }
 #pragma unroll

@@ -442,11 +442,22 @@ struct CacheEntry {
 std::map<std::tuple<int, int, int64_t, int>, CacheEntry> g_cache;  // (op, dtype, n, algo filter)
 }  // namespace
 
+// The entry for (op, dtype, n) over every algorithm; if only per-algorithm
+// (per-family) entries were tuned, the fastest of them.
 bool cached_config(int op, int dtype, int64_t n, ppx_config &c) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_cache.find({op, dtype, n, -1});
-    if (it == g_cache.end()) return false;
-    c = it->second.cfg;
+    if (it != g_cache.end()) {
+        c = it->second.cfg;
+        return true;
+    }
+    const CacheEntry *best = nullptr;
+    for (int a = 0; a < 4; ++a) {
+        auto jt = g_cache.find({op, dtype, n, a});
+        if (jt != g_cache.end() && jt->second.us > 0 && (!best || jt->second.us < best->us)) best = &jt->second;
+    }
+    if (!best) return false;
+    c = best->cfg;
     return true;
 }
 
