@@ -13,9 +13,11 @@ and writes its own buffers, so a call's data was last touched a full step
 earlier (far more than the 256 MB Infinity Cache holds in between).
 
 Prints one JSON line: the whole step's GElem/s, the dominant kernel's
-achieved HBM bandwidth against the 8 TB/s peak (from HIP events around every
-launch in the timed region, on the stream the kernels run on), and the CPU
-oracle timed on a bounded sample of the same workload.
+achieved HBM bandwidth against the 8 TB/s peak, and the CPU oracle timed on a
+bounded sample of the same workload.  The dominant call is the slowest one of
+an untimed pass with an event pair around every call (--detail writes that
+pass per call); in the timed steps only the dominant call is bracketed by HIP
+events (on the stream the kernels run on), which gives its live mean duration.
 """
 from __future__ import annotations
 
@@ -106,10 +108,10 @@ def _with_algo(ppx, code, n, batch, algo):
     if cfg is not None:
         return cfg
     c = ppx.resolve_config(ppx.OP_TRIDIAG, code, n, batch)
-    if (c.algo & 1) == algo:
+    if ppx.tri_family(c.algo) == algo:
         return c
     for cc in ppx.enumerate_configs(ppx.OP_TRIDIAG, code, n):
-        if (cc.algo & 1) == algo:
+        if ppx.tri_family(cc.algo) == algo:
             return cc
     raise RuntimeError("no valid tridiagonal configuration")
 
@@ -200,15 +202,43 @@ def main():
             c["run"]()
     torch.cuda.synchronize()
 
+    # per-call breakdown, outside the timed region: an event pair around every
+    # call (each pair adds about 1-2 us to the call it brackets and a few us of
+    # idle time between launches, so it is kept out of the timed steps)
+    detail_steps = 3
     events = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in calls] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
+               for _ in calls] for _ in range(detail_steps)]
+    for s in range(detail_steps):
         for c, (e0, e1) in zip(calls, events[s]):
             e0.record(stream)
             c["run"]()
             e1.record(stream)
+    torch.cuda.synchronize()
+    per = []
+    for i, c in enumerate(calls):
+        ts = np.array([events[s][i][0].elapsed_time(events[s][i][1]) for s in range(detail_steps)])
+        us = float(np.mean(ts)) * 1e3
+        byt = c["bpe"] * c["n"] * c["batch"]
+        per.append(dict(op=c["op"], dtype=c["dtype"], n=c["n"], batch=c["batch"], bpe=c["bpe"],
+                        cfg=c["cfg"].as_dict(), us=us, us_median=float(np.median(ts)) * 1e3,
+                        gelem_s=c["n"] * c["batch"] / us / 1e3, gb_s=byt / us / 1e3,
+                        hbm_frac=byt / us / 1e3 / HBM_PEAK_GBS))
+    di = max(range(len(per)), key=lambda i: per[i]["us"])
+
+    # timed region: K whole steps; the dominant call alone is bracketed by an
+    # event pair on its stream, which gives its live mean duration
+    dom_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        for i, c in enumerate(calls):
+            if i == di:
+                dom_ev[s][0].record(stream)
+                c["run"]()
+                dom_ev[s][1].record(stream)
+            else:
+                c["run"]()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
@@ -216,16 +246,10 @@ def main():
     elems = sum(c["n"] * c["batch"] for c in calls)
     value = elems / (ms_per_step * 1e-3) / 1e9
 
-    per = []
-    for i, c in enumerate(calls):
-        ts = np.array([events[s][i][0].elapsed_time(events[s][i][1]) for s in range(args.steps)])
-        us = float(np.mean(ts)) * 1e3
-        byt = c["bpe"] * c["n"] * c["batch"]
-        per.append(dict(op=c["op"], dtype=c["dtype"], n=c["n"], batch=c["batch"], bpe=c["bpe"],
-                        cfg=c["cfg"].as_dict(), us=us, us_median=float(np.median(ts)) * 1e3,
-                        gelem_s=c["n"] * c["batch"] / us / 1e3, gb_s=byt / us / 1e3,
-                        hbm_frac=byt / us / 1e3 / HBM_PEAK_GBS))
-    dom = max(per, key=lambda r: r["us"])
+    dom = dict(per[di])
+    dom_us = float(np.mean([a.elapsed_time(b) for a, b in dom_ev])) * 1e3
+    dom_bytes = dom["bpe"] * dom["n"] * dom["batch"]
+    dom.update(us=dom_us, gb_s=dom_bytes / dom_us / 1e3, hbm_frac=dom_bytes / dom_us / 1e3 / HBM_PEAK_GBS)
     bytes_step = sum(c["bpe"] * c["n"] * c["batch"] for c in calls)
     traffic = measured_traffic(dom)
 

@@ -65,8 +65,11 @@ extern "C" {
 #define PPX_TRI_PCR 1       /* parallel cyclic reduction (Sec. III), LDS exchange */
 #define PPX_TRI_CR_SHFL 2   /* CR inside a wave: registers + lane shuffles, no
                                LDS (S = 0); valid when n / P <= 64, P <= 16 */
-#define PPX_TRI_PCR_SHFL 3  /* PCR inside a wave (S = 0); n / P <= 64, P <= 16
-                               (float32) or 8 (float64) */
+#define PPX_TRI_PCR_SHFL 3  /* PCR inside a wave (S = 0); n / P <= 64, P <= 16 */
+#define PPX_TRI_PCR_REG 4   /* PCR inside a wave, the cross-lane exchange through
+                               a per-wave LDS buffer of 3 * 64 * min(P, 4)
+                               values (16-byte accesses) instead of shuffles;
+                               S = 0, n / P <= 64, P <= 16 */
 
 /* ---- tuning methods ---- */
 #define PPX_TUNE_EXHAUSTIVE 0 /* time every valid configuration (Sec. VI) */
@@ -128,8 +131,9 @@ int scan_batched(const void *in, void *out, int64_t n, int64_t batch,
  * (the solve then overwrites the right-hand side); no other aliasing.
  * No pivoting: systems are assumed diagonally dominant.  cfg->algo picks CR
  * or PCR and the exchange (LDS, or lane shuffles when a system fits a wave:
- * the paper's "shuffle" option); the wave variants use a refined hardware
- * reciprocal instead of IEEE division.
+ * the paper's "shuffle" option).  Every variant keeps each equation scaled to
+ * unit diagonal (one reciprocal per elimination, a refined hardware estimate
+ * rather than IEEE division); the solution is that of the unscaled system.
  */
 int tridiag_batched(const void *a, const void *b, const void *c, const void *d,
                     void *x, int64_t n, int64_t batch, int dtype,

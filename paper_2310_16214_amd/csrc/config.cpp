@@ -27,7 +27,7 @@ static int64_t lds_needed(int op, int dtype, int64_t n, const ppx_config &c) {
     switch (op) {
         case PPX_OP_FFT: return fft_lds_bytes((int)n, c.problems_per_block, c.algo);
         case PPX_OP_SCAN: return scan_lds_bytes((int)n, c.problems_per_block, c.elems_per_thread, dtype);
-        default: return tridiag_lds_bytes((int)n, c.problems_per_block, dtype, c.algo);
+        default: return tridiag_lds_bytes((int)n, c, dtype);
     }
 }
 
@@ -40,7 +40,7 @@ static int lds_elems(int op, int64_t n, const ppx_config &c) {
             return T > kWave ? c.threads_per_block / kWave : 0;
         }
         default:
-            if (c.algo == PPX_TRI_CR_SHFL || c.algo == PPX_TRI_PCR_SHFL) return 0;
+            if (tri_in_wave(c.algo)) return 0;
             return (int)((c.algo == PPX_TRI_PCR ? 2 : 1) * c.problems_per_block * n);
     }
 }
@@ -86,9 +86,9 @@ int validate_config(int op, int dtype, int64_t n, const ppx_config &c) {
             break;
         case PPX_OP_TRIDIAG:
             if (c.radix != 0 && c.radix != 2) return fail(PPX_ECONFIG, "tridiagonal radix must be 2");
-            if (c.algo < PPX_TRI_CR || c.algo > PPX_TRI_PCR_SHFL)
-                return fail(PPX_ECONFIG, "tridiagonal algo must be PPX_TRI_CR, _PCR, _CR_SHFL or _PCR_SHFL");
-            if (c.algo >= PPX_TRI_CR_SHFL) {
+            if (c.algo < PPX_TRI_CR || c.algo > PPX_TRI_PCR_REG)
+                return fail(PPX_ECONFIG, "tridiagonal algo must be PPX_TRI_CR, _PCR, _CR_SHFL, _PCR_SHFL or _PCR_REG");
+            if (tri_in_wave(c.algo)) {
                 if (n / P > kWave) return fail(PPX_ECONFIG, "shuffle variant needs n / P <= 64 (a system within a wave)");
                 if (P > tri_wave_max_p(c.algo, dtype)) return fail(PPX_ECONFIG, "shuffle variant: too many elements per thread");
                 if (L > kTriWaveMaxThreads) return fail(PPX_ECONFIG, "shuffle variant allows at most 256 threads");
@@ -127,7 +127,7 @@ int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap) {
     static const int radix_two[] = {2};
     const int *radices = op == PPX_OP_FFT ? radices_fft : radix_two;
     const int nr = op == PPX_OP_FFT ? 4 : 1;
-    const int nalgo = op == PPX_OP_TRIDIAG ? 4 : 2;
+    const int nalgo = op == PPX_OP_TRIDIAG ? 5 : 2;
     int count = 0;
     for (int ri = 0; ri < nr; ++ri)
         for (int L = 64; L <= 1024; L *= 2)

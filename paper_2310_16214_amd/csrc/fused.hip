@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(const FusedJob *__restr
 int64_t fused_tile_problems(int op, int dtype, int64_t n, int algo) {
     if (op == PPX_OP_FFT) return std::max<int64_t>(1, kFusedFftElems / n);
     if (op == PPX_OP_SCAN) return std::max<int64_t>(1, kFusedScanElems / n);
-    const int64_t per_sys = (algo == PPX_TRI_PCR ? 8 : 4) * (dtype == PPX_F64 ? 8 : 4) * n;
+    const int64_t per_sys = tri_lds_arrays(algo) * (dtype == PPX_F64 ? 8 : 4) * n;
     const int64_t by_lds = kFusedLds / per_sys;
     const int64_t by_threads = 2 * kFusedThreads / n > 0 ? 2 * kFusedThreads / n : 1;
     return std::min(by_lds, std::max<int64_t>(1, by_threads));
@@ -225,7 +225,7 @@ int check_job(const ppx_job &j) {
             if (j.algo != PPX_TRI_CR && j.algo != PPX_TRI_PCR) return fail(PPX_EINVAL, "job: tridiagonal algo");
             if (!j.b || !j.c || !j.d || !al(j.b) || !al(j.c) || !al(j.d))
                 return fail(PPX_EINVAL, "job: tridiagonal coefficient pointers");
-            const int64_t per_sys = (j.algo == PPX_TRI_PCR ? 8 : 4) * (j.dtype == PPX_F64 ? 8 : 4) * j.n;
+            const int64_t per_sys = tri_lds_arrays(j.algo) * (j.dtype == PPX_F64 ? 8 : 4) * j.n;
             if (per_sys > kFusedLds) return fail(PPX_EINVAL, "job: tridiagonal system too large for a fused tile");
             break;
         }

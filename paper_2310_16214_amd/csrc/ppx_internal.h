@@ -61,7 +61,7 @@ inline int ilog2(int64_t v) {
 // ---- LDS footprint of each kernel family (bytes per workgroup) ----
 int64_t fft_lds_bytes(int n, int gb, int algo);
 int64_t scan_lds_bytes(int n, int gb, int P, int dtype);
-int64_t tridiag_lds_bytes(int n, int gb, int dtype, int algo);
+int64_t tridiag_lds_bytes(int n, const ppx_config &c, int dtype);
 
 // ---- kernel launchers (validated arguments only) ----
 constexpr int kFftLog2NMax = 14;
@@ -72,8 +72,11 @@ constexpr int fft_max_threads(int P) { return P >= 32 ? 512 : 1024; }
 // Limits of the in-wave tridiagonal kernels (registers hold P equations of
 // four coefficients; PCR needs twice that again for the neighbours).
 constexpr int kTriWaveMaxThreads = 256;
-constexpr int tri_wave_max_p(int algo, int dtype) {
-    return algo == PPX_TRI_PCR_SHFL && dtype == PPX_F64 ? 8 : 16;
+constexpr int tri_wave_max_p(int, int) { return 16; }
+// In-wave variants (registers + lane exchange) and the algorithm family.
+constexpr bool tri_in_wave(int algo) { return algo >= PPX_TRI_CR_SHFL; }
+constexpr int tri_family(int algo) {
+    return algo == PPX_TRI_CR || algo == PPX_TRI_CR_SHFL ? PPX_TRI_CR : PPX_TRI_PCR;
 }
 int launch_fft(const void *in, void *out, int log2n, int64_t batch,
                const ppx_config &c, bool inverse, hipStream_t s);

@@ -126,7 +126,7 @@ int launch_single(const ppx_job &j, hipStream_t st) {
         default: {
             ppx_config c{};
             if (ppx_resolve_config(PPX_OP_TRIDIAG, j.dtype, j.n, j.batch, &c) != PPX_OK) return PPX_EINVAL;
-            if ((c.algo & 1) != (j.algo & 1)) {
+            if (tri_family(c.algo) != tri_family(j.algo)) {
                 // the tuned entry of the requested algorithm, else the plain default
                 if (ppx_tuned_config(PPX_OP_TRIDIAG, j.dtype, j.n, j.algo, &c) != PPX_OK) {
                     if (default_config(PPX_OP_TRIDIAG, j.dtype, j.n, c) != PPX_OK) return PPX_EINVAL;

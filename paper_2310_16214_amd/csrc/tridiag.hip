@@ -8,10 +8,16 @@ namespace ppx {
 
 // ------------------------------------------------------------------- host
 
-int64_t tridiag_lds_bytes(int n, int gb, int dtype, int algo) {
-    if (algo == PPX_TRI_CR_SHFL || algo == PPX_TRI_PCR_SHFL) return 0;
+int64_t tridiag_lds_bytes(int n, const ppx_config &c, int dtype) {
     const int64_t es = dtype == PPX_F64 ? 8 : 4;
-    return (algo == PPX_TRI_PCR ? 8 : 4) * es * (int64_t)gb * n;
+    if (c.algo == PPX_TRI_PCR_REG) {  // exchange buffer: 3 * 64 * min(P, 4) values per wave
+        const int64_t waves = (c.threads_per_block + 63) / 64;
+        const int64_t P = c.elems_per_thread > 0 ? c.elems_per_thread
+                                                 : (int64_t)n * c.problems_per_block / c.threads_per_block;
+        return waves * 3 * 64 * (P < 4 ? P : 4) * es;
+    }
+    if (tri_in_wave(c.algo)) return 0;
+    return tri_lds_arrays(c.algo) * es * (int64_t)c.problems_per_block * n;
 }
 
 template <typename T, int A>
@@ -20,10 +26,7 @@ static const void *wave_kernel_p(int P) {
         case 2: return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 2>);
         case 4: return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 4>);
         case 8: return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 8>);
-        case 16:
-            if constexpr (A == PPX_TRI_CR_SHFL || std::is_same<T, float>::value)
-                return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 16>);
-            return nullptr;
+        case 16: return reinterpret_cast<const void *>(&k_tridiag_wave<T, A, 16>);
         default: return nullptr;
     }
 }
@@ -36,6 +39,8 @@ const void *tridiag_kernel(int dtype, int algo, int P) {
         return dtype == PPX_F64 ? wave_kernel_p<double, PPX_TRI_CR_SHFL>(P) : dtype == PPX_F32 ? wave_kernel_p<float, PPX_TRI_CR_SHFL>(P) : nullptr;
     if (algo == PPX_TRI_PCR_SHFL)
         return dtype == PPX_F64 ? wave_kernel_p<double, PPX_TRI_PCR_SHFL>(P) : dtype == PPX_F32 ? wave_kernel_p<float, PPX_TRI_PCR_SHFL>(P) : nullptr;
+    if (algo == PPX_TRI_PCR_REG)
+        return dtype == PPX_F64 ? wave_kernel_p<double, PPX_TRI_PCR_REG>(P) : dtype == PPX_F32 ? wave_kernel_p<float, PPX_TRI_PCR_REG>(P) : nullptr;
     if (dtype == PPX_F32) {
         if (algo == PPX_TRI_CR) return reinterpret_cast<const void *>(&k_tridiag<float, PPX_TRI_CR>);
         if (algo == PPX_TRI_PCR) return reinterpret_cast<const void *>(&k_tridiag<float, PPX_TRI_PCR>);
@@ -65,7 +70,7 @@ int launch_tridiag(const void *a, const void *b, const void *c, const void *d, v
     if (!di) return PPX_EDEVICE;
     const void *k = tridiag_kernel(dtype, cfg.algo, cfg.elems_per_thread);
     if (!k) return fail(PPX_ECONFIG, "no tridiagonal kernel for this dtype / algo");
-    const int64_t lds = tridiag_lds_bytes(1 << log2n, cfg.problems_per_block, dtype, cfg.algo);
+    const int64_t lds = tridiag_lds_bytes(1 << log2n, cfg, dtype);
     if (lds > di->lds_per_block)
         return fail(PPX_ECONFIG, "tridiagonal configuration exceeds the LDS per workgroup");
     if (dtype == PPX_F64) return launch_t<double>(k, a, b, c, d, x, log2n, batch, cfg, (size_t)lds, s);

@@ -1,33 +1,44 @@
 // Tridiagonal CR and PCR inside one wave (the paper's "shuffle" variant of
 // Sec. V-A, where a problem small enough for one warp exchanges through
 // shuffles instead of shared memory; on gfx950 the wave has 64 lanes, so the
-// condition is n / P <= 64).
+// condition is n / P <= 64).  Rows are kept at unit diagonal and eliminated by
+// unit_eliminate, as in the LDS kernels of tridiag_device.h.
 //
 // Each system is owned by n / P consecutive lanes; lane t holds the P
-// consecutive equations t*P .. t*P + P - 1 in registers (a, b, c, d).
+// consecutive equations t*P .. t*P + P - 1 in registers (a, c, d after the
+// scaling at load).
 //
 // CR, forward level with stride s: equations i = 2s*m + 2s - 1 eliminate
-// i - s and i + s (same update as the LDS kernel).  While 2s <= P the active
-// equations and their left neighbours are in the lane's own registers and
-// only i + s may be equation s - 1 of the next lane (one shuffle of four
-// values).  From s = P on, the reduced system lives in each lane's last
-// equation and the neighbours are the last equations of the lanes s/P away.
-// The 2x2 system of equations n/2 - 1 and n - 1 is solved by both of their
-// lanes; back substitution mirrors the levels, x overwriting d.
+// i - s and i + s.  While 2s <= P the active equations and their left
+// neighbours are in the lane's own registers and only i + s may be equation
+// s - 1 of the next lane (one shuffle of three values).  From s = P on, the
+// reduced system lives in each lane's last equation and the neighbours are the
+// last equations of the lanes s/P away.  The 2x2 system of equations n/2 - 1
+// and n - 1 is solved by both of their lanes; back substitution mirrors the
+// levels, x overwriting d.
 //
 // PCR, step with stride s: every equation updates from its neighbours at
 // distance s: for s < P the s nearest equations of the adjacent lanes come by
 // shuffles, from s = P on each equation's neighbours are the same registers of
-// the lanes s/P away.  After log2 n steps x_i = d_i / b_i.
+// the lanes s/P away.  After log2 n steps x_i = d_i.
 //
-// Out-of-system neighbours act as identity equations, which the row-index
-// predicates implement; so several systems may share a wave and shuffles that
-// cross a system boundary are ignored.  No LDS, no barriers.
+// Neighbours outside the system are identity rows.  CR replaces them by zeros
+// explicitly.  PCR shuffles within the system's lanes only, so a lane whose
+// neighbour lies outside the system receives one of its own (finite) values,
+// and that value is multiplied by an exact zero: before the step with stride
+// s, a_i = 0 for every i < s and c_i = 0 for every i >= n - s (true at load,
+// where a_0 = c_{n-1} = 0, and kept by the update, whose new a_i is a product
+// with a_{i-s} and a_i, and new c_i one with c_{i+s} and c_i).  Several
+// systems may thus share a wave and no value crosses between them.  No LDS,
+// no barriers.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ppx_internal.h"
+#include "tridiag_device.h"
 
 namespace ppx {
 
@@ -35,18 +46,12 @@ template <typename T>
 __device__ __forceinline__ T shfl_up(T v, int d) { return __shfl_up(v, (unsigned)d, 64); }
 template <typename T>
 __device__ __forceinline__ T shfl_down(T v, int d) { return __shfl_down(v, (unsigned)d, 64); }
-
-// Reciprocal: hardware estimate refined by Newton steps (two for double,
-// one for float), instead of the IEEE division sequence.
-__device__ __forceinline__ float rcp(float x) {
-    float r = __builtin_amdgcn_rcpf(x);
-    return r * (2.0f - x * r);
-}
-__device__ __forceinline__ double rcp(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    r = r * (2.0 - x * r);
-    return r * (2.0 - x * r);
-}
+// Shuffles confined to a system's lps lanes: a lane whose source would lie
+// outside its system gets its own value back.
+template <typename T>
+__device__ __forceinline__ T sys_up(T v, int d, int lps) { return __shfl_up(v, (unsigned)d, lps); }
+template <typename T>
+__device__ __forceinline__ T sys_down(T v, int d, int lps) { return __shfl_down(v, (unsigned)d, lps); }
 
 template <typename T, int P>
 __device__ __forceinline__ void wave_load(const T *src, T (&v)[P]) {
@@ -88,93 +93,59 @@ __device__ __forceinline__ void wave_store(T *dst, const T (&v)[P]) {
 // CR on the registers of one lane group; t = lane index within the system,
 // lps = lanes per system, n = P * lps.
 template <typename T, int P>
-__device__ __forceinline__ void wave_cr(T (&a)[P], T (&b)[P], T (&c)[P], T (&d)[P], int t, int lps,
-                                        int log2n) {
+__device__ __forceinline__ void wave_cr(T (&a)[P], T (&c)[P], T (&d)[P], int t, int lps) {
     const int n = P * lps;
+    const bool last_lane = t + 1 == lps;
     // ---- forward levels inside the lane (2s <= P)
 #pragma unroll
     for (int s = 1; 2 * s <= P; s *= 2) {
         if (2 * s > n / 2) break;  // the last level leaves two equations
-        // equation s - 1 of the next lane (current values)
-        const T na = shfl_down(a[s - 1], 1), nb = shfl_down(b[s - 1], 1);
-        const T nc = shfl_down(c[s - 1], 1), nd = shfl_down(d[s - 1], 1);
+        // equation s - 1 of the next lane: right neighbour of equation P - 1
+        T na = shfl_down(a[s - 1], 1), nc = shfl_down(c[s - 1], 1), nd = shfl_down(d[s - 1], 1);
+        if (last_lane) na = nc = nd = T(0);
 #pragma unroll
         for (int r = 2 * s - 1; r < P; r += 2 * s) {
-            const T k1 = a[r] * rcp(b[r - s]);
-            T nb_ = b[r] - c[r - s] * k1, nd_ = d[r] - d[r - s] * k1, na_ = -a[r - s] * k1, nc_ = T(0);
-            const bool right_local = r + s < P;
-            const bool has_right = right_local || t + 1 < lps;
-            if (has_right) {
-                const T ra = right_local ? a[(r + s) % P] : na;
-                const T rb = right_local ? b[(r + s) % P] : nb;
-                const T rc = right_local ? c[(r + s) % P] : nc;
-                const T rd = right_local ? d[(r + s) % P] : nd;
-                const T k2 = c[r] * rcp(rb);
-                nb_ -= ra * k2;
-                nd_ -= rd * k2;
-                nc_ = -rc * k2;
-            }
-            a[r] = na_;
-            b[r] = nb_;
-            c[r] = nc_;
-            d[r] = nd_;
+            const bool local = r + s < P;
+            unit_eliminate(a[r], c[r], d[r], a[r - s], c[r - s], d[r - s], local ? a[(r + s) % P] : na,
+                           local ? c[(r + s) % P] : nc, local ? d[(r + s) % P] : nd);
         }
     }
     // ---- forward levels across lanes (s >= P): last equation of each lane
     for (int s = P; s <= n / 4; s *= 2) {
         const int dl = s / P;
-        const T la = shfl_up(a[P - 1], dl), lb = shfl_up(b[P - 1], dl);
-        const T lc = shfl_up(c[P - 1], dl), ld = shfl_up(d[P - 1], dl);
-        const T ra = shfl_down(a[P - 1], dl), rb = shfl_down(b[P - 1], dl);
-        const T rc = shfl_down(c[P - 1], dl), rd = shfl_down(d[P - 1], dl);
-        if (((t + 1) & (2 * dl - 1)) == 0) {  // equation t*P + P - 1 is 2s*m + 2s - 1
-            const T k1 = a[P - 1] * rcp(lb);
-            T nb_ = b[P - 1] - lc * k1, nd_ = d[P - 1] - ld * k1, na_ = -la * k1, nc_ = T(0);
-            if (t + dl < lps) {
-                const T k2 = c[P - 1] * rcp(rb);
-                nb_ -= ra * k2;
-                nd_ -= rd * k2;
-                nc_ = -rc * k2;
-            }
-            a[P - 1] = na_;
-            b[P - 1] = nb_;
-            c[P - 1] = nc_;
-            d[P - 1] = nd_;
-        }
+        const T la = shfl_up(a[P - 1], dl), lc = shfl_up(c[P - 1], dl), ld = shfl_up(d[P - 1], dl);
+        T ra = shfl_down(a[P - 1], dl), rc = shfl_down(c[P - 1], dl), rd = shfl_down(d[P - 1], dl);
+        if (t + dl >= lps) ra = rc = rd = T(0);
+        // equation t*P + P - 1 is 2s*m + 2s - 1; its left neighbour exists
+        if (((t + 1) & (2 * dl - 1)) == 0) unit_eliminate(a[P - 1], c[P - 1], d[P - 1], la, lc, ld, ra, rc, rd);
     }
     // ---- the 2x2 system of equations n/2 - 1 and n - 1
     if (lps == 1) {
-        const int i1 = n / 2 - 1, i2 = n - 1;
-        const T det = b[i1 % P] * b[i2 % P] - c[i1 % P] * a[i2 % P];
-        const T x1 = (d[i1 % P] * b[i2 % P] - c[i1 % P] * d[i2 % P]) * rcp(det);
-        const T x2 = (b[i1 % P] * d[i2 % P] - d[i1 % P] * a[i2 % P]) * rcp(det);
-        d[i1 % P] = x1;
-        d[i2 % P] = x2;
+        constexpr int i1 = P / 2 - 1, i2 = P - 1;
+        const T r = rcp(T(1) - c[i1] * a[i2]);
+        const T x1 = (d[i1] - c[i1] * d[i2]) * r;
+        const T x2 = (d[i2] - a[i2] * d[i1]) * r;
+        d[i1] = x1;
+        d[i2] = x2;
     } else {
         const int h = lps / 2;  // lanes h-1 and lps-1 hold the two equations
-        const T oa = shfl_down(a[P - 1], h), ob = shfl_down(b[P - 1], h);
-        const T oc = shfl_down(c[P - 1], h), od = shfl_down(d[P - 1], h);
-        const T ua = shfl_up(a[P - 1], h), ub = shfl_up(b[P - 1], h);
+        const T oa = shfl_down(a[P - 1], h), od = shfl_down(d[P - 1], h);
         const T uc = shfl_up(c[P - 1], h), ud = shfl_up(d[P - 1], h);
         if (t == h - 1) {  // row 1 here, row 2 from lane t + h
-            const T det = b[P - 1] * ob - c[P - 1] * oa;
-            d[P - 1] = (d[P - 1] * ob - c[P - 1] * od) * rcp(det);
-        } else if (t == lps - 1) {  // row 2 here, row 1 from lane t - h
-            const T det = ub * b[P - 1] - uc * a[P - 1];
-            d[P - 1] = (ub * d[P - 1] - ud * a[P - 1]) * rcp(det);
+            d[P - 1] = (d[P - 1] - c[P - 1] * od) * rcp(T(1) - c[P - 1] * oa);
+        } else if (last_lane) {  // row 2 here, row 1 from lane t - h
+            d[P - 1] = (d[P - 1] - a[P - 1] * ud) * rcp(T(1) - uc * a[P - 1]);
         }
-        (void)uc;
-        (void)oc;
     }
     // ---- back substitution across lanes (s >= P)
     for (int s = n / 4; s >= P; s /= 2) {
         const int dl = s / P;
         const T xl = shfl_up(d[P - 1], dl), xr = shfl_down(d[P - 1], dl);
         if (((t + 1) & (2 * dl - 1)) == dl) {  // equation 2s*m + s - 1
-            T r = d[P - 1];
-            if (t - dl >= 0) r -= a[P - 1] * xl;
-            if (t + dl < lps) r -= c[P - 1] * xr;
-            d[P - 1] = r * rcp(b[P - 1]);
+            T x = d[P - 1];
+            if (t - dl >= 0) x -= a[P - 1] * xl;
+            if (t + dl < lps) x -= c[P - 1] * xr;
+            d[P - 1] = x;
         }
     }
     // ---- back substitution inside the lane (s < P)
@@ -184,93 +155,58 @@ __device__ __forceinline__ void wave_cr(T (&a)[P], T (&b)[P], T (&c)[P], T (&d)[
         const T xl = shfl_up(d[P - 1], 1);  // x of the previous lane's last equation
 #pragma unroll
         for (int r = s - 1; r < P; r += 2 * s) {
-            T v = d[r];
-            if (r >= s) v -= a[r] * d[r - s];
-            else if (t > 0) v -= a[r] * xl;
-            if (r + s < P) v -= c[r] * d[r + s];  // always local: r + s <= P - 1
-            d[r] = v * rcp(b[r]);
+            T x = d[r];
+            if (r >= s) x -= a[r] * d[r - s];
+            else if (t > 0) x -= a[r] * xl;
+            x -= c[r] * d[r + s];  // r + s <= P - 1: always local
+            d[r] = x;
         }
     }
-    (void)log2n;
-}
-
-// PCR update of one equation from its left (l*) and right (r*) neighbours;
-// has_l / has_r false mean identity neighbours.
-template <typename T>
-__device__ __forceinline__ void pcr_update(T &a, T &b, T &c, T &d, T la, T lb, T lc, T ld, T ra, T rb,
-                                           T rc, T rd, bool has_l, bool has_r) {
-    T na = T(0), nc = T(0), nb = b, nd = d;
-    if (has_l) {
-        const T k1 = a * rcp(lb);
-        na = -la * k1;
-        nb -= lc * k1;
-        nd -= ld * k1;
-    }
-    if (has_r) {
-        const T k2 = c * rcp(rb);
-        nc = -rc * k2;
-        nb -= ra * k2;
-        nd -= rd * k2;
-    }
-    a = na;
-    b = nb;
-    c = nc;
-    d = nd;
 }
 
 // PCR steps with stride S < P, unrolled: the left neighbours of equations
 // r < S are equations P - S + r of the previous lane, the right neighbours of
-// r >= P - S equations r + S - P of the next lane (8 S shuffles per step).
+// r >= P - S equations r + S - P of the next lane (6 S shuffles per step).
 template <typename T, int P, int S>
-__device__ __forceinline__ void pcr_inlane_steps(T (&a)[P], T (&b)[P], T (&c)[P], T (&d)[P], int t,
-                                                 int n) {
+__device__ __forceinline__ void pcr_inlane_steps(T (&a)[P], T (&c)[P], T (&d)[P], int lps) {
     if constexpr (S < P) {
-        if (S >= n) return;
-        T ua[S], ub[S], uc[S], ud[S], wa[S], wb[S], wc[S], wd[S];
+        T ua[S], uc[S], ud[S], wa[S], wc[S], wd[S];
 #pragma unroll
         for (int k = 0; k < S; ++k) {
-            ua[k] = shfl_up(a[P - S + k], 1);
-            ub[k] = shfl_up(b[P - S + k], 1);
-            uc[k] = shfl_up(c[P - S + k], 1);
-            ud[k] = shfl_up(d[P - S + k], 1);
-            wa[k] = shfl_down(a[k], 1);
-            wb[k] = shfl_down(b[k], 1);
-            wc[k] = shfl_down(c[k], 1);
-            wd[k] = shfl_down(d[k], 1);
+            ua[k] = sys_up(a[P - S + k], 1, lps);
+            uc[k] = sys_up(c[P - S + k], 1, lps);
+            ud[k] = sys_up(d[P - S + k], 1, lps);
+            wa[k] = sys_down(a[k], 1, lps);
+            wc[k] = sys_down(c[k], 1, lps);
+            wd[k] = sys_down(d[k], 1, lps);
         }
-        T na[P], nb[P], nc[P], nd[P];
+        T na[P], nc[P], nd[P];
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-            const int i = t * P + r;
             na[r] = a[r];
-            nb[r] = b[r];
             nc[r] = c[r];
             nd[r] = d[r];
-            const T la = r >= S ? a[r - S] : ua[r % S], lb = r >= S ? b[r - S] : ub[r % S];
-            const T lc = r >= S ? c[r - S] : uc[r % S], ld = r >= S ? d[r - S] : ud[r % S];
-            const T ra = r + S < P ? a[(r + S) % P] : wa[(r + S) % S];
-            const T rb = r + S < P ? b[(r + S) % P] : wb[(r + S) % S];
-            const T rc = r + S < P ? c[(r + S) % P] : wc[(r + S) % S];
-            const T rd = r + S < P ? d[(r + S) % P] : wd[(r + S) % S];
-            pcr_update(na[r], nb[r], nc[r], nd[r], la, lb, lc, ld, ra, rb, rc, rd, i - S >= 0, i + S < n);
+            const bool lloc = r >= S, rloc = r + S < P;
+            unit_eliminate(na[r], nc[r], nd[r], lloc ? a[(r + P - S) % P] : ua[r % S],
+                           lloc ? c[(r + P - S) % P] : uc[r % S], lloc ? d[(r + P - S) % P] : ud[r % S],
+                           rloc ? a[(r + S) % P] : wa[(r + S) % S], rloc ? c[(r + S) % P] : wc[(r + S) % S],
+                           rloc ? d[(r + S) % P] : wd[(r + S) % S]);
         }
 #pragma unroll
         for (int r = 0; r < P; ++r) {
             a[r] = na[r];
-            b[r] = nb[r];
             c[r] = nc[r];
             d[r] = nd[r];
         }
-        pcr_inlane_steps<T, P, 2 * S>(a, b, c, d, t, n);
+        pcr_inlane_steps<T, P, 2 * S>(a, c, d, lps);
     }
 }
 
 // PCR on the registers of one lane group.
 template <typename T, int P>
-__device__ __forceinline__ void wave_pcr(T (&a)[P], T (&b)[P], T (&c)[P], T (&d)[P], int t, int lps,
-                                         int log2n) {
+__device__ __forceinline__ void wave_pcr(T (&a)[P], T (&c)[P], T (&d)[P], int lps) {
     const int n = P * lps;
-    pcr_inlane_steps<T, P, 1>(a, b, c, d, t, n);
+    pcr_inlane_steps<T, P, 1>(a, c, d, lps);
     // strides s >= P: the neighbours are the same registers of the lanes s/P
     // away; each equation only needs its own old values and the shuffled
     // ones, so the update is in place (all lanes step through r together)
@@ -278,57 +214,146 @@ __device__ __forceinline__ void wave_pcr(T (&a)[P], T (&b)[P], T (&c)[P], T (&d)
         const int dl = s / P;
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-            const T la = shfl_up(a[r], dl), lb = shfl_up(b[r], dl);
-            const T lc = shfl_up(c[r], dl), ld = shfl_up(d[r], dl);
-            const T ra = shfl_down(a[r], dl), rb = shfl_down(b[r], dl);
-            const T rc = shfl_down(c[r], dl), rd = shfl_down(d[r], dl);
-            pcr_update(a[r], b[r], c[r], d[r], la, lb, lc, ld, ra, rb, rc, rd, t - dl >= 0, t + dl < lps);
+            const T la = sys_up(a[r], dl, lps), lc = sys_up(c[r], dl, lps), ld = sys_up(d[r], dl, lps);
+            const T ra = sys_down(a[r], dl, lps), rc = sys_down(c[r], dl, lps), rd = sys_down(d[r], dl, lps);
+            unit_eliminate(a[r], c[r], d[r], la, lc, ld, ra, rc, rd);
+            // 16 doubles per lane: keep the scheduler from hoisting every
+            // row's shuffles (register pressure would halve the occupancy)
+            if constexpr (P * sizeof(T) >= 128)
+                if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
     }
+}
+
+// ---- PCR with the cross-lane exchange through LDS (PPX_TRI_PCR_REG)
+//
+// Same steps as wave_pcr, but for strides s >= P the lanes exchange through a
+// per-wave LDS buffer instead of shuffles: a shuffle moves 4 bytes per lane
+// through the LDS crossbar, while 16-byte LDS stores and loads move four times
+// as much per instruction.  Per chunk of K registers, every lane stores its
+// (a, c, d) chunk and loads the chunks of the lanes dl to either side (its own
+// at the system's ends, which meet exact-zero coefficients as with the
+// confined shuffles).  A wave's LDS instructions execute in issue order, so
+// the loads see the stores before them and finish before the next chunk's
+// stores; the fences only keep the compiler from reordering them.
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A lane's K values as words of 16 bytes (8 when K * sizeof(T) = 8), word w
+// of lane l at index w * 64 + l: each access instruction covers 64
+// consecutive words.
+template <typename T, int K>
+struct XWords {
+    static constexpr int bytes = K * (int)sizeof(T);
+    static constexpr int wb = bytes >= 16 ? 16 : bytes;
+    static constexpr int nw = bytes / wb;
+    static constexpr int per = wb / (int)sizeof(T);
+    using W = typename std::conditional<wb == 16, int4, int2>::type;
+};
+
+template <typename T, int K>
+__device__ __forceinline__ void xstore(T *buf, int lane, const T *v) {
+    using X = XWords<T, K>;
+    typename X::W *w = reinterpret_cast<typename X::W *>(buf);
 #pragma unroll
-    for (int r = 0; r < P; ++r) d[r] = d[r] * rcp(b[r]);
-    (void)log2n;
+    for (int k = 0; k < X::nw; ++k) {
+        typename X::W x;
+        __builtin_memcpy(&x, v + k * X::per, X::wb);
+        w[k * 64 + lane] = x;
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void xload(const T *buf, int lane, T *v) {
+    using X = XWords<T, K>;
+    const typename X::W *w = reinterpret_cast<const typename X::W *>(buf);
+#pragma unroll
+    for (int k = 0; k < X::nw; ++k) {
+        const typename X::W x = w[k * 64 + lane];
+        __builtin_memcpy(v + k * X::per, &x, X::wb);
+    }
+}
+
+// xb: this wave's 3 * 64 * K values of LDS.
+template <typename T, int P>
+__device__ __forceinline__ void wave_pcr_reg(T (&a)[P], T (&c)[P], T (&d)[P], int t, int lps, T *xb) {
+    constexpr int K = P < 4 ? P : 4;
+    constexpr int PL = 64 * K;
+    const int n = P * lps;
+    const int lane = threadIdx.x & 63;
+    pcr_inlane_steps<T, P, 1>(a, c, d, lps);
+    for (int s = P; s < n; s *= 2) {
+        const int dl = s / P;
+        const int ll = t >= dl ? lane - dl : lane;
+        const int rl = t + dl < lps ? lane + dl : lane;
+#pragma unroll
+        for (int r0 = 0; r0 < P; r0 += K) {
+            xstore<T, K>(xb, lane, a + r0);
+            xstore<T, K>(xb + PL, lane, c + r0);
+            xstore<T, K>(xb + 2 * PL, lane, d + r0);
+            wave_lds_order();
+            T la[K], lc[K], ld[K], ra[K], rc[K], rd[K];
+            xload<T, K>(xb, ll, la);
+            xload<T, K>(xb + PL, ll, lc);
+            xload<T, K>(xb + 2 * PL, ll, ld);
+            xload<T, K>(xb, rl, ra);
+            xload<T, K>(xb + PL, rl, rc);
+            xload<T, K>(xb + 2 * PL, rl, rd);
+            wave_lds_order();
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                unit_eliminate(a[r0 + k], c[r0 + k], d[r0 + k], la[k], lc[k], ld[k], ra[k], rc[k], rd[k]);
+        }
+    }
 }
 
 // One workgroup's share: systems [first, first + nsys) of size n = P * lps,
 // lps = n / P <= 64 lanes each; every lane owns P equations.
 template <typename T, int ALGO, int P>
 __device__ __forceinline__ void tridiag_wave_block(const T *A, const T *B, const T *C, const T *D,
-                                                   T *X, int log2n, long long first, int nsys) {
+                                                   T *X, int log2n, long long first, int nsys, T *smem) {
     const int n = 1 << log2n;
     const int lps = n / P;
     const int sys_local = threadIdx.x / lps;
     const int t = threadIdx.x % lps;
     const bool active = sys_local < nsys;
     const long long base = (first + sys_local) * n + (long long)t * P;
-    T a[P], b[P], c[P], d[P];
+    T a[P], c[P], d[P];
     if (active) {
+        T b[P];
         wave_load<T, P>(A + base, a);
         wave_load<T, P>(B + base, b);
         wave_load<T, P>(C + base, c);
         wave_load<T, P>(D + base, d);
         if (t == 0) a[0] = T(0);            // multiplies the absent x_{-1}
         if (t == lps - 1) c[P - 1] = T(0);  // multiplies the absent x_n
+#pragma unroll
+        for (int j = 0; j < P; ++j) {  // scale every row to unit diagonal
+            const T r = rcp(b[j]);
+            a[j] *= r;
+            c[j] *= r;
+            d[j] *= r;
+        }
     } else {
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            a[j] = T(0);
-            b[j] = T(1);
-            c[j] = T(0);
-            d[j] = T(0);
-        }
+        for (int j = 0; j < P; ++j) a[j] = c[j] = d[j] = T(0);
     }
-    if constexpr (ALGO == PPX_TRI_CR_SHFL) wave_cr<T, P>(a, b, c, d, t, lps, log2n);
-    else wave_pcr<T, P>(a, b, c, d, t, lps, log2n);
+    if constexpr (ALGO == PPX_TRI_CR_SHFL) wave_cr<T, P>(a, c, d, t, lps);
+    else if constexpr (ALGO == PPX_TRI_PCR_SHFL) wave_pcr<T, P>(a, c, d, lps);
+    else wave_pcr_reg<T, P>(a, c, d, t, lps, smem + (threadIdx.x >> 6) * (3 * 64 * (P < 4 ? P : 4)));
     if (active) wave_store<T, P>(X + base, d);
 }
 
 template <typename T, int ALGO, int P>
 __global__ __launch_bounds__(256) void k_tridiag_wave(const T *a, const T *b, const T *c, const T *d,
                                                       T *x, int log2n, long long batch, int gb) {
+    extern __shared__ float4 smem_raw[];  // PPX_TRI_PCR_REG: 3 * 64 * min(P, 4) values per wave
     const long long first = (long long)blockIdx.x * gb;
     const int nsys = (int)min((long long)gb, batch - first);
-    tridiag_wave_block<T, ALGO, P>(a, b, c, d, x, log2n, first, nsys);
+    tridiag_wave_block<T, ALGO, P>(a, b, c, d, x, log2n, first, nsys, reinterpret_cast<T *>(smem_raw));
 }
 
 }  // namespace ppx

@@ -452,7 +452,7 @@ bool cached_config(int op, int dtype, int64_t n, ppx_config &c) {
         return true;
     }
     const CacheEntry *best = nullptr;
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a <= PPX_TRI_PCR_REG; ++a) {
         auto jt = g_cache.find({op, dtype, n, a});
         if (jt != g_cache.end() && jt->second.us > 0 && (!best || jt->second.us < best->us)) best = &jt->second;
     }
@@ -477,8 +477,7 @@ void store_cached_config(int op, int dtype, int64_t n, const ppx_config &c) {
 static int static_vgprs(int op, int dtype, int P, int algo) {
     if (op == PPX_OP_FFT) return P <= 2 ? 16 : P <= 4 ? 29 : P <= 8 ? 55 : P <= 16 ? 107 : 200;
     if (op == PPX_OP_SCAN) return P <= 2 ? 10 : P <= 4 ? 12 : P <= 8 ? 16 : P <= 16 ? 24 : 40;
-    if (algo == PPX_TRI_CR_SHFL || algo == PPX_TRI_PCR_SHFL)
-        return (dtype == PPX_F64 ? 2 : 1) * (algo == PPX_TRI_PCR_SHFL ? 12 : 5) * P + 16;
+    if (tri_in_wave(algo)) return (dtype == PPX_F64 ? 2 : 1) * (algo == PPX_TRI_CR_SHFL ? 5 : 6) * P + 16;
     return dtype == PPX_F64 ? (algo == PPX_TRI_PCR ? 44 : 40) : (algo == PPX_TRI_PCR ? 32 : 28);
 }
 
@@ -494,7 +493,7 @@ static int64_t dyn_lds(int op, int dtype, int64_t n, const ppx_config &c) {
     switch (op) {
         case PPX_OP_FFT: return fft_lds_bytes((int)n, c.problems_per_block, c.algo);
         case PPX_OP_SCAN: return scan_lds_bytes((int)n, c.problems_per_block, c.elems_per_thread, dtype);
-        default: return tridiag_lds_bytes((int)n, c.problems_per_block, dtype, c.algo);
+        default: return tridiag_lds_bytes((int)n, c, dtype);
     }
 }
 
@@ -732,7 +731,7 @@ static int tune_impl(int op, int dtype, int64_t n, int64_t batch, int method, in
     enumerate_configs(op, dtype, n, all.data(), total);
     std::vector<ppx_config> cands;
     for (const auto &c : all)
-        if (algo < 0 || (op == PPX_OP_TRIDIAG ? (c.algo & 1) == (algo & 1) : c.algo == algo))
+        if (algo < 0 || (op == PPX_OP_TRIDIAG ? tri_family(c.algo) == tri_family(algo) : c.algo == algo))
             cands.push_back(c);
     if (cands.empty()) return fail(PPX_ECONFIG, "no valid configuration to tune");
     if (!device_info()) return PPX_EDEVICE;

@@ -25,7 +25,12 @@ I32, F32, F64, C64 = 0, 1, 2, 3
 OP_FFT, OP_SCAN, OP_TRIDIAG = 0, 1, 2
 FFT_LDS, FFT_LDS_SPLIT = 0, 1
 SCAN_KS, SCAN_LF = 0, 1
-TRI_CR, TRI_PCR, TRI_CR_SHFL, TRI_PCR_SHFL = 0, 1, 2, 3
+TRI_CR, TRI_PCR, TRI_CR_SHFL, TRI_PCR_SHFL, TRI_PCR_REG = 0, 1, 2, 3, 4
+
+
+def tri_family(algo):
+    """TRI_CR for the CR variants, TRI_PCR for the PCR variants."""
+    return TRI_CR if algo in (TRI_CR, TRI_CR_SHFL) else TRI_PCR
 TUNE_EXHAUSTIVE, TUNE_ANALYTICAL, TUNE_LEARNED = 0, 1, 2
 MIN_N, MAX_N = 16, 16384
 

@@ -45,7 +45,8 @@ def test_every_config(cuda, n, dtype):
           f"|x-oracle| {fe:.2e}, |x-x_true| {np.max(np.abs(x - xt)):.2e}")
 
 
-@pytest.mark.parametrize("algo", [ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL])
+@pytest.mark.parametrize("algo", [ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL,
+                                  ppx.TRI_PCR_REG])
 def test_boundary_coefficients_are_ignored(cuda, algo):
     n, batch = 256, 8
     a, b, c, d, _ = inputs.tridiag_input(n, batch, np.float32, seed=2)
@@ -71,7 +72,8 @@ def test_x_may_alias_d(cuda):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("n", [32, 1024])
-@pytest.mark.parametrize("algo", [ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL])
+@pytest.mark.parametrize("algo", [ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL,
+                                  ppx.TRI_PCR_REG])
 def test_full_size(cuda, n, dtype, algo):
     """Benchmark sweep size: 2^22 unknowns per call; every system checked."""
     batch = (1 << 22) // n
