@@ -59,6 +59,11 @@ extern "C" {
 #define PPX_FFT_LDS 0       /* exchange complex values through LDS */
 #define PPX_FFT_LDS_SPLIT 1 /* real parts, then imaginary parts, through a
                                half-size LDS buffer (Sec. V-C) */
+#define PPX_FFT_LDS_PIPE 2  /* PPX_FFT_LDS in persistent workgroups (as many as
+                               are resident) that load the next group of
+                               problems into registers while transforming the
+                               current one; radix = P = 8 or 16 only */
+#define PPX_FFT_LDS_SPLIT_PIPE 3 /* PPX_FFT_LDS_SPLIT, persistent as above */
 #define PPX_SCAN_KS 0       /* Kogge-Stone lane network (DPP row shifts) */
 #define PPX_SCAN_LF 1       /* Ladner-Fischer lane network (swizzle bcasts) */
 #define PPX_TRI_CR 0        /* cyclic reduction (Sec. III), LDS exchange */

@@ -25,7 +25,7 @@ static bool is_valid_dtype(int op, int dtype) {
 
 static int64_t lds_needed(int op, int dtype, int64_t n, const ppx_config &c) {
     switch (op) {
-        case PPX_OP_FFT: return fft_lds_bytes((int)n, c.problems_per_block, c.algo);
+        case PPX_OP_FFT: return fft_lds_bytes((int)n, c.problems_per_block, c.algo, c.radix);
         case PPX_OP_SCAN: return scan_lds_bytes((int)n, c.problems_per_block, c.elems_per_thread, dtype);
         default: return tridiag_lds_bytes((int)n, c, dtype);
     }
@@ -34,7 +34,7 @@ static int64_t lds_needed(int op, int dtype, int64_t n, const ppx_config &c) {
 // Elements held in LDS per workgroup (the paper's S).
 static int lds_elems(int op, int64_t n, const ppx_config &c) {
     switch (op) {
-        case PPX_OP_FFT: return (int)(c.problems_per_block * n);
+        case PPX_OP_FFT: return n <= c.radix ? 0 : (int)(c.problems_per_block * n);
         case PPX_OP_SCAN: {
             const int64_t T = n / c.elems_per_thread;  // threads per problem
             return T > kWave ? c.threads_per_block / kWave : 0;
@@ -76,8 +76,10 @@ int validate_config(int op, int dtype, int64_t n, const ppx_config &c) {
             if (c.radix > P) return fail(PPX_ECONFIG, "FFT radix must not exceed elements per thread");
             if (L > fft_max_threads((int)P))
                 return fail(PPX_ECONFIG, "FFT with 32 elements per thread allows at most 512 threads");
-            if (c.algo != PPX_FFT_LDS && c.algo != PPX_FFT_LDS_SPLIT)
-                return fail(PPX_ECONFIG, "FFT algo must be PPX_FFT_LDS or PPX_FFT_LDS_SPLIT");
+            if (c.algo < PPX_FFT_LDS || c.algo > PPX_FFT_LDS_SPLIT_PIPE)
+                return fail(PPX_ECONFIG, "FFT algo must be PPX_FFT_LDS, _LDS_SPLIT, _LDS_PIPE or _LDS_SPLIT_PIPE");
+            if ((c.algo & PPX_FFT_LDS_PIPE) && !fft_pipe_available(c.radix, (int)P))
+                return fail(PPX_ECONFIG, "the persistent FFT variants need radix = elements per thread = 8 or 16");
             break;
         case PPX_OP_SCAN:
             if (c.radix != 0 && c.radix != 2) return fail(PPX_ECONFIG, "scan radix must be 2");
@@ -112,13 +114,13 @@ int default_config(int op, int dtype, int64_t n, ppx_config &c) {
     c.problems_per_block = 1;
     c.threads_per_block = (int)(n / 2 < kMaxThreadsPerBlock ? n / 2 : kMaxThreadsPerBlock);
     c.algo = 0;
-    if (op == PPX_OP_FFT && fft_lds_bytes((int)n, 1, PPX_FFT_LDS) > lds_limit()) c.algo = PPX_FFT_LDS_SPLIT;
+    if (op == PPX_OP_FFT && fft_lds_bytes((int)n, 1, PPX_FFT_LDS, c.radix) > lds_limit()) c.algo = PPX_FFT_LDS_SPLIT;
     complete_config(op, dtype, n, c);
     return validate_config(op, dtype, n, c);
 }
 
 // The search space enumerated by the tuners: r in {2,4,8,16} (FFT only),
-// L in {64,...,1024}, G_b in {1,...,16}, and the algorithm variants of each
+// L in {64,...,1024}, G_b in {1,...,64}, and the algorithm variants of each
 // operation; invalid points are dropped.
 int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap) {
     if (!is_valid_dtype(op, dtype)) return fail(PPX_EINVAL, "unsupported op / dtype");
@@ -127,11 +129,11 @@ int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap) {
     static const int radix_two[] = {2};
     const int *radices = op == PPX_OP_FFT ? radices_fft : radix_two;
     const int nr = op == PPX_OP_FFT ? 4 : 1;
-    const int nalgo = op == PPX_OP_TRIDIAG ? 5 : 2;
+    const int nalgo = op == PPX_OP_TRIDIAG ? 5 : op == PPX_OP_FFT ? 4 : 2;
     int count = 0;
     for (int ri = 0; ri < nr; ++ri)
         for (int L = 64; L <= 1024; L *= 2)
-            for (int G = 1; G <= 16; G *= 2)
+            for (int G = 1; G <= kMaxProblemsPerBlock; G *= 2)
                 for (int a = 0; a < nalgo; ++a) {
                     ppx_config c{};
                     c.radix = radices[ri];
@@ -142,7 +144,7 @@ int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap) {
                     if (validate_config(op, dtype, n, c) != PPX_OK) continue;
                     // FFT: the split exchange only when it is needed or saves LDS
                     // (a single-stage transform uses no LDS at all).
-                    if (op == PPX_OP_FFT && a == PPX_FFT_LDS_SPLIT && n <= c.radix) continue;
+                    if (op == PPX_OP_FFT && (a & PPX_FFT_LDS_SPLIT) && n <= c.radix) continue;
                     if (count < cap && out) out[count] = c;
                     ++count;
                 }

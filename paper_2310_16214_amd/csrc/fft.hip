@@ -1,6 +1,10 @@
 // Host launcher of the kernels in fft_device.h.
 #include "fft_device.h"
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace ppx {
 
 // ------------------------------------------------------------------- host
@@ -14,8 +18,9 @@ void fft_host_twiddles(float *out2) {
     }
 }
 
-int64_t fft_lds_bytes(int n, int gb, int algo) {
-    return (int64_t)gb * n * (algo == PPX_FFT_LDS_SPLIT ? 4 : 8);
+int64_t fft_lds_bytes(int n, int gb, int algo, int radix) {
+    if (n <= radix) return 0;  // a single stage: no exchange
+    return (int64_t)gb * n * ((algo & PPX_FFT_LDS_SPLIT) ? 4 : 8);
 }
 
 using FftKernel = void (*)(const float2 *, float2 *, const float2 *, int, long long, int, float);
@@ -45,24 +50,54 @@ static FftKernel fft_lookup_s(int radix, int P) {
     }
 }
 
-static FftKernel fft_lookup(int radix, int P, int algo) {
-    return algo == PPX_FFT_LDS_SPLIT ? fft_lookup_s<true>(radix, P) : fft_lookup_s<false>(radix, P);
+// The kernel of a configuration: the one specialised on log2 n where radix =
+// P = 8 or 16 (the persistent variants exist only there), else the generic.
+static FftKernel fft_lookup(int radix, int P, int algo, int log2n) {
+    const bool split = (algo & PPX_FFT_LDS_SPLIT) != 0, pipe = (algo & PPX_FFT_LDS_PIPE) != 0;
+    if (fft_pipe_available(radix, P)) {
+        const void *k = P == 8 ? fft_spec8_kernel(log2n, split, pipe) : fft_spec16_kernel(log2n, split, pipe);
+        if (k || pipe) return reinterpret_cast<FftKernel>(const_cast<void *>(k));
+    }
+    if (pipe) return nullptr;
+    return split ? fft_lookup_s<true>(radix, P) : fft_lookup_s<false>(radix, P);
 }
 
-const void *fft_kernel(int radix, int P, int algo) {
-    return reinterpret_cast<const void *>(fft_lookup(radix, P, algo));
+const void *fft_kernel(int radix, int P, int algo, int log2n) {
+    return reinterpret_cast<const void *>(fft_lookup(radix, P, algo, log2n));
+}
+
+// Resident workgroups per CU of a persistent kernel at (L, LDS bytes), from
+// the occupancy query, made once per (kernel, L, LDS).
+static int resident_blocks_per_cu(FftKernel k, int L, int64_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, int64_t>, int> memo;
+    const auto key = std::make_tuple(reinterpret_cast<const void *>(k), L, lds);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, L, (size_t)lds) != hipSuccess || nb < 1) nb = 1;
+    std::lock_guard<std::mutex> lk(mu);
+    memo[key] = nb;
+    return nb;
 }
 
 int launch_fft(const void *in, void *out, int log2n, int64_t batch, const ppx_config &c,
                bool inverse, hipStream_t s) {
     const DeviceInfo *di = device_info();
     if (!di) return PPX_EDEVICE;
-    FftKernel k = fft_lookup(c.radix, c.elems_per_thread, c.algo);
+    FftKernel k = fft_lookup(c.radix, c.elems_per_thread, c.algo, log2n);
     if (!k) return fail(PPX_ECONFIG, "no FFT kernel for this radix / elements-per-thread");
     const int n = 1 << log2n;
-    const int64_t lds = fft_lds_bytes(n, c.problems_per_block, c.algo);
+    const int64_t lds = fft_lds_bytes(n, c.problems_per_block, c.algo, c.radix);
     if (lds > di->lds_per_block) return fail(PPX_ECONFIG, "FFT configuration exceeds the LDS per workgroup");
-    const int64_t grid = (batch + c.problems_per_block - 1) / c.problems_per_block;
+    int64_t grid = (batch + c.problems_per_block - 1) / c.problems_per_block;
+    if (c.algo & PPX_FFT_LDS_PIPE) {  // persistent: at most the resident workgroups
+        const int64_t resident = (int64_t)resident_blocks_per_cu(k, c.threads_per_block, lds) * di->cus;
+        if (resident < grid) grid = resident;
+    }
     hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(c.threads_per_block), (size_t)lds, s,
                        static_cast<const float2 *>(in), static_cast<float2 *>(out),
                        static_cast<const float2 *>(di->twiddles), log2n, (long long)batch,

@@ -41,25 +41,41 @@ __device__ __forceinline__ int swz_f(int p) { return p ^ ((p >> 5) & 31); }  // 
 // w^k, w^{4k} and w^{8k} are read (as the radix needs them) and the other
 // powers are products of at most three of them, so a butterfly issues at most
 // three table loads instead of RS - 1.
+// The table entries a radix-RS butterfly reads: w^k, w^{4k}, w^{8k}.
+struct TwBase {
+    float2 w1, w4, w8;
+};
 template <int RS>
-__device__ __forceinline__ void stage_twiddles(float2 (&w)[RS], const float2 *__restrict__ tw, int k,
-                                               int shift) {
-    w[1] = tw[k << shift];
+__device__ __forceinline__ TwBase stage_twiddle_base(const float2 *__restrict__ tw, int k, int shift) {
+    TwBase b;
+    b.w1 = tw[k << shift];
+    if constexpr (RS >= 8) b.w4 = tw[(4 * k) << shift];
+    if constexpr (RS >= 16) b.w8 = tw[(8 * k) << shift];
+    return b;
+}
+template <int RS>
+__device__ __forceinline__ void stage_twiddles_from(float2 (&w)[RS], const TwBase &b) {
+    w[1] = b.w1;
     if constexpr (RS >= 4) {
         w[2] = cmul(w[1], w[1]);
         w[3] = cmul(w[2], w[1]);
     }
     if constexpr (RS >= 8) {
-        w[4] = tw[(4 * k) << shift];
+        w[4] = b.w4;
         w[5] = cmul(w[4], w[1]);
         w[6] = cmul(w[4], w[2]);
         w[7] = cmul(w[4], w[3]);
     }
     if constexpr (RS >= 16) {
-        w[8] = tw[(8 * k) << shift];
+        w[8] = b.w8;
 #pragma unroll
         for (int q = 9; q < 16; ++q) w[q] = cmul(w[8], w[q - 8]);
     }
+}
+template <int RS>
+__device__ __forceinline__ void stage_twiddles(float2 (&w)[RS], const float2 *__restrict__ tw, int k,
+                                               int shift) {
+    stage_twiddles_from<RS>(w, stage_twiddle_base<RS>(tw, k, shift));
 }
 
 // The first stage (span 1) has no twiddles; it is a separate instantiation
@@ -190,14 +206,16 @@ __device__ __forceinline__ void fft_block(const float2 *in, float2 *out, const f
     float2 v[P];
     if (active) {
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const float2 x = src[tid + j * T];
-            v[j] = make_float2(x.x, sgn * x.y);
-        }
+        for (int j = 0; j < P; ++j) v[j] = src[tid + j * T];
     } else {
 #pragma unroll
         for (int j = 0; j < P; ++j) v[j] = make_float2(0.f, 0.f);
     }
+    // all P loads in flight before the first use (the conjugation of the
+    // inverse transform would otherwise be interleaved with them)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) v[j].y *= sgn;
 
     // first stage: radix 2^(log2 n mod log2 R) when R does not divide log2 n
     int lns = 0;
@@ -223,6 +241,175 @@ __global__ __launch_bounds__(fft_max_threads(P)) void k_fft(const float2 *in, fl
     const long long p0 = (long long)blockIdx.x * gb;
     const int nprob = (int)min((long long)gb, batch - p0);
     fft_block<R, P, SPLIT>(in, out, tw, log2n, p0, nprob, sgn, lds_raw);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels specialised on log2 n (radix R = P, the shape the tuners pick for
+// n >= 128): with n a constant, the stage sequence is unrolled at compile
+// time, every index offset (j*T, q << lns) is a constant, and where a
+// constant has no bits in 4..7 the swizzle commutes with it, so most LDS and
+// global addresses become one base register plus an immediate.  This removes
+// most of the integer work and about a third of the registers of the generic
+// kernel; the transform is the same.
+constexpr int clog2(int x) { return x <= 1 ? 0 : 1 + clog2(x / 2); }
+
+template <int R, int P, bool SPLIT, int LOG2N, int LNS>
+__device__ __forceinline__ void fft_stages_ct(float2 (&v)[P], void *lds, int poff, float2 *dst, int tid,
+                                              bool active, float sgn, const float2 *__restrict__ tw) {
+    constexpr int REM = LOG2N % clog2(R);
+    constexpr int RS = (LNS == 0 && REM != 0) ? (1 << REM) : R;  // mixed-radix first stage
+    constexpr int LRS = clog2(RS);
+    constexpr int T = 1 << (LOG2N - clog2(P));
+    stage_butterflies<RS, P, LNS == 0>(v, tid, T, LNS, tw);
+    if constexpr (LNS + LRS == LOG2N) {
+        if (active) stage_store<RS, P>(v, dst, tid, T, LNS, sgn);
+    } else {
+        stage_exchange<RS, P, SPLIT>(v, lds, poff, tid, T, LNS);
+        fft_stages_ct<R, P, SPLIT, LOG2N, LNS + LRS>(v, lds, poff, dst, tid, active, sgn, tw);
+    }
+}
+
+// The thread's slots X[tid + j*T] as stored (zeros for threads beyond the
+// group's problems).  All P loads are issued before anything consumes them.
+template <int P, int LOG2N>
+__device__ __forceinline__ void fft_load_raw_ct(float2 (&v)[P], const float2 *src, int tid, bool active) {
+    constexpr int T = 1 << (LOG2N - clog2(P));
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[j] = src[tid + j * T];
+    } else {
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[j] = make_float2(0.f, 0.f);
+    }
+}
+
+// Conjugation of the inputs for the inverse transform (sgn = -1).
+template <int P>
+__device__ __forceinline__ void fft_conj(float2 (&v)[P], float sgn) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) v[j].y *= sgn;
+}
+
+// Same arguments as k_fft (log2n is implied by LOG2N).
+template <int R, int P, bool SPLIT, int LOG2N>
+__global__ __launch_bounds__(fft_max_threads(P)) void k_fft_n(const float2 *in, float2 *out,
+                                                               const float2 *__restrict__ tw, int,
+                                                               long long batch, int gb, float sgn) {
+    extern __shared__ float4 lds_raw[];
+    constexpr int n = 1 << LOG2N;
+    constexpr int lT = LOG2N - clog2(P);
+    const long long p0 = (long long)blockIdx.x * gb;
+    const int nprob = (int)min((long long)gb, batch - p0);
+    const int lp = threadIdx.x >> lT;
+    const int tid = threadIdx.x & ((1 << lT) - 1);
+    const long long prob = p0 + lp;
+    const bool active = lp < nprob;
+    float2 v[P];
+    fft_load_raw_ct<P, LOG2N>(v, in + prob * n, tid, active);
+    // keep the scheduler from interleaving the loads with their first use,
+    // which would leave only a few of them in flight
+    __builtin_amdgcn_sched_barrier(0);
+    fft_conj<P>(v, sgn);
+    fft_stages_ct<R, P, SPLIT, LOG2N, 0>(v, lds_raw, lp * n, out + prob * n, tid, active, sgn, tw);
+}
+
+// --- persistent variant
+//
+// The twiddle-table reads of every stage depend on the thread only, so the
+// persistent kernel issues them at the top of each iteration, before the
+// next group's loads: vector-memory loads complete in issue order, and a
+// twiddle read issued after the prefetch would make the stage that uses it
+// wait for the whole prefetch.
+
+template <int R, int LOG2N>
+constexpr int fft_twiddled_stages() {
+    return (LOG2N + clog2(R) - 1) / clog2(R) - 1;  // every stage but the first
+}
+
+template <int R, int P, int LOG2N, int LNS, int IDX, int NBASE>
+__device__ __forceinline__ void fft_preload_bases(TwBase (&b)[NBASE], const float2 *__restrict__ tw,
+                                                  int tid) {
+    constexpr int REM = LOG2N % clog2(R);
+    constexpr int RS = (LNS == 0 && REM != 0) ? (1 << REM) : R;
+    constexpr int NEXT = LNS + clog2(RS);
+    if constexpr (NEXT < LOG2N) {  // the stage starting at NEXT (radix R) has twiddles
+        const int k = tid & ((1 << NEXT) - 1);
+        b[IDX] = stage_twiddle_base<R>(tw, k, kFftLog2NMax - (NEXT + clog2(R)));
+        fft_preload_bases<R, P, LOG2N, NEXT, IDX + 1, NBASE>(b, tw, tid);
+    }
+}
+
+template <int R, int P, bool SPLIT, int LOG2N, int LNS, int IDX, int NBASE>
+__device__ __forceinline__ void fft_stages_pre(float2 (&v)[P], const TwBase (&b)[NBASE], void *lds, int poff,
+                                               float2 *dst, int tid, bool active, float sgn) {
+    constexpr int REM = LOG2N % clog2(R);
+    constexpr int RS = (LNS == 0 && REM != 0) ? (1 << REM) : R;
+    constexpr int LRS = clog2(RS);
+    constexpr int T = 1 << (LOG2N - clog2(P));
+    if constexpr (LNS == 0) {
+        stage_butterflies<RS, P, true>(v, tid, T, 0, nullptr);
+    } else {  // radix R = P: one butterfly per thread
+        float2 w[RS];
+        stage_twiddles_from<RS>(w, b[IDX]);
+#pragma unroll
+        for (int q = 1; q < RS; ++q) v[q] = cmul(v[q], w[q]);
+        RegDFT<RS>::run(v);
+    }
+    constexpr int NEXT_IDX = LNS == 0 ? IDX : IDX + 1;
+    if constexpr (LNS + LRS == LOG2N) {
+        if (active) stage_store<RS, P>(v, dst, tid, T, LNS, sgn);
+    } else {
+        stage_exchange<RS, P, SPLIT>(v, lds, poff, tid, T, LNS);
+        fft_stages_pre<R, P, SPLIT, LOG2N, LNS + LRS, NEXT_IDX, NBASE>(v, b, lds, poff, dst, tid, active, sgn);
+    }
+}
+
+// Persistent variant of k_fft_n: a grid of resident workgroups walks the
+// groups of gb problems (g, g + gridDim.x, ...) and loads the next group's
+// inputs into a second register set while it transforms the current one, so
+// a workgroup's global loads overlap its own stages.  This matters where the
+// LDS buffer allows only one or two workgroups per CU (large n): otherwise a
+// CU alternates between loading and computing.  Every thread of a workgroup
+// runs the same number of iterations, so all of them reach every barrier.
+template <int R, int P, bool SPLIT, int LOG2N>
+__global__ __launch_bounds__(fft_max_threads(P)) void k_fft_np(const float2 *in, float2 *out,
+                                                                const float2 *__restrict__ tw, int,
+                                                                long long batch, int gb, float sgn) {
+    static_assert(R == P, "one butterfly per thread and stage");
+    extern __shared__ float4 lds_raw[];
+    constexpr int n = 1 << LOG2N;
+    constexpr int lT = LOG2N - clog2(P);
+    constexpr int NBASE = fft_twiddled_stages<R, LOG2N>() > 0 ? fft_twiddled_stages<R, LOG2N>() : 1;
+    const int lp = threadIdx.x >> lT;
+    const int tid0 = threadIdx.x & ((1 << lT) - 1);
+    const long long ngroups = (batch + gb - 1) / gb;
+    long long g = blockIdx.x;
+    // Every load is unconditional, from a problem index clamped into the
+    // batch (the data of a clamped load is never used): a conditional load
+    // would put a control-flow join before the first use of v, where the
+    // wait for v's loads would also have to wait for the prefetch.
+    const long long last = batch - 1;
+    float2 v[P], w[P];
+    fft_load_raw_ct<P, LOG2N>(v, in + min(g * gb + lp, last) * n, tid0, true);
+    for (; g < ngroups; g += gridDim.x) {
+        // An empty asm that claims to change tid: without it the compiler
+        // hoists every tid-derived LDS and twiddle address out of the loop
+        // and keeps them live, which with the second register set exceeds
+        // the register budget of 1024-thread workgroups and spills.
+        int tid = tid0;
+        asm volatile("" : "+v"(tid));
+        TwBase b[NBASE];
+        fft_preload_bases<R, P, LOG2N, 0, 0, NBASE>(b, tw, tid);
+        const long long gn = g + gridDim.x;
+        fft_load_raw_ct<P, LOG2N>(w, in + min(gn * gb + lp, last) * n, tid, true);
+        __builtin_amdgcn_sched_barrier(0);
+        fft_conj<P>(v, sgn);
+        const long long prob = g * gb + lp;
+        fft_stages_pre<R, P, SPLIT, LOG2N, 0, 0, NBASE>(v, b, lds_raw, lp * n, out + prob * n, tid,
+                                                        prob < batch, sgn);
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[j] = w[j];
+    }
 }
 
 }  // namespace ppx

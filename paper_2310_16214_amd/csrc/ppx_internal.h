@@ -59,7 +59,7 @@ inline int ilog2(int64_t v) {
 }
 
 // ---- LDS footprint of each kernel family (bytes per workgroup) ----
-int64_t fft_lds_bytes(int n, int gb, int algo);
+int64_t fft_lds_bytes(int n, int gb, int algo, int radix);
 int64_t scan_lds_bytes(int n, int gb, int P, int dtype);
 int64_t tridiag_lds_bytes(int n, const ppx_config &c, int dtype);
 
@@ -87,7 +87,12 @@ int launch_tridiag(const void *a, const void *b, const void *c, const void *d,
                    const ppx_config &cfg, hipStream_t s);
 
 // Device function pointers for occupancy queries (nullptr if no such kernel).
-const void *fft_kernel(int radix, int P, int algo);
+const void *fft_kernel(int radix, int P, int algo, int log2n);
+// Kernels specialised on log2 n for radix = P = 8 / 16 (nullptr where none).
+const void *fft_spec8_kernel(int log2n, bool split, bool pipe);
+const void *fft_spec16_kernel(int log2n, bool split, bool pipe);
+// The persistent FFT variants exist for radix = P = 8 or 16.
+constexpr bool fft_pipe_available(int radix, int P) { return radix == P && (P == 8 || P == 16); }
 const void *scan_kernel(int dtype, int P, int algo);
 const void *tridiag_kernel(int dtype, int algo, int P);
 

@@ -325,14 +325,22 @@ static double expected_improvement(double mu, double sigma, double best) {
     return (best - mu) * norm_cdf(z) + sigma * norm_pdf(z);
 }
 
+// GP inputs: log2 radix, log2 L, log2 G_b, and one indicator per algorithm
+// variant present among the candidates (the variants are categories, not an
+// ordered scale); each column scaled to [0, 1].
 static void features(const ppx_config *c, int n, std::vector<double> &F, int &d) {
-    d = 4;
+    std::vector<int> algos;
+    for (int i = 0; i < n; ++i)
+        if (std::find(algos.begin(), algos.end(), c[i].algo) == algos.end()) algos.push_back(c[i].algo);
+    std::sort(algos.begin(), algos.end());
+    const int na = algos.size() > 1 ? (int)algos.size() : 0;
+    d = 3 + na;
     F.assign((size_t)n * d, 0.0);
     for (int i = 0; i < n; ++i) {
         F[i * d + 0] = std::log2((double)std::max(1, c[i].radix));
         F[i * d + 1] = std::log2((double)std::max(1, c[i].threads_per_block));
         F[i * d + 2] = std::log2((double)std::max(1, c[i].problems_per_block));
-        F[i * d + 3] = (double)c[i].algo;
+        for (int a = 0; a < na; ++a) F[i * d + 3 + a] = c[i].algo == algos[a] ? 1.0 : 0.0;
     }
     for (int k = 0; k < d; ++k) {
         double lo = 1e300, hi = -1e300;
@@ -481,9 +489,9 @@ static int static_vgprs(int op, int dtype, int P, int algo) {
     return dtype == PPX_F64 ? (algo == PPX_TRI_PCR ? 44 : 40) : (algo == PPX_TRI_PCR ? 32 : 28);
 }
 
-static const void *kernel_for(int op, int dtype, const ppx_config &c) {
+static const void *kernel_for(int op, int dtype, int64_t n, const ppx_config &c) {
     switch (op) {
-        case PPX_OP_FFT: return fft_kernel(c.radix, c.elems_per_thread, c.algo);
+        case PPX_OP_FFT: return fft_kernel(c.radix, c.elems_per_thread, c.algo, ilog2(n));
         case PPX_OP_SCAN: return scan_kernel(dtype, c.elems_per_thread, c.algo);
         default: return tridiag_kernel(dtype, c.algo, c.elems_per_thread);
     }
@@ -491,7 +499,7 @@ static const void *kernel_for(int op, int dtype, const ppx_config &c) {
 
 static int64_t dyn_lds(int op, int dtype, int64_t n, const ppx_config &c) {
     switch (op) {
-        case PPX_OP_FFT: return fft_lds_bytes((int)n, c.problems_per_block, c.algo);
+        case PPX_OP_FFT: return fft_lds_bytes((int)n, c.problems_per_block, c.algo, c.radix);
         case PPX_OP_SCAN: return scan_lds_bytes((int)n, c.problems_per_block, c.elems_per_thread, dtype);
         default: return tridiag_lds_bytes((int)n, c, dtype);
     }
@@ -509,7 +517,7 @@ static int resources(int op, int dtype, int64_t n, const ppx_config &c, bool hav
     r.lds_bytes = (int32_t)dyn_lds(op, dtype, n, c);
     r.regs_per_thread = static_vgprs(op, dtype, c.elems_per_thread, c.algo);
     if (have_device) {
-        const void *k = kernel_for(op, dtype, c);
+        const void *k = kernel_for(op, dtype, n, c);
         hipFuncAttributes a;
         if (!k || hipFuncGetAttributes(&a, k) != hipSuccess) return fail(PPX_EHIP, "hipFuncGetAttributes failed");
         r.regs_per_thread = a.numRegs;

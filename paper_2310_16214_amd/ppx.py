@@ -23,7 +23,7 @@ HEADERS = [HEADER] + [os.path.join(os.path.dirname(_PKG), "include", h)
 OK, EINVAL, ECONFIG, EDEVICE, EHIP, ENOMEM, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 I32, F32, F64, C64 = 0, 1, 2, 3
 OP_FFT, OP_SCAN, OP_TRIDIAG = 0, 1, 2
-FFT_LDS, FFT_LDS_SPLIT = 0, 1
+FFT_LDS, FFT_LDS_SPLIT, FFT_LDS_PIPE, FFT_LDS_SPLIT_PIPE = 0, 1, 2, 3
 SCAN_KS, SCAN_LF = 0, 1
 TRI_CR, TRI_PCR, TRI_CR_SHFL, TRI_PCR_SHFL, TRI_PCR_REG = 0, 1, 2, 3, 4
 

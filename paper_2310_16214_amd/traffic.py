@@ -18,7 +18,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 SOURCES = {
-    "fft": ["fft_device.h", "device.h", "fft.hip"],
+    "fft": ["fft_device.h", "device.h", "fft.hip", "fft_spec8.hip", "fft_spec16.hip"],
     "scan": ["scan_device.h", "device.h", "scan.hip"],
     "tridiag": ["tridiag_device.h", "tridiag_wave_device.h", "tridiag.hip"],
 }
@@ -37,7 +37,10 @@ def kernel_name_prefix(d):
     """The demangled name prefix (kernel and template arguments) of a call."""
     c = d["cfg"]
     if d["op"] == "fft":
-        split = "true" if c["algo"] == 1 else "false"
+        split = "true" if c["algo"] & 1 else "false"
+        if c["radix"] == c["elems_per_thread"] and c["radix"] in (8, 16):  # specialised on log2 n
+            name = "k_fft_np" if c["algo"] & 2 else "k_fft_n"
+            return f"{name}<{c['radix']}, {c['elems_per_thread']}, {split}, {d['n'].bit_length() - 1}>"
         return f"k_fft<{c['radix']}, {c['elems_per_thread']}, {split}>"
     if d["op"] == "scan":
         t = "int" if d["dtype"] == "int32" else "float"
@@ -70,8 +73,9 @@ def main(fetch_csv, write_csv, detail_jsonl, out_json):
         c = d["cfg"]
         grid = -(-d["batch"] // c["problems_per_block"]) * c["threads_per_block"]
         name = kernel_name_prefix(d)
-        hits = [(f, w) for f, w in zip(F, W) if name in f[1] and f[2] == grid
-                and f[3] == c["threads_per_block"]]
+        hits = [(f, w) for f, w in zip(F, W) if name in f[1] and f[3] == c["threads_per_block"]]
+        exact = [h for h in hits if h[0][2] == grid]  # persistent kernels launch fewer workgroups
+        hits = exact or hits
         if not hits:
             continue
         f, w = hits[-1]

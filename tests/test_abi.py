@@ -79,7 +79,7 @@ def test_enumeration_respects_the_space():
                 assert ppx.config_valid(op, dt, n, c)
                 assert c.elems_per_thread * c.threads_per_block == n * c.problems_per_block
                 assert 64 <= c.threads_per_block <= 1024
-                assert 1 <= c.problems_per_block <= 16
+                assert 1 <= c.problems_per_block <= 64
                 if op == ppx.OP_FFT:
                     assert c.radix in (2, 4, 8, 16) and c.radix <= c.elems_per_thread
     # FFT space per size: radix x L x G_b x exchange variant, before validity

@@ -118,3 +118,47 @@ def test_rejects_bad_arguments(cuda):
     with pytest.raises(ppx.PpxError) as e:
         ppx.fft_batched(x, x, 64, 1, cfg=ppx.make_config(16, 64, 1))  # P = 1 < radix
     assert e.value.code == ppx.ECONFIG
+
+
+# (n, radix, L, G_b, algo): the persistent (prefetching) variants with batches
+# that make every workgroup loop several times and leave a ragged last round
+PERSISTENT = [(16384, 16, 1024, 1, ppx.FFT_LDS_PIPE), (8192, 16, 512, 1, ppx.FFT_LDS_SPLIT_PIPE),
+              (4096, 16, 512, 2, ppx.FFT_LDS_PIPE), (1024, 8, 128, 1, ppx.FFT_LDS_PIPE),
+              (64, 16, 64, 16, ppx.FFT_LDS_SPLIT_PIPE)]
+
+
+@pytest.mark.parametrize("n,radix,L,G,algo", PERSISTENT)
+def test_persistent_variants_loop_and_tail(cuda, n, radix, L, G, algo):
+    """Several problems per workgroup (grid = resident workgroups) and a ragged
+    last round: sampled problems against the oracle (forward and inverse), and
+    every problem against the plain kernel of the same shape, which runs the
+    same stages (agreement to the FFT bound, not bitwise: the compiler may
+    contract multiply-adds differently in the two kernels)."""
+    import torch
+    batch = {16384: 2048 + 37, 8192: 4096 + 21, 4096: 8192 + 3, 1024: 12000 + 5, 64: 300000 + 7}[n]
+    cfg = ppx.make_config(radix, L, G, algo)
+    plain = ppx.make_config(radix, L, G, algo & ppx.FFT_LDS_SPLIT)
+    assert ppx.config_valid(ppx.OP_FFT, ppx.C64, n, cfg)
+    x = inputs.fft_input(n, batch, seed=n + 1)
+    xd = to_dev(x, cuda)
+    idx = np.unique(np.array([0, 1, G, batch // 3, batch // 2, batch - G - 1, batch - 2, batch - 1]))
+    for direction in (-1, +1):
+        banner(f"fft persistent n={n} batch={batch} {cfg} direction={direction}")
+        y = torch.empty_like(xd)
+        ppx.fft_batched(xd, y, n, batch, direction, cfg)
+        ys = to_host(y[torch.from_numpy(idx).to(cuda)])
+        err = oracle.rel_l2(ys, oracle.dft(x[idx], inverse=direction > 0))
+        assert err.max() <= fft_tol(n), f"rel-L2 {err.max():.3e}"
+        y2 = torch.empty_like(xd)
+        ppx.fft_batched(xd, y2, n, batch, direction, plain)
+        d = oracle.rel_l2(to_host(y), to_host(y2))
+        print(f"n={n} direction={direction}: max rel-L2 persistent vs plain {d.max():.2e}")
+        assert d.max() <= fft_tol(n)
+
+
+def test_persistent_needs_radix_equal_p(cuda):
+    import torch
+    x = torch.zeros(1024, dtype=torch.complex64, device=cuda)
+    with pytest.raises(ppx.PpxError) as e:
+        ppx.fft_batched(x, x, 1024, 1, cfg=ppx.make_config(4, 64, 1, ppx.FFT_LDS_PIPE))  # P = 16, radix 4
+    assert e.value.code == ppx.ECONFIG
