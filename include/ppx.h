@@ -66,6 +66,10 @@ extern "C" {
 #define PPX_FFT_LDS_SPLIT_PIPE 3 /* PPX_FFT_LDS_SPLIT, persistent as above */
 #define PPX_SCAN_KS 0       /* Kogge-Stone lane network (DPP row shifts) */
 #define PPX_SCAN_LF 1       /* Ladner-Fischer lane network (swizzle bcasts) */
+#define PPX_SCAN_KS_PIPE 2  /* PPX_SCAN_KS in persistent workgroups (as many as
+                               are resident) that load the next group of
+                               problems while scanning the current one */
+#define PPX_SCAN_LF_PIPE 3  /* PPX_SCAN_LF, persistent as above */
 #define PPX_TRI_CR 0        /* cyclic reduction (Sec. III), LDS exchange */
 #define PPX_TRI_PCR 1       /* parallel cyclic reduction (Sec. III), LDS exchange */
 #define PPX_TRI_CR_SHFL 2   /* CR inside a wave: registers + lane shuffles, no
@@ -75,6 +79,11 @@ extern "C" {
                                a per-wave LDS buffer of 3 * 64 * min(P, 4)
                                values (16-byte accesses) instead of shuffles;
                                S = 0, n / P <= 64, P <= 16 */
+#define PPX_TRI_PIPE 8      /* flag, OR-ed onto PPX_TRI_CR_SHFL, _PCR_SHFL or
+                               _PCR_REG: persistent workgroups (as many as are
+                               resident) that load the next group of systems
+                               while solving the current one; needs
+                               P * sizeof(element) <= 32 */
 
 /* ---- tuning methods ---- */
 #define PPX_TUNE_EXHAUSTIVE 0 /* time every valid configuration (Sec. VI) */

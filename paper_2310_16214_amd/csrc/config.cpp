@@ -83,13 +83,17 @@ int validate_config(int op, int dtype, int64_t n, const ppx_config &c) {
             break;
         case PPX_OP_SCAN:
             if (c.radix != 0 && c.radix != 2) return fail(PPX_ECONFIG, "scan radix must be 2");
-            if (c.algo != PPX_SCAN_KS && c.algo != PPX_SCAN_LF)
-                return fail(PPX_ECONFIG, "scan algo must be PPX_SCAN_KS or PPX_SCAN_LF");
+            if (c.algo < PPX_SCAN_KS || c.algo > PPX_SCAN_LF_PIPE)
+                return fail(PPX_ECONFIG, "scan algo must be PPX_SCAN_KS, _LF, _KS_PIPE or _LF_PIPE");
             break;
         case PPX_OP_TRIDIAG:
             if (c.radix != 0 && c.radix != 2) return fail(PPX_ECONFIG, "tridiagonal radix must be 2");
-            if (c.algo < PPX_TRI_CR || c.algo > PPX_TRI_PCR_REG)
-                return fail(PPX_ECONFIG, "tridiagonal algo must be PPX_TRI_CR, _PCR, _CR_SHFL, _PCR_SHFL or _PCR_REG");
+            if (tri_base(c.algo) < PPX_TRI_CR || tri_base(c.algo) > PPX_TRI_PCR_REG ||
+                (c.algo & ~(PPX_TRI_PIPE | 7)) != 0)
+                return fail(PPX_ECONFIG, "tridiagonal algo must be PPX_TRI_CR, _PCR, _CR_SHFL, _PCR_SHFL or _PCR_REG (the last three optionally | PPX_TRI_PIPE)");
+            if ((c.algo & PPX_TRI_PIPE) &&
+                (!tri_in_wave(c.algo) || P * (dtype == PPX_F64 ? 8 : 4) > kTriPipeMaxBytes))
+                return fail(PPX_ECONFIG, "PPX_TRI_PIPE needs an in-wave variant and P * element size <= 32 bytes");
             if (tri_in_wave(c.algo)) {
                 if (n / P > kWave) return fail(PPX_ECONFIG, "shuffle variant needs n / P <= 64 (a system within a wave)");
                 if (P > tri_wave_max_p(c.algo, dtype)) return fail(PPX_ECONFIG, "shuffle variant: too many elements per thread");
@@ -129,12 +133,18 @@ int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap) {
     static const int radix_two[] = {2};
     const int *radices = op == PPX_OP_FFT ? radices_fft : radix_two;
     const int nr = op == PPX_OP_FFT ? 4 : 1;
-    const int nalgo = op == PPX_OP_TRIDIAG ? 5 : op == PPX_OP_FFT ? 4 : 2;
+    static const int algos_two[] = {0, 1, 2, 3};
+    static const int algos_tri[] = {PPX_TRI_CR, PPX_TRI_PCR, PPX_TRI_CR_SHFL, PPX_TRI_PCR_SHFL, PPX_TRI_PCR_REG,
+                                    PPX_TRI_CR_SHFL | PPX_TRI_PIPE, PPX_TRI_PCR_SHFL | PPX_TRI_PIPE,
+                                    PPX_TRI_PCR_REG | PPX_TRI_PIPE};
+    const int *algos = op == PPX_OP_TRIDIAG ? algos_tri : algos_two;
+    const int nalgo = op == PPX_OP_TRIDIAG ? 8 : 4;
     int count = 0;
     for (int ri = 0; ri < nr; ++ri)
         for (int L = 64; L <= 1024; L *= 2)
             for (int G = 1; G <= kMaxProblemsPerBlock; G *= 2)
-                for (int a = 0; a < nalgo; ++a) {
+                for (int ai = 0; ai < nalgo; ++ai) {
+                    const int a = algos[ai];
                     ppx_config c{};
                     c.radix = radices[ri];
                     c.threads_per_block = L;

@@ -18,9 +18,23 @@ void fft_host_twiddles(float *out2) {
     }
 }
 
+// The persistent kernels keep every stage's twiddle bases in LDS after the
+// exchange buffer: per twiddled stage with span Ns, Ns entries of each of w^k,
+// w^{4k}, w^{8k} that the radix reads (see k_fft_np).
+static int64_t fft_pipe_twiddle_bytes(int n, int radix) {
+    const int log2n = ilog2(n), lr = ilog2(radix);
+    const int stages = (log2n + lr - 1) / lr - 1;
+    const int per_k = 1 + (radix >= 8) + (radix >= 16);
+    const int first = log2n % lr ? log2n % lr : lr;
+    int64_t entries = 0;
+    for (int i = 0; i < stages; ++i) entries += (int64_t)per_k << (first + i * lr);
+    return entries * 8;
+}
+
 int64_t fft_lds_bytes(int n, int gb, int algo, int radix) {
     if (n <= radix) return 0;  // a single stage: no exchange
-    return (int64_t)gb * n * ((algo & PPX_FFT_LDS_SPLIT) ? 4 : 8);
+    const int64_t exch = (int64_t)gb * n * ((algo & PPX_FFT_LDS_SPLIT) ? 4 : 8);
+    return exch + ((algo & PPX_FFT_LDS_PIPE) ? fft_pipe_twiddle_bytes(n, radix) : 0);
 }
 
 using FftKernel = void (*)(const float2 *, float2 *, const float2 *, int, long long, int, float);

@@ -315,62 +315,155 @@ __global__ __launch_bounds__(fft_max_threads(P)) void k_fft_n(const float2 *in, 
 
 // --- persistent variant
 //
-// The twiddle-table reads of every stage depend on the thread only, so the
-// persistent kernel issues them at the top of each iteration, before the
-// next group's loads: vector-memory loads complete in issue order, and a
-// twiddle read issued after the prefetch would make the stage that uses it
-// wait for the whole prefetch.
+// The twiddle-table entries every stage reads depend on the thread only, so
+// the persistent kernel copies them into LDS (after the exchange buffer) once
+// per workgroup and reads its bases from there.  Global twiddle reads inside
+// the loop would be issued after the previous group's stores, and vector
+// memory operations complete in issue order, so the first stage that needs a
+// twiddle would wait for those stores; LDS reads use a separate counter.
 
 template <int R, int LOG2N>
 constexpr int fft_twiddled_stages() {
     return (LOG2N + clog2(R) - 1) / clog2(R) - 1;  // every stage but the first
 }
+// log2 of the span of twiddled stage i (the stage's lns)
+template <int R, int LOG2N>
+constexpr int fft_tw_lns(int i) {
+    return (LOG2N % clog2(R) ? LOG2N % clog2(R) : clog2(R)) + i * clog2(R);
+}
+// table entries a radix-R butterfly reads per k: w^k, w^{4k}, w^{8k}
+template <int R>
+constexpr int fft_tw_per_k() { return 1 + (R >= 8) + (R >= 16); }
+// LDS offset (float2 entries) of twiddled stage i's bases, and their total
+template <int R, int LOG2N>
+constexpr int fft_tw_offset(int i) {
+    int off = 0;
+    for (int j = 0; j < i; ++j) off += fft_tw_per_k<R>() << fft_tw_lns<R, LOG2N>(j);
+    return off;
+}
+template <int R, int LOG2N>
+constexpr int fft_tw_entries() { return fft_tw_offset<R, LOG2N>(fft_twiddled_stages<R, LOG2N>()); }
 
-template <int R, int P, int LOG2N, int LNS, int IDX, int NBASE>
-__device__ __forceinline__ void fft_preload_bases(TwBase (&b)[NBASE], const float2 *__restrict__ tw,
-                                                  int tid) {
-    constexpr int REM = LOG2N % clog2(R);
-    constexpr int RS = (LNS == 0 && REM != 0) ? (1 << REM) : R;
-    constexpr int NEXT = LNS + clog2(RS);
-    if constexpr (NEXT < LOG2N) {  // the stage starting at NEXT (radix R) has twiddles
-        const int k = tid & ((1 << NEXT) - 1);
-        b[IDX] = stage_twiddle_base<R>(tw, k, kFftLog2NMax - (NEXT + clog2(R)));
-        fft_preload_bases<R, P, LOG2N, NEXT, IDX + 1, NBASE>(b, tw, tid);
+// Copies every stage's bases into twl: stage i, power p (1, 4, 8), k < span.
+template <int R, int LOG2N>
+__device__ __forceinline__ void fft_tw_to_lds(float2 *twl, const float2 *__restrict__ tw) {
+    constexpr int NS = fft_twiddled_stages<R, LOG2N>();
+    for (int e = threadIdx.x; e < fft_tw_entries<R, LOG2N>(); e += blockDim.x) {
+        int i = 0;
+#pragma unroll
+        for (int j = 1; j < NS; ++j)
+            if (e >= fft_tw_offset<R, LOG2N>(j)) i = j;
+        int lns = 0, off = 0;
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+            if (j == i) {
+                lns = fft_tw_lns<R, LOG2N>(j);
+                off = fft_tw_offset<R, LOG2N>(j);
+            }
+        const int r = e - off;
+        const int pw = r >> lns;  // 0, 1, 2 -> w^k, w^{4k}, w^{8k}
+        const int k = r & ((1 << lns) - 1);
+        const int mult = pw == 0 ? 1 : pw == 1 ? 4 : 8;
+        twl[e] = tw[(mult * k) << (kFftLog2NMax - (lns + clog2(R)))];
     }
 }
 
-template <int R, int P, bool SPLIT, int LOG2N, int LNS, int IDX, int NBASE>
-__device__ __forceinline__ void fft_stages_pre(float2 (&v)[P], const TwBase (&b)[NBASE], void *lds, int poff,
-                                               float2 *dst, int tid, bool active, float sgn) {
+// Buffer-resource access (raw buffer loads and stores): lanes whose offset
+// falls outside the descriptor's byte range read zeros and write nothing,
+// with no branch.  The descriptor of a group covers exactly its problems that
+// lie inside the batch.
+constexpr int kBufferFlags = 0x00020000;  // word 3 of a raw buffer descriptor (32-bit data format)
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t group_rsrc(const float2 *base, long long group, int gb, int n,
+                                                            long long batch) {
+    const long long left = batch - group * gb;  // problems of the batch from this group on
+    const int bytes = left <= 0 ? 0 : (int)((left >= gb ? gb : left) * n * (long long)sizeof(float2));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(base) + (left > 0 ? group * gb * n : 0),
+                                             (short)0, bytes, kBufferFlags);
+}
+
+template <int P, int LOG2N>
+__device__ __forceinline__ void fft_load_buf(float2 (&v)[P], __amdgpu_buffer_rsrc_t r, int poff, int tid) {
+    constexpr int T = 1 << (LOG2N - clog2(P));
+    const int voff = (poff + tid) * (int)sizeof(float2);
+#pragma unroll
+    for (int j = 0; j < P; ++j)  // the constant part of the offset in the scalar operand
+        v[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
+                                               r, voff, j * T * (int)sizeof(float2), 0));
+}
+
+template <int RS, int P>
+__device__ __forceinline__ void stage_store_buf(const float2 (&v)[P], __amdgpu_buffer_rsrc_t r, int poff,
+                                                int tid, int T, int lns, float sgn) {
+    constexpr int NB = P / RS;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        // stage_out_pos(t, lns, q) = stage_out_pos(t, lns, 0) + (q << lns): the
+        // q part goes in the scalar offset operand
+        const int voff = (poff + stage_out_pos<RS>(tid + i * T, lns, 0)) * (int)sizeof(float2);
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+            const float2 o = v[i + q * NB];
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, make_float2(o.x, sgn * o.y)), r, voff,
+                                                  (q << lns) * (int)sizeof(float2), 0);
+        }
+    }
+}
+
+template <int R, int P, bool SPLIT, int LOG2N, int LNS, int IDX>
+__device__ __forceinline__ void fft_stages_pre(float2 (&v)[P], const float2 *twl, void *lds, int poff,
+                                               __amdgpu_buffer_rsrc_t dst, int tid, float sgn) {
     constexpr int REM = LOG2N % clog2(R);
     constexpr int RS = (LNS == 0 && REM != 0) ? (1 << REM) : R;
     constexpr int LRS = clog2(RS);
     constexpr int T = 1 << (LOG2N - clog2(P));
     if constexpr (LNS == 0) {
         stage_butterflies<RS, P, true>(v, tid, T, 0, nullptr);
-    } else {  // radix R = P: one butterfly per thread
+    } else {  // radix R = P: one butterfly per thread; bases from LDS
+        constexpr int OFF = fft_tw_offset<R, LOG2N>(IDX);
+        const int k = tid & ((1 << LNS) - 1);
+        TwBase b;
+        b.w1 = twl[OFF + k];
+        if constexpr (RS >= 8) b.w4 = twl[OFF + (1 << LNS) + k];
+        if constexpr (RS >= 16) b.w8 = twl[OFF + (2 << LNS) + k];
         float2 w[RS];
-        stage_twiddles_from<RS>(w, b[IDX]);
+        stage_twiddles_from<RS>(w, b);
 #pragma unroll
         for (int q = 1; q < RS; ++q) v[q] = cmul(v[q], w[q]);
         RegDFT<RS>::run(v);
     }
     constexpr int NEXT_IDX = LNS == 0 ? IDX : IDX + 1;
     if constexpr (LNS + LRS == LOG2N) {
-        if (active) stage_store<RS, P>(v, dst, tid, T, LNS, sgn);
+        stage_store_buf<RS, P>(v, dst, poff, tid, T, LNS, sgn);
     } else {
         stage_exchange<RS, P, SPLIT>(v, lds, poff, tid, T, LNS);
-        fft_stages_pre<R, P, SPLIT, LOG2N, LNS + LRS, NEXT_IDX, NBASE>(v, b, lds, poff, dst, tid, active, sgn);
+        fft_stages_pre<R, P, SPLIT, LOG2N, LNS + LRS, NEXT_IDX>(v, twl, lds, poff, dst, tid, sgn);
     }
 }
 
-// Persistent variant of k_fft_n: a grid of resident workgroups walks the
-// groups of gb problems (g, g + gridDim.x, ...) and loads the next group's
-// inputs into a second register set while it transforms the current one, so
-// a workgroup's global loads overlap its own stages.  This matters where the
-// LDS buffer allows only one or two workgroups per CU (large n): otherwise a
-// CU alternates between loading and computing.  Every thread of a workgroup
-// runs the same number of iterations, so all of them reach every barrier.
+// Persistent variant of k_fft_n: a grid of resident workgroups (at most one
+// per group) walks the groups of gb problems (g, g + gridDim.x, ...) and loads
+// the next group's inputs into a second register set while it transforms the
+// current one, so a workgroup's global traffic overlaps its own stages.  This
+// matters where the LDS buffer allows only one or two workgroups per CU
+// (large n): otherwise a CU alternates between loading and computing.
+//
+// Vector-memory operations complete in issue order, so the wait for the
+// prefetched values must not also cover the stores issued after them; the
+// code keeps the compiler's wait at exactly that point:
+//  * loads and stores go through buffer descriptors, so no lane needs a
+//    branch (a branch around a store or load makes the paths that meet after
+//    it differ, and the wait after the join must cover the worse one);
+//  * the first iteration is peeled, so the loop is entered only from paths
+//    with the same history (prefetch, then stores) as its back edge, and the
+//    loop body is unrolled twice with the two register sets swapping roles,
+//    so no register copy (which would wait for the prefetch) is needed;
+//  * the twiddle bases are read from LDS, not global memory;
+//  * an empty asm that claims to change tid keeps the compiler from hoisting
+//    every tid-derived address out of the loop and keeping it live, which
+//    with the second register set spilled at 1024 threads.
+// Every thread runs the same number of iterations, so all reach every barrier.
 template <int R, int P, bool SPLIT, int LOG2N>
 __global__ __launch_bounds__(fft_max_threads(P)) void k_fft_np(const float2 *in, float2 *out,
                                                                 const float2 *__restrict__ tw, int,
@@ -379,36 +472,37 @@ __global__ __launch_bounds__(fft_max_threads(P)) void k_fft_np(const float2 *in,
     extern __shared__ float4 lds_raw[];
     constexpr int n = 1 << LOG2N;
     constexpr int lT = LOG2N - clog2(P);
-    constexpr int NBASE = fft_twiddled_stages<R, LOG2N>() > 0 ? fft_twiddled_stages<R, LOG2N>() : 1;
     const int lp = threadIdx.x >> lT;
     const int tid0 = threadIdx.x & ((1 << lT) - 1);
+    const int poff = lp * n;
     const long long ngroups = (batch + gb - 1) / gb;
-    long long g = blockIdx.x;
-    // Every load is unconditional, from a problem index clamped into the
-    // batch (the data of a clamped load is never used): a conditional load
-    // would put a control-flow join before the first use of v, where the
-    // wait for v's loads would also have to wait for the prefetch.
-    const long long last = batch - 1;
-    float2 v[P], w[P];
-    fft_load_raw_ct<P, LOG2N>(v, in + min(g * gb + lp, last) * n, tid0, true);
-    for (; g < ngroups; g += gridDim.x) {
-        // An empty asm that claims to change tid: without it the compiler
-        // hoists every tid-derived LDS and twiddle address out of the loop
-        // and keeps them live, which with the second register set exceeds
-        // the register budget of 1024-thread workgroups and spills.
+    // the twiddle bases follow the exchange buffer (gb * n complex values, or
+    // gb * n floats with the split exchange)
+    float2 *twl = reinterpret_cast<float2 *>(reinterpret_cast<char *>(lds_raw) +
+                                             (size_t)gb * n * (SPLIT ? sizeof(float) : sizeof(float2)));
+    fft_tw_to_lds<R, LOG2N>(twl, tw);
+    __syncthreads();
+
+    long long g = blockIdx.x;  // < ngroups: the grid never exceeds the groups
+    const long long G = gridDim.x;
+    // Two register sets take turns (no copies between them): one iteration
+    // transforms `cur` while the next group's loads land in `nxt`.
+    float2 A[P], B[P];
+    auto iteration = [&](long long grp, float2 (&cur)[P], float2 (&nxt)[P]) {
         int tid = tid0;
         asm volatile("" : "+v"(tid));
-        TwBase b[NBASE];
-        fft_preload_bases<R, P, LOG2N, 0, 0, NBASE>(b, tw, tid);
-        const long long gn = g + gridDim.x;
-        fft_load_raw_ct<P, LOG2N>(w, in + min(gn * gb + lp, last) * n, tid, true);
+        fft_load_buf<P, LOG2N>(nxt, group_rsrc(in, grp + G, gb, n, batch), poff, tid);
         __builtin_amdgcn_sched_barrier(0);
-        fft_conj<P>(v, sgn);
-        const long long prob = g * gb + lp;
-        fft_stages_pre<R, P, SPLIT, LOG2N, 0, 0, NBASE>(v, b, lds_raw, lp * n, out + prob * n, tid,
-                                                        prob < batch, sgn);
-#pragma unroll
-        for (int j = 0; j < P; ++j) v[j] = w[j];
+        fft_conj<P>(cur, sgn);
+        fft_stages_pre<R, P, SPLIT, LOG2N, 0, 0>(cur, twl, lds_raw, poff, group_rsrc(out, grp, gb, n, batch),
+                                                 tid, sgn);
+    };
+    fft_load_buf<P, LOG2N>(A, group_rsrc(in, g, gb, n, batch), poff, tid0);
+    iteration(g, A, B);
+    for (g += G; g < ngroups; g += 2 * G) {
+        iteration(g, B, A);
+        if (g + G >= ngroups) break;
+        iteration(g + G, A, B);
     }
 }
 

@@ -73,11 +73,16 @@ constexpr int fft_max_threads(int P) { return P >= 32 ? 512 : 1024; }
 // four coefficients; PCR needs twice that again for the neighbours).
 constexpr int kTriWaveMaxThreads = 256;
 constexpr int tri_wave_max_p(int, int) { return 16; }
-// In-wave variants (registers + lane exchange) and the algorithm family.
-constexpr bool tri_in_wave(int algo) { return algo >= PPX_TRI_CR_SHFL; }
+// The variant without the persistent flag, in-wave variants (registers +
+// lane exchange) and the algorithm family.
+constexpr int tri_base(int algo) { return algo & ~PPX_TRI_PIPE; }
+constexpr bool tri_in_wave(int algo) { return tri_base(algo) >= PPX_TRI_CR_SHFL; }
 constexpr int tri_family(int algo) {
-    return algo == PPX_TRI_CR || algo == PPX_TRI_CR_SHFL ? PPX_TRI_CR : PPX_TRI_PCR;
+    return tri_base(algo) == PPX_TRI_CR || tri_base(algo) == PPX_TRI_CR_SHFL ? PPX_TRI_CR : PPX_TRI_PCR;
 }
+// Largest P * sizeof(element) of the persistent in-wave variants (the second
+// register set).
+constexpr int kTriPipeMaxBytes = 32;
 int launch_fft(const void *in, void *out, int log2n, int64_t batch,
                const ppx_config &c, bool inverse, hipStream_t s);
 int launch_scan(const void *in, void *out, int log2n, int64_t batch, int dtype,

@@ -64,28 +64,11 @@ __device__ __forceinline__ void store_chunk(T *dst, const T (&v)[P]) {
     }
 }
 
-// One workgroup's share: problems [p0, p0 + nprob), T = n/P threads per
-// problem (threads of problems beyond nprob compute on zeros and store
-// nothing).  `wave_tot` holds blockDim.x / 64 values.  Used by k_scan and by
-// the fused kernel.
-template <typename T, int P, int ALGO>
-__device__ __forceinline__ void scan_block(const T *in, T *out, int log2n, long long p0, int nprob,
-                                           T *wave_tot) {
-    constexpr int LP = P == 2 ? 1 : P == 4 ? 2 : P == 8 ? 3 : P == 16 ? 4 : 5;
-    // integer adds wrap modulo 2^32: do them on unsigned values
-    using U = typename std::conditional<std::is_same<T, int>::value, unsigned, T>::type;
-    const int lT = log2n - LP;  // log2 threads per problem
-    const int lp = threadIdx.x >> lT;
-    const bool active = lp < nprob;
-    const long long off = p0 * (1LL << log2n) + (long long)threadIdx.x * P;
-
-    U v[P];
-    if (active) {
-        load_chunk<U, P>(reinterpret_cast<const U *>(in) + off, v);
-    } else {
-#pragma unroll
-        for (int j = 0; j < P; ++j) v[j] = U(0);
-    }
+// Steps 1-4 on the P values a thread holds (lT = log2 threads per problem).
+// `wave_tot` holds blockDim.x / 64 values; with T > 64 threads per problem
+// there is one barrier, which every thread of the workgroup must reach.
+template <typename T, int P, int ALGO, typename U>
+__device__ __forceinline__ void scan_values(U (&v)[P], int lT, T *wave_tot) {
     // 1. serial scan within the thread
 #pragma unroll
     for (int j = 1; j < P; ++j) v[j] = v[j] + v[j - 1];
@@ -107,9 +90,37 @@ __device__ __forceinline__ void scan_block(const T *in, T *out, int log2n, long 
         for (int u = w0; u < w; ++u) prefix = prefix + __builtin_bit_cast(U, wave_tot[u]);
     }
 
-    // 4. add the prefix and store
+    // 4. add the prefix
 #pragma unroll
     for (int j = 0; j < P; ++j) v[j] = v[j] + prefix;
+}
+
+// Integer adds wrap modulo 2^32: they are done on unsigned values.
+template <typename T>
+using ScanArith = typename std::conditional<std::is_same<T, int>::value, unsigned, T>::type;
+
+// One workgroup's share: problems [p0, p0 + nprob), T = n/P threads per
+// problem (threads of problems beyond nprob compute on zeros and store
+// nothing).  `wave_tot` holds blockDim.x / 64 values.  Used by k_scan and by
+// the fused kernel.
+template <typename T, int P, int ALGO>
+__device__ __forceinline__ void scan_block(const T *in, T *out, int log2n, long long p0, int nprob,
+                                           T *wave_tot) {
+    constexpr int LP = P == 2 ? 1 : P == 4 ? 2 : P == 8 ? 3 : P == 16 ? 4 : 5;
+    using U = ScanArith<T>;
+    const int lT = log2n - LP;  // log2 threads per problem
+    const int lp = threadIdx.x >> lT;
+    const bool active = lp < nprob;
+    const long long off = p0 * (1LL << log2n) + (long long)threadIdx.x * P;
+
+    U v[P];
+    if (active) {
+        load_chunk<U, P>(reinterpret_cast<const U *>(in) + off, v);
+    } else {
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[j] = U(0);
+    }
+    scan_values<T, P, ALGO>(v, lT, wave_tot);
     if (active) store_chunk<U, P>(reinterpret_cast<U *>(out) + off, v);
 }
 
@@ -119,6 +130,44 @@ __global__ __launch_bounds__(1024) void k_scan(const T *in, T *out, int log2n, l
     __shared__ T wave_tot[kMaxThreadsPerBlock / kWave];
     const long long p0 = (long long)blockIdx.x * gb;
     scan_block<T, P, ALGO>(in, out, log2n, p0, (int)min((long long)gb, batch - p0), wave_tot);
+}
+
+// Persistent variant: a grid of resident workgroups walks the groups of gb
+// problems (g, g + gridDim.x, ...) and loads the next group's values into a
+// second register set while it scans the current one, so the loads overlap
+// the barrier-bound steps of workgroups that span many waves.  The loads are
+// unconditional, from an offset clamped into the batch (a clamped load's data
+// only reaches problems beyond the batch, which store nothing): a
+// conditional load would force the first use of v to wait for the prefetch
+// too.  The wave totals alternate between two buffers, since a wave may start
+// the next group before a slower one has read this group's totals; the
+// barrier of every group keeps the waves within one group of each other.
+template <typename T, int P, int ALGO>
+__global__ __launch_bounds__(1024) void k_scan_pipe(const T *in, T *out, int log2n, long long batch,
+                                                    int gb) {
+    constexpr int LP = P == 2 ? 1 : P == 4 ? 2 : P == 8 ? 3 : P == 16 ? 4 : 5;
+    using U = ScanArith<T>;
+    __shared__ T wave_tot[2][kMaxThreadsPerBlock / kWave];
+    const int lT = log2n - LP;
+    const long long total = batch << log2n;        // elements in the batch
+    const long long group = (long long)gb << log2n;  // elements per group
+    const long long ngroups = (batch + gb - 1) / gb;
+    const U *src = reinterpret_cast<const U *>(in);
+    U *dst = reinterpret_cast<U *>(out);
+    long long g = blockIdx.x;
+    long long off = g * group + (long long)threadIdx.x * P;
+    U v[P], w[P];
+    load_chunk<U, P>(src + (off < total ? off : total - P), v);
+    for (int it = 0; g < ngroups; g += gridDim.x, ++it) {
+        const long long offn = off + (long long)gridDim.x * group;
+        load_chunk<U, P>(src + (offn < total ? offn : total - P), w);
+        __builtin_amdgcn_sched_barrier(0);
+        scan_values<T, P, ALGO>(v, lT, wave_tot[it & 1]);
+        if (off < total) store_chunk<U, P>(dst + off, v);
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[j] = w[j];
+        off = offn;
+    }
 }
 
 }  // namespace ppx

@@ -310,8 +310,28 @@ __device__ __forceinline__ void wave_pcr_reg(T (&a)[P], T (&c)[P], T (&d)[P], in
     }
 }
 
+// Boundary zeros, unit-diagonal scaling and the solve of the equations a
+// lane holds (b is consumed; x ends in d).
+template <typename T, int ALGO, int P>
+__device__ __forceinline__ void tridiag_wave_solve(T (&a)[P], const T (&b)[P], T (&c)[P], T (&d)[P], int t,
+                                                   int lps, T *smem) {
+    if (t == 0) a[0] = T(0);            // multiplies the absent x_{-1}
+    if (t == lps - 1) c[P - 1] = T(0);  // multiplies the absent x_n
+#pragma unroll
+    for (int j = 0; j < P; ++j) {  // scale every row to unit diagonal
+        const T r = rcp(b[j]);
+        a[j] *= r;
+        c[j] *= r;
+        d[j] *= r;
+    }
+    if constexpr (ALGO == PPX_TRI_CR_SHFL) wave_cr<T, P>(a, c, d, t, lps);
+    else if constexpr (ALGO == PPX_TRI_PCR_SHFL) wave_pcr<T, P>(a, c, d, lps);
+    else wave_pcr_reg<T, P>(a, c, d, t, lps, smem + (threadIdx.x >> 6) * (3 * 64 * (P < 4 ? P : 4)));
+}
+
 // One workgroup's share: systems [first, first + nsys) of size n = P * lps,
-// lps = n / P <= 64 lanes each; every lane owns P equations.
+// lps = n / P <= 64 lanes each; every lane owns P equations.  Lanes of
+// systems beyond nsys solve identity rows and store nothing.
 template <typename T, int ALGO, int P>
 __device__ __forceinline__ void tridiag_wave_block(const T *A, const T *B, const T *C, const T *D,
                                                    T *X, int log2n, long long first, int nsys, T *smem) {
@@ -321,29 +341,20 @@ __device__ __forceinline__ void tridiag_wave_block(const T *A, const T *B, const
     const int t = threadIdx.x % lps;
     const bool active = sys_local < nsys;
     const long long base = (first + sys_local) * n + (long long)t * P;
-    T a[P], c[P], d[P];
+    T a[P], b[P], c[P], d[P];
     if (active) {
-        T b[P];
         wave_load<T, P>(A + base, a);
         wave_load<T, P>(B + base, b);
         wave_load<T, P>(C + base, c);
         wave_load<T, P>(D + base, d);
-        if (t == 0) a[0] = T(0);            // multiplies the absent x_{-1}
-        if (t == lps - 1) c[P - 1] = T(0);  // multiplies the absent x_n
-#pragma unroll
-        for (int j = 0; j < P; ++j) {  // scale every row to unit diagonal
-            const T r = rcp(b[j]);
-            a[j] *= r;
-            c[j] *= r;
-            d[j] *= r;
-        }
     } else {
 #pragma unroll
-        for (int j = 0; j < P; ++j) a[j] = c[j] = d[j] = T(0);
+        for (int j = 0; j < P; ++j) {
+            a[j] = c[j] = d[j] = T(0);
+            b[j] = T(1);
+        }
     }
-    if constexpr (ALGO == PPX_TRI_CR_SHFL) wave_cr<T, P>(a, c, d, t, lps);
-    else if constexpr (ALGO == PPX_TRI_PCR_SHFL) wave_pcr<T, P>(a, c, d, lps);
-    else wave_pcr_reg<T, P>(a, c, d, t, lps, smem + (threadIdx.x >> 6) * (3 * 64 * (P < 4 ? P : 4)));
+    tridiag_wave_solve<T, ALGO, P>(a, b, c, d, t, lps, smem);
     if (active) wave_store<T, P>(X + base, d);
 }
 
@@ -354,6 +365,57 @@ __global__ __launch_bounds__(256) void k_tridiag_wave(const T *a, const T *b, co
     const long long first = (long long)blockIdx.x * gb;
     const int nsys = (int)min((long long)gb, batch - first);
     tridiag_wave_block<T, ALGO, P>(a, b, c, d, x, log2n, first, nsys, reinterpret_cast<T *>(smem_raw));
+}
+
+// Persistent variant (algo | PPX_TRI_PIPE): a grid of resident workgroups
+// walks the groups of gb systems (g, g + gridDim.x, ...) and loads the next
+// group's coefficients into a second register set while it solves the
+// current one.  With every wave resident at once the plain kernel runs in
+// one round, so all waves load, then all compute, then all store; here the
+// loads of one group overlap the solve of the previous.  The loads are
+// unconditional, from an offset clamped into the batch: a conditional load
+// would make the first use of the current values wait for the prefetch too.
+// Lanes past the batch solve the clamped copies (finite, and confined to
+// their own lanes as any system is) and store nothing.
+template <typename T, int ALGO, int P>
+__global__ __launch_bounds__(256) void k_tridiag_wave_pipe(const T *A, const T *B, const T *C, const T *D,
+                                                           T *X, int log2n, long long batch, int gb) {
+    extern __shared__ float4 smem_raw[];
+    const int n = 1 << log2n;
+    const int lps = n / P;
+    const int sys_local = threadIdx.x / lps;
+    const int t = threadIdx.x % lps;
+    const long long total = batch << log2n;
+    const long long step = (long long)gridDim.x * gb << log2n;  // elements between a block's groups
+    const long long ngroups = (batch + gb - 1) / gb;
+    long long off = ((long long)blockIdx.x * gb + sys_local) * n + (long long)t * P;
+    T a[P], b[P], c[P], d[P], na[P], nb[P], nc[P], nd[P];
+    {
+        const long long o = off < total ? off : total - P;
+        wave_load<T, P>(A + o, a);
+        wave_load<T, P>(B + o, b);
+        wave_load<T, P>(C + o, c);
+        wave_load<T, P>(D + o, d);
+    }
+    for (long long g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const long long offn = off + step;
+        const long long o = offn < total ? offn : total - P;
+        wave_load<T, P>(A + o, na);
+        wave_load<T, P>(B + o, nb);
+        wave_load<T, P>(C + o, nc);
+        wave_load<T, P>(D + o, nd);
+        __builtin_amdgcn_sched_barrier(0);
+        tridiag_wave_solve<T, ALGO, P>(a, b, c, d, t, lps, reinterpret_cast<T *>(smem_raw));
+        if (off < total) wave_store<T, P>(X + off, d);
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            a[j] = na[j];
+            b[j] = nb[j];
+            c[j] = nc[j];
+            d[j] = nd[j];
+        }
+        off = offn;
+    }
 }
 
 }  // namespace ppx

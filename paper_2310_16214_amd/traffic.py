@@ -44,10 +44,12 @@ def kernel_name_prefix(d):
         return f"k_fft<{c['radix']}, {c['elems_per_thread']}, {split}>"
     if d["op"] == "scan":
         t = "int" if d["dtype"] == "int32" else "float"
-        return f"k_scan<{t}, {c['elems_per_thread']}, {c['algo']}>"
+        name = "k_scan_pipe" if c["algo"] & 2 else "k_scan"
+        return f"{name}<{t}, {c['elems_per_thread']}, {c['algo'] & 1}>"
     t = "double" if d["dtype"] == "float64" else "float"
-    if c["algo"] >= 2:
-        return f"k_tridiag_wave<{t}, {c['algo']}, {c['elems_per_thread']}>"
+    if c["algo"] & 7 >= 2:
+        name = "k_tridiag_wave_pipe" if c["algo"] & 8 else "k_tridiag_wave"
+        return f"{name}<{t}, {c['algo'] & 7}, {c['elems_per_thread']}>"
     return f"k_tridiag<{t}, {c['algo']}>"
 
 

@@ -89,3 +89,26 @@ def test_full_size(cuda, n, dtype):
         assert np.array_equal(y, ref)
     else:
         assert np.all(np.abs(y.astype(np.float64) - ref) <= scan_f32_bound(x))
+
+
+# (n, P, L, G_b, algo): persistent variants with batches that make every
+# workgroup loop several times and leave a ragged last round
+PERSISTENT = [(8192, 8, 1024, 1, ppx.SCAN_LF_PIPE), (4096, 4, 1024, 1, ppx.SCAN_KS_PIPE),
+              (256, 2, 128, 1, ppx.SCAN_LF_PIPE), (64, 4, 256, 16, ppx.SCAN_KS_PIPE)]
+
+
+@pytest.mark.parametrize("n,P,L,G,algo", PERSISTENT)
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_persistent_variants_loop_and_tail(cuda, n, P, L, G, algo, dtype):
+    batch = {8192: 2048 + 5, 4096: 4096 + 3, 256: 100000 + 3, 64: (1 << 18) + 7}[n]
+    code = ppx.I32 if dtype == np.int32 else ppx.F32
+    cfg = ppx.make_config(2, L, G, algo)
+    assert ppx.config_valid(ppx.OP_SCAN, code, n, cfg) and n * G // L == P
+    x = inputs.scan_input(n, batch, dtype, seed=n + 7)
+    banner(f"scan persistent n={n} batch={batch} {np.dtype(dtype).name} {cfg}")
+    y = _run(to_dev(x, cuda), n, batch, code, cfg)
+    ref = oracle.scan(x)
+    if dtype == np.int32:
+        assert np.array_equal(y, ref)
+    else:
+        assert np.all(np.abs(y.astype(np.float64) - ref) <= scan_f32_bound(x))

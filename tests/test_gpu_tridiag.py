@@ -45,8 +45,11 @@ def test_every_config(cuda, n, dtype):
           f"|x-oracle| {fe:.2e}, |x-x_true| {np.max(np.abs(x - xt)):.2e}")
 
 
-@pytest.mark.parametrize("algo", [ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL,
-                                  ppx.TRI_PCR_REG])
+IN_WAVE = [ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL, ppx.TRI_PCR_REG]
+ALL_ALGOS = [ppx.TRI_CR, ppx.TRI_PCR] + IN_WAVE + [a | ppx.TRI_PIPE for a in IN_WAVE]
+
+
+@pytest.mark.parametrize("algo", ALL_ALGOS)
 def test_boundary_coefficients_are_ignored(cuda, algo):
     n, batch = 256, 8
     a, b, c, d, _ = inputs.tridiag_input(n, batch, np.float32, seed=2)
@@ -72,8 +75,7 @@ def test_x_may_alias_d(cuda):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("n", [32, 1024])
-@pytest.mark.parametrize("algo", [ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL,
-                                  ppx.TRI_PCR_REG])
+@pytest.mark.parametrize("algo", ALL_ALGOS)
 def test_full_size(cuda, n, dtype, algo):
     """Benchmark sweep size: 2^22 unknowns per call; every system checked."""
     batch = (1 << 22) // n
@@ -85,9 +87,31 @@ def test_full_size(cuda, n, dtype, algo):
     if not ppx.config_valid(ppx.OP_TRIDIAG, CODE[dtype], n, cfg):
         valid = [c for c in ppx.enumerate_configs(ppx.OP_TRIDIAG, CODE[dtype], n) if c.algo == algo]
         if not valid:
-            pytest.skip("no configuration of this variant exists at this size (n / P > 64)")
+            pytest.skip("no configuration of this variant exists at this size "
+                        "(n / P > 64, or P too large for the persistent variant)")
         cfg = valid[0]
     banner(f"tridiag full n={n} {np.dtype(dtype).name} {cfg}")
     x = _solve(dev, n, batch, dtype, cfg)
+    r = oracle.tridiag_residual(a, b, c, d, x)
+    assert r.max() <= TOL[dtype]
+
+
+# (n, dtype, L, G_b, algo): persistent variants with batches that make every
+# workgroup loop several times and leave a ragged last round
+PERSISTENT = [(64, np.float32, 64, 4, ppx.TRI_CR_SHFL | ppx.TRI_PIPE),
+              (256, np.float32, 128, 4, ppx.TRI_PCR_REG | ppx.TRI_PIPE),
+              (128, np.float64, 64, 2, ppx.TRI_PCR_REG | ppx.TRI_PIPE),
+              (32, np.float64, 128, 16, ppx.TRI_PCR_SHFL | ppx.TRI_PIPE),
+              (128, np.float32, 256, 16, ppx.TRI_CR_SHFL | ppx.TRI_PIPE)]
+
+
+@pytest.mark.parametrize("n,dtype,L,G,algo", PERSISTENT)
+def test_persistent_variants_loop_and_tail(cuda, n, dtype, L, G, algo):
+    batch = (1 << 22) // n + 5
+    cfg = ppx.make_config(2, L, G, algo)
+    assert ppx.config_valid(ppx.OP_TRIDIAG, CODE[dtype], n, cfg)
+    a, b, c, d, _ = inputs.tridiag_input(n, batch, dtype, seed=n + 3)
+    banner(f"tridiag persistent n={n} batch={batch} {np.dtype(dtype).name} {cfg}")
+    x = _solve([to_dev(v, cuda) for v in (a, b, c, d)], n, batch, dtype, cfg)
     r = oracle.tridiag_residual(a, b, c, d, x)
     assert r.max() <= TOL[dtype]

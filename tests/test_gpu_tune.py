@@ -51,8 +51,10 @@ def test_tridiag_family_filter(cuda):
     banner("tune_ex tridiag CR family")
     rep, trace = ppx.tune_ex(ppx.OP_TRIDIAG, ppx.F32, 64, 1 << 12, ppx.TUNE_EXHAUSTIVE,
                              algo=ppx.TRI_CR, reps=5)
-    assert {c.algo for c, _ in trace} == {ppx.TRI_CR, ppx.TRI_CR_SHFL}
-    assert ppx.tuned_config(ppx.OP_TRIDIAG, ppx.F32, 64, ppx.TRI_CR).algo in (0, 2)
+    algos = {c.algo for c, _ in trace}
+    assert {ppx.TRI_CR, ppx.TRI_CR_SHFL} <= algos
+    assert all(ppx.tri_family(a) == ppx.TRI_CR for a in algos)
+    assert ppx.tri_family(ppx.tuned_config(ppx.OP_TRIDIAG, ppx.F32, 64, ppx.TRI_CR).algo) == ppx.TRI_CR
     ppx.clear_tune_cache()
 
 
