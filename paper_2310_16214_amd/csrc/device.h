@@ -77,6 +77,68 @@ struct RegDFT<1> {
     __host__ __device__ __forceinline__ static void run(float2 (&)[1]) {}
 };
 
+// ------------------------------------------------------- buffer accesses
+// Raw buffer loads and stores through a descriptor: a lane whose byte offset
+// falls outside the descriptor's range reads zeros and writes nothing, with
+// no branch.  Used by the persistent kernels, whose per-group descriptors
+// cover exactly the group's problems inside the batch.
+constexpr int kBufferFlags = 0x00020000;  // word 3 of a raw buffer descriptor (32-bit data format)
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// The descriptor of group `group` (gb problems of `elems` elements of `es`
+// bytes each) of an array of `batch` problems.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t group_rsrc(const void *base, long long group, int gb,
+                                                            long long elems, int es, long long batch) {
+    const long long left = batch - group * gb;  // problems of the batch from this group on
+    const int bytes = left <= 0 ? 0 : (int)((left >= gb ? gb : left) * elems * es);
+    const char *p = static_cast<const char *>(base) + (left > 0 ? group * gb * elems * es : 0);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, bytes, kBufferFlags);
+}
+
+// K contiguous 4- or 8-byte values at byte offset voff (16-byte words where
+// the size allows; the constant part of each offset in the scalar operand).
+template <typename T, int K>
+__device__ __forceinline__ void buf_load(T (&v)[K], __amdgpu_buffer_rsrc_t r, int voff) {
+    constexpr int B = K * (int)sizeof(T);
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int w = 0; w < B / 16; ++w) {
+            const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 16 * w, 0);
+            __builtin_memcpy(&v[w * 16 / (int)sizeof(T)], &x, 16);
+        }
+    } else if constexpr (B == 8) {
+        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
+        __builtin_memcpy(&v[0], &x, 8);
+    } else {
+        static_assert(B == 4, "4, 8 or a multiple of 16 bytes");
+        const unsigned x = __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0);
+        __builtin_memcpy(&v[0], &x, 4);
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void buf_store(const T (&v)[K], __amdgpu_buffer_rsrc_t r, int voff) {
+    constexpr int B = K * (int)sizeof(T);
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int w = 0; w < B / 16; ++w) {
+            u32x4 x;
+            __builtin_memcpy(&x, &v[w * 16 / (int)sizeof(T)], 16);
+            __builtin_amdgcn_raw_buffer_store_b128(x, r, voff, 16 * w, 0);
+        }
+    } else if constexpr (B == 8) {
+        u32x2 x;
+        __builtin_memcpy(&x, &v[0], 8);
+        __builtin_amdgcn_raw_buffer_store_b64(x, r, voff, 0, 0);
+    } else {
+        static_assert(B == 4, "4, 8 or a multiple of 16 bytes");
+        unsigned x;
+        __builtin_memcpy(&x, &v[0], 4);
+        __builtin_amdgcn_raw_buffer_store_b32(x, r, voff, 0, 0);
+    }
+}
+
 // ------------------------------------------------------------ lane networks
 // DPP controls (GFX9 encoding).
 constexpr int kDppRowShr = 0x110;     // + shift (1..15), within 16-lane rows

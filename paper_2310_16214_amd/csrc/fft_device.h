@@ -368,21 +368,6 @@ __device__ __forceinline__ void fft_tw_to_lds(float2 *twl, const float2 *__restr
     }
 }
 
-// Buffer-resource access (raw buffer loads and stores): lanes whose offset
-// falls outside the descriptor's byte range read zeros and write nothing,
-// with no branch.  The descriptor of a group covers exactly its problems that
-// lie inside the batch.
-constexpr int kBufferFlags = 0x00020000;  // word 3 of a raw buffer descriptor (32-bit data format)
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t group_rsrc(const float2 *base, long long group, int gb, int n,
-                                                            long long batch) {
-    const long long left = batch - group * gb;  // problems of the batch from this group on
-    const int bytes = left <= 0 ? 0 : (int)((left >= gb ? gb : left) * n * (long long)sizeof(float2));
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(base) + (left > 0 ? group * gb * n : 0),
-                                             (short)0, bytes, kBufferFlags);
-}
-
 template <int P, int LOG2N>
 __device__ __forceinline__ void fft_load_buf(float2 (&v)[P], __amdgpu_buffer_rsrc_t r, int poff, int tid) {
     constexpr int T = 1 << (LOG2N - clog2(P));
@@ -491,13 +476,13 @@ __global__ __launch_bounds__(fft_max_threads(P)) void k_fft_np(const float2 *in,
     auto iteration = [&](long long grp, float2 (&cur)[P], float2 (&nxt)[P]) {
         int tid = tid0;
         asm volatile("" : "+v"(tid));
-        fft_load_buf<P, LOG2N>(nxt, group_rsrc(in, grp + G, gb, n, batch), poff, tid);
+        fft_load_buf<P, LOG2N>(nxt, group_rsrc(in, grp + G, gb, n, sizeof(float2), batch), poff, tid);
         __builtin_amdgcn_sched_barrier(0);
         fft_conj<P>(cur, sgn);
-        fft_stages_pre<R, P, SPLIT, LOG2N, 0, 0>(cur, twl, lds_raw, poff, group_rsrc(out, grp, gb, n, batch),
-                                                 tid, sgn);
+        fft_stages_pre<R, P, SPLIT, LOG2N, 0, 0>(
+            cur, twl, lds_raw, poff, group_rsrc(out, grp, gb, n, sizeof(float2), batch), tid, sgn);
     };
-    fft_load_buf<P, LOG2N>(A, group_rsrc(in, g, gb, n, batch), poff, tid0);
+    fft_load_buf<P, LOG2N>(A, group_rsrc(in, g, gb, n, sizeof(float2), batch), poff, tid0);
     iteration(g, A, B);
     for (g += G; g < ngroups; g += 2 * G) {
         iteration(g, B, A);

@@ -132,16 +132,18 @@ __global__ __launch_bounds__(1024) void k_scan(const T *in, T *out, int log2n, l
     scan_block<T, P, ALGO>(in, out, log2n, p0, (int)min((long long)gb, batch - p0), wave_tot);
 }
 
-// Persistent variant: a grid of resident workgroups walks the groups of gb
-// problems (g, g + gridDim.x, ...) and loads the next group's values into a
-// second register set while it scans the current one, so the loads overlap
-// the barrier-bound steps of workgroups that span many waves.  The loads are
-// unconditional, from an offset clamped into the batch (a clamped load's data
-// only reaches problems beyond the batch, which store nothing): a
-// conditional load would force the first use of v to wait for the prefetch
-// too.  The wave totals alternate between two buffers, since a wave may start
-// the next group before a slower one has read this group's totals; the
-// barrier of every group keeps the waves within one group of each other.
+// Persistent variant: a grid of resident workgroups (at most one per group)
+// walks the groups of gb problems (g, g + gridDim.x, ...) and loads the next
+// group's values into a second register set while it scans the current one,
+// so the loads overlap the barrier-bound steps of workgroups that span many
+// waves.  Loads and stores go through per-group buffer descriptors (lanes
+// past the batch read zeros and store nothing, without a branch); the first
+// iteration is peeled and the loop unrolled twice with the two register sets
+// swapping roles, so the wait for the prefetched group never also covers the
+// stores issued after it.  The wave totals alternate between two buffers: a
+// wave may start the next group before a slower one has read this group's
+// totals, and the barrier of every group keeps the waves within one group of
+// each other.
 template <typename T, int P, int ALGO>
 __global__ __launch_bounds__(1024) void k_scan_pipe(const T *in, T *out, int log2n, long long batch,
                                                     int gb) {
@@ -149,24 +151,24 @@ __global__ __launch_bounds__(1024) void k_scan_pipe(const T *in, T *out, int log
     using U = ScanArith<T>;
     __shared__ T wave_tot[2][kMaxThreadsPerBlock / kWave];
     const int lT = log2n - LP;
-    const long long total = batch << log2n;        // elements in the batch
-    const long long group = (long long)gb << log2n;  // elements per group
+    const long long n = 1LL << log2n;
+    const int voff = threadIdx.x * P * (int)sizeof(T);  // byte offset within a group
     const long long ngroups = (batch + gb - 1) / gb;
-    const U *src = reinterpret_cast<const U *>(in);
-    U *dst = reinterpret_cast<U *>(out);
-    long long g = blockIdx.x;
-    long long off = g * group + (long long)threadIdx.x * P;
-    U v[P], w[P];
-    load_chunk<U, P>(src + (off < total ? off : total - P), v);
-    for (int it = 0; g < ngroups; g += gridDim.x, ++it) {
-        const long long offn = off + (long long)gridDim.x * group;
-        load_chunk<U, P>(src + (offn < total ? offn : total - P), w);
+    const long long G = gridDim.x;
+    U v0[P], v1[P];
+    auto iteration = [&](long long grp, int parity, U (&cur)[P], U (&nxt)[P]) {
+        buf_load<U, P>(nxt, group_rsrc(in, grp + G, gb, n, sizeof(T), batch), voff);
         __builtin_amdgcn_sched_barrier(0);
-        scan_values<T, P, ALGO>(v, lT, wave_tot[it & 1]);
-        if (off < total) store_chunk<U, P>(dst + off, v);
-#pragma unroll
-        for (int j = 0; j < P; ++j) v[j] = w[j];
-        off = offn;
+        scan_values<T, P, ALGO>(cur, lT, wave_tot[parity]);
+        buf_store<U, P>(cur, group_rsrc(out, grp, gb, n, sizeof(T), batch), voff);
+    };
+    long long g = blockIdx.x;  // < ngroups: the grid never exceeds the groups
+    buf_load<U, P>(v0, group_rsrc(in, g, gb, n, sizeof(T), batch), voff);
+    iteration(g, 0, v0, v1);
+    for (g += G; g < ngroups; g += 2 * G) {
+        iteration(g, 1, v1, v0);
+        if (g + G >= ngroups) break;
+        iteration(g + G, 0, v0, v1);
     }
 }
 

@@ -37,6 +37,7 @@
 
 #include <type_traits>
 
+#include "device.h"
 #include "ppx_internal.h"
 #include "tridiag_device.h"
 
@@ -368,53 +369,51 @@ __global__ __launch_bounds__(256) void k_tridiag_wave(const T *a, const T *b, co
 }
 
 // Persistent variant (algo | PPX_TRI_PIPE): a grid of resident workgroups
-// walks the groups of gb systems (g, g + gridDim.x, ...) and loads the next
-// group's coefficients into a second register set while it solves the
-// current one.  With every wave resident at once the plain kernel runs in
-// one round, so all waves load, then all compute, then all store; here the
-// loads of one group overlap the solve of the previous.  The loads are
-// unconditional, from an offset clamped into the batch: a conditional load
-// would make the first use of the current values wait for the prefetch too.
-// Lanes past the batch solve the clamped copies (finite, and confined to
-// their own lanes as any system is) and store nothing.
+// (at most one per group) walks the groups of gb systems (g, g + gridDim.x,
+// ...) and loads the next group's coefficients into a second register set
+// while it solves the current one.  With every wave resident at once the
+// plain kernel runs in one round, so all waves load, then all compute, then
+// all store; here one group's loads overlap the previous group's solve.
+// Loads and stores go through per-group buffer descriptors (lanes past the
+// batch read zeros and store nothing, without a branch); the first iteration
+// is peeled and the loop unrolled twice with the two register sets swapping
+// roles, so the wait for the prefetched group never also covers the stores
+// issued after it.  Lanes past the batch solve rows of zeros, whose
+// non-finite results stay in their own lanes, as any system's do.
 template <typename T, int ALGO, int P>
 __global__ __launch_bounds__(256) void k_tridiag_wave_pipe(const T *A, const T *B, const T *C, const T *D,
                                                            T *X, int log2n, long long batch, int gb) {
     extern __shared__ float4 smem_raw[];
+    T *smem = reinterpret_cast<T *>(smem_raw);
     const int n = 1 << log2n;
     const int lps = n / P;
     const int sys_local = threadIdx.x / lps;
     const int t = threadIdx.x % lps;
-    const long long total = batch << log2n;
-    const long long step = (long long)gridDim.x * gb << log2n;  // elements between a block's groups
+    const int voff = (sys_local * n + t * P) * (int)sizeof(T);  // byte offset within a group
     const long long ngroups = (batch + gb - 1) / gb;
-    long long off = ((long long)blockIdx.x * gb + sys_local) * n + (long long)t * P;
-    T a[P], b[P], c[P], d[P], na[P], nb[P], nc[P], nd[P];
-    {
-        const long long o = off < total ? off : total - P;
-        wave_load<T, P>(A + o, a);
-        wave_load<T, P>(B + o, b);
-        wave_load<T, P>(C + o, c);
-        wave_load<T, P>(D + o, d);
-    }
-    for (long long g = blockIdx.x; g < ngroups; g += gridDim.x) {
-        const long long offn = off + step;
-        const long long o = offn < total ? offn : total - P;
-        wave_load<T, P>(A + o, na);
-        wave_load<T, P>(B + o, nb);
-        wave_load<T, P>(C + o, nc);
-        wave_load<T, P>(D + o, nd);
+    const long long G = gridDim.x;
+    constexpr int es = sizeof(T);
+    T a0[P], b0[P], c0[P], d0[P], a1[P], b1[P], c1[P], d1[P];
+    auto load = [&](long long grp, T (&a)[P], T (&b)[P], T (&c)[P], T (&d)[P]) {
+        buf_load<T, P>(a, group_rsrc(A, grp, gb, n, es, batch), voff);
+        buf_load<T, P>(b, group_rsrc(B, grp, gb, n, es, batch), voff);
+        buf_load<T, P>(c, group_rsrc(C, grp, gb, n, es, batch), voff);
+        buf_load<T, P>(d, group_rsrc(D, grp, gb, n, es, batch), voff);
+    };
+    auto iteration = [&](long long grp, T (&a)[P], T (&b)[P], T (&c)[P], T (&d)[P], T (&na)[P], T (&nb)[P],
+                         T (&nc)[P], T (&nd)[P]) {
+        load(grp + G, na, nb, nc, nd);
         __builtin_amdgcn_sched_barrier(0);
-        tridiag_wave_solve<T, ALGO, P>(a, b, c, d, t, lps, reinterpret_cast<T *>(smem_raw));
-        if (off < total) wave_store<T, P>(X + off, d);
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            a[j] = na[j];
-            b[j] = nb[j];
-            c[j] = nc[j];
-            d[j] = nd[j];
-        }
-        off = offn;
+        tridiag_wave_solve<T, ALGO, P>(a, b, c, d, t, lps, smem);
+        buf_store<T, P>(d, group_rsrc(X, grp, gb, n, es, batch), voff);
+    };
+    long long g = blockIdx.x;  // < ngroups: the grid never exceeds the groups
+    load(g, a0, b0, c0, d0);
+    iteration(g, a0, b0, c0, d0, a1, b1, c1, d1);
+    for (g += G; g < ngroups; g += 2 * G) {
+        iteration(g, a1, b1, c1, d1, a0, b0, c0, d0);
+        if (g + G >= ngroups) break;
+        iteration(g + G, a0, b0, c0, d0, a1, b1, c1, d1);
     }
 }
 

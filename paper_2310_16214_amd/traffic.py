@@ -20,7 +20,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 SOURCES = {
     "fft": ["fft_device.h", "device.h", "fft.hip", "fft_spec8.hip", "fft_spec16.hip"],
     "scan": ["scan_device.h", "device.h", "scan.hip"],
-    "tridiag": ["tridiag_device.h", "tridiag_wave_device.h", "tridiag.hip"],
+    "tridiag": ["tridiag_device.h", "tridiag_wave_device.h", "device.h", "tridiag.hip"],
 }
 COPY_BYTES = 256 * 2 ** 20
 
