@@ -16,6 +16,8 @@ import json
 import re
 import statistics
 
+from paper_2310_16214_amd.traffic import kernel_name_prefix
+
 
 def short(name):
     name = re.sub(r"HIP_vector_type<float, 2u>", "float2", name)
@@ -49,16 +51,15 @@ def main():
                  f"{'mean_us':>9s} {'med_us':>9s}  call / events_us")
     rows = sorted(groups.items(), key=lambda kv: -statistics.mean(kv[1]))[:args.top]
     for (k, grid, wg, lds, vgpr), ts in rows:
-        match = ""
+        calls = []
         for d in detail:
             c = d["cfg"]
-            if grid // wg == -(-d["batch"] // c["problems_per_block"]) and c["threads_per_block"] == wg:
-                kind = {"fft": "k_fft", "scan": "k_scan"}.get(d["op"], "k_tridiag")
-                if kind in k and (d["op"] != "scan" or (("int" in k) == (d["dtype"] == "int32"))) and \
-                        (not d["op"].startswith("tridiag") or
-                         ("double" in k) == (d["dtype"] == "float64")):
-                    match = f"{d['op']} n={d['n']} {d['dtype']} / {d['us']:.1f}"
-                    break
+            if not k.startswith("ppx::" + kernel_name_prefix(d)) or c["threads_per_block"] != wg:
+                continue
+            persistent = "_np<" in k or "_pipe<" in k  # launched with the resident grid
+            if persistent or grid // wg == -(-d["batch"] // c["problems_per_block"]):
+                calls.append(f"{d['op']} n={d['n']} {d['dtype']} / {d['us']:.1f}")
+        match = "; ".join(calls)
         lines.append(f"{k[:34]:34s} {grid // wg:9d} {wg:5d} {lds:7d} {vgpr:5d} {len(ts):4d} "
                      f"{statistics.mean(ts):9.2f} {statistics.median(ts):9.2f}  {match}")
     if args.stats:
