@@ -532,22 +532,75 @@ static int resources(int op, int dtype, int64_t n, const ppx_config &c, bool hav
 // Premise (i) of the analytical model (coalesced global accesses) restated
 // for these kernels on gfx950: the scan kernel gives each lane P contiguous
 // elements, so a load instruction is contiguous across the wave only when
-// those P elements are one 16-byte vector (P <= 4).  The FFT and tridiagonal
-// kernels read consecutive elements with consecutive lanes for every P.
+// those P elements are one 16-byte vector (P <= 4); where no such
+// configuration exists (n > 4096) the smallest P comes closest.  The FFT and
+// tridiagonal kernels read consecutive elements with consecutive lanes for
+// every P.
 static bool coalesced(int op, const ppx_config &c) {
     return op != PPX_OP_SCAN || c.elems_per_thread * 4 <= 16;
+}
+
+static bool persistent(int op, int algo) {
+    switch (op) {
+        case PPX_OP_FFT: return (algo & PPX_FFT_LDS_PIPE) != 0;
+        case PPX_OP_SCAN: return (algo & PPX_SCAN_KS_PIPE) != 0;
+        default: return (algo & PPX_TRI_PIPE) != 0;
+    }
+}
+static int persistent_flag(int op) {
+    return op == PPX_OP_FFT ? PPX_FFT_LDS_PIPE : op == PPX_OP_SCAN ? PPX_SCAN_KS_PIPE : PPX_TRI_PIPE;
 }
 
 // Flags of the gfx950 analytical model: the paper's guideline plus our grid
 // fill term and a 50% occupancy window.
 constexpr int kGfx950Flags = PPX_ANALYTICAL_GRID_FILL | PPX_ANALYTICAL_WINDOW_50;
 
+// The candidates the gfx950 guideline ranks:
+//  * coalesced ones (above);
+//  * no persistent variants: the occupancy model does not see what they
+//    change; the choice is mapped to its persistent twin afterwards (see
+//    analytical_select);
+//  * tridiagonal: the in-wave variants whenever one is valid (the paper's
+//    rule to use the warp-level exchange when a system fits one), and for
+//    PCR the LDS-exchange variant rather than the shuffle one: on gfx950 a
+//    shuffle moves a quarter of the bytes per instruction that a 16-byte LDS
+//    access moves, and PCR exchanges six values per equation and step; with
+//    no family filter, the CR family (less work).
 static std::vector<ppx_config> analytical_candidates(int op, const std::vector<ppx_config> &all) {
-    std::vector<ppx_config> out;
+    std::vector<ppx_config> base;
     for (const auto &c : all)
+        if (!persistent(op, c.algo)) base.push_back(c);
+    if (base.empty()) base = all;
+    std::vector<ppx_config> out;
+    for (const auto &c : base)
         if (coalesced(op, c)) out.push_back(c);
-    return out.empty() ? all : out;
+    if (out.empty()) {  // no fully coalesced shape: the smallest P
+        int pmin = 1 << 30;
+        for (const auto &c : base) pmin = std::min(pmin, c.elems_per_thread);
+        for (const auto &c : base)
+            if (c.elems_per_thread == pmin) out.push_back(c);
+    }
+    if (op == PPX_OP_TRIDIAG) {
+        std::vector<ppx_config> wave;
+        for (const auto &c : out)
+            if (tri_in_wave(c.algo) && c.algo != PPX_TRI_PCR_SHFL) wave.push_back(c);
+        if (!wave.empty()) out.swap(wave);
+        // with both families present (no family filter), CR: O(n) work per
+        // system against PCR's O(n log n)
+        std::vector<ppx_config> cr;
+        for (const auto &c : out)
+            if (tri_family(c.algo) == PPX_TRI_CR) cr.push_back(c);
+        if (!cr.empty()) out.swap(cr);
+    }
+    return out;
 }
+
+// Rule (v) of the gfx950 model, after the guideline has ranked: a choice that
+// keeps at most two workgroups resident per CU runs as its persistent twin
+// when one exists (the resident workgroups then overlap their own loads with
+// their computation instead of alternating between the two).
+static int analytical_select(int op, int dtype, int64_t n, int64_t batch, const std::vector<ppx_config> &cands,
+                             bool have_device, ppx_config &out);
 
 // ============================================================ analytical config
 int analytical_config(int op, int dtype, int64_t n, int64_t batch, ppx_config &c) {
@@ -567,18 +620,33 @@ int analytical_config(int op, int dtype, int64_t n, int64_t batch, ppx_config &c
     if (total <= 0) return default_config(op, dtype, n, c);
     std::vector<ppx_config> all(total);
     enumerate_configs(op, dtype, n, all.data(), total);
-    std::vector<ppx_config> cands = analytical_candidates(op, all);
-    const int cnt = (int)cands.size();
-    std::vector<ppx_resource> res(cnt);
-    for (int i = 0; i < cnt; ++i)
-        if (resources(op, dtype, n, cands[i], have_device, res[i]) != PPX_OK) return PPX_EHIP;
-    ppx_device_model m = gfx950_model();
-    const int pick = analytical_pick_impl(m, cands.data(), res.data(), cnt, batch, kGfx950Flags);
-    if (pick < 0) return default_config(op, dtype, n, c);
-    c = cands[pick];
+    if (analytical_select(op, dtype, n, batch, all, have_device, c) != PPX_OK)
+        return default_config(op, dtype, n, c);
     std::lock_guard<std::mutex> lk(memo_mu);
     memo[key] = c;
     fail(PPX_OK, "");
+    return PPX_OK;
+}
+
+static int analytical_select(int op, int dtype, int64_t n, int64_t batch, const std::vector<ppx_config> &cands,
+                             bool have_device, ppx_config &out) {
+    const std::vector<ppx_config> sub = analytical_candidates(op, cands);
+    const int cnt = (int)sub.size();
+    if (cnt == 0) return fail(PPX_ECONFIG, "no candidate");
+    std::vector<ppx_resource> res(cnt);
+    int rc;
+    for (int i = 0; i < cnt; ++i)
+        if ((rc = resources(op, dtype, n, sub[i], have_device, res[i]))) return rc;
+    const ppx_device_model m = gfx950_model();
+    const int k = analytical_pick_impl(m, sub.data(), res.data(), cnt, batch, kGfx950Flags);
+    if (k < 0) return fail(PPX_ECONFIG, "no candidate fits the device");
+    out = sub[k];
+    if (occupancy_blocks(m, res[k], nullptr) <= 2) {
+        ppx_config twin = out;
+        twin.algo |= persistent_flag(op);
+        for (const auto &c : cands)
+            if (std::memcmp(&c, &twin, sizeof twin) == 0) out = twin;
+    }
     return PPX_OK;
 }
 
@@ -767,14 +835,10 @@ static int tune_impl(int op, int dtype, int64_t n, int64_t batch, int method, in
             }
         }
     } else if (method == PPX_TUNE_ANALYTICAL) {
-        const std::vector<ppx_config> sub = analytical_candidates(op, cands);
-        std::vector<ppx_resource> res(sub.size());
-        for (size_t i = 0; i < sub.size(); ++i)
-            if ((rc = resources(op, dtype, n, sub[i], true, res[i]))) return rc;
-        const int k = analytical_pick_impl(gfx950_model(), sub.data(), res.data(), (int)sub.size(),
-                                           batch, kGfx950Flags);
-        for (int i = 0; k >= 0 && i < nc; ++i)
-            if (std::memcmp(&cands[i], &sub[k], sizeof(ppx_config)) == 0) best = i;
+        ppx_config pick{};
+        if ((rc = analytical_select(op, dtype, n, batch, cands, true, pick))) return rc;
+        for (int i = 0; i < nc; ++i)
+            if (std::memcmp(&cands[i], &pick, sizeof(ppx_config)) == 0) best = i;
         if (best >= 0) eval_gpu(&cands[best], &ctx);  // timed once, for the report
     } else {
         std::vector<int> order(nc);
