@@ -135,6 +135,34 @@ def measured_traffic(dom):
     return None
 
 
+def stream_ceiling(ppx, dom, dev, stream, reps=10):
+    """Rate of the library's plain streaming reference moving exactly the
+    dominant call's HBM bytes with its number of input streams (1 for FFT and
+    scan, 4 for the tridiagonal solvers) and one output: the practical ceiling
+    for a call of that size and pattern.  Median of `reps` launches over three
+    buffer sets, so no launch reads data a previous one left in the caches."""
+    import torch
+    k = 4 if dom["op"].startswith("tridiag") else 1
+    es = dom["bpe"] // (k + 1)
+    nbytes = dom["n"] * dom["batch"] * es
+    sets = [[torch.empty(nbytes // 4, dtype=torch.float32, device=dev) for _ in range(k + 1)] for _ in range(3)]
+    for bufs in sets:
+        for b in bufs:
+            b.fill_(1.0)
+    for r in range(3):
+        ppx.stream_reference(sets[r % 3][:k], sets[r % 3][k], nbytes, stream)
+    ts = []
+    for r in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ppx.stream_reference(sets[r % 3][:k], sets[r % 3][k], nbytes, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3)
+    del sets
+    return (k + 1) * nbytes / float(np.median(ts)) / 1e3  # GB/s
+
+
 def cpu_baseline(calls_meta, nthreads, budget_s=20.0):
     """Time the oracle on a bounded sample of every call of the step and
     scale to the whole step (elements per second)."""
@@ -250,6 +278,7 @@ def main():
     dom_us = float(np.mean([a.elapsed_time(b) for a, b in dom_ev])) * 1e3
     dom_bytes = dom["bpe"] * dom["n"] * dom["batch"]
     dom.update(us=dom_us, gb_s=dom_bytes / dom_us / 1e3, hbm_frac=dom_bytes / dom_us / 1e3 / HBM_PEAK_GBS)
+    ref_gbs = stream_ceiling(ppx, dom, dev, stream)
     bytes_step = sum(c["bpe"] * c["n"] * c["batch"] for c in calls)
     traffic = measured_traffic(dom)
 
@@ -275,7 +304,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(dom["gb_s"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(dom["hbm_frac"], 4), "traffic": traffic,
                      "kernel": f"{dom['op']} n={dom['n']} {dom['dtype']}",
-                     "kernel_us": round(dom["us"], 2)},
+                     "kernel_us": round(dom["us"], 2),
+                     "stream_ref_gbs": round(ref_gbs, 1),
+                     "frac_of_stream_ref": round(dom["gb_s"] / ref_gbs, 4)},
     }
     if args.detail:
         with open(args.detail, "w") as f:

@@ -159,6 +159,18 @@ int ppx_kernel_resources(int op, int dtype, int64_t n, const ppx_config *cfg,
                          ppx_resource *out);
 
 /*
+ * ppx_stream_reference -- measurement reference, not part of the method: a
+ * plain streaming kernel that reads k in [1, 4] input arrays of `bytes` bytes
+ * each and writes their element-wise float sum (16-byte accesses, one per
+ * thread) to `out`.  It moves exactly the HBM bytes of a batched call with k
+ * input streams and one output stream, so its rate is the practical ceiling
+ * that a call of that size and pattern can reach.  in[0..k-1], out: device
+ * pointers, 16-byte aligned; bytes > 0, a multiple of 16, at most 2^36.
+ * Asynchronous on `stream`; PPX_EINVAL on bad arguments.
+ */
+int ppx_stream_reference(const void *const *in, int k, void *out, int64_t bytes, void *stream);
+
+/*
  * Tune cache: tuned configurations keyed by (op, dtype, n, algo filter) for
  * the running device architecture.  Text file, one entry per line:
  *   arch op dtype n algo radix P L G_b S algo_cfg us method

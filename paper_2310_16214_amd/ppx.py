@@ -253,6 +253,8 @@ _tune_sigs = {
     "ppx_time_config": ([ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                          ctypes.POINTER(Config), ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
                         ctypes.c_int),
+    "ppx_stream_reference": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                              ctypes.c_void_p], ctypes.c_int),
     "ppx_kernel_resources": ([ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.POINTER(Config),
                               ctypes.POINTER(Resource)], ctypes.c_int),
     "ppx_tune_cache_load": ([ctypes.c_char_p], ctypes.c_int),
@@ -357,6 +359,14 @@ def kernel_resources(op, dtype, n, cfg):
     r = Resource()
     _check(_tl("ppx_kernel_resources")(op, dtype, n, ctypes.byref(cfg), ctypes.byref(r)))
     return r
+
+
+def stream_reference(inputs, out, nbytes, stream=None):
+    """Plain streaming kernel over len(inputs) input arrays and one output of
+    nbytes bytes each (the practical bandwidth ceiling of a call with that
+    many input streams); torch tensors or raw device pointers."""
+    arr = (ctypes.c_void_p * len(inputs))(*[_ptr(t) for t in inputs])
+    _check(_tl("ppx_stream_reference")(arr, len(inputs), _ptr(out), nbytes, _stream(stream, out)))
 
 
 def load_tune_cache(path):

@@ -99,3 +99,12 @@ def test_resolve_without_gpu_is_valid():
         for n in (16, 1024):
             c = ppx.resolve_config(op, dt, n, 1 << 16)
             assert ppx.config_valid(op, dt, n, c), (op, n, c)
+
+
+def test_stream_reference_rejects_bad_arguments():
+    # validation runs before any HIP call
+    for k, nbytes in ((0, 64), (5, 64), (1, 0), (1, 20)):
+        ins = [16] * max(k, 1)
+        with pytest.raises(ppx.PpxError) as e:
+            ppx.stream_reference(ins[:k] if k else [], 16, nbytes)
+        assert e.value.code == ppx.EINVAL

@@ -66,3 +66,14 @@ def test_time_config_and_resources(cuda):
     assert r.threads == 512 and r.regs_per_thread > 0 and r.lds_bytes >= 1024 * 8
     with pytest.raises(ppx.PpxError):
         ppx.time_config(ppx.OP_FFT, ppx.C64, 1024, 16, ppx.make_config(3, 64, 1))
+
+
+def test_stream_reference_sums_its_inputs(cuda):
+    import torch
+    banner("stream reference")
+    ins = [torch.full((4096,), float(i + 1), dtype=torch.float32, device=cuda) for i in range(4)]
+    out = torch.empty(4096, dtype=torch.float32, device=cuda)
+    for k in (1, 2, 4):
+        ppx.stream_reference(ins[:k], out, 4096 * 4)
+        torch.cuda.synchronize()
+        assert torch.all(out == float(k * (k + 1) // 2))
