@@ -65,7 +65,8 @@ static FftKernel fft_lookup_s(int radix, int P) {
 }
 
 // The kernel of a configuration: the one specialised on log2 n where radix =
-// P = 8 or 16 (the persistent variants exist only there), else the generic.
+// P = 8 or 16 (the persistent variants exist only there) or radix = P = 4 and
+// n = 16, else the generic.
 static FftKernel fft_lookup(int radix, int P, int algo, int log2n) {
     const bool split = (algo & PPX_FFT_LDS_SPLIT) != 0, pipe = (algo & PPX_FFT_LDS_PIPE) != 0;
     if (fft_pipe_available(radix, P)) {
@@ -73,6 +74,9 @@ static FftKernel fft_lookup(int radix, int P, int algo, int log2n) {
         if (k || pipe) return reinterpret_cast<FftKernel>(const_cast<void *>(k));
     }
     if (pipe) return nullptr;
+    if (radix == 4 && P == 4) {
+        if (const void *k = fft_spec4_kernel(log2n, split)) return reinterpret_cast<FftKernel>(const_cast<void *>(k));
+    }
     return split ? fft_lookup_s<true>(radix, P) : fft_lookup_s<false>(radix, P);
 }
 

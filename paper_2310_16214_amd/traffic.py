@@ -18,7 +18,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 SOURCES = {
-    "fft": ["fft_device.h", "device.h", "fft.hip", "fft_spec8.hip", "fft_spec16.hip"],
+    "fft": ["fft_device.h", "device.h", "fft.hip", "fft_spec4.hip", "fft_spec8.hip", "fft_spec16.hip"],
     "scan": ["scan_device.h", "device.h", "scan.hip"],
     "tridiag": ["tridiag_device.h", "tridiag_wave_device.h", "device.h", "tridiag.hip"],
 }
@@ -38,9 +38,11 @@ def kernel_name_prefix(d):
     c = d["cfg"]
     if d["op"] == "fft":
         split = "true" if c["algo"] & 1 else "false"
-        if c["radix"] == c["elems_per_thread"] and c["radix"] in (8, 16):  # specialised on log2 n
+        log2n = d["n"].bit_length() - 1
+        if c["radix"] == c["elems_per_thread"] and (c["radix"] in (8, 16) or (c["radix"] == 4 and log2n == 4)):
+            # specialised on log2 n
             name = "k_fft_np" if c["algo"] & 2 else "k_fft_n"
-            return f"{name}<{c['radix']}, {c['elems_per_thread']}, {split}, {d['n'].bit_length() - 1}>"
+            return f"{name}<{c['radix']}, {c['elems_per_thread']}, {split}, {log2n}>"
         return f"k_fft<{c['radix']}, {c['elems_per_thread']}, {split}>"
     if d["op"] == "scan":
         t = "int" if d["dtype"] == "int32" else "float"

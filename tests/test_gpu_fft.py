@@ -122,9 +122,16 @@ def test_rejects_bad_arguments(cuda):
 
 # (n, radix, L, G_b, algo): the persistent (prefetching) variants with batches
 # that make every workgroup loop several times and leave a ragged last round
+# Covers mixed-radix first stages of every radix below R, full-radix first
+# stages (4096 with R = 16, 512 with R = 8), two to five stages (so one to
+# four chunks of prefetched loads), both exchanges and several problems per
+# workgroup.
 PERSISTENT = [(16384, 16, 1024, 1, ppx.FFT_LDS_PIPE), (8192, 16, 512, 1, ppx.FFT_LDS_SPLIT_PIPE),
-              (4096, 16, 512, 2, ppx.FFT_LDS_PIPE), (1024, 8, 128, 1, ppx.FFT_LDS_PIPE),
-              (64, 16, 64, 16, ppx.FFT_LDS_SPLIT_PIPE)]
+              (8192, 8, 1024, 1, ppx.FFT_LDS_PIPE), (4096, 16, 512, 2, ppx.FFT_LDS_PIPE),
+              (2048, 16, 128, 1, ppx.FFT_LDS_PIPE), (1024, 8, 128, 1, ppx.FFT_LDS_PIPE),
+              (512, 8, 128, 2, ppx.FFT_LDS_SPLIT_PIPE), (128, 16, 64, 8, ppx.FFT_LDS_SPLIT_PIPE),
+              (64, 16, 64, 16, ppx.FFT_LDS_SPLIT_PIPE), (32, 16, 64, 32, ppx.FFT_LDS_PIPE),
+              (16, 8, 64, 32, ppx.FFT_LDS_PIPE)]
 
 
 @pytest.mark.parametrize("n,radix,L,G,algo", PERSISTENT)
@@ -135,7 +142,8 @@ def test_persistent_variants_loop_and_tail(cuda, n, radix, L, G, algo):
     same stages (agreement to the FFT bound, not bitwise: the compiler may
     contract multiply-adds differently in the two kernels)."""
     import torch
-    batch = {16384: 2048 + 37, 8192: 4096 + 21, 4096: 8192 + 3, 1024: 12000 + 5, 64: 300000 + 7}[n]
+    batch = {16384: 2048 + 37, 8192: 4096 + 21, 4096: 8192 + 3, 2048: 9000 + 11, 1024: 12000 + 5,
+             512: 30000 + 1, 128: 100000 + 3, 64: 300000 + 7, 32: 400000 + 9, 16: 500000 + 13}[n]
     cfg = ppx.make_config(radix, L, G, algo)
     plain = ppx.make_config(radix, L, G, algo & ppx.FFT_LDS_SPLIT)
     assert ppx.config_valid(ppx.OP_FFT, ppx.C64, n, cfg)
