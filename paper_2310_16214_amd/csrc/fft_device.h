@@ -163,7 +163,7 @@ __device__ __forceinline__ void stage_store(const float2 (&v)[P], float2 *dst, i
 #pragma unroll
         for (int q = 0; q < RS; ++q) {
             const float2 o = v[i + q * NB];
-            dst[stage_out_pos<RS>(tid + i * T, lns, q)] = make_float2(o.x, sgn * o.y);
+            store_nt_any(dst + stage_out_pos<RS>(tid + i * T, lns, q), make_float2(o.x, sgn * o.y));
         }
 }
 
@@ -394,7 +394,7 @@ __device__ __forceinline__ void stage_store_buf(const float2 (&v)[P], __amdgpu_b
         for (int q = 0; q < RS; ++q) {
             const float2 o = v[i + q * NB];
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, make_float2(o.x, sgn * o.y)), r, voff,
-                                                  (q << lns) * (int)sizeof(float2), 0);
+                                                  (q << lns) * (int)sizeof(float2), kStoreNT);
         }
     }
 }

@@ -1,8 +1,11 @@
 // Streaming reference kernel (ppx_stream_reference in ppx_tune.h): k input
-// arrays summed into one output with 16-byte accesses, one per thread.  It
-// moves the same HBM bytes as a batched call with k input streams, so its
-// rate is the practical ceiling for that call size and pattern.
+// arrays summed into one output with 16-byte accesses, one per thread, the
+// output stored non-temporally like the library's results.  It moves the
+// same HBM bytes as a batched call with k input streams, so its rate is the
+// practical ceiling for that call size and pattern.
 #include <hip/hip_runtime.h>
+
+#include "device.h"
 
 #include "ppx_internal.h"
 #include "ppx_tune.h"
@@ -28,7 +31,7 @@ __global__ __launch_bounds__(256) void k_stream(const float4 *__restrict__ a, co
         const float4 w = d[i];
         v = make_float4(v.x + w.x, v.y + w.y, v.z + w.z, v.w + w.w);
     }
-    x[i] = v;
+    __builtin_nontemporal_store(__builtin_bit_cast(u32x4, v), reinterpret_cast<u32x4 *>(x + i));
 }
 
 }  // namespace ppx
