@@ -359,8 +359,18 @@ __device__ __forceinline__ void tridiag_wave_block(const T *A, const T *B, const
     if (active) wave_store<T, P>(X + base, d);
 }
 
+// Minimum waves per SIMD the compiler must leave room for: 3 for 16 doubles
+// per lane and array with CR or the LDS-exchange PCR (left alone it allocated
+// up to 253 VGPRs there, two waves per SIMD, so the 16 systems per CU of an
+// n = 1024 batch ran in two rounds), else no constraint (the shuffle PCR
+// spills under it).
 template <typename T, int ALGO, int P>
-__global__ __launch_bounds__(256) void k_tridiag_wave(const T *a, const T *b, const T *c, const T *d,
+constexpr int tri_wave_min_waves() {
+    return P * (int)sizeof(T) >= 128 && ALGO != PPX_TRI_PCR_SHFL ? 3 : 1;
+}
+
+template <typename T, int ALGO, int P>
+__global__ __launch_bounds__(256, (tri_wave_min_waves<T, ALGO, P>())) void k_tridiag_wave(const T *a, const T *b, const T *c, const T *d,
                                                       T *x, int log2n, long long batch, int gb) {
     extern __shared__ float4 smem_raw[];  // PPX_TRI_PCR_REG: 3 * 64 * min(P, 4) values per wave
     const long long first = (long long)blockIdx.x * gb;
