@@ -154,17 +154,36 @@ __device__ __forceinline__ void stage_exchange(float2 (&v)[P], void *lds, int po
     }
 }
 
+// The last stage's stores.  The T threads of a problem write T consecutive
+// values per store instruction; where that run is at least kFftNtRun bytes
+// the stores are non-temporal (kStoreNT), else default: with runs of 8 or 16
+// bytes every instruction writes small pieces of many lines, and the
+// streaming hint sends each piece to memory on its own (n = 16 at one thread
+// per problem measured 3.6x slower with it).
+constexpr int kFftNtRun = 32;
+__device__ __forceinline__ bool fft_nt_stores(int T) { return T * (int)sizeof(float2) >= kFftNtRun; }
+
 template <int RS, int P>
 __device__ __forceinline__ void stage_store(const float2 (&v)[P], float2 *dst, int tid, int T,
                                             int lns, float sgn) {
     constexpr int NB = P / RS;
+    if (fft_nt_stores(T)) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int q = 0; q < RS; ++q) {
-            const float2 o = v[i + q * NB];
-            store_nt_any(dst + stage_out_pos<RS>(tid + i * T, lns, q), make_float2(o.x, sgn * o.y));
-        }
+            for (int q = 0; q < RS; ++q) {
+                const float2 o = v[i + q * NB];
+                store_nt_any(dst + stage_out_pos<RS>(tid + i * T, lns, q), make_float2(o.x, sgn * o.y));
+            }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int q = 0; q < RS; ++q) {
+                const float2 o = v[i + q * NB];
+                dst[stage_out_pos<RS>(tid + i * T, lns, q)] = make_float2(o.x, sgn * o.y);
+            }
+    }
 }
 
 // One stage of radix RS followed by either the LDS exchange or, for the last
@@ -381,7 +400,7 @@ __device__ __forceinline__ void fft_load_chunk(float2 (&v)[P], __amdgpu_buffer_r
                                                    r, voff, j * T * (int)sizeof(float2), 0));
 }
 
-template <int RS, int P>
+template <int RS, int P, int POLICY>
 __device__ __forceinline__ void stage_store_buf(const float2 (&v)[P], __amdgpu_buffer_rsrc_t r, int poff,
                                                 int tid, int T, int lns, float sgn) {
     constexpr int NB = P / RS;
@@ -394,7 +413,7 @@ __device__ __forceinline__ void stage_store_buf(const float2 (&v)[P], __amdgpu_b
         for (int q = 0; q < RS; ++q) {
             const float2 o = v[i + q * NB];
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, make_float2(o.x, sgn * o.y)), r, voff,
-                                                  (q << lns) * (int)sizeof(float2), kStoreNT);
+                                                  (q << lns) * (int)sizeof(float2), POLICY);
         }
     }
 }
@@ -436,7 +455,7 @@ __device__ __forceinline__ void fft_stages_pre(float2 (&v)[P], const float2 *twl
     }
     constexpr int NEXT_IDX = LNS == 0 ? IDX : IDX + 1;
     if constexpr (LNS + LRS == LOG2N) {
-        stage_store_buf<RS, P>(v, dst, poff, tid, T, LNS, sgn);
+        stage_store_buf<RS, P, (T * (int)sizeof(float2) >= kFftNtRun ? kStoreNT : 0)>(v, dst, poff, tid, T, LNS, sgn);
     } else {
         stage_exchange<RS, P, SPLIT>(v, lds, poff, tid, T, LNS);
         fft_stages_pre<R, P, SPLIT, LOG2N, LNS + LRS, NEXT_IDX>(v, twl, lds, poff, dst, tid, sgn, nxt, src);
