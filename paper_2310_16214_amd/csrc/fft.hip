@@ -66,7 +66,8 @@ static FftKernel fft_lookup_s(int radix, int P) {
 
 // The kernel of a configuration: the one specialised on log2 n where radix =
 // P = 8 or 16 (the persistent variants exist only there) or radix = P = 4 and
-// n = 16, else the generic.
+// n <= 64, else the generic.  (The entry points take 16-byte aligned buffers
+// only, which the specialised kernels' 16-byte staged accesses rely on.)
 static FftKernel fft_lookup(int radix, int P, int algo, int log2n) {
     const bool split = (algo & PPX_FFT_LDS_SPLIT) != 0, pipe = (algo & PPX_FFT_LDS_PIPE) != 0;
     if (fft_pipe_available(radix, P)) {

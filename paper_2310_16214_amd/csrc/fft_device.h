@@ -272,7 +272,9 @@ __global__ __launch_bounds__(fft_max_threads(P)) void k_fft(const float2 *in, fl
 // kernel; the transform is the same.
 constexpr int clog2(int x) { return x <= 1 ? 0 : 1 + clog2(x / 2); }
 
-template <int R, int P, bool SPLIT, int LOG2N, int LNS>
+// With STAGED the last stage leaves its results in the LDS buffer, at their
+// output positions, instead of storing them (see k_fft_n).
+template <int R, int P, bool SPLIT, int LOG2N, int LNS, bool STAGED = false>
 __device__ __forceinline__ void fft_stages_ct(float2 (&v)[P], void *lds, int poff, float2 *dst, int tid,
                                               bool active, float sgn, const float2 *__restrict__ tw) {
     constexpr int REM = LOG2N % clog2(R);
@@ -281,10 +283,53 @@ __device__ __forceinline__ void fft_stages_ct(float2 (&v)[P], void *lds, int pof
     constexpr int T = 1 << (LOG2N - clog2(P));
     stage_butterflies<RS, P, LNS == 0>(v, tid, T, LNS, tw);
     if constexpr (LNS + LRS == LOG2N) {
-        if (active) stage_store<RS, P>(v, dst, tid, T, LNS, sgn);
+        if constexpr (STAGED) {
+            constexpr int NB = P / RS;
+            float2 *buf = static_cast<float2 *>(lds);
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int q = 0; q < RS; ++q) buf[swz_c(poff + stage_out_pos<RS>(tid + i * T, LNS, q))] = v[i + q * NB];
+        } else {
+            if (active) stage_store<RS, P>(v, dst, tid, T, LNS, sgn);
+        }
     } else {
         stage_exchange<RS, P, SPLIT>(v, lds, poff, tid, T, LNS);
-        fft_stages_ct<R, P, SPLIT, LOG2N, LNS + LRS>(v, lds, poff, dst, tid, active, sgn, tw);
+        fft_stages_ct<R, P, SPLIT, LOG2N, LNS + LRS, STAGED>(v, lds, poff, dst, tid, active, sgn, tw);
+    }
+}
+
+// Global I/O staged through LDS, for small n: the workgroup's G_b * n
+// contiguous values are read (and at the end written) as one sweep of
+// 16-byte words, consecutive lanes on consecutive words, and rearranged in
+// the exchange buffer.  Direct accesses would move runs of only T values per
+// problem per instruction (T = n / P <= 16 here).  Used where the exchange
+// buffer holds complex values (not SPLIT), there is an exchange (n > radix)
+// and n <= 64; measured in one process at the tuned shapes: n = 16 92 -> 77
+// us, n = 64 (radix 8) 109 -> 83 us per 256 MiB call, while from n = 256 on
+// the extra LDS passes cost more than they save.
+template <int R, int P, bool SPLIT, int LOG2N>
+constexpr bool fft_staged_io() {
+    return !SPLIT && LOG2N <= 6 && LOG2N > clog2(R) && (1 << (LOG2N - clog2(P))) <= 16;
+}
+
+// Words [0, total/2) of the block into the buffer (swizzled float2 slots).
+__device__ __forceinline__ void fft_stage_in(float2 *buf, const float2 *src, int total) {
+    const float4 *src4 = reinterpret_cast<const float4 *>(src);
+    for (int e = threadIdx.x; 2 * e < total; e += blockDim.x) {
+        const float4 w = src4[e];
+        buf[swz_c(2 * e)] = make_float2(w.x, w.y);
+        buf[swz_c(2 * e + 1)] = make_float2(w.z, w.w);
+    }
+}
+
+// The buffer's first total values to dst as 16-byte words (conjugated for the
+// inverse transform), with non-temporal stores.
+__device__ __forceinline__ void fft_stage_out(const float2 *buf, float2 *dst, int total, float sgn) {
+    u32x4 *dst4 = reinterpret_cast<u32x4 *>(dst);
+    for (int e = threadIdx.x; 2 * e < total; e += blockDim.x) {
+        const float2 a = buf[swz_c(2 * e)], b = buf[swz_c(2 * e + 1)];
+        store_nt(dst4 + e, __builtin_bit_cast(u32x4, make_float4(a.x, sgn * a.y, b.x, sgn * b.y)));
     }
 }
 
@@ -324,12 +369,29 @@ __global__ __launch_bounds__(fft_max_threads(P)) void k_fft_n(const float2 *in, 
     const long long prob = p0 + lp;
     const bool active = lp < nprob;
     float2 v[P];
-    fft_load_raw_ct<P, LOG2N>(v, in + prob * n, tid, active);
-    // keep the scheduler from interleaving the loads with their first use,
-    // which would leave only a few of them in flight
-    __builtin_amdgcn_sched_barrier(0);
-    fft_conj<P>(v, sgn);
-    fft_stages_ct<R, P, SPLIT, LOG2N, 0>(v, lds_raw, lp * n, out + prob * n, tid, active, sgn, tw);
+    if constexpr (fft_staged_io<R, P, SPLIT, LOG2N>()) {
+        // threads of problems beyond nprob transform stale buffer contents and
+        // store nothing: the sweeps cover the nprob problems only
+        constexpr int T = 1 << lT;
+        float2 *buf = reinterpret_cast<float2 *>(lds_raw);
+        const int total = nprob * n;
+        fft_stage_in(buf, in + p0 * n, total);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[j] = buf[swz_c(lp * n + tid + j * T)];
+        __syncthreads();
+        fft_conj<P>(v, sgn);
+        fft_stages_ct<R, P, SPLIT, LOG2N, 0, true>(v, lds_raw, lp * n, nullptr, tid, active, sgn, tw);
+        __syncthreads();
+        fft_stage_out(buf, out + p0 * n, total, sgn);
+    } else {
+        fft_load_raw_ct<P, LOG2N>(v, in + prob * n, tid, active);
+        // keep the scheduler from interleaving the loads with their first use,
+        // which would leave only a few of them in flight
+        __builtin_amdgcn_sched_barrier(0);
+        fft_conj<P>(v, sgn);
+        fft_stages_ct<R, P, SPLIT, LOG2N, 0>(v, lds_raw, lp * n, out + prob * n, tid, active, sgn, tw);
+    }
 }
 
 // --- persistent variant

@@ -1,16 +1,23 @@
 // Instantiations of the FFT kernel specialised on log2 n for radix = P = 4
-// (fft_device.h), for n = 16, the smallest size the library takes.  There it
-// takes about a tenth off the generic kernel's time at the tuned shape (4
-// threads per problem, 64 problems per workgroup); at n = 64 and 256 it
-// measured 1% slower than the generic kernel, so larger sizes keep that one.
+// (fft_device.h), for n = 16, 32 and 64, where the tuners pick that shape and
+// the specialised kernel stages its global I/O through LDS (fft_staged_io).
+// At n = 16 the specialisation alone takes about a tenth off the generic
+// kernel's time at the tuned shape; at n = 64 and 256, without the staging,
+// it measured 1% slower than the generic kernel, so larger sizes keep that.
 #include "fft_device.h"
 
 namespace ppx {
 
-const void *fft_spec4_kernel(int log2n, bool split) {
-    if (log2n != 4) return nullptr;
-    return split ? reinterpret_cast<const void *>(&k_fft_n<4, 4, true, 4>)
-                 : reinterpret_cast<const void *>(&k_fft_n<4, 4, false, 4>);
+template <bool S>
+static const void *spec4(int log2n) {
+    switch (log2n) {
+        case 4: return reinterpret_cast<const void *>(&k_fft_n<4, 4, S, 4>);
+        case 5: return reinterpret_cast<const void *>(&k_fft_n<4, 4, S, 5>);
+        case 6: return reinterpret_cast<const void *>(&k_fft_n<4, 4, S, 6>);
+        default: return nullptr;
+    }
 }
+
+const void *fft_spec4_kernel(int log2n, bool split) { return split ? spec4<true>(log2n) : spec4<false>(log2n); }
 
 }  // namespace ppx

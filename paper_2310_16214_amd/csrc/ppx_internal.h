@@ -96,7 +96,7 @@ const void *fft_kernel(int radix, int P, int algo, int log2n);
 // Kernels specialised on log2 n for radix = P = 8 / 16 (nullptr where none).
 const void *fft_spec8_kernel(int log2n, bool split, bool pipe);
 const void *fft_spec16_kernel(int log2n, bool split, bool pipe);
-const void *fft_spec4_kernel(int log2n, bool split);  // radix = P = 4, n = 16; else nullptr
+const void *fft_spec4_kernel(int log2n, bool split);  // radix = P = 4, n = 16..64; else nullptr
 // The persistent FFT variants exist for radix = P = 8 or 16.
 constexpr bool fft_pipe_available(int radix, int P) { return radix == P && (P == 8 || P == 16); }
 const void *scan_kernel(int dtype, int P, int algo);

@@ -39,7 +39,7 @@ def kernel_name_prefix(d):
     if d["op"] == "fft":
         split = "true" if c["algo"] & 1 else "false"
         log2n = d["n"].bit_length() - 1
-        if c["radix"] == c["elems_per_thread"] and (c["radix"] in (8, 16) or (c["radix"] == 4 and log2n == 4)):
+        if c["radix"] == c["elems_per_thread"] and (c["radix"] in (8, 16) or (c["radix"] == 4 and log2n <= 6)):
             # specialised on log2 n
             name = "k_fft_np" if c["algo"] & 2 else "k_fft_n"
             return f"{name}<{c['radix']}, {c['elems_per_thread']}, {split}, {log2n}>"

@@ -78,6 +78,26 @@ def test_in_place(cuda):
     assert oracle.rel_l2(y, oracle.dft(x)).max() <= fft_tol(n)
 
 
+@pytest.mark.parametrize("n,radix,L,G", [(16, 4, 256, 64), (32, 4, 128, 16), (64, 8, 256, 32), (64, 4, 64, 4)])
+def test_staged_io_in_place(cuda, n, radix, L, G):
+    """Small n, where the specialised kernel reads and writes its workgroup's
+    block as 16-byte words through LDS: in place with a ragged last
+    workgroup, against the oracle; an 8-byte aligned buffer is refused."""
+    import torch
+    batch = 3 * G + 5
+    x = inputs.fft_input(n, batch, seed=n + 7)
+    ref = oracle.dft(x)
+    cfg = ppx.make_config(radix, L, G, 0)
+    banner(f"fft staged io n={n} {cfg}")
+    xd = to_dev(x, cuda)
+    y = _run(xd, n, batch, cfg, out=xd)
+    assert oracle.rel_l2(y, ref).max() <= fft_tol(n)
+    src = torch.zeros(batch * n + 1, dtype=torch.complex64, device=cuda)
+    with pytest.raises(ppx.PpxError) as e:
+        ppx.fft_batched(src[1:], src[1:], n, batch, -1, cfg)
+    assert e.value.code == ppx.EINVAL
+
+
 def test_single_problem_and_closed_forms(cuda):
     # impulse -> constant spectrum; constant -> N * delta (exact in FP32)
     n = 512
