@@ -97,16 +97,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t group_rsrc(const void *base, l
 }
 
 // Non-temporal stores (the nt bit of gfx950's cache-policy operand), used for
-// the FFT kernels' results.  Timed against the default policy in one process,
-// they take 10-17% off the per-call time at every FFT size (n = 16384: 112 ->
-// 95 us) and 1% off the whole benchmark step (2.199 -> 2.174 ms); the smaller
-// step gain suggests that part of the default policy's cost lands on the
-// calls that follow.  The scan and tridiagonal kernels keep the default
-// policy: with the hint they measured neutral to 33% slower per call (worst
-// where each lane stores a contiguous chunk, so that one store instruction
-// covers only part of each line) and the step no faster.  Loads keep the
-// default policy: on a plain copy, hinting both directions was slower than
-// hinting the stores alone.
+// the FFT kernels' results.  Timed inside whole benchmark steps against the
+// default policy (builds alternating step by step), they take 2-6% off the
+// FFT calls from n = 32 on and up to 18% off the scans that follow them (less
+// dirty data left in the caches to drain), and 1.5% off the step; the first
+// call of the step (n = 16) is 12% slower with them.  Repeated calls of one
+// kernel on the same buffers show larger gains (n = 16384: 112 -> 95 us), part
+// of which is the input staying cached between the calls.  The scan and
+// tridiagonal kernels keep the default policy: with the hint they measured
+// neutral to 33% slower per call (worst where each lane stores a contiguous
+// chunk, so that one store instruction covers only part of each line) and the
+// step no faster.  Loads keep the default policy: on a plain copy, hinting
+// both directions was slower than hinting the stores alone.
 constexpr int kStoreNT = 2;
 
 __device__ __forceinline__ void store_nt(unsigned *p, unsigned v) { __builtin_nontemporal_store(v, p); }
