@@ -305,9 +305,9 @@ __device__ __forceinline__ void fft_stages_ct(float2 (&v)[P], void *lds, int pof
 // the exchange buffer.  Direct accesses would move runs of only T values per
 // problem per instruction (T = n / P <= 16 here).  Used where the exchange
 // buffer holds complex values (not SPLIT), there is an exchange (n > radix)
-// and n <= 64; measured in one process at the tuned shapes: n = 16 92 -> 77
-// us, n = 64 (radix 8) 109 -> 83 us per 256 MiB call, while from n = 256 on
-// the extra LDS passes cost more than they save.
+// and n <= 64.  Inside whole benchmark steps this took n = 16 from 117 to 92
+// us and n = 32 from 105 to 92 us per 256 MiB call; from n = 256 on the two
+// extra LDS passes cost more than they save.
 template <int R, int P, bool SPLIT, int LOG2N>
 constexpr bool fft_staged_io() {
     return !SPLIT && LOG2N <= 6 && LOG2N > clog2(R) && (1 << (LOG2N - clog2(P))) <= 16;
