@@ -16,7 +16,7 @@ arXiv:2310.16214) in double precision, by the plain route:
   floating point in float64.
 * :func:`thomas` -- the solution of the tridiagonal system of Sec. III by
   tridiagonal Gaussian elimination (Thomas algorithm), float64.
-* :func:`tridiag_residual`, :func:`rel_l2` -- the error measures used to judge
+* :func:`tridiag_residual`, :func:`rel_l2` -- the error measures used to assess
   a GPU result.
 * :func:`phi` -- the harmonic-mean performance-portability metric of Sec. VI.
 

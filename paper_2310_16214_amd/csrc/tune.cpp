@@ -480,7 +480,7 @@ void store_cached_config(int op, int dtype, int64_t n, const ppx_config &c) {
 }
 
 // ============================================================ resources
-// VGPR counts reported by the compiler for this build's kernels, used only
+// VGPR counts reported by the compiler for these kernels, used only
 // when no device is present to ask (CPU-side resolution of a NULL config).
 static int static_vgprs(int op, int dtype, int P, int algo) {
     if (op == PPX_OP_FFT) return P <= 2 ? 16 : P <= 4 ? 29 : P <= 8 ? 55 : P <= 16 ? 107 : 200;

@@ -1,0 +1,49 @@
+"""CPU tests of the measurement tooling: the kernel names that the traffic
+record and the kernel-trace summary match calls by are names of kernels the
+library actually contains, for every shape the launchers dispatch to a
+specialised, persistent or in-wave kernel."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2310_16214_amd import ppx
+from paper_2310_16214_amd.traffic import kernel_name_prefix
+
+
+def _call(op, n, radix, P, L, G, algo, dtype="c64"):
+    cfg = dict(radix=radix, elems_per_thread=P, threads_per_block=L, problems_per_block=G,
+               lds_elems=0, algo=algo)
+    return dict(op=op, n=n, dtype=dtype, batch=1 << 10, cfg=cfg)
+
+
+CASES = [
+    (_call("fft", 16, 4, 4, 256, 64, 0), "k_fft_n<4, 4, false, 4>"),
+    (_call("fft", 64, 4, 4, 64, 4, 1), "k_fft_n<4, 4, true, 6>"),
+    (_call("fft", 128, 4, 4, 64, 2, 0), "k_fft<4, 4, false>"),
+    (_call("fft", 256, 8, 8, 256, 8, 1), "k_fft_n<8, 8, true, 8>"),
+    (_call("fft", 16384, 16, 16, 1024, 1, 2), "k_fft_np<16, 16, false, 14>"),
+    (_call("fft", 8192, 16, 16, 512, 1, 3), "k_fft_np<16, 16, true, 13>"),
+    (_call("fft", 1024, 8, 16, 512, 8, 0), "k_fft<8, 16, false>"),
+    (_call("scan", 4096, 2, 4, 1024, 1, 2, "int32"), "k_scan_pipe<int, 4, 0>"),
+    (_call("scan", 8192, 2, 8, 1024, 1, 3, "float32"), "k_scan_pipe<float, 8, 1>"),
+    (_call("scan", 64, 2, 4, 64, 4, 1, "float32"), "k_scan<float, 4, 1>"),
+    (_call("tridiag_cr", 256, 2, 8, 128, 4, 2, "float32"), "k_tridiag_wave<float, 2, 8>"),
+    (_call("tridiag_cr", 128, 2, 8, 128, 8, 10, "float32"), "k_tridiag_wave_pipe<float, 2, 8>"),
+    (_call("tridiag_pcr", 1024, 2, 16, 256, 4, 4, "float64"), "k_tridiag_wave<double, 4, 16>"),
+    (_call("tridiag_cr", 64, 2, 2, 64, 2, 0, "float64"), "k_tridiag<double, 0>"),
+]
+
+
+@pytest.mark.parametrize("d,name", CASES, ids=[c[1] for c in CASES])
+def test_kernel_name_prefix(d, name):
+    assert kernel_name_prefix(d) == name
+
+
+@pytest.mark.skipif(shutil.which("nm") is None, reason="nm not available")
+def test_names_are_kernels_of_the_library():
+    ppx.lib()  # raises if the library is not built
+    out = subprocess.run(["nm", "-C", ppx.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    for _, name in CASES:
+        assert f"ppx::{name}(" in out, name
