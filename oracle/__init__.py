@@ -54,14 +54,15 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB_PATH):
-                build(force=False)
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+                build(force=True)
             lib = ctypes.CDLL(_LIB_PATH)
             dp = ctypes.POINTER(ctypes.c_double)
             u32p = ctypes.POINTER(ctypes.c_uint32)
             i64 = ctypes.c_int64
             ci = ctypes.c_int
             lib.oracle_dft.argtypes = [dp, dp, i64, i64, ci, ci]
+            lib.oracle_dft_bins.argtypes = [dp, dp, i64, i64, ctypes.POINTER(ctypes.c_int64), i64, ci, ci]
             lib.oracle_scan_u32.argtypes = [u32p, u32p, i64, i64, ci]
             lib.oracle_scan_f64.argtypes = [dp, dp, i64, i64, ci]
             lib.oracle_thomas.argtypes = [dp, dp, dp, dp, dp, i64, i64, ci]
@@ -109,6 +110,23 @@ def dft(x, inverse: bool = False, nthreads: int = 0) -> np.ndarray:
     rc = _load().oracle_dft(_ptr(xr, ctypes.c_double), _ptr(out, ctypes.c_double),
                             n, batch, 1 if inverse else -1, nthreads)
     _check(rc, "oracle_dft")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def dft_bins(x, ks, inverse: bool = False, nthreads: int = 0) -> np.ndarray:
+    """Bins ``ks`` of the DFT of every row of ``x``, each by its O(N)
+    definition: [batch][len(ks)] complex128 (same convention as :func:`dft`)."""
+    x = _as_2d(x)
+    batch, n = x.shape
+    ks = np.ascontiguousarray(ks, dtype=np.int64)
+    xr = np.empty((batch, n, 2), dtype=np.float64)
+    xr[..., 0] = np.real(x)
+    xr[..., 1] = np.imag(x)
+    out = np.empty((batch, len(ks), 2), dtype=np.float64)
+    rc = _load().oracle_dft_bins(_ptr(xr, ctypes.c_double), _ptr(out, ctypes.c_double), n, batch,
+                                 ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(ks),
+                                 1 if inverse else -1, nthreads)
+    _check(rc, "oracle_dft_bins")
     return out[..., 0] + 1j * out[..., 1]
 
 

@@ -10,6 +10,7 @@
  *   oracle_dft       complex DFT by its O(N^2) definition (Sec. III, "Fast
  *                    Fourier Transform": the complex FFT the Stockham kernels
  *                    compute; Sec. VI-C gives the 5 N log2 N flop convention).
+ *   oracle_dft_bins  selected outputs of that DFT, each by the definition.
  *   oracle_scan_u32  inclusive sum scan, integer: each output is the sum of
  *                    all inputs up to and including itself (Sec. III, "Scan
  *                    Operator"); arithmetic modulo 2^32.
@@ -143,6 +144,64 @@ int oracle_dft(const double *x, double *X, int64_t n, int64_t batch, int sign,
     }
     dft_ctx ctx = {x, X, wre, wim, n};
     int rc = run_ranges(dft_range, &ctx, batch, nthreads);
+    free(wre); free(wim);
+    return rc;
+}
+
+/*
+ * Selected bins of the same DFT: X[b][i] = sum_{j<n} x[b][j] * exp(sign * 2 pi
+ * i j ks[i] / n) for i < nk, each bin by the definition (O(n) per bin), for
+ * sizes whose full O(n^2) transform is too slow to check every output.
+ */
+typedef struct {
+    const double *x;
+    double *X; /* [batch][nk][2] */
+    const double *wre, *wim;
+    const int64_t *ks;
+    int64_t n, nk;
+} bins_ctx;
+
+static void bins_range(void *vctx, int64_t first, int64_t last)
+{
+    bins_ctx *c = (bins_ctx *)vctx;
+    const int64_t n = c->n;
+    for (int64_t job = first; job < last; ++job) {
+        const int64_t b = job / c->nk, i = job % c->nk;
+        const int64_t k = c->ks[i];
+        const double *x = c->x + 2 * n * b;
+        double sre = 0.0, sim = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const int64_t m = (j * k) % n;
+            const double xr = x[2 * j], xi = x[2 * j + 1];
+            sre += xr * c->wre[m] - xi * c->wim[m];
+            sim += xr * c->wim[m] + xi * c->wre[m];
+        }
+        c->X[2 * job] = sre;
+        c->X[2 * job + 1] = sim;
+    }
+}
+
+int oracle_dft_bins(const double *x, double *X, int64_t n, int64_t batch, const int64_t *ks,
+                    int64_t nk, int sign, int nthreads)
+{
+    if (!x || !X || !ks || n < 1 || batch < 0 || nk < 0 || (sign != -1 && sign != 1))
+        return -1;
+    for (int64_t i = 0; i < nk; ++i)
+        if (ks[i] < 0 || ks[i] >= n)
+            return -1;
+    double *wre = (double *)malloc(sizeof(double) * (size_t)n);
+    double *wim = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!wre || !wim) {
+        free(wre); free(wim);
+        return -2;
+    }
+    for (int64_t m = 0; m < n; ++m) {
+        const double ang = 2.0 * M_PI * (double)m / (double)n;
+        wre[m] = cos(ang);
+        wim[m] = (double)sign * sin(ang);
+    }
+    bins_ctx ctx = {x, X, wre, wim, ks, n, nk};
+    int rc = run_ranges(bins_range, &ctx, batch * nk, nthreads);
     free(wre); free(wim);
     return rc;
 }

@@ -141,3 +141,40 @@ def test_rel_l2_pins():
     ref = np.array([[3.0 + 4.0j, 0.0]])
     assert oracle.rel_l2(ref, ref)[0] == 0.0
     assert np.isclose(oracle.rel_l2(np.array([[3.0 + 4.0j, 5.0]]), ref)[0], 1.0)
+
+
+# ---------------------------------------------------------------- per-bin DFT
+# Pins of oracle.dft_bins, the check for sizes whose full O(N^2) transform is
+# too slow: closed forms (an impulse at j0 gives exp(-2 pi i j0 k / N) in every
+# bin, a constant gives N at bin 0 and 0 elsewhere), numpy's FFT at a few
+# bins of a large random input, and the direction sign.
+
+def test_dft_bins_closed_forms():
+    n, j0 = 1 << 15, 12345
+    ks = np.array([0, 1, 2, 777, n // 2, n - 1])
+    x = np.zeros((2, n), np.complex128)
+    x[0, j0] = 1.0
+    x[1, :] = 1.0
+    X = oracle.dft_bins(x, ks)
+    assert np.allclose(X[0], np.exp(-2j * np.pi * j0 * ks / n), atol=1e-12)
+    ref = np.where(ks == 0, float(n), 0.0)
+    assert np.allclose(X[1], ref, atol=1e-7)
+
+
+def test_dft_bins_match_numpy_and_direction():
+    n = 1 << 16
+    x = inputs.fft_input(n, 2, seed=5).astype(np.complex128)
+    ks = np.array([0, 3, 4096, 31337, n - 1])
+    X = oracle.dft_bins(x, ks)
+    F = np.fft.fft(x, axis=1)[:, ks]
+    assert np.max(np.abs(X - F)) <= 1e-9 * np.max(np.abs(F))
+    Xi = oracle.dft_bins(x, ks, inverse=True)
+    Fi = np.fft.ifft(x, axis=1)[:, ks] * n
+    assert np.max(np.abs(Xi - Fi)) <= 1e-9 * np.max(np.abs(Fi))
+    # a wrong sign would be caught: forward and inverse differ at these bins
+    assert np.max(np.abs(X - Xi)) > 1.0
+
+
+def test_dft_bins_reject_out_of_range_bins():
+    with pytest.raises(RuntimeError):
+        oracle.dft_bins(np.zeros((1, 16), np.complex64), [16])
