@@ -123,9 +123,73 @@ typedef struct ppx_config {
  * direction = -1 (forward) or +1 (inverse); neither is normalised.  Output is
  * in natural order.  in/out: device pointers to batch*n interleaved complex
  * floats (PPX_C64).  in == out (in place) is allowed; partial overlap is not.
+ * For PPX_MAX_N < n <= PPX_MAX_N_LARGE see fft_batched_large (cfg must then
+ * be NULL).
  */
 int fft_batched(const void *in, void *out, int64_t n, int64_t batch,
                 int direction, const ppx_config *cfg, void *stream);
+
+/*
+ * Large-N FFT (PPX_MAX_N < n <= PPX_MAX_N_LARGE) -- the multi-kernel case of
+ * Sec. IV-A: n = n1 * n2 is transformed by two launches of column FFTs (pass
+ * A over the n2 dimension of the input viewed as n2 rows of n1 columns, with
+ * the twiddles w_n^{j1 k2}, writing the transposed intermediate to `out`;
+ * pass B over the n1 dimension, in place in `out`).  A plan fixes the split
+ * and each pass's radix (= values per thread):
+ *   log2_n1    log2 n1; both passes need a column length in the range their
+ *              radix supports (radix 16: 2^6..2^10, radix 8: 2^5..2^9)
+ *   radix_a    radix of pass A (column length n2 = n / n1)
+ *   radix_b    radix of pass B (column length n1)
+ * Each pass's workgroup transforms 16 adjacent columns, 16 * len / radix
+ * threads.  Tuning the plan (tune_fft_large) is the interdependent
+ * per-kernel search of the paper's learned tuner.
+ */
+#define PPX_MAX_N_LARGE 1048576
+typedef struct ppx_fft_plan {
+    int32_t log2_n1;
+    int32_t radix_a;
+    int32_t radix_b;
+} ppx_fft_plan;
+
+/*
+ * fft_batched_large -- same transform and conventions as fft_batched, for
+ * PPX_MAX_N < n <= PPX_MAX_N_LARGE.  in and out must not overlap at all (out
+ * holds the intermediate between the passes).  plan == NULL: the plan
+ * tune_fft_large recorded for n, else ppx_default_fft_plan.  Errors:
+ * PPX_EINVAL (pointers, n, batch, direction, overlap), PPX_ECONFIG (plan).
+ * fft_batched with such an n and cfg == NULL forwards here.
+ */
+int fft_batched_large(const void *in, void *out, int64_t n, int64_t batch, int direction,
+                      const ppx_fft_plan *plan, void *stream);
+
+/* PPX_OK if plan is valid for n, else PPX_ECONFIG (reason in ppx_last_error()). */
+int ppx_fft_plan_valid(int64_t n, const ppx_fft_plan *plan);
+
+/*
+ * Every valid plan for n, ordered by log2_n1, then radix_a, then radix_b:
+ * writes min(count, cap) plans to out (out may be NULL when cap == 0) and
+ * returns the count, or a negative PPX_E* code.
+ */
+int ppx_enumerate_fft_plans(int64_t n, ppx_fft_plan *out, int cap);
+
+/*
+ * The untuned plan: the most even split (n1 <= n2) with radix 8 in both
+ * passes where valid.  The analytical plan (tune_fft_large with
+ * PPX_TUNE_ANALYTICAL) is the gfx950 occupancy guideline applied per pass.
+ */
+int ppx_default_fft_plan(int64_t n, ppx_fft_plan *out);
+
+/*
+ * tune_fft_large -- tune() for the large-N FFT: the candidates are the valid
+ * plans for n, timed as whole two-pass calls (median of 100 after warm-ups,
+ * rotating buffer sets as in tune()).  EXHAUSTIVE times every plan, LEARNED
+ * runs the Bayesian search over the plan features (log2 n1, log2 radix_a,
+ * log2 radix_b), ANALYTICAL applies the occupancy guideline to each pass's
+ * kernel separately over its radix choices and takes the most even split.
+ * The winner is recorded for fft_batched_large(plan == NULL).
+ */
+int tune_fft_large(int64_t n, int64_t batch, int method, int max_evals, ppx_fft_plan *best,
+                   double *best_us, int *evals_used);
 
 /*
  * scan_batched -- Sec. III ("Scan Operator"): inclusive sum scan,

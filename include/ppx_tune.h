@@ -148,6 +148,16 @@ typedef struct ppx_tune_report {
 int ppx_tune_ex(int op, int dtype, int64_t n, int64_t batch, int method, int max_evals,
                 int algo, int reps, ppx_tune_report *report);
 
+/*
+ * ppx_tune_large_trace -- tune_fft_large with `reps` timed launches per plan
+ * (<= 0: 100) and the timed plans in evaluation order: up to trace_cap
+ * entries of trace_plan / trace_us (either may be NULL).  Returns the number
+ * of timed plans (>= 0) or a negative PPX_E* code.  Needs a GPU.
+ */
+int ppx_tune_large_trace(int64_t n, int64_t batch, int method, int max_evals, int reps, ppx_fft_plan *best,
+                         double *best_us, int *evals_used, ppx_fft_plan *trace_plan, double *trace_us,
+                         int trace_cap);
+
 /* Median microseconds of `reps` launches of one explicit configuration, timed
  * like a tuning candidate (the default-vs-tuned baseline uses this). */
 int ppx_time_config(int op, int dtype, int64_t n, int64_t batch, const ppx_config *cfg,

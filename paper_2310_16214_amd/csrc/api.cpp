@@ -1,6 +1,7 @@
 // Exported C entry points of libppx.so: argument validation (before any HIP
 // runtime call), configuration resolution and kernel dispatch, plus the
 // per-device state (limits, twiddle table) and thread-local error messages.
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -88,6 +89,19 @@ const DeviceInfo *device_info() {
         return nullptr;
     }
     di->twiddles = dtw;
+    std::vector<float> lo(2 * 1024), hi(2 * 1024);
+    fft_large_host_twiddles(lo.data(), hi.data());
+    void *dlo = nullptr, *dhi = nullptr;
+    if (hipMalloc(&dlo, lo.size() * sizeof(float)) != hipSuccess ||
+        hipMalloc(&dhi, hi.size() * sizeof(float)) != hipSuccess ||
+        hipMemcpy(dlo, lo.data(), lo.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dhi, hi.data(), hi.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        fail(PPX_ENOMEM, "could not create the large-FFT twiddle tables");
+        delete di;
+        return nullptr;
+    }
+    di->twiddles_large_lo = dlo;
+    di->twiddles_large_hi = dhi;
     if ((int)g_devices.size() <= dev) g_devices.resize(dev + 1, nullptr);
     g_devices[dev] = di;
     g_any_device = true;
@@ -135,6 +149,10 @@ const char *ppx_last_error(void) { return t_err.c_str(); }
 int fft_batched(const void *in, void *out, int64_t n, int64_t batch, int direction,
                 const ppx_config *cfg, void *stream) {
     t_err.clear();
+    if (is_pow2(n) && n > PPX_MAX_N && n <= PPX_MAX_N_LARGE) {
+        if (cfg) return fail(PPX_EINVAL, "n > 16384 takes a plan (fft_batched_large), not a ppx_config");
+        return fft_batched_large(in, out, n, batch, direction, nullptr, stream);
+    }
     if (!in || !out) return fail(PPX_EINVAL, "null pointer");
     if (!aligned16(in) || !aligned16(out)) return fail(PPX_EINVAL, "pointers must be 16-byte aligned");
     if (direction != -1 && direction != 1) return fail(PPX_EINVAL, "direction must be -1 or +1");
@@ -146,6 +164,55 @@ int fft_batched(const void *in, void *out, int64_t n, int64_t batch, int directi
     if ((batch + c.problems_per_block - 1) / c.problems_per_block > INT32_MAX)
         return fail(PPX_EINVAL, "too many workgroups");
     return launch_fft(in, out, ilog2(n), batch, c, direction == 1, static_cast<hipStream_t>(stream));
+}
+
+int fft_batched_large(const void *in, void *out, int64_t n, int64_t batch, int direction,
+                      const ppx_fft_plan *plan, void *stream) {
+    t_err.clear();
+    if (!in || !out) return fail(PPX_EINVAL, "null pointer");
+    if (!aligned16(in) || !aligned16(out)) return fail(PPX_EINVAL, "pointers must be 16-byte aligned");
+    if (direction != -1 && direction != 1) return fail(PPX_EINVAL, "direction must be -1 or +1");
+    if (!is_pow2(n) || n <= PPX_MAX_N || n > PPX_MAX_N_LARGE)
+        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 1048576]");
+    if (batch < 1) return fail(PPX_EINVAL, "batch must be >= 1");
+    if (batch > (int64_t(1) << 40) / n) return fail(PPX_EINVAL, "batch * n is too large");
+    const int64_t bytes = batch * n * 8;
+    const char *pi = static_cast<const char *>(in), *po = static_cast<const char *>(out);
+    if (pi < po + bytes && po < pi + bytes)
+        return fail(PPX_EINVAL, "large FFT: in and out must not overlap (out holds the intermediate)");
+    ppx_fft_plan p;
+    if (plan) p = *plan;
+    else if (!fft_tuned_plan(n, p)) fft_default_plan(n, p);
+    int rc = fft_plan_check(n, p);
+    if (rc) return rc;
+    if (batch * (std::max<int64_t>(int64_t(1) << p.log2_n1, n >> p.log2_n1) / 16) > INT32_MAX)
+        return fail(PPX_EINVAL, "too many workgroups");
+    return launch_fft_large(in, out, ilog2(n), batch, p, direction == 1, static_cast<hipStream_t>(stream));
+}
+
+int ppx_fft_plan_valid(int64_t n, const ppx_fft_plan *plan) {
+    t_err.clear();
+    if (!plan) return fail(PPX_EINVAL, "null plan");
+    return fft_plan_check(n, *plan);
+}
+
+int ppx_enumerate_fft_plans(int64_t n, ppx_fft_plan *out, int cap) {
+    t_err.clear();
+    if (!is_pow2(n) || n <= PPX_MAX_N || n > PPX_MAX_N_LARGE)
+        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 1048576]");
+    if (cap < 0 || (cap > 0 && !out)) return fail(PPX_EINVAL, "bad output buffer");
+    const std::vector<ppx_fft_plan> all = fft_enumerate_plans(n);
+    for (int i = 0; i < cap && i < (int)all.size(); ++i) out[i] = all[i];
+    return (int)all.size();
+}
+
+int ppx_default_fft_plan(int64_t n, ppx_fft_plan *out) {
+    t_err.clear();
+    if (!out) return fail(PPX_EINVAL, "null plan");
+    if (!is_pow2(n) || n <= PPX_MAX_N || n > PPX_MAX_N_LARGE)
+        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 1048576]");
+    fft_default_plan(n, *out);
+    return PPX_OK;
 }
 
 int scan_batched(const void *in, void *out, int64_t n, int64_t batch, int dtype,

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/ppx.h"
 
@@ -35,6 +36,9 @@ struct DeviceInfo {
     int64_t l2_bytes = 0;
     std::string arch;
     const void *twiddles = nullptr;  // device table w[m] = exp(-2 pi i m/NMAX)
+    // large-N tables: w_{2^20}^j and w_{2^20}^{1024 j}, j < 1024
+    const void *twiddles_large_lo = nullptr;
+    const void *twiddles_large_hi = nullptr;
 };
 
 // Returns the cached info for the current device, initialising it (and the
@@ -105,6 +109,19 @@ const void *tridiag_kernel(int dtype, int algo, int P);
 // Builds the forward twiddle table for NMAX = 2^kFftLog2NMax in host memory
 // (float pairs from double-precision sincos).
 void fft_host_twiddles(float *out2);
+
+// ---- large-N FFT (fft_large.hip) ----
+void fft_large_host_twiddles(float *lo2, float *hi2);  // 1024 pairs each
+const void *fft_tile_kernel(int radix, int log2len, bool pass_a);
+bool fft_tile_shape_valid(int radix, int log2len);  // a pass of column length 2^log2len
+int64_t fft_tile_lds_bytes(int log2len);
+int launch_fft_large(const void *in, void *out, int log2n, int64_t batch, const ppx_fft_plan &p, bool inverse,
+                     hipStream_t s);
+int fft_plan_check(int64_t n, const ppx_fft_plan &p);  // PPX_OK or a failure with reason
+void fft_default_plan(int64_t n, ppx_fft_plan &p);
+std::vector<ppx_fft_plan> fft_enumerate_plans(int64_t n);
+bool fft_tuned_plan(int64_t n, ppx_fft_plan &p);
+void fft_record_plan(int64_t n, const ppx_fft_plan &p);
 
 // ---- mixed launch (fused.hip) ----
 int check_job(const ppx_job &j);

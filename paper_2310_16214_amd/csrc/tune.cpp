@@ -328,7 +328,37 @@ static double expected_improvement(double mu, double sigma, double best) {
 // GP inputs: log2 radix, log2 L, log2 G_b, and one indicator per algorithm
 // variant present among the candidates (the variants are categories, not an
 // ordered scale); each column scaled to [0, 1].
+// Large-FFT plans are timed and searched as configurations tagged with
+// kLargePlanAlgo: radix = radix_a, elems_per_thread = radix_b,
+// threads_per_block = n1.  Their GP inputs are log2 radix_a, log2 n1 and
+// log2 radix_b.
+constexpr int kLargePlanAlgo = 0x40;
+static ppx_config plan_to_config(const ppx_fft_plan &p) {
+    return ppx_config{p.radix_a, p.radix_b, 1 << p.log2_n1, 1, 0, kLargePlanAlgo};
+}
+static ppx_fft_plan config_to_plan(const ppx_config &c) {
+    return ppx_fft_plan{ilog2(c.threads_per_block), c.radix, c.elems_per_thread};
+}
+
 static void features(const ppx_config *c, int n, std::vector<double> &F, int &d) {
+    if (n > 0 && c[0].algo == kLargePlanAlgo) {
+        d = 3;
+        F.assign((size_t)n * d, 0.0);
+        for (int i = 0; i < n; ++i) {
+            F[i * d + 0] = std::log2((double)c[i].radix);
+            F[i * d + 1] = std::log2((double)c[i].threads_per_block);
+            F[i * d + 2] = std::log2((double)c[i].elems_per_thread);
+        }
+        for (int k = 0; k < d; ++k) {
+            double lo = 1e300, hi = -1e300;
+            for (int i = 0; i < n; ++i) {
+                lo = std::min(lo, F[i * d + k]);
+                hi = std::max(hi, F[i * d + k]);
+            }
+            for (int i = 0; i < n; ++i) F[i * d + k] = hi > lo ? (F[i * d + k] - lo) / (hi - lo) : 0.0;
+        }
+        return;
+    }
     std::vector<int> algos;
     for (int i = 0; i < n; ++i)
         if (std::find(algos.begin(), algos.end(), c[i].algo) == algos.end()) algos.push_back(c[i].algo);
@@ -744,6 +774,8 @@ struct Bench {
     int launch(const ppx_config &c, int set) {
         auto &b = sets[set % sets.size()];
         const int ln = ilog2(n);
+        if (op == PPX_OP_FFT && c.algo == kLargePlanAlgo)
+            return launch_fft_large(b[0], b[1], ln, batch, config_to_plan(c), false, stream);
         if (op == PPX_OP_FFT) return launch_fft(b[0], b[1], ln, batch, c, false, stream);
         if (op == PPX_OP_SCAN) return launch_scan(b[0], b[1], ln, batch, dtype, c, stream);
         return launch_tridiag(b[0], b[1], b[2], b[3], b[4], ln, batch, dtype, c, stream);
@@ -872,6 +904,99 @@ static int tune_impl(int op, int dtype, int64_t n, int64_t batch, int method, in
 }  // namespace ppx
 
 using namespace ppx;
+
+// The analytical plan: the most even split (as the default plan), and for
+// each pass the radix that the occupancy guideline picks among the tile
+// kernels valid for its column length.
+static int analytical_plan(int64_t n, int64_t batch, ppx_fft_plan &out) {
+    fft_default_plan(n, out);
+    if (!out.log2_n1) return fail(PPX_ECONFIG, "no valid plan");
+    const ppx_device_model m = gfx950_model();
+    const int ln = ilog2(n);
+    for (int pass = 0; pass < 2; ++pass) {
+        const int l = pass == 0 ? ln - out.log2_n1 : out.log2_n1;      // column length
+        const int64_t groups = batch * ((int64_t(1) << (ln - l)) / 16);  // workgroups of the pass
+        std::vector<ppx_config> c;
+        std::vector<ppx_resource> r;
+        for (int radix : {8, 16}) {
+            if (!fft_tile_shape_valid(radix, l)) continue;
+            const int threads = 16 * ((1 << l) / radix);
+            hipFuncAttributes a;
+            if (hipFuncGetAttributes(&a, fft_tile_kernel(radix, l, pass == 0)) != hipSuccess)
+                return fail(PPX_EHIP, "hipFuncGetAttributes failed");
+            c.push_back(ppx_config{radix, radix, threads, 1, 0, 0});
+            r.push_back(ppx_resource{threads, a.numRegs, (int32_t)(fft_tile_lds_bytes(l) + a.sharedSizeBytes)});
+        }
+        const int k = analytical_pick_impl(m, c.data(), r.data(), (int)c.size(), groups,
+                                           PPX_ANALYTICAL_GRID_FILL | PPX_ANALYTICAL_WINDOW_50);
+        if (k < 0) return fail(PPX_ECONFIG, "no pass kernel fits a CU");
+        (pass == 0 ? out.radix_a : out.radix_b) = c[k].radix;
+    }
+    return PPX_OK;
+}
+
+static int tune_large_impl(int64_t n, int64_t batch, int method, int max_evals, int reps, ppx_fft_plan *best_out,
+                           double *best_us_out, int *evals_out, std::vector<std::pair<ppx_config, double>> *trace_out) {
+    if (method < PPX_TUNE_EXHAUSTIVE || method > PPX_TUNE_LEARNED) return fail(PPX_EINVAL, "unknown tuning method");
+    if (!is_pow2(n) || n <= PPX_MAX_N || n > PPX_MAX_N_LARGE)
+        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 1048576]");
+    if (batch < 1) return fail(PPX_EINVAL, "batch must be >= 1");
+    if (reps <= 0) reps = 100;
+    std::vector<ppx_config> cands;
+    for (const auto &p : fft_enumerate_plans(n)) cands.push_back(plan_to_config(p));
+    if (cands.empty()) return fail(PPX_ECONFIG, "no valid plan to tune");
+    if (!device_info()) return PPX_EDEVICE;
+    Bench bench;
+    bench.op = PPX_OP_FFT;
+    bench.dtype = PPX_C64;
+    bench.n = n;
+    bench.batch = batch;
+    int rc = bench.init(reps);
+    if (rc) return rc;
+    std::vector<std::pair<ppx_config, double>> trace;
+    EvalCtx ctx{&bench, reps, &trace};
+    const int nc = (int)cands.size();
+    int best = -1;
+    if (method == PPX_TUNE_EXHAUSTIVE) {
+        double bv = 1e300;
+        const int lim = max_evals > 0 ? std::min(max_evals, nc) : nc;
+        for (int i = 0; i < lim; ++i) {
+            const double v = eval_gpu(&cands[i], &ctx);
+            if (v >= 0 && v < bv) {
+                bv = v;
+                best = i;
+            }
+        }
+    } else if (method == PPX_TUNE_ANALYTICAL) {
+        ppx_fft_plan p;
+        if ((rc = analytical_plan(n, batch, p))) return rc;
+        const ppx_config pc = plan_to_config(p);
+        for (int i = 0; i < nc; ++i)
+            if (std::memcmp(&cands[i], &pc, sizeof(ppx_config)) == 0) best = i;
+        if (best >= 0) eval_gpu(&cands[best], &ctx);  // timed once, for the report
+    } else {
+        std::vector<int> order(nc);
+        std::vector<double> vals(nc);
+        int used = 0;
+        rc = bo_search_impl(cands.data(), nc, eval_gpu, &ctx, max_evals, 0, 5, 0.01, 0x2310'16214ULL,
+                            order.data(), vals.data(), &used, &best);
+        if (rc) return rc;
+    }
+    if (best < 0) return fail(PPX_ETIMEOUT, "no plan ran successfully");
+    double best_us = -1;
+    for (auto it = trace.rbegin(); it != trace.rend(); ++it)
+        if (std::memcmp(&it->first, &cands[best], sizeof(ppx_config)) == 0) {
+            best_us = it->second;
+            break;
+        }
+    *best_out = config_to_plan(cands[best]);
+    if (best_us_out) *best_us_out = best_us;
+    if (evals_out) *evals_out = method == PPX_TUNE_ANALYTICAL ? 0 : (int)trace.size();
+    if (trace_out) *trace_out = trace;
+    fft_record_plan(n, *best_out);
+    fail(PPX_OK, "");
+    return PPX_OK;
+}
 
 extern "C" {
 
@@ -1021,6 +1146,25 @@ int ppx_tune_cache_clear(void) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     g_cache.clear();
     return PPX_OK;
+}
+
+int tune_fft_large(int64_t n, int64_t batch, int method, int max_evals, ppx_fft_plan *best, double *best_us,
+                   int *evals_used) {
+    if (!best) return fail(PPX_EINVAL, "null plan");
+    return tune_large_impl(n, batch, method, max_evals, 100, best, best_us, evals_used, nullptr);
+}
+
+int ppx_tune_large_trace(int64_t n, int64_t batch, int method, int max_evals, int reps, ppx_fft_plan *best,
+                         double *best_us, int *evals_used, ppx_fft_plan *trace_plan, double *trace_us, int trace_cap) {
+    if (!best) return fail(PPX_EINVAL, "null plan");
+    std::vector<std::pair<ppx_config, double>> trace;
+    const int rc = tune_large_impl(n, batch, method, max_evals, reps, best, best_us, evals_used, &trace);
+    if (rc) return rc;
+    for (int i = 0; i < (int)trace.size() && i < trace_cap; ++i) {
+        if (trace_plan) trace_plan[i] = config_to_plan(trace[i].first);
+        if (trace_us) trace_us[i] = trace[i].second;
+    }
+    return (int)trace.size();
 }
 
 int ppx_tuned_config(int op, int dtype, int64_t n, int algo, ppx_config *out) {

@@ -230,7 +230,31 @@ class TuneReport(ctypes.Structure):
 EVAL_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(Config), ctypes.c_void_p)
 ANALYTICAL_GRID_FILL, ANALYTICAL_WINDOW_50 = 1, 4
 
+class FftPlan(ctypes.Structure):
+    """ppx_fft_plan: (log2 n1, radix of pass A, radix of pass B)."""
+    _fields_ = [("log2_n1", ctypes.c_int32), ("radix_a", ctypes.c_int32), ("radix_b", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.log2_n1, self.radix_a, self.radix_b)
+
+    def __repr__(self):
+        return "FftPlan(log2_n1=%d, radix_a=%d, radix_b=%d)" % self.as_tuple()
+
+
+MAX_N = 16384
+MAX_N_LARGE = 1 << 20
+
 _tune_sigs = {
+    "fft_batched_large": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                           ctypes.POINTER(FftPlan), ctypes.c_void_p], ctypes.c_int),
+    "ppx_fft_plan_valid": ([ctypes.c_int64, ctypes.POINTER(FftPlan)], ctypes.c_int),
+    "ppx_enumerate_fft_plans": ([ctypes.c_int64, ctypes.POINTER(FftPlan), ctypes.c_int], ctypes.c_int),
+    "ppx_default_fft_plan": ([ctypes.c_int64, ctypes.POINTER(FftPlan)], ctypes.c_int),
+    "tune_fft_large": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(FftPlan),
+                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "ppx_tune_large_trace": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.POINTER(FftPlan), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(FftPlan), ctypes.POINTER(ctypes.c_double), ctypes.c_int], ctypes.c_int),
     "ppx_occupancy": ([ctypes.POINTER(DeviceModel), ctypes.POINTER(Resource),
                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "ppx_device_model_gfx950": ([ctypes.POINTER(DeviceModel)], ctypes.c_int),
@@ -271,6 +295,49 @@ def _tl(name):
         f.argtypes, f.restype = _tune_sigs[name]
         f._ppx_typed = True
     return f
+
+
+def fft_batched_large(inp, out, n, batch, direction=-1, plan=None, stream=None):
+    """Two-pass FFT for 16384 < n <= 2^20 (see include/ppx.h); in and out must
+    not overlap."""
+    _check(_tl("fft_batched_large")(_ptr(inp), _ptr(out), n, batch, direction,
+                                    ctypes.byref(plan) if plan is not None else None,
+                                    _stream(stream, inp, out)))
+
+
+def make_plan(log2_n1, radix_a, radix_b):
+    return FftPlan(log2_n1, radix_a, radix_b)
+
+
+def fft_plan_valid(n, plan) -> bool:
+    return _tl("ppx_fft_plan_valid")(n, ctypes.byref(plan)) == 0
+
+
+def enumerate_fft_plans(n):
+    f = _tl("ppx_enumerate_fft_plans")
+    cnt = _check(f(n, None, 0))
+    arr = (FftPlan * max(cnt, 1))()
+    _check(f(n, arr, cnt))
+    return [FftPlan(*arr[i].as_tuple()) for i in range(cnt)]
+
+
+def default_fft_plan(n):
+    p = FftPlan()
+    _check(_tl("ppx_default_fft_plan")(n, ctypes.byref(p)))
+    return p
+
+
+def tune_fft_large(n, batch, method, max_evals=0, reps=100, trace_cap=64):
+    """Returns (plan, best_us, evals_used, [(plan, us) timed in order])."""
+    best = FftPlan()
+    us = ctypes.c_double(0.0)
+    ev = ctypes.c_int(0)
+    tp = (FftPlan * trace_cap)()
+    tu = (ctypes.c_double * trace_cap)()
+    cnt = _check(_tl("ppx_tune_large_trace")(n, batch, method, max_evals, reps, ctypes.byref(best),
+                                              ctypes.byref(us), ctypes.byref(ev), tp, tu, trace_cap))
+    trace = [(FftPlan(*tp[i].as_tuple()), tu[i]) for i in range(min(cnt, trace_cap))]
+    return best, us.value, ev.value, trace
 
 
 def occupancy(model, res):

@@ -29,7 +29,7 @@ BUF = 4096  # a fake, 16-byte aligned "device" address: never dereferenced
     ((BUF + 4, BUF, 1024, 1, -1), "aligned"),
     ((BUF, BUF, 1000, 1, -1), "power of two"),
     ((BUF, BUF, 8, 1, -1), "power of two"),
-    ((BUF, BUF, 32768, 1, -1), "power of two"),
+    ((BUF, BUF, 1 << 21, 1, -1), "power of two"),
     ((BUF, BUF, 1024, 0, -1), "batch"),
     ((BUF, BUF, 1024, 1, 0), "direction"),
     ((BUF, BUF + 16, 1024, 4, -1), "overlap"),
@@ -37,6 +37,59 @@ BUF = 4096  # a fake, 16-byte aligned "device" address: never dereferenced
 def test_fft_argument_errors(args, msg):
     rc, err = _rc(lambda: L.fft_batched(*args, None, None))
     assert rc == ppx.EINVAL and msg in err
+
+
+# ------------------------------------------------------------ large-N FFT
+
+@pytest.mark.parametrize("args,msg", [
+    ((0, BUF, 1 << 16, 1, -1), "null"),
+    ((BUF + 8, 1 << 30, 1 << 16, 1, -1), "aligned"),
+    ((BUF, 1 << 30, 1 << 14, 1, -1), "power of two"),
+    ((BUF, 1 << 30, 1 << 21, 1, -1), "power of two"),
+    ((BUF, 1 << 30, 3 << 15, 1, -1), "power of two"),
+    ((BUF, 1 << 30, 1 << 16, 0, -1), "batch"),
+    ((BUF, 1 << 30, 1 << 16, 1, 2), "direction"),
+    ((BUF, BUF, 1 << 16, 1, -1), "overlap"),
+    ((BUF, BUF + (1 << 19), 1 << 16, 2, -1), "overlap"),
+])
+def test_fft_large_argument_errors(args, msg):
+    rc, err = _rc(lambda: ppx._tl("fft_batched_large")(*args, None, None))
+    assert rc == ppx.EINVAL and msg in err, err
+
+
+def test_fft_batched_forwards_large_n_and_rejects_a_config():
+    # the large path checks its own arguments: in == out is refused
+    rc, err = _rc(lambda: L.fft_batched(BUF, BUF, 1 << 16, 1, -1, None, None))
+    assert rc == ppx.EINVAL and "overlap" in err
+    cfg = ppx.make_config(16, 1024, 1)
+    rc, err = _rc(lambda: L.fft_batched(BUF, 1 << 30, 1 << 16, 1, -1, ctypes.byref(cfg), None))
+    assert rc == ppx.EINVAL and "plan" in err
+
+
+def test_fft_plans():
+    for ln in range(15, 21):
+        n = 1 << ln
+        plans = ppx.enumerate_fft_plans(n)
+        assert plans, n
+        for p in plans:
+            assert ppx.fft_plan_valid(n, p)
+            l2 = ln - p.log2_n1
+            for radix, length in ((p.radix_a, l2), (p.radix_b, p.log2_n1)):
+                lo, hi = (6, 10) if radix == 16 else (5, 9)
+                assert lo <= length <= hi and radix in (8, 16)
+        keys = [p.as_tuple() for p in plans]
+        assert keys == sorted(keys) and len(set(keys)) == len(keys)
+        d = ppx.default_fft_plan(n)
+        assert d.as_tuple() in keys
+        assert d.log2_n1 <= ln - d.log2_n1  # n1 <= n2, the most even such split
+        assert not any(q[0] > d.log2_n1 and q[0] <= ln - q[0] for q in keys)
+    assert [p.as_tuple() for p in ppx.enumerate_fft_plans(1 << 20)] == [(10, 16, 16)]
+    assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 4, 16))      # radix 4
+    assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(11, 16, 16))    # n1 = 2048 too long
+    assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(6, 8, 16))      # n2 = 1024 with radix 8
+    assert not ppx.fft_plan_valid(1 << 14, ppx.make_plan(7, 16, 16))     # not a large size
+    with pytest.raises(ppx.PpxError):
+        ppx.enumerate_fft_plans(1 << 14)
 
 
 def test_scan_and_tridiag_argument_errors():
