@@ -140,15 +140,21 @@ int fft_batched(const void *in, void *out, int64_t n, int64_t batch,
  *              radix supports (radix 16: 2^6..2^10, radix 8: 2^5..2^9)
  *   radix_a    radix of pass A (column length n2 = n / n1)
  *   radix_b    radix of pass B (column length n1)
- * Each pass's workgroup transforms 16 adjacent columns, 16 * len / radix
- * threads.  Tuning the plan (tune_fft_large) is the interdependent
- * per-kernel search of the paper's learned tuner.
+ *   tile_a     columns per workgroup of pass A (16, 32 or 64)
+ *   tile_b     columns per workgroup of pass B (16, 32 or 64)
+ * A pass's workgroup transforms tile adjacent columns of length len with
+ * tile * len / radix threads (64..1024) and tile * (len + 1) complex values
+ * of LDS (<= 160 KiB); the tile must divide the pass's column count (n1 for
+ * pass A, n2 for pass B).  Tuning the plan (tune_fft_large) is the
+ * interdependent per-kernel search of the paper's learned tuner.
  */
 #define PPX_MAX_N_LARGE 1048576
 typedef struct ppx_fft_plan {
     int32_t log2_n1;
     int32_t radix_a;
     int32_t radix_b;
+    int32_t tile_a;
+    int32_t tile_b;
 } ppx_fft_plan;
 
 /*
@@ -166,7 +172,7 @@ int fft_batched_large(const void *in, void *out, int64_t n, int64_t batch, int d
 int ppx_fft_plan_valid(int64_t n, const ppx_fft_plan *plan);
 
 /*
- * Every valid plan for n, ordered by log2_n1, then radix_a, then radix_b:
+ * Every valid plan for n, ordered by log2_n1, radix_a, radix_b, tile_a, tile_b:
  * writes min(count, cap) plans to out (out may be NULL when cap == 0) and
  * returns the count, or a negative PPX_E* code.
  */
@@ -174,7 +180,7 @@ int ppx_enumerate_fft_plans(int64_t n, ppx_fft_plan *out, int cap);
 
 /*
  * The untuned plan: the most even split (n1 <= n2) with radix 8 in both
- * passes where valid.  The analytical plan (tune_fft_large with
+ * passes where valid and 16-column tiles.  The analytical plan (tune_fft_large with
  * PPX_TUNE_ANALYTICAL) is the gfx950 occupancy guideline applied per pass.
  */
 int ppx_default_fft_plan(int64_t n, ppx_fft_plan *out);
@@ -183,9 +189,10 @@ int ppx_default_fft_plan(int64_t n, ppx_fft_plan *out);
  * tune_fft_large -- tune() for the large-N FFT: the candidates are the valid
  * plans for n, timed as whole two-pass calls (median of 100 after warm-ups,
  * rotating buffer sets as in tune()).  EXHAUSTIVE times every plan, LEARNED
- * runs the Bayesian search over the plan features (log2 n1, log2 radix_a,
- * log2 radix_b), ANALYTICAL applies the occupancy guideline to each pass's
- * kernel separately over its radix choices and takes the most even split.
+ * runs the Bayesian search over the plan features (log2 of n1, both radices
+ * and both tile widths), ANALYTICAL applies the occupancy guideline to each
+ * pass's kernels separately over its (radix, tile) choices and takes the
+ * most even split.
  * The winner is recorded for fft_batched_large(plan == NULL).
  */
 int tune_fft_large(int64_t n, int64_t batch, int method, int max_evals, ppx_fft_plan *best,

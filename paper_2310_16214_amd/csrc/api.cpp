@@ -185,7 +185,7 @@ int fft_batched_large(const void *in, void *out, int64_t n, int64_t batch, int d
     else if (!fft_tuned_plan(n, p)) fft_default_plan(n, p);
     int rc = fft_plan_check(n, p);
     if (rc) return rc;
-    if (batch * (std::max<int64_t>(int64_t(1) << p.log2_n1, n >> p.log2_n1) / 16) > INT32_MAX)
+    if (batch * std::max<int64_t>((int64_t(1) << p.log2_n1) / p.tile_a, (n >> p.log2_n1) / p.tile_b) > INT32_MAX)
         return fail(PPX_EINVAL, "too many workgroups");
     return launch_fft_large(in, out, ilog2(n), batch, p, direction == 1, static_cast<hipStream_t>(stream));
 }

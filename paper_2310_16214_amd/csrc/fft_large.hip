@@ -11,17 +11,19 @@
 // where it lies.  So the output buffer holds Z and no workspace is needed,
 // but the input must be a different buffer.
 //
-// A workgroup takes a tile of kTileCols = 16 adjacent columns: it reads them
-// row by row (16 lanes on 16 consecutive values, 128-byte runs) into LDS,
+// A workgroup takes a tile of TC = 16, 32 or 64 adjacent columns (a plan
+// parameter per pass): it reads them row by row (TC lanes on TC consecutive
+// values, runs of 128 to 512 bytes) into LDS,
 // transforms the 16 columns with the single-pass stage code (radix R = P,
 // T = len/P threads per column, exchanges in LDS), and writes the tile back
 // the same way (pass B) or row by row (pass A, 512-byte runs per wave).  The
-// LDS tile pads each column to len + 1 values, so that the 16 values a row
+// LDS tile pads each column to len + 1 values, so that the TC values a row
 // read or write touches fall on different banks.
 //
 // The pass-A twiddles w_n^m (m < n <= 2^20) are the product of two table
 // entries, w_{2^20}^{m' mod 1024} * w_{2^20}^{1024 (m' div 1024)} with
-// m' = m * 2^20 / n: 2 x 1024 values built on the host in double precision.
+// m' = m * 2^20 / n: 2 x 1024 values built on the host in double precision,
+// copied into LDS by every pass-A workgroup.
 #include "fft_device.h"
 
 #include <map>
@@ -29,11 +31,16 @@
 
 namespace ppx {
 
-constexpr int kTileCols = 16;
-
 __device__ __forceinline__ int tile_slot(int c, int e, int len) { return swz_c(c * (len + 1) + e); }
 
-template <int R, int LOG2LEN, bool PASS_A>
+__device__ __forceinline__ int tw_swz(int j) { return j ^ ((j >> 5) & 31); }
+
+// float2 slots of a tile: TC padded columns, rounded up to whole 256-value
+// blocks (the swizzle permutes within aligned blocks of 256)
+__host__ __device__ constexpr int tile_vals(int log2len, int tc) { return (tc * ((1 << log2len) + 1) + 255) / 256 * 256; }
+
+// TC: columns per tile (16, 32 or 64: runs of 128, 256 or 512 bytes)
+template <int R, int LOG2LEN, bool PASS_A, int TC>
 __global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out, const float2 *__restrict__ tw,
                                                     const float2 *__restrict__ tw_lo,
                                                     const float2 *__restrict__ tw_hi, int log2n,
@@ -42,14 +49,28 @@ __global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out
     constexpr int P = R;
     constexpr int lT = LOG2LEN - clog2(P);
     constexpr int T = 1 << lT;
+    constexpr int LTC = clog2(TC);
     extern __shared__ float4 lds_raw[];
     float2 *buf = reinterpret_cast<float2 *>(lds_raw);
     const long long prob = blockIdx.x / tiles;
-    const int c0 = (int)(blockIdx.x % tiles) * kTileCols;
+    const int c0 = (int)(blockIdx.x % tiles) * TC;
     const long long base = prob << log2n;
     const long long cols = 1LL << log2cols;
-    for (int i = threadIdx.x; i < len * kTileCols; i += blockDim.x) {
-        const int c = i & (kTileCols - 1), e = i >> 4;
+    // pass A: both twiddle tables in LDS after the tile.  Read from global
+    // memory in the store loop, each table read would wait for the stores
+    // issued before it (vector memory operations complete in issue order).
+    // The lanes of the store loop read the low table at a stride of (column
+    // index) * n / 2^20 entries, often a multiple of 32; the tables are
+    // stored XOR-swizzled (bits 5..9 into 0..4) so that such strides spread
+    // over the banks.
+    float2 *tlo = buf + tile_vals(LOG2LEN, TC), *thi = tlo + 1024;
+    if constexpr (PASS_A)
+        for (int j = threadIdx.x; j < 1024; j += blockDim.x) {
+            tlo[tw_swz(j)] = tw_lo[j];
+            thi[tw_swz(j)] = tw_hi[j];
+        }
+    for (int i = threadIdx.x; i < len * TC; i += blockDim.x) {
+        const int c = i & (TC - 1), e = i >> LTC;
         buf[tile_slot(c, e, len)] = in[base + e * cols + c0 + c];
     }
     __syncthreads();
@@ -63,16 +84,29 @@ __global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out
     fft_stages_ct<R, P, false, LOG2LEN, 0, true>(v, buf, lp * (len + 1), nullptr, tid, true, sgn, tw);
     __syncthreads();
     if constexpr (PASS_A) {
+        // The workgroup has len * TC / R threads, so thread t stores element
+        // e = t mod len of columns ct + k * CS (ct = t div len, CS = TC / R,
+        // k < R): its twiddles w^{(c0 + c) e} form a geometric sequence with
+        // ratio w^{CS e}, started and stepped from the tables (R - 1 products,
+        // so a few ulp of drift at most).
+        constexpr int CS = TC / R;
         const int shift = 20 - log2n;
-        for (int i = threadIdx.x; i < len * kTileCols; i += blockDim.x) {
-            const int e = i & (len - 1), c = i >> LOG2LEN;
-            const unsigned m = ((unsigned)(c0 + c) * (unsigned)e) << shift;  // < 2^20
-            const float2 w = cmul(tw_lo[m & 1023u], tw_hi[m >> 10]);
+        auto table_tw = [&](unsigned m) {  // w_n^m for m < n
+            const unsigned q = m << shift;  // < 2^20
+            return cmul(tlo[tw_swz((int)(q & 1023u))], thi[tw_swz((int)(q >> 10))]);
+        };
+        const int e = threadIdx.x & (len - 1), ct = threadIdx.x >> LOG2LEN;
+        float2 w = table_tw((unsigned)(c0 + ct) * (unsigned)e);
+        const float2 step = table_tw((unsigned)CS * (unsigned)e);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int c = ct + k * CS;
             store_nt_any(out + base + (long long)(c0 + c) * len + e, cmul(buf[tile_slot(c, e, len)], w));
+            w = cmul(w, step);
         }
     } else {
-        for (int i = threadIdx.x; i < len * kTileCols; i += blockDim.x) {
-            const int c = i & (kTileCols - 1), e = i >> 4;
+        for (int i = threadIdx.x; i < len * TC; i += blockDim.x) {
+            const int c = i & (TC - 1), e = i >> LTC;
             const float2 y = buf[tile_slot(c, e, len)];
             store_nt_any(out + base + e * cols + c0 + c, make_float2(y.x, sgn * y.y));
         }
@@ -82,46 +116,52 @@ __global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out
 using TileKernel = void (*)(const float2 *, float2 *, const float2 *, const float2 *, const float2 *, int, int,
                             long long, float);
 
+constexpr int kTileLdsMax = 160 * 1024;
+// LDS bytes of a pass: the tile, plus the twiddle tables (2 x 1024 values) in pass A
+constexpr int64_t tile_lds(int log2len, int tc, bool pass_a) {
+    return ((int64_t)tile_vals(log2len, tc) + (pass_a ? 2048 : 0)) * (int64_t)sizeof(float2);
+}
+constexpr bool tile_ok(int radix, int log2len, int tc) {
+    return (radix == 8 || radix == 16) && log2len >= clog2(radix) && tc * ((1 << log2len) / radix) >= 64 &&
+           tc * ((1 << log2len) / radix) <= 1024 && tile_lds(log2len, tc, true) <= kTileLdsMax;
+}
+
+template <int R, int L, bool A, int TC>
+static TileKernel tile_entry() {
+    if constexpr (tile_ok(R, L, TC)) return &k_fft_tile<R, L, A, TC>;
+    else return nullptr;
+}
+template <int R, bool A, int TC>
+static TileKernel tile_len(int log2len) {
+    switch (log2len) {
+        case 5: return tile_entry<R, 5, A, TC>();
+        case 6: return tile_entry<R, 6, A, TC>();
+        case 7: return tile_entry<R, 7, A, TC>();
+        case 8: return tile_entry<R, 8, A, TC>();
+        case 9: return tile_entry<R, 9, A, TC>();
+        case 10: return tile_entry<R, 10, A, TC>();
+        default: return nullptr;
+    }
+}
 template <bool A>
-static TileKernel tile_lookup(int radix, int log2len) {
-    if (radix == 16) {
-        switch (log2len) {
-            case 6: return &k_fft_tile<16, 6, A>;
-            case 7: return &k_fft_tile<16, 7, A>;
-            case 8: return &k_fft_tile<16, 8, A>;
-            case 9: return &k_fft_tile<16, 9, A>;
-            case 10: return &k_fft_tile<16, 10, A>;
-            default: return nullptr;
-        }
-    }
-    if (radix == 8) {
-        switch (log2len) {
-            case 5: return &k_fft_tile<8, 5, A>;
-            case 6: return &k_fft_tile<8, 6, A>;
-            case 7: return &k_fft_tile<8, 7, A>;
-            case 8: return &k_fft_tile<8, 8, A>;
-            case 9: return &k_fft_tile<8, 9, A>;
-            default: return nullptr;
-        }
-    }
+static TileKernel tile_lookup(int radix, int log2len, int tc) {
+    if (radix == 16) return tc == 16 ? tile_len<16, A, 16>(log2len) : tc == 32 ? tile_len<16, A, 32>(log2len)
+                                       : tc == 64 ? tile_len<16, A, 64>(log2len) : nullptr;
+    if (radix == 8) return tc == 16 ? tile_len<8, A, 16>(log2len) : tc == 32 ? tile_len<8, A, 32>(log2len)
+                                      : tc == 64 ? tile_len<8, A, 64>(log2len) : nullptr;
     return nullptr;
 }
 
-const void *fft_tile_kernel(int radix, int log2len, bool pass_a) {
-    return reinterpret_cast<const void *>(pass_a ? tile_lookup<true>(radix, log2len)
-                                                 : tile_lookup<false>(radix, log2len));
+const void *fft_tile_kernel(int radix, int log2len, int tc, bool pass_a) {
+    return reinterpret_cast<const void *>(pass_a ? tile_lookup<true>(radix, log2len, tc)
+                                                 : tile_lookup<false>(radix, log2len, tc));
 }
 
-bool fft_tile_shape_valid(int radix, int log2len) {
-    if (radix != 8 && radix != 16) return false;
-    const int threads = kTileCols * ((1 << log2len) / radix);
-    return threads >= 64 && threads <= 1024 && tile_lookup<true>(radix, log2len) != nullptr;
+bool fft_tile_shape_valid(int radix, int log2len, int tc) {
+    return tile_lookup<true>(radix, log2len, tc) != nullptr;
 }
 
-int64_t fft_tile_lds_bytes(int log2len) {
-    const int64_t vals = (int64_t)kTileCols * ((1 << log2len) + 1);
-    return (vals + 255) / 256 * 256 * (int64_t)sizeof(float2);  // the swizzle stays in aligned 256-value blocks
-}
+int64_t fft_tile_lds_bytes(int log2len, int tc, bool pass_a) { return tile_lds(log2len, tc, pass_a); }
 
 void fft_large_host_twiddles(float *lo2, float *hi2) {
     const double two_pi = 6.283185307179586476925286766559;
@@ -141,10 +181,12 @@ int fft_plan_check(int64_t n, const ppx_fft_plan &p) {
         return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 1048576]");
     const int ln = ilog2(n);
     if (p.log2_n1 < 1 || p.log2_n1 >= ln) return fail(PPX_ECONFIG, "plan: log2_n1 out of range");
-    if (!fft_tile_shape_valid(p.radix_a, ln - p.log2_n1))
-        return fail(PPX_ECONFIG, "plan: radix_a does not support column length n / n1");
-    if (!fft_tile_shape_valid(p.radix_b, p.log2_n1))
-        return fail(PPX_ECONFIG, "plan: radix_b does not support column length n1");
+    if (!fft_tile_shape_valid(p.radix_a, ln - p.log2_n1, p.tile_a))
+        return fail(PPX_ECONFIG, "plan: no pass-A tile kernel for this radix / tile width and column length n / n1");
+    if (!fft_tile_shape_valid(p.radix_b, p.log2_n1, p.tile_b))
+        return fail(PPX_ECONFIG, "plan: no pass-B tile kernel for this radix / tile width and column length n1");
+    if ((int64_t(1) << p.log2_n1) % p.tile_a || (n >> p.log2_n1) % p.tile_b)
+        return fail(PPX_ECONFIG, "plan: tile width exceeds the number of columns");
     return PPX_OK;
 }
 
@@ -154,23 +196,25 @@ std::vector<ppx_fft_plan> fft_enumerate_plans(int64_t n) {
     const int ln = ilog2(n);
     for (int l1 = 1; l1 < ln; ++l1)
         for (int ra : {8, 16})
-            for (int rb : {8, 16}) {
-                const ppx_fft_plan p{l1, ra, rb};
-                if (fft_tile_shape_valid(ra, ln - l1) && fft_tile_shape_valid(rb, l1)) out.push_back(p);
-            }
+            for (int rb : {8, 16})
+                for (int ta : {16, 32, 64})
+                    for (int tb : {16, 32, 64}) {
+                        const ppx_fft_plan p{l1, ra, rb, ta, tb};
+                        if (fft_tile_shape_valid(ra, ln - l1, ta) && fft_tile_shape_valid(rb, l1, tb) &&
+                            (int64_t(1) << l1) % ta == 0 && (n >> l1) % tb == 0)
+                            out.push_back(p);
+                    }
     return out;
 }
 
 void fft_default_plan(int64_t n, ppx_fft_plan &p) {
     const int ln = ilog2(n);
-    p = ppx_fft_plan{0, 0, 0};
-    for (int l1 = ln / 2; l1 >= 1; --l1) {  // the most even split with n1 <= n2
+    p = ppx_fft_plan{0, 0, 0, 0, 0};
+    for (int l1 = ln / 2; l1 >= 1 && !p.log2_n1; --l1)  // the most even split with n1 <= n2
         for (int ra : {8, 16})
             for (int rb : {8, 16})
-                if (fft_tile_shape_valid(ra, ln - l1) && fft_tile_shape_valid(rb, l1) && !p.log2_n1)
-                    p = ppx_fft_plan{l1, ra, rb};
-        if (p.log2_n1) return;
-    }
+                if (!p.log2_n1 && fft_tile_shape_valid(ra, ln - l1, 16) && fft_tile_shape_valid(rb, l1, 16))
+                    p = ppx_fft_plan{l1, ra, rb, 16, 16};
 }
 
 namespace {
@@ -196,22 +240,22 @@ int launch_fft_large(const void *in, void *out, int log2n, int64_t batch, const 
     const DeviceInfo *di = device_info();
     if (!di) return PPX_EDEVICE;
     const int l1 = p.log2_n1, l2 = log2n - l1;
-    TileKernel ka = tile_lookup<true>(p.radix_a, l2), kb = tile_lookup<false>(p.radix_b, l1);
+    TileKernel ka = tile_lookup<true>(p.radix_a, l2, p.tile_a), kb = tile_lookup<false>(p.radix_b, l1, p.tile_b);
     if (!ka || !kb) return fail(PPX_ECONFIG, "no tile kernel for this plan");
     const float sgn = inverse ? -1.0f : 1.0f;
     const float2 *tw = static_cast<const float2 *>(di->twiddles);
     const float2 *lo = static_cast<const float2 *>(di->twiddles_large_lo);
     const float2 *hi = static_cast<const float2 *>(di->twiddles_large_hi);
-    // pass A: columns of length n2 of the [n2][n1] input, tiles of 16 of the n1 columns
-    const long long tiles_a = (1LL << l1) / kTileCols, tiles_b = (1LL << l2) / kTileCols;
-    hipLaunchKernelGGL(ka, dim3((unsigned)(batch * tiles_a)), dim3(kTileCols * ((1 << l2) / p.radix_a)),
-                       (size_t)fft_tile_lds_bytes(l2), s, static_cast<const float2 *>(in), static_cast<float2 *>(out),
+    // pass A: columns of length n2 of the [n2][n1] input, tiles of the n1 columns
+    const long long tiles_a = (1LL << l1) / p.tile_a, tiles_b = (1LL << l2) / p.tile_b;
+    hipLaunchKernelGGL(ka, dim3((unsigned)(batch * tiles_a)), dim3(p.tile_a * ((1 << l2) / p.radix_a)),
+                       (size_t)tile_lds(l2, p.tile_a, true), s, static_cast<const float2 *>(in), static_cast<float2 *>(out),
                        tw, lo, hi, log2n, l1, tiles_a, sgn);
     int rc = fail_hip(hipGetLastError(), "large FFT pass A launch");
     if (rc) return rc;
     // pass B: columns of length n1 of the [n1][n2] intermediate, in place
-    hipLaunchKernelGGL(kb, dim3((unsigned)(batch * tiles_b)), dim3(kTileCols * ((1 << l1) / p.radix_b)),
-                       (size_t)fft_tile_lds_bytes(l1), s, static_cast<const float2 *>(out), static_cast<float2 *>(out),
+    hipLaunchKernelGGL(kb, dim3((unsigned)(batch * tiles_b)), dim3(p.tile_b * ((1 << l1) / p.radix_b)),
+                       (size_t)tile_lds(l1, p.tile_b, false), s, static_cast<const float2 *>(out), static_cast<float2 *>(out),
                        tw, lo, hi, log2n, l2, tiles_b, sgn);
     return fail_hip(hipGetLastError(), "large FFT pass B launch");
 }

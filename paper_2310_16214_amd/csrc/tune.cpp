@@ -330,24 +330,27 @@ static double expected_improvement(double mu, double sigma, double best) {
 // ordered scale); each column scaled to [0, 1].
 // Large-FFT plans are timed and searched as configurations tagged with
 // kLargePlanAlgo: radix = radix_a, elems_per_thread = radix_b,
-// threads_per_block = n1.  Their GP inputs are log2 radix_a, log2 n1 and
-// log2 radix_b.
+// threads_per_block = n1, problems_per_block = tile_a, lds_elems = tile_b.
+// Their GP inputs are the log2 of those five values.
 constexpr int kLargePlanAlgo = 0x40;
 static ppx_config plan_to_config(const ppx_fft_plan &p) {
-    return ppx_config{p.radix_a, p.radix_b, 1 << p.log2_n1, 1, 0, kLargePlanAlgo};
+    return ppx_config{p.radix_a, p.radix_b, 1 << p.log2_n1, p.tile_a, p.tile_b, kLargePlanAlgo};
 }
 static ppx_fft_plan config_to_plan(const ppx_config &c) {
-    return ppx_fft_plan{ilog2(c.threads_per_block), c.radix, c.elems_per_thread};
+    return ppx_fft_plan{ilog2(c.threads_per_block), c.radix, c.elems_per_thread, c.problems_per_block,
+                        c.lds_elems};
 }
 
 static void features(const ppx_config *c, int n, std::vector<double> &F, int &d) {
     if (n > 0 && c[0].algo == kLargePlanAlgo) {
-        d = 3;
+        d = 5;
         F.assign((size_t)n * d, 0.0);
         for (int i = 0; i < n; ++i) {
             F[i * d + 0] = std::log2((double)c[i].radix);
             F[i * d + 1] = std::log2((double)c[i].threads_per_block);
             F[i * d + 2] = std::log2((double)c[i].elems_per_thread);
+            F[i * d + 3] = std::log2((double)c[i].problems_per_block);
+            F[i * d + 4] = std::log2((double)c[i].lds_elems);
         }
         for (int k = 0; k < d; ++k) {
             double lo = 1e300, hi = -1e300;
@@ -906,31 +909,43 @@ static int tune_impl(int op, int dtype, int64_t n, int64_t batch, int method, in
 using namespace ppx;
 
 // The analytical plan: the most even split (as the default plan), and for
-// each pass the radix that the occupancy guideline picks among the tile
-// kernels valid for its column length.
+// each pass the (radix, tile) that the occupancy guideline picks among the
+// tile kernels valid for its column length.
 static int analytical_plan(int64_t n, int64_t batch, ppx_fft_plan &out) {
     fft_default_plan(n, out);
     if (!out.log2_n1) return fail(PPX_ECONFIG, "no valid plan");
     const ppx_device_model m = gfx950_model();
     const int ln = ilog2(n);
     for (int pass = 0; pass < 2; ++pass) {
-        const int l = pass == 0 ? ln - out.log2_n1 : out.log2_n1;      // column length
-        const int64_t groups = batch * ((int64_t(1) << (ln - l)) / 16);  // workgroups of the pass
+        const int l = pass == 0 ? ln - out.log2_n1 : out.log2_n1;  // column length
+        const int64_t ncols = int64_t(1) << (ln - l);
         std::vector<ppx_config> c;
         std::vector<ppx_resource> r;
-        for (int radix : {8, 16}) {
-            if (!fft_tile_shape_valid(radix, l)) continue;
-            const int threads = 16 * ((1 << l) / radix);
-            hipFuncAttributes a;
-            if (hipFuncGetAttributes(&a, fft_tile_kernel(radix, l, pass == 0)) != hipSuccess)
-                return fail(PPX_EHIP, "hipFuncGetAttributes failed");
-            c.push_back(ppx_config{radix, radix, threads, 1, 0, 0});
-            r.push_back(ppx_resource{threads, a.numRegs, (int32_t)(fft_tile_lds_bytes(l) + a.sharedSizeBytes)});
-        }
-        const int k = analytical_pick_impl(m, c.data(), r.data(), (int)c.size(), groups,
+        for (int radix : {8, 16})
+            for (int tile : {16, 32, 64}) {
+                if (!fft_tile_shape_valid(radix, l, tile) || ncols % tile) continue;
+                const int threads = tile * ((1 << l) / radix);
+                hipFuncAttributes a;
+                if (hipFuncGetAttributes(&a, fft_tile_kernel(radix, l, tile, pass == 0)) != hipSuccess)
+                    return fail(PPX_EHIP, "hipFuncGetAttributes failed");
+                // a column is a "problem" and a tile of them a workgroup: the
+                // grid-fill term then sees the pass's workgroup count
+                c.push_back(ppx_config{radix, radix, threads, tile, 0, 0});
+                r.push_back(ppx_resource{threads, a.numRegs,
+                                         (int32_t)(fft_tile_lds_bytes(l, tile, pass == 0) + a.sharedSizeBytes)});
+            }
+        if (c.empty()) return fail(PPX_ECONFIG, "no pass kernel");
+        const int k = analytical_pick_impl(m, c.data(), r.data(), (int)c.size(), batch * ncols,
                                            PPX_ANALYTICAL_GRID_FILL | PPX_ANALYTICAL_WINDOW_50);
         if (k < 0) return fail(PPX_ECONFIG, "no pass kernel fits a CU");
-        (pass == 0 ? out.radix_a : out.radix_b) = c[k].radix;
+        const int tile = c[k].problems_per_block;
+        if (pass == 0) {
+            out.radix_a = c[k].radix;
+            out.tile_a = tile;
+        } else {
+            out.radix_b = c[k].radix;
+            out.tile_b = tile;
+        }
     }
     return PPX_OK;
 }

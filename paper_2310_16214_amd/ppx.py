@@ -231,14 +231,15 @@ EVAL_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(Config), ctypes.c_voi
 ANALYTICAL_GRID_FILL, ANALYTICAL_WINDOW_50 = 1, 4
 
 class FftPlan(ctypes.Structure):
-    """ppx_fft_plan: (log2 n1, radix of pass A, radix of pass B)."""
-    _fields_ = [("log2_n1", ctypes.c_int32), ("radix_a", ctypes.c_int32), ("radix_b", ctypes.c_int32)]
+    """ppx_fft_plan: (log2 n1, radix and tile width of pass A and of pass B)."""
+    _fields_ = [("log2_n1", ctypes.c_int32), ("radix_a", ctypes.c_int32), ("radix_b", ctypes.c_int32),
+                ("tile_a", ctypes.c_int32), ("tile_b", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.log2_n1, self.radix_a, self.radix_b)
+        return (self.log2_n1, self.radix_a, self.radix_b, self.tile_a, self.tile_b)
 
     def __repr__(self):
-        return "FftPlan(log2_n1=%d, radix_a=%d, radix_b=%d)" % self.as_tuple()
+        return "FftPlan(log2_n1=%d, radix_a=%d, radix_b=%d, tile_a=%d, tile_b=%d)" % self.as_tuple()
 
 
 MAX_N = 16384
@@ -305,8 +306,8 @@ def fft_batched_large(inp, out, n, batch, direction=-1, plan=None, stream=None):
                                     _stream(stream, inp, out)))
 
 
-def make_plan(log2_n1, radix_a, radix_b):
-    return FftPlan(log2_n1, radix_a, radix_b)
+def make_plan(log2_n1, radix_a, radix_b, tile_a=16, tile_b=16):
+    return FftPlan(log2_n1, radix_a, radix_b, tile_a, tile_b)
 
 
 def fft_plan_valid(n, plan) -> bool:
@@ -327,7 +328,7 @@ def default_fft_plan(n):
     return p
 
 
-def tune_fft_large(n, batch, method, max_evals=0, reps=100, trace_cap=64):
+def tune_fft_large(n, batch, method, max_evals=0, reps=100, trace_cap=256):
     """Returns (plan, best_us, evals_used, [(plan, us) timed in order])."""
     best = FftPlan()
     us = ctypes.c_double(0.0)

@@ -74,20 +74,26 @@ def test_fft_plans():
         for p in plans:
             assert ppx.fft_plan_valid(n, p)
             l2 = ln - p.log2_n1
-            for radix, length in ((p.radix_a, l2), (p.radix_b, p.log2_n1)):
-                lo, hi = (6, 10) if radix == 16 else (5, 9)
-                assert lo <= length <= hi and radix in (8, 16)
+            for radix, length, tile, ncols in ((p.radix_a, l2, p.tile_a, 1 << p.log2_n1),
+                                               (p.radix_b, p.log2_n1, p.tile_b, 1 << l2)):
+                threads = tile * (1 << length) // radix
+                lds = -(-tile * ((1 << length) + 1) // 256) * 256 * 8
+                assert radix in (8, 16) and tile in (16, 32, 64) and ncols % tile == 0
+                assert 64 <= threads <= 1024 and lds <= 160 * 1024
         keys = [p.as_tuple() for p in plans]
         assert keys == sorted(keys) and len(set(keys)) == len(keys)
         d = ppx.default_fft_plan(n)
         assert d.as_tuple() in keys
         assert d.log2_n1 <= ln - d.log2_n1  # n1 <= n2, the most even such split
         assert not any(q[0] > d.log2_n1 and q[0] <= ln - q[0] for q in keys)
-    assert [p.as_tuple() for p in ppx.enumerate_fft_plans(1 << 20)] == [(10, 16, 16)]
+    assert [p.as_tuple() for p in ppx.enumerate_fft_plans(1 << 20)] == [(10, 16, 16, 16, 16)]
     assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 4, 16))      # radix 4
     assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(11, 16, 16))    # n1 = 2048 too long
     assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(6, 8, 16))      # n2 = 1024 with radix 8
     assert not ppx.fft_plan_valid(1 << 14, ppx.make_plan(7, 16, 16))     # not a large size
+    assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 16, 16, 32, 128))  # tile 128
+    assert not ppx.fft_plan_valid(1 << 20, ppx.make_plan(10, 16, 16, 32, 16))  # 32 x 1025 values of LDS
+    assert ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 16, 16, 64, 64))
     with pytest.raises(ppx.PpxError):
         ppx.enumerate_fft_plans(1 << 14)
 
