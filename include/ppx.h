@@ -201,11 +201,22 @@ int tune_fft_large(int64_t n, int64_t batch, int method, int max_evals, ppx_fft_
 /*
  * scan_batched -- Sec. III ("Scan Operator"): inclusive sum scan,
  *   out[b][i] = sum_{j<=i} in[b][j]
- * dtype PPX_I32 (wraps modulo 2^32, bit-exact) or PPX_F32.  in == out is
- * allowed; partial overlap is not.
+ * in, out: device arrays [batch][n], 16-byte aligned, of dtype PPX_I32 (wraps
+ * modulo 2^32, bit-exact), PPX_F32 or PPX_F64 (float64: at most 16 elements
+ * per thread).  in == out is allowed; partial overlap is not.
  */
 int scan_batched(const void *in, void *out, int64_t n, int64_t batch,
                  int dtype, const ppx_config *cfg, void *stream);
+
+/*
+ * scan_exclusive_batched -- the exclusive form of the scan operator of
+ * Sec. III (the prescan): out[b][i] = sum_{j<i} in[b][j], out[b][0] = 0.
+ * Arguments, dtypes, aliasing and the configuration space as for
+ * scan_batched; cfg == NULL takes the configuration scan_batched would use
+ * (the two kernels differ only in the thread-serial step).
+ */
+int scan_exclusive_batched(const void *in, void *out, int64_t n, int64_t batch,
+                           int dtype, const ppx_config *cfg, void *stream);
 
 /*
  * tridiag_batched -- Sec. III (tridiagonal system solvers, CR and PCR):

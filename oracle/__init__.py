@@ -13,7 +13,8 @@ arXiv:2310.16214) in double precision, by the plain route:
   forward sign -1, unnormalised inverse sign +1).
 * :func:`scan` -- inclusive sum scan (Sec. III, "Scan Operator": every element
   becomes the sum from the first element up to itself), int32 modulo 2^32,
-  floating point in float64.
+  floating point in float64; ``exclusive=True`` gives the exclusive form (the
+  sum of the elements strictly before, 0 for the first).
 * :func:`thomas` -- the solution of the tridiagonal system of Sec. III by
   tridiagonal Gaussian elimination (Thomas algorithm), float64.
 * :func:`tridiag_residual`, :func:`rel_l2` -- the error measures used to assess
@@ -65,10 +66,13 @@ def _load():
             lib.oracle_dft_bins.argtypes = [dp, dp, i64, i64, ctypes.POINTER(ctypes.c_int64), i64, ci, ci]
             lib.oracle_scan_u32.argtypes = [u32p, u32p, i64, i64, ci]
             lib.oracle_scan_f64.argtypes = [dp, dp, i64, i64, ci]
+            lib.oracle_scan_excl_u32.argtypes = [u32p, u32p, i64, i64, ci]
+            lib.oracle_scan_excl_f64.argtypes = [dp, dp, i64, i64, ci]
             lib.oracle_thomas.argtypes = [dp, dp, dp, dp, dp, i64, i64, ci]
             lib.oracle_tridiag_residual.argtypes = [dp, dp, dp, dp, dp, dp,
                                                     i64, i64, ci]
-            for f in (lib.oracle_dft, lib.oracle_scan_u32, lib.oracle_scan_f64,
+            for f in (lib.oracle_dft, lib.oracle_dft_bins, lib.oracle_scan_u32, lib.oracle_scan_f64,
+                      lib.oracle_scan_excl_u32, lib.oracle_scan_excl_f64,
                       lib.oracle_thomas, lib.oracle_tridiag_residual):
                 f.restype = ci
             _lib = lib
@@ -130,11 +134,11 @@ def dft_bins(x, ks, inverse: bool = False, nthreads: int = 0) -> np.ndarray:
     return out[..., 0] + 1j * out[..., 1]
 
 
-def scan(x, nthreads: int = 0) -> np.ndarray:
-    """Inclusive sum scan of every row.
+def scan(x, nthreads: int = 0, exclusive: bool = False) -> np.ndarray:
+    """Inclusive (or, with ``exclusive``, exclusive) sum scan of every row.
 
     int32 input -> int32 output computed modulo 2^32 (bit pattern of the
-    wrapped sum); any floating input -> float64 output.
+    wrapped sum); any floating input -> float64 output, summed left to right.
     """
     x = _as_2d(x)
     batch, n = x.shape
@@ -142,17 +146,17 @@ def scan(x, nthreads: int = 0) -> np.ndarray:
     if x.dtype == np.int32 or x.dtype == np.uint32:
         xi = np.ascontiguousarray(x).view(np.uint32)
         y = np.empty((batch, n), dtype=np.uint32)
-        rc = lib.oracle_scan_u32(_ptr(xi, ctypes.c_uint32), _ptr(y, ctypes.c_uint32),
-                                 n, batch, nthreads)
-        _check(rc, "oracle_scan_u32")
+        f = lib.oracle_scan_excl_u32 if exclusive else lib.oracle_scan_u32
+        rc = f(_ptr(xi, ctypes.c_uint32), _ptr(y, ctypes.c_uint32), n, batch, nthreads)
+        _check(rc, "oracle scan (u32)")
         return y.view(x.dtype)
     if not np.issubdtype(x.dtype, np.floating):
         raise TypeError("scan oracle takes int32 or floating input")
     xf = np.ascontiguousarray(x, dtype=np.float64)
     y = np.empty((batch, n), dtype=np.float64)
-    rc = lib.oracle_scan_f64(_ptr(xf, ctypes.c_double), _ptr(y, ctypes.c_double),
-                             n, batch, nthreads)
-    _check(rc, "oracle_scan_f64")
+    f = lib.oracle_scan_excl_f64 if exclusive else lib.oracle_scan_f64
+    rc = f(_ptr(xf, ctypes.c_double), _ptr(y, ctypes.c_double), n, batch, nthreads)
+    _check(rc, "oracle scan (f64)")
     return y
 
 

@@ -15,6 +15,9 @@
  *                    all inputs up to and including itself (Sec. III, "Scan
  *                    Operator"); arithmetic modulo 2^32.
  *   oracle_scan_f64  the same scan in double precision.
+ *   oracle_scan_excl_u32, oracle_scan_excl_f64
+ *                    the exclusive scan: each output is the sum of the
+ *                    inputs strictly before it (0 for the first).
  *   oracle_thomas    the solution of the tridiagonal system
  *                    a_i x_{i-1} + b_i x_i + c_i x_{i+1} = d_i (Sec. III,
  *                    "Tridiagonal system solvers"), x_{-1} = x_N = 0, by
@@ -260,6 +263,59 @@ int oracle_scan_f64(const double *x, double *y, int64_t n, int64_t batch,
         return -1;
     scan_ctx ctx = {x, y, n};
     return run_ranges(scan_f64_range, &ctx, batch, nthreads);
+}
+
+/* Exclusive form: every output is the sum of the inputs strictly before it,
+ * so the first output of each problem is 0 (the scan operator of Sec. III
+ * with the element itself left out). */
+static void scan_excl_u32_range(void *vctx, int64_t first, int64_t last)
+{
+    scan_ctx *c = (scan_ctx *)vctx;
+    const uint32_t *x = (const uint32_t *)c->x;
+    uint32_t *y = (uint32_t *)c->y;
+    for (int64_t b = first; b < last; ++b) {
+        uint32_t before = 0u;
+        for (int64_t i = 0; i < c->n; ++i) {
+            const uint32_t xi = x[b * c->n + i]; /* read first: y may be x */
+            y[b * c->n + i] = before;
+            before += xi;
+        }
+    }
+}
+
+static void scan_excl_f64_range(void *vctx, int64_t first, int64_t last)
+{
+    scan_ctx *c = (scan_ctx *)vctx;
+    const double *x = (const double *)c->x;
+    double *y = (double *)c->y;
+    for (int64_t b = first; b < last; ++b) {
+        double before = 0.0;
+        for (int64_t i = 0; i < c->n; ++i) {
+            const double xi = x[b * c->n + i];
+            y[b * c->n + i] = before;
+            before += xi;
+        }
+    }
+}
+
+/* y[b][i] = sum_{j<i} x[b][j]  (mod 2^32), y[b][0] = 0. */
+int oracle_scan_excl_u32(const uint32_t *x, uint32_t *y, int64_t n, int64_t batch,
+                         int nthreads)
+{
+    if (!x || !y || n < 1 || batch < 0)
+        return -1;
+    scan_ctx ctx = {x, y, n};
+    return run_ranges(scan_excl_u32_range, &ctx, batch, nthreads);
+}
+
+/* y[b][i] = sum_{j<i} x[b][j] in double precision, summed left to right. */
+int oracle_scan_excl_f64(const double *x, double *y, int64_t n, int64_t batch,
+                         int nthreads)
+{
+    if (!x || !y || n < 1 || batch < 0)
+        return -1;
+    scan_ctx ctx = {x, y, n};
+    return run_ranges(scan_excl_f64_range, &ctx, batch, nthreads);
 }
 
 /* -------------------------------------------------------- tridiagonal -- */

@@ -215,21 +215,33 @@ int ppx_default_fft_plan(int64_t n, ppx_fft_plan *out) {
     return PPX_OK;
 }
 
-int scan_batched(const void *in, void *out, int64_t n, int64_t batch, int dtype,
-                 const ppx_config *cfg, void *stream) {
+static int scan_common(const void *in, void *out, int64_t n, int64_t batch, int dtype,
+                       const ppx_config *cfg, void *stream, bool exclusive) {
     t_err.clear();
     if (!in || !out) return fail(PPX_EINVAL, "null pointer");
     if (!aligned16(in) || !aligned16(out)) return fail(PPX_EINVAL, "pointers must be 16-byte aligned");
-    if (dtype != PPX_I32 && dtype != PPX_F32) return fail(PPX_EINVAL, "scan dtype must be PPX_I32 or PPX_F32");
-    int rc = check_shape(n, batch, 4);
+    if (dtype != PPX_I32 && dtype != PPX_F32 && dtype != PPX_F64)
+        return fail(PPX_EINVAL, "scan dtype must be PPX_I32, PPX_F32 or PPX_F64");
+    const int64_t es = dtype == PPX_F64 ? 8 : 4;
+    int rc = check_shape(n, batch, es);
     if (rc) return rc;
-    if (overlap_partial(in, out, batch * n * 4)) return fail(PPX_EINVAL, "in and out overlap partially");
+    if (overlap_partial(in, out, batch * n * es)) return fail(PPX_EINVAL, "in and out overlap partially");
     ppx_config c;
     if ((rc = resolve(PPX_OP_SCAN, dtype, n, batch, cfg, c))) return rc;
     if ((batch + c.problems_per_block - 1) / c.problems_per_block > INT32_MAX)
         return fail(PPX_EINVAL, "too many workgroups");
     if (!device_info()) return PPX_EDEVICE;
-    return launch_scan(in, out, ilog2(n), batch, dtype, c, static_cast<hipStream_t>(stream));
+    return launch_scan(in, out, ilog2(n), batch, dtype, c, static_cast<hipStream_t>(stream), exclusive);
+}
+
+int scan_batched(const void *in, void *out, int64_t n, int64_t batch, int dtype,
+                 const ppx_config *cfg, void *stream) {
+    return scan_common(in, out, n, batch, dtype, cfg, stream, false);
+}
+
+int scan_exclusive_batched(const void *in, void *out, int64_t n, int64_t batch, int dtype,
+                           const ppx_config *cfg, void *stream) {
+    return scan_common(in, out, n, batch, dtype, cfg, stream, true);
 }
 
 int tridiag_batched(const void *a, const void *b, const void *c, const void *d, void *x,

@@ -17,7 +17,7 @@ namespace ppx {
 static bool is_valid_dtype(int op, int dtype) {
     switch (op) {
         case PPX_OP_FFT: return dtype == PPX_C64;
-        case PPX_OP_SCAN: return dtype == PPX_I32 || dtype == PPX_F32;
+        case PPX_OP_SCAN: return dtype == PPX_I32 || dtype == PPX_F32 || dtype == PPX_F64;
         case PPX_OP_TRIDIAG: return dtype == PPX_F32 || dtype == PPX_F64;
         default: return false;
     }
@@ -85,6 +85,8 @@ int validate_config(int op, int dtype, int64_t n, const ppx_config &c) {
             if (c.radix != 0 && c.radix != 2) return fail(PPX_ECONFIG, "scan radix must be 2");
             if (c.algo < PPX_SCAN_KS || c.algo > PPX_SCAN_LF_PIPE)
                 return fail(PPX_ECONFIG, "scan algo must be PPX_SCAN_KS, _LF, _KS_PIPE or _LF_PIPE");
+            if (dtype == PPX_F64 && P > kScanF64MaxElems)
+                return fail(PPX_ECONFIG, "float64 scan allows at most 16 elements per thread");
             break;
         case PPX_OP_TRIDIAG:
             if (c.radix != 0 && c.radix != 2) return fail(PPX_ECONFIG, "tridiagonal radix must be 2");

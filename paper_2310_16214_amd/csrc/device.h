@@ -174,16 +174,29 @@ constexpr int kDppRowShr = 0x110;     // + shift (1..15), within 16-lane rows
 constexpr int kDppRowBcast15 = 0x142; // lane 15 of each row -> next row
 constexpr int kDppRowBcast31 = 0x143; // lane 31 -> rows 2 and 3
 
-template <typename T>
-__device__ __forceinline__ int as_int(T v) { return __builtin_bit_cast(int, v); }
-template <typename T>
-__device__ __forceinline__ T from_int(int v) { return __builtin_bit_cast(T, v); }
+// A 32-bit lane operation applied to each 32-bit word of a 4- or 8-byte
+// value (the cross-lane instructions move 32 bits per lane).
+struct Words2 {
+    int lo, hi;
+};
+template <typename T, typename F>
+__device__ __forceinline__ T per_word(T v, F f) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, f(__builtin_bit_cast(int, v)));
+    } else {
+        static_assert(sizeof(T) == 8, "4- or 8-byte values");
+        Words2 w = __builtin_bit_cast(Words2, v);
+        w.lo = f(w.lo);
+        w.hi = f(w.hi);
+        return __builtin_bit_cast(T, w);
+    }
+}
 
 // Value of lane (lane - D) within the same 16-lane row, 0 where that lane is
 // outside the row.
 template <int D, typename T>
 __device__ __forceinline__ T dpp_row_shr(T v) {
-    return from_int<T>(__builtin_amdgcn_update_dpp(0, as_int(v), kDppRowShr + D, 0xf, 0xf, false));
+    return per_word(v, [](int x) { return __builtin_amdgcn_update_dpp(0, x, kDppRowShr + D, 0xf, 0xf, false); });
 }
 
 // Inclusive scan over aligned segments of SEG lanes (SEG power of two <= 64),
@@ -198,11 +211,11 @@ __device__ __forceinline__ T lanes_scan_ks(T x, int seg, int lane) {
     if (seg > 8) { T y = dpp_row_shr<8>(x); if (ls >= 8) x += y; }
     if (seg > 16) {
         // rows 1 and 3 receive the last lane of rows 0 and 2
-        x += from_int<T>(__builtin_amdgcn_update_dpp(0, as_int(x), kDppRowBcast15, 0xa, 0xf, false));
+        x += per_word(x, [](int w) { return __builtin_amdgcn_update_dpp(0, w, kDppRowBcast15, 0xa, 0xf, false); });
     }
     if (seg > 32) {
         // rows 2 and 3 receive lane 31
-        x += from_int<T>(__builtin_amdgcn_update_dpp(0, as_int(x), kDppRowBcast31, 0xc, 0xf, false));
+        x += per_word(x, [](int w) { return __builtin_amdgcn_update_dpp(0, w, kDppRowBcast31, 0xc, 0xf, false); });
     }
     return x;
 }
@@ -211,7 +224,7 @@ __device__ __forceinline__ T lanes_scan_ks(T x, int seg, int lane) {
 // (lane & AND) | OR.
 template <int AND, int OR, typename T>
 __device__ __forceinline__ T swz(T v) {
-    return from_int<T>(__builtin_amdgcn_ds_swizzle(as_int(v), (AND & 31) | ((OR & 31) << 5)));
+    return per_word(v, [](int w) { return __builtin_amdgcn_ds_swizzle(w, (AND & 31) | ((OR & 31) << 5)); });
 }
 
 // Inclusive scan over aligned segments of SEG lanes, Ladner-Fischer shape
@@ -225,7 +238,7 @@ __device__ __forceinline__ T lanes_scan_lf(T x, int seg, int lane) {
     if (seg > 8) { T y = swz<0x10, 0x07>(x); if (lane & 8) x += y; }
     if (seg > 16) { T y = swz<0x00, 0x0f>(x); if (lane & 16) x += y; }
     if (seg > 32) {
-        T y = from_int<T>(__builtin_amdgcn_readlane(as_int(x), 31));
+        T y = per_word(x, [](int w) { return __builtin_amdgcn_readlane(w, 31); });
         if (lane & 32) x += y;
     }
     return x;

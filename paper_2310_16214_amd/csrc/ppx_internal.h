@@ -24,6 +24,9 @@ constexpr int kMaxThreadsPerBlock = 1024;
 constexpr int kMinThreadsPerBlock = 64;
 constexpr int kMaxProblemsPerBlock = 64;
 constexpr int kMaxElemsPerThread = 32;
+// float64 scan: at most 16 values per thread (two sets of 32 do not fit the
+// registers of a 1024-thread workgroup).
+constexpr int kScanF64MaxElems = 16;
 constexpr int64_t kStaticLdsPerBlock = 160 * 1024;  // gfx950 LDS per CU
 
 struct DeviceInfo {
@@ -89,8 +92,9 @@ constexpr int tri_family(int algo) {
 constexpr int kTriPipeMaxBytes = 32;
 int launch_fft(const void *in, void *out, int log2n, int64_t batch,
                const ppx_config &c, bool inverse, hipStream_t s);
+// exclusive: each output is the sum of the inputs before it (0 first).
 int launch_scan(const void *in, void *out, int log2n, int64_t batch, int dtype,
-                const ppx_config &c, hipStream_t s);
+                const ppx_config &c, hipStream_t s, bool exclusive = false);
 int launch_tridiag(const void *a, const void *b, const void *c, const void *d,
                    void *x, int log2n, int64_t batch, int dtype,
                    const ppx_config &cfg, hipStream_t s);
@@ -103,7 +107,7 @@ const void *fft_spec16_kernel(int log2n, bool split, bool pipe);
 const void *fft_spec4_kernel(int log2n, bool split);  // radix = P = 4, n = 16..64; else nullptr
 // The persistent FFT variants exist for radix = P = 8 or 16.
 constexpr bool fft_pipe_available(int radix, int P) { return radix == P && (P == 8 || P == 16); }
-const void *scan_kernel(int dtype, int P, int algo);
+const void *scan_kernel(int dtype, int P, int algo, bool exclusive = false);
 const void *tridiag_kernel(int dtype, int algo, int P);
 
 // Builds the forward twiddle table for NMAX = 2^kFftLog2NMax in host memory

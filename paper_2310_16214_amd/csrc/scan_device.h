@@ -1,5 +1,5 @@
-// Batched inclusive sum scan (Sec. III "Scan Operator" of arXiv:2310.16214),
-// int32 (modulo 2^32) and float32, for gfx950.
+// Batched inclusive and exclusive sum scans (Sec. III "Scan Operator" of
+// arXiv:2310.16214), int32 (modulo 2^32), float32 and float64, for gfx950.
 //
 // A workgroup of L threads scans G_b problems of size n; problem p is owned by
 // T = n/P consecutive threads and thread `tid` holds the P contiguous elements
@@ -25,54 +25,67 @@
 
 namespace ppx {
 
+// P contiguous values as 16-byte words (8-byte ones where P values are
+// fewer than 16 bytes' worth).
 template <typename T, int P>
 __device__ __forceinline__ void load_chunk(const T *src, T (&v)[P]) {
-    if constexpr (P * sizeof(T) % 16 == 0) {
+    constexpr int B = P * (int)sizeof(T);
+    if constexpr (B % 16 == 0) {
         const int4 *s4 = reinterpret_cast<const int4 *>(src);
 #pragma unroll
-        for (int j = 0; j < (int)(P * sizeof(T) / 16); ++j) {
+        for (int j = 0; j < B / 16; ++j) {
             const int4 w = s4[j];
-            v[4 * j + 0] = __builtin_bit_cast(T, w.x);
-            v[4 * j + 1] = __builtin_bit_cast(T, w.y);
-            v[4 * j + 2] = __builtin_bit_cast(T, w.z);
-            v[4 * j + 3] = __builtin_bit_cast(T, w.w);
+            __builtin_memcpy(&v[j * 16 / (int)sizeof(T)], &w, 16);
         }
     } else {
-        const int2 *s2 = reinterpret_cast<const int2 *>(src);
-#pragma unroll
-        for (int j = 0; j < P / 2; ++j) {
-            const int2 w = s2[j];
-            v[2 * j + 0] = __builtin_bit_cast(T, w.x);
-            v[2 * j + 1] = __builtin_bit_cast(T, w.y);
-        }
+        static_assert(B == 8, "8 bytes or a multiple of 16");
+        const int2 w = *reinterpret_cast<const int2 *>(src);
+        __builtin_memcpy(&v[0], &w, 8);
     }
 }
 
 template <typename T, int P>
 __device__ __forceinline__ void store_chunk(T *dst, const T (&v)[P]) {
-    if constexpr (P * sizeof(T) % 16 == 0) {
+    constexpr int B = P * (int)sizeof(T);
+    if constexpr (B % 16 == 0) {
         int4 *d4 = reinterpret_cast<int4 *>(dst);
 #pragma unroll
-        for (int j = 0; j < (int)(P * sizeof(T) / 16); ++j)
-            d4[j] = make_int4(__builtin_bit_cast(int, v[4 * j]), __builtin_bit_cast(int, v[4 * j + 1]),
-                              __builtin_bit_cast(int, v[4 * j + 2]), __builtin_bit_cast(int, v[4 * j + 3]));
+        for (int j = 0; j < B / 16; ++j) {
+            int4 w;
+            __builtin_memcpy(&w, &v[j * 16 / (int)sizeof(T)], 16);
+            d4[j] = w;
+        }
     } else {
-        int2 *d2 = reinterpret_cast<int2 *>(dst);
-#pragma unroll
-        for (int j = 0; j < P / 2; ++j)
-            d2[j] = make_int2(__builtin_bit_cast(int, v[2 * j]), __builtin_bit_cast(int, v[2 * j + 1]));
+        static_assert(B == 8, "8 bytes or a multiple of 16");
+        int2 w;
+        __builtin_memcpy(&w, &v[0], 8);
+        *reinterpret_cast<int2 *>(dst) = w;
     }
 }
 
 // Steps 1-4 on the P values a thread holds (lT = log2 threads per problem).
 // `wave_tot` holds blockDim.x / 64 values; with T > 64 threads per problem
 // there is one barrier, which every thread of the workgroup must reach.
-template <typename T, int P, int ALGO, typename U>
+// EXCL: the exclusive scan (each output the sum of the inputs before it):
+// step 1 is then the thread-serial exclusive scan, the rest is unchanged.
+template <typename T, int P, int ALGO, bool EXCL = false, typename U>
 __device__ __forceinline__ void scan_values(U (&v)[P], int lT, T *wave_tot) {
     // 1. serial scan within the thread
+    U total;
+    if constexpr (EXCL) {
+        U run = U(0);
 #pragma unroll
-    for (int j = 1; j < P; ++j) v[j] = v[j] + v[j - 1];
-    const U total = v[P - 1];
+        for (int j = 0; j < P; ++j) {
+            const U x = v[j];
+            v[j] = run;
+            run = run + x;
+        }
+        total = run;
+    } else {
+#pragma unroll
+        for (int j = 1; j < P; ++j) v[j] = v[j] + v[j - 1];
+        total = v[P - 1];
+    }
 
     // 2. lane network over the problem's segment of the wave
     const int lane = threadIdx.x & (kWave - 1);
@@ -103,7 +116,7 @@ using ScanArith = typename std::conditional<std::is_same<T, int>::value, unsigne
 // problem (threads of problems beyond nprob compute on zeros and store
 // nothing).  `wave_tot` holds blockDim.x / 64 values.  Used by k_scan and by
 // the fused kernel.
-template <typename T, int P, int ALGO>
+template <typename T, int P, int ALGO, bool EXCL = false>
 __device__ __forceinline__ void scan_block(const T *in, T *out, int log2n, long long p0, int nprob,
                                            T *wave_tot) {
     constexpr int LP = P == 2 ? 1 : P == 4 ? 2 : P == 8 ? 3 : P == 16 ? 4 : 5;
@@ -120,16 +133,16 @@ __device__ __forceinline__ void scan_block(const T *in, T *out, int log2n, long 
 #pragma unroll
         for (int j = 0; j < P; ++j) v[j] = U(0);
     }
-    scan_values<T, P, ALGO>(v, lT, wave_tot);
+    scan_values<T, P, ALGO, EXCL>(v, lT, wave_tot);
     if (active) store_chunk<U, P>(reinterpret_cast<U *>(out) + off, v);
 }
 
-template <typename T, int P, int ALGO>
+template <typename T, int P, int ALGO, bool EXCL>
 __global__ __launch_bounds__(1024) void k_scan(const T *in, T *out, int log2n, long long batch,
                                                int gb) {
     __shared__ T wave_tot[kMaxThreadsPerBlock / kWave];
     const long long p0 = (long long)blockIdx.x * gb;
-    scan_block<T, P, ALGO>(in, out, log2n, p0, (int)min((long long)gb, batch - p0), wave_tot);
+    scan_block<T, P, ALGO, EXCL>(in, out, log2n, p0, (int)min((long long)gb, batch - p0), wave_tot);
 }
 
 // Persistent variant: a grid of resident workgroups (at most one per group)
@@ -144,7 +157,7 @@ __global__ __launch_bounds__(1024) void k_scan(const T *in, T *out, int log2n, l
 // wave may start the next group before a slower one has read this group's
 // totals, and the barrier of every group keeps the waves within one group of
 // each other.
-template <typename T, int P, int ALGO>
+template <typename T, int P, int ALGO, bool EXCL>
 __global__ __launch_bounds__(1024) void k_scan_pipe(const T *in, T *out, int log2n, long long batch,
                                                     int gb) {
     constexpr int LP = P == 2 ? 1 : P == 4 ? 2 : P == 8 ? 3 : P == 16 ? 4 : 5;
@@ -159,7 +172,7 @@ __global__ __launch_bounds__(1024) void k_scan_pipe(const T *in, T *out, int log
     auto iteration = [&](long long grp, int parity, U (&cur)[P], U (&nxt)[P]) {
         buf_load<U, P>(nxt, group_rsrc(in, grp + G, gb, n, sizeof(T), batch), voff);
         __builtin_amdgcn_sched_barrier(0);
-        scan_values<T, P, ALGO>(cur, lT, wave_tot[parity]);
+        scan_values<T, P, ALGO, EXCL>(cur, lT, wave_tot[parity]);
         buf_store<U, P>(cur, group_rsrc(out, grp, gb, n, sizeof(T), batch), voff);
     };
     long long g = blockIdx.x;  // < ngroups: the grid never exceeds the groups

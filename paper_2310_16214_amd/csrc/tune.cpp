@@ -517,7 +517,8 @@ void store_cached_config(int op, int dtype, int64_t n, const ppx_config &c) {
 // when no device is present to ask (CPU-side resolution of a NULL config).
 static int static_vgprs(int op, int dtype, int P, int algo) {
     if (op == PPX_OP_FFT) return P <= 2 ? 16 : P <= 4 ? 29 : P <= 8 ? 55 : P <= 16 ? 107 : 200;
-    if (op == PPX_OP_SCAN) return P <= 2 ? 10 : P <= 4 ? 12 : P <= 8 ? 16 : P <= 16 ? 24 : 40;
+    if (op == PPX_OP_SCAN)
+        return (dtype == PPX_F64 ? 2 : 1) * (P <= 2 ? 10 : P <= 4 ? 12 : P <= 8 ? 16 : P <= 16 ? 24 : 40);
     if (tri_in_wave(algo))
         return (dtype == PPX_F64 ? 2 : 1) * (tri_base(algo) == PPX_TRI_CR_SHFL ? 5 : 6) * P *
                    ((algo & PPX_TRI_PIPE) ? 2 : 1) + 16;
@@ -542,7 +543,7 @@ static int64_t dyn_lds(int op, int dtype, int64_t n, const ppx_config &c) {
 
 static int elem_bytes(int op, int dtype) {
     if (op == PPX_OP_FFT) return 8;
-    if (op == PPX_OP_SCAN) return 4;
+    if (op == PPX_OP_SCAN) return dtype == PPX_F64 ? 8 : 4;
     return dtype == PPX_F64 ? 32 : 16;  // four coefficients per equation
 }
 
@@ -558,19 +559,18 @@ static int resources(int op, int dtype, int64_t n, const ppx_config &c, bool hav
         r.regs_per_thread = a.numRegs;
         r.lds_bytes += (int32_t)a.sharedSizeBytes;
     }
-    (void)elem_bytes;
     return PPX_OK;
 }
 
 // Premise (i) of the analytical model (coalesced global accesses) restated
 // for these kernels on gfx950: the scan kernel gives each lane P contiguous
 // elements, so a load instruction is contiguous across the wave only when
-// those P elements are one 16-byte vector (P <= 4); where no such
-// configuration exists (n > 4096) the smallest P comes closest.  The FFT and
-// tridiagonal kernels read consecutive elements with consecutive lanes for
-// every P.
-static bool coalesced(int op, const ppx_config &c) {
-    return op != PPX_OP_SCAN || c.elems_per_thread * 4 <= 16;
+// those P elements are one 16-byte vector (P * element size <= 16); where no
+// such configuration exists (large n) the smallest P comes closest.  The FFT
+// and tridiagonal kernels read consecutive elements with consecutive lanes
+// for every P.
+static bool coalesced(int op, int dtype, const ppx_config &c) {
+    return op != PPX_OP_SCAN || c.elems_per_thread * elem_bytes(op, dtype) <= 16;
 }
 
 static bool persistent(int op, int algo) {
@@ -599,14 +599,14 @@ constexpr int kGfx950Flags = PPX_ANALYTICAL_GRID_FILL | PPX_ANALYTICAL_WINDOW_50
 //    shuffle moves a quarter of the bytes per instruction that a 16-byte LDS
 //    access moves, and PCR exchanges six values per equation and step; with
 //    no family filter, the CR family (less work).
-static std::vector<ppx_config> analytical_candidates(int op, const std::vector<ppx_config> &all) {
+static std::vector<ppx_config> analytical_candidates(int op, int dtype, const std::vector<ppx_config> &all) {
     std::vector<ppx_config> base;
     for (const auto &c : all)
         if (!persistent(op, c.algo)) base.push_back(c);
     if (base.empty()) base = all;
     std::vector<ppx_config> out;
     for (const auto &c : base)
-        if (coalesced(op, c)) out.push_back(c);
+        if (coalesced(op, dtype, c)) out.push_back(c);
     if (out.empty()) {  // no fully coalesced shape: the smallest P
         int pmin = 1 << 30;
         for (const auto &c : base) pmin = std::min(pmin, c.elems_per_thread);
@@ -663,7 +663,7 @@ int analytical_config(int op, int dtype, int64_t n, int64_t batch, ppx_config &c
 
 static int analytical_select(int op, int dtype, int64_t n, int64_t batch, const std::vector<ppx_config> &cands,
                              bool have_device, ppx_config &out) {
-    const std::vector<ppx_config> sub = analytical_candidates(op, cands);
+    const std::vector<ppx_config> sub = analytical_candidates(op, dtype, cands);
     const int cnt = (int)sub.size();
     if (cnt == 0) return fail(PPX_ECONFIG, "no candidate");
     std::vector<ppx_resource> res(cnt);
@@ -719,7 +719,8 @@ struct Bench {
             bytes = {size_t(cnt) * 8, size_t(cnt) * 8};
             nin = 1;
         } else if (op == PPX_OP_SCAN) {
-            bytes = {size_t(cnt) * 4, size_t(cnt) * 4};
+            const size_t es = dtype == PPX_F64 ? 8 : 4;
+            bytes = {size_t(cnt) * es, size_t(cnt) * es};
             nin = 1;
         } else {
             const size_t es = dtype == PPX_F64 ? 8 : 4;
@@ -741,6 +742,9 @@ struct Bench {
             if (dtype == PPX_I32) {
                 int *v = reinterpret_cast<int *>(host[0].data());
                 for (int64_t i = 0; i < cnt; ++i) v[i] = (int)(splitmix(s) % 201) - 100;
+            } else if (dtype == PPX_F64) {
+                double *v = reinterpret_cast<double *>(host[0].data());
+                for (int64_t i = 0; i < cnt; ++i) v[i] = unif(s);
             } else {
                 float *v = reinterpret_cast<float *>(host[0].data());
                 for (int64_t i = 0; i < cnt; ++i) v[i] = (float)unif(s);

@@ -45,6 +45,15 @@ def scan_input(n: int, batch: int, dtype, seed: int = 0) -> np.ndarray:
     raise TypeError(f"unsupported scan dtype {dtype}")
 
 
+def scan_input_dyadic(n: int, batch: int, seed: int = 0):
+    """float64 values k * 2^-20, integer k uniform on [0, 2^20), shape
+    [batch][n]; returns (k as int64, values).  Every partial sum of up to 2^33
+    such values is exact in float64, so any summation order gives the same
+    bits."""
+    k = np.random.default_rng(seed).integers(0, 1 << 20, size=(batch, n))
+    return k, k.astype(np.float64) * 2.0 ** -20
+
+
 def tridiag_input(n: int, batch: int, dtype, seed: int = 0):
     """Diagonally dominant tridiagonal systems with a known solution.
 

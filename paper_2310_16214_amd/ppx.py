@@ -107,6 +107,7 @@ def lib():
             cfgp = ctypes.POINTER(Config)
             L.fft_batched.argtypes = [vp, vp, i64, i64, ci, cfgp, vp]
             L.scan_batched.argtypes = [vp, vp, i64, i64, ci, cfgp, vp]
+            L.scan_exclusive_batched.argtypes = [vp, vp, i64, i64, ci, cfgp, vp]
             L.tridiag_batched.argtypes = [vp, vp, vp, vp, vp, i64, i64, ci, cfgp, vp]
             L.tune.argtypes = [ci, ci, i64, i64, ci, ci, cfgp,
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ci)]
@@ -116,7 +117,8 @@ def lib():
             L.ppx_default_config.argtypes = [ci, ci, i64, cfgp]
             L.ppx_resolve_config.argtypes = [ci, ci, i64, i64, cfgp]
             L.ppx_enumerate_configs.argtypes = [ci, ci, i64, cfgp, ci]
-            for name in ("fft_batched", "scan_batched", "tridiag_batched", "tune",
+            for name in ("fft_batched", "scan_batched", "scan_exclusive_batched",
+                         "tridiag_batched", "tune",
                          "ppx_config_valid", "ppx_default_config", "ppx_resolve_config",
                          "ppx_enumerate_configs"):
                 getattr(L, name).restype = ci
@@ -163,9 +165,15 @@ def fft_batched(inp, out, n, batch, direction=-1, cfg=None, stream=None):
 
 
 def scan_batched(inp, out, n, batch, dtype, cfg=None, stream=None):
-    """Batched inclusive sum scan, dtype I32 or F32."""
+    """Batched inclusive sum scan, dtype I32, F32 or F64."""
     _check(lib().scan_batched(_ptr(inp), _ptr(out), n, batch, dtype, _cfgp(cfg),
                               _stream(stream, inp, out)))
+
+
+def scan_exclusive_batched(inp, out, n, batch, dtype, cfg=None, stream=None):
+    """Batched exclusive sum scan (out[0] = 0), dtype I32, F32 or F64."""
+    _check(lib().scan_exclusive_batched(_ptr(inp), _ptr(out), n, batch, dtype, _cfgp(cfg),
+                                        _stream(stream, inp, out)))
 
 
 def tridiag_batched(a, b, c, d, x, n, batch, dtype, cfg=None, stream=None):

@@ -45,9 +45,10 @@ def kernel_name_prefix(d):
             return f"{name}<{c['radix']}, {c['elems_per_thread']}, {split}, {log2n}>"
         return f"k_fft<{c['radix']}, {c['elems_per_thread']}, {split}>"
     if d["op"] == "scan":
-        t = "int" if d["dtype"] == "int32" else "float"
+        t = {"int32": "int", "float32": "float", "float64": "double"}[d["dtype"]]
         name = "k_scan_pipe" if c["algo"] & 2 else "k_scan"
-        return f"{name}<{t}, {c['elems_per_thread']}, {c['algo'] & 1}>"
+        excl = "true" if d.get("exclusive") else "false"
+        return f"{name}<{t}, {c['elems_per_thread']}, {c['algo'] & 1}, {excl}>"
     t = "double" if d["dtype"] == "float64" else "float"
     if c["algo"] & 7 >= 2:
         name = "k_tridiag_wave_pipe" if c["algo"] & 8 else "k_tridiag_wave"

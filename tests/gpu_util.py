@@ -31,3 +31,22 @@ def scan_f32_bound(x):
     ulp-units (2^-23) times the running sum of |x|."""
     n = x.shape[1]
     return (np.ceil(np.log2(n)) + 32) * 2.0 ** -23 * np.cumsum(np.abs(x.astype(np.float64)), axis=1)
+
+
+def scan_bound(x, unit, exclusive=False, oracle_rounds=False):
+    """Elementwise bound for a blocked-tree sum scan in a precision with unit
+    roundoff `unit`: (log2 N + 32) units times the running sum of |x|.
+
+    exclusive: the lane network adds thread totals, so an exclusive output
+    carries the rounding of a sum running to the end of its thread's chunk
+    (at most 31 elements on): the running sum is taken there.
+    oracle_rounds: the oracle itself rounds (float64 inputs summed left to
+    right in float64): add its i * unit at element i."""
+    n = x.shape[1]
+    s = np.cumsum(np.abs(x.astype(np.float64)), axis=1)
+    if exclusive:
+        s = s[:, np.minimum(np.arange(n) + 31, n - 1)]
+    k = np.ceil(np.log2(n)) + 32
+    if oracle_rounds:
+        k = k + np.arange(n)
+    return k * unit * s

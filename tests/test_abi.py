@@ -99,8 +99,14 @@ def test_fft_plans():
 
 
 def test_scan_and_tridiag_argument_errors():
-    assert L.scan_batched(BUF, BUF, 64, 1, ppx.F64, None, None) == ppx.EINVAL
-    assert L.scan_batched(BUF, 0, 64, 1, ppx.I32, None, None) == ppx.EINVAL
+    for fn in (L.scan_batched, L.scan_exclusive_batched):
+        assert fn(BUF, BUF, 64, 1, ppx.C64, None, None) == ppx.EINVAL
+        assert fn(BUF, 0, 64, 1, ppx.I32, None, None) == ppx.EINVAL
+        assert fn(BUF + 8, BUF, 64, 1, ppx.F64, None, None) == ppx.EINVAL
+        assert fn(BUF, BUF, 48, 1, ppx.F64, None, None) == ppx.EINVAL
+        # float64: 8 bytes per element when checking overlap
+        rc = fn(BUF, BUF + 256, 64, 1, ppx.F64, None, None)
+        assert rc == ppx.EINVAL and "overlap" in ppx.last_error()
     assert L.tridiag_batched(BUF, BUF * 2, BUF * 3, BUF * 4, BUF * 5, 64, 1, ppx.I32,
                              None, None) == ppx.EINVAL
     # x may alias d but nothing else
@@ -124,6 +130,18 @@ def test_explicit_config_errors():
     assert not ppx.config_valid(ppx.OP_SCAN, ppx.I32, 4096, c)
     c = ppx.make_config(16, 256, 1, lds_elems=7)
     assert not ppx.config_valid(ppx.OP_FFT, ppx.C64, 4096, c)
+
+
+def test_scan_float64_space():
+    # float64 scan keeps at most 16 elements per thread
+    assert ppx.config_valid(ppx.OP_SCAN, ppx.F64, 4096, ppx.make_config(2, 256, 1))
+    assert not ppx.config_valid(ppx.OP_SCAN, ppx.F64, 4096, ppx.make_config(2, 128, 1))
+    assert ppx.config_valid(ppx.OP_SCAN, ppx.F32, 4096, ppx.make_config(2, 128, 1))
+    for n in (16, 1024, 16384):
+        cs = ppx.enumerate_configs(ppx.OP_SCAN, ppx.F64, n)
+        assert cs and all(c.elems_per_thread <= 16 for c in cs)
+        c = ppx.resolve_config(ppx.OP_SCAN, ppx.F64, n, 1 << 16)
+        assert ppx.config_valid(ppx.OP_SCAN, ppx.F64, n, c)
 
 
 def test_fft_p32_thread_cap():

@@ -26,9 +26,10 @@ CASES = [
     (_call("fft", 16384, 16, 16, 1024, 1, 2), "k_fft_np<16, 16, false, 14>"),
     (_call("fft", 8192, 16, 16, 512, 1, 3), "k_fft_np<16, 16, true, 13>"),
     (_call("fft", 1024, 8, 16, 512, 8, 0), "k_fft<8, 16, false>"),
-    (_call("scan", 4096, 2, 4, 1024, 1, 2, "int32"), "k_scan_pipe<int, 4, 0>"),
-    (_call("scan", 8192, 2, 8, 1024, 1, 3, "float32"), "k_scan_pipe<float, 8, 1>"),
-    (_call("scan", 64, 2, 4, 64, 4, 1, "float32"), "k_scan<float, 4, 1>"),
+    (_call("scan", 4096, 2, 4, 1024, 1, 2, "int32"), "k_scan_pipe<int, 4, 0, false>"),
+    (_call("scan", 8192, 2, 8, 1024, 1, 3, "float32"), "k_scan_pipe<float, 8, 1, false>"),
+    (_call("scan", 64, 2, 4, 64, 4, 1, "float32"), "k_scan<float, 4, 1, false>"),
+    (dict(_call("scan", 1024, 2, 16, 64, 1, 0, "float64"), exclusive=True), "k_scan<double, 16, 0, true>"),
     (_call("tridiag_cr", 256, 2, 8, 128, 4, 2, "float32"), "k_tridiag_wave<float, 2, 8>"),
     (_call("tridiag_cr", 128, 2, 8, 128, 8, 10, "float32"), "k_tridiag_wave_pipe<float, 2, 8>"),
     (_call("tridiag_pcr", 1024, 2, 16, 256, 4, 4, "float64"), "k_tridiag_wave<double, 4, 16>"),

@@ -102,3 +102,78 @@ def test_pins_catch_planted_mistakes(name):
         except AssertionError:
             failed += 1
     assert failed >= 1, f"no pin caught mutant {name}"
+
+
+# ------------------------------------------------------------ exclusive form
+# Each output is the sum of the elements strictly before it (0 first).
+
+def _excl(x):
+    return oracle.scan(x, exclusive=True)
+
+
+def test_exclusive_closed_forms():
+    n = 100
+    assert np.array_equal(_excl(np.ones((1, n), np.int32))[0], np.arange(n))
+    ar = np.arange(n, dtype=np.int32)[None]
+    assert np.array_equal(_excl(ar)[0], np.arange(n) * (np.arange(n) - 1) // 2)
+    imp = np.zeros((1, 16), np.int32)
+    imp[0, 5] = 7
+    assert np.array_equal(_excl(imp)[0], np.where(np.arange(16) > 5, 7, 0))
+    x = np.random.default_rng(2).integers(-9, 9, (3, 33), dtype=np.int32)
+    assert np.all(_excl(x)[:, 0] == 0)
+    assert np.all(_excl(x.astype(np.float64))[:, 0] == 0.0)
+
+
+def test_exclusive_brute_force_01():
+    vecs = np.array(list(itertools.product([0, 1], repeat=10)), dtype=np.int32)
+    y = _excl(vecs)
+    for v, yy in zip(vecs[::29], y[::29]):
+        ref, before = [], 0
+        for e in v:
+            ref.append(before)
+            before += int(e)
+        assert list(yy) == ref
+
+
+def test_exclusive_against_numpy_with_wrap():
+    x = np.random.default_rng(4).integers(-2 ** 31, 2 ** 31, (5, 1000), dtype=np.int32)
+    want = np.zeros((5, 1000), dtype=np.int64)
+    want[:, 1:] = np.cumsum(x.astype(np.int64), axis=1)[:, :-1]
+    want = (want % (1 << 32)).astype(np.uint32).view(np.int32)
+    assert np.array_equal(_excl(x), want)
+
+
+def test_exclusive_in_place_buffer_semantics():
+    # the exclusive output at i never depends on x[i]: changing the last
+    # element of a row changes no output of that row
+    x = inputs.scan_input(64, 3, np.int32, seed=8)
+    x2 = x.copy()
+    x2[:, -1] += 5
+    assert np.array_equal(_excl(x), _excl(x2))
+
+
+# ------------------------------------------------------------ float64 inputs
+
+@pytest.mark.parametrize("exclusive", [False, True])
+def test_float64_exact_on_dyadic_values(exclusive):
+    k, x = inputs.scan_input_dyadic(4096, 3, seed=12)
+    s = np.cumsum(k, axis=1)
+    if exclusive:
+        s = np.concatenate([np.zeros((3, 1), np.int64), s[:, :-1]], axis=1)
+    assert np.array_equal(oracle.scan(x, exclusive=exclusive), s.astype(np.float64) * 2.0 ** -20)
+
+
+def test_float64_within_recursive_summation_bound():
+    # Left-to-right summation of i+1 terms is within i * u / (1 - i u) of
+    # the exact sum, relative to the sum of |x| (Higham, Accuracy and
+    # Stability of Numerical Algorithms, Sec. 4.2); math.fsum gives the
+    # correctly rounded exact sum.
+    import math
+    x = np.random.default_rng(13).standard_normal((2, 600))
+    y = oracle.scan(x)
+    u = 2.0 ** -53
+    for b in range(2):
+        for i in range(0, 600, 7):
+            exact = math.fsum(x[b, :i + 1])
+            s_abs = math.fsum(np.abs(x[b, :i + 1]))
+            assert abs(y[b, i] - exact) <= (i * u / (1 - i * u)) * s_abs + u * abs(exact)
