@@ -79,8 +79,15 @@ extern "C" {
                                a per-wave LDS buffer of 3 * 64 * min(P, 4)
                                values (16-byte accesses) instead of shuffles;
                                S = 0, n / P <= 64, P <= 16 */
-#define PPX_TRI_PIPE 8      /* flag, OR-ed onto PPX_TRI_CR_SHFL, _PCR_SHFL or
-                               _PCR_REG: persistent workgroups (as many as are
+#define PPX_TRI_WM 5        /* Wang & Mou divide and conquer inside a wave
+                               (Sec. III): blocks of equations merge in pairs,
+                               each equation kept solved in terms of its
+                               block's two outer unknowns; radix P (a lane's P
+                               equations form the first node), then radix 2
+                               across lanes by broadcasts; S = 0, n / P <= 64,
+                               P <= 16 */
+#define PPX_TRI_PIPE 8      /* flag, OR-ed onto PPX_TRI_CR_SHFL, _PCR_SHFL,
+                               _PCR_REG or _WM: persistent workgroups (as many as are
                                resident) that load the next group of systems
                                while solving the current one; needs
                                P * sizeof(element) <= 32 */

@@ -85,8 +85,12 @@ constexpr int tri_wave_max_p(int, int) { return 16; }
 constexpr int tri_base(int algo) { return algo & ~PPX_TRI_PIPE; }
 constexpr bool tri_in_wave(int algo) { return tri_base(algo) >= PPX_TRI_CR_SHFL; }
 constexpr int tri_family(int algo) {
-    return tri_base(algo) == PPX_TRI_CR || tri_base(algo) == PPX_TRI_CR_SHFL ? PPX_TRI_CR : PPX_TRI_PCR;
+    return tri_base(algo) == PPX_TRI_CR || tri_base(algo) == PPX_TRI_CR_SHFL ? PPX_TRI_CR
+           : tri_base(algo) == PPX_TRI_WM                                   ? PPX_TRI_WM
+                                                                             : PPX_TRI_PCR;
 }
+// Largest variant code without the persistent flag.
+constexpr int kTriMaxBase = PPX_TRI_WM;
 // Largest P * sizeof(element) of the persistent in-wave variants (the second
 // register set).
 constexpr int kTriPipeMaxBytes = 32;

@@ -1,4 +1,4 @@
-// Tridiagonal CR and PCR inside one wave (the paper's "shuffle" variant of
+// Tridiagonal CR, PCR and Wang & Mou inside one wave (the paper's "shuffle" variant of
 // Sec. V-A, where a problem small enough for one warp exchanges through
 // shuffles instead of shared memory; on gfx950 the wave has 64 lanes, so the
 // condition is n / P <= 64).  Rows are kept at unit diagonal and eliminated by
@@ -311,6 +311,127 @@ __device__ __forceinline__ void wave_pcr_reg(T (&a)[P], T (&c)[P], T (&d)[P], in
     }
 }
 
+// ---- Wang & Mou divide and conquer (PPX_TRI_WM)
+//
+// Every equation i of a block [s, e] of consecutive equations is kept solved
+// for its own unknown in terms of the two unknowns just outside the block:
+//     x_i = d_i - a_i x_{s-1} - c_i x_{e+1}
+// (a unit-diagonal row is this form for the block [i, i]).  Two adjacent
+// blocks L = [s, m] and R = [m+1, e] merge by solving the last equation of L
+// and the first of R for x_m and x_{m+1} (pivot 1 - c_m a_{m+1}), which gives
+// both in terms of x_{s-1} and x_{e+1}; every equation of L then replaces its
+// x_{m+1} term, every equation of R its x_m term.  Blocks double at each level:
+// after log2 n levels the block is the whole system, whose outer unknowns are
+// absent, and x_i = d_i.  The first log2 P levels merge a lane's own P
+// equations (the radix-P node); each further level needs only the two
+// boundary equations, broadcast to the lanes of the merging pair of lane
+// blocks.  A block that starts at equation 0 keeps a = 0 and one that ends at
+// n - 1 keeps c = 0 (the pivot terms that would change them are products with
+// those zeros), so several systems may share a wave: no merge crosses a
+// system, whose lanes form an aligned group of lps lanes.
+
+// The values the two halves apply: x_{m+1} = dn - an X - cn Y (for L) and
+// x_m = dm - am X - cm Y (for R), X = x_{s-1}, Y = x_{e+1}.
+template <typename T>
+struct WmJoin {
+    T an, cn, dn, am, cm, dm;
+};
+
+template <typename T>
+__device__ __forceinline__ WmJoin<T> wm_join(T aL, T cL, T dL, T aR, T cR, T dR) {
+    const T r = rcp(T(1) - cL * aR);
+    WmJoin<T> j;
+    j.dn = (dR - aR * dL) * r;
+    j.an = -(aR * aL) * r;
+    j.cn = cR * r;
+    j.dm = (dL - cL * dR) * r;
+    j.am = aL * r;
+    j.cm = -(cL * cR) * r;
+    return j;
+}
+
+// Equation of L: substitute x_{m+1}.
+template <typename T>
+__device__ __forceinline__ void wm_left(T &a, T &c, T &d, const WmJoin<T> &j) {
+    d -= c * j.dn;
+    a -= c * j.an;
+    c = -(c * j.cn);
+}
+
+// Equation of R: substitute x_m.
+template <typename T>
+__device__ __forceinline__ void wm_right(T &a, T &c, T &d, const WmJoin<T> &j) {
+    d -= a * j.dm;
+    c -= a * j.cm;
+    a = -(a * j.am);
+}
+
+// The levels inside a lane: blocks of s equations merge in pairs, s < P.
+template <typename T, int P>
+__device__ __forceinline__ void wm_inlane(T (&a)[P], T (&c)[P], T (&d)[P]) {
+#pragma unroll
+    for (int s = 1; s < P; s *= 2) {
+#pragma unroll
+        for (int b = 0; b < P; b += 2 * s) {
+            const int m = b + s - 1;
+            const WmJoin<T> j = wm_join(a[m], c[m], d[m], a[m + 1], c[m + 1], d[m + 1]);
+#pragma unroll
+            for (int i = b; i <= m; ++i) wm_left(a[i], c[i], d[i], j);
+#pragma unroll
+            for (int i = m + 1; i < b + 2 * s; ++i) wm_right(a[i], c[i], d[i], j);
+        }
+    }
+}
+
+// Lane level K: blocks of 2^K lanes merge in pairs.  The last equation of the
+// left block sits in lane (lane & ~(2^(K+1) - 1)) + 2^K - 1, the first of the
+// right block in the next lane; swizzle broadcasts within 32-lane halves for
+// K < 5, lanes 31 and 32 for K = 5 (one system per wave).  Branch-free: a
+// lane of the left block substitutes x_{m+1} (through c), one of the right
+// block x_m (through a).
+template <typename T, int P, int K>
+__device__ __forceinline__ void wm_lane_level(T (&a)[P], T (&c)[P], T (&d)[P], int t) {
+    T aL, cL, dL, aR, cR, dR;
+    if constexpr (K < 5) {
+        constexpr int AND = 0x1f & ~((2 << K) - 1);
+        aL = swz<AND, (1 << K) - 1>(a[P - 1]);
+        cL = swz<AND, (1 << K) - 1>(c[P - 1]);
+        dL = swz<AND, (1 << K) - 1>(d[P - 1]);
+        aR = swz<AND, (1 << K)>(a[0]);
+        cR = swz<AND, (1 << K)>(c[0]);
+        dR = swz<AND, (1 << K)>(d[0]);
+    } else {
+        aL = per_word(a[P - 1], [](int w) { return __builtin_amdgcn_readlane(w, 31); });
+        cL = per_word(c[P - 1], [](int w) { return __builtin_amdgcn_readlane(w, 31); });
+        dL = per_word(d[P - 1], [](int w) { return __builtin_amdgcn_readlane(w, 31); });
+        aR = per_word(a[0], [](int w) { return __builtin_amdgcn_readlane(w, 32); });
+        cR = per_word(c[0], [](int w) { return __builtin_amdgcn_readlane(w, 32); });
+        dR = per_word(d[0], [](int w) { return __builtin_amdgcn_readlane(w, 32); });
+    }
+    const WmJoin<T> j = wm_join(aL, cL, dL, aR, cR, dR);
+    const bool left = ((t >> K) & 1) == 0;
+    const T al = left ? j.an : j.am, cl = left ? j.cn : j.cm, dl = left ? j.dn : j.dm;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const T u = left ? c[i] : a[i];  // the coefficient of the substituted unknown
+        const T ka = left ? a[i] : T(0), kc = left ? T(0) : c[i];
+        d[i] -= u * dl;
+        a[i] = ka - u * al;
+        c[i] = kc - u * cl;
+    }
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void wave_wm(T (&a)[P], T (&c)[P], T (&d)[P], int t, int lps) {
+    wm_inlane<T, P>(a, c, d);
+    if (lps > 1) wm_lane_level<T, P, 0>(a, c, d, t);
+    if (lps > 2) wm_lane_level<T, P, 1>(a, c, d, t);
+    if (lps > 4) wm_lane_level<T, P, 2>(a, c, d, t);
+    if (lps > 8) wm_lane_level<T, P, 3>(a, c, d, t);
+    if (lps > 16) wm_lane_level<T, P, 4>(a, c, d, t);
+    if (lps > 32) wm_lane_level<T, P, 5>(a, c, d, t);
+}
+
 // Boundary zeros, unit-diagonal scaling and the solve of the equations a
 // lane holds (b is consumed; x ends in d).
 template <typename T, int ALGO, int P>
@@ -327,6 +448,7 @@ __device__ __forceinline__ void tridiag_wave_solve(T (&a)[P], const T (&b)[P], T
     }
     if constexpr (ALGO == PPX_TRI_CR_SHFL) wave_cr<T, P>(a, c, d, t, lps);
     else if constexpr (ALGO == PPX_TRI_PCR_SHFL) wave_pcr<T, P>(a, c, d, lps);
+    else if constexpr (ALGO == PPX_TRI_WM) wave_wm<T, P>(a, c, d, t, lps);
     else wave_pcr_reg<T, P>(a, c, d, t, lps, smem + (threadIdx.x >> 6) * (3 * 64 * (P < 4 ? P : 4)));
 }
 

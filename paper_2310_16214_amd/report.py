@@ -10,7 +10,7 @@ import json
 import sys
 
 DT = {0: "int32", 1: "f32", 2: "f64", 3: "c64"}
-ALGO = {-1: "", 0: " CR", 1: " PCR"}
+ALGO = {-1: "", 0: " CR", 1: " PCR", 5: " WM"}
 
 
 def cfg_str(c):
@@ -28,6 +28,18 @@ def tuning(path):
                    f"{r['gelem_s']:.0f} | {cfg_str(r['analytical']['cfg'])} ({r['e_analytical']:.2f}) | "
                    f"{cfg_str(r['learned']['cfg'])} ({r['e_learned']:.2f}, {r['learned']['evals']}/{r['exhaustive']['space']}) | "
                    f"{r['default']['us']:.1f} | {r['tuned_vs_default']:.2f} | {r.get('batched_vs_plain', float('nan')):.0f} |")
+    forms = [r for r in d["records"] if "forms_us" in r]
+    if forms:
+        out += ["", "Scan forms with the exhaustive-best configuration (events per launch, median, input sets rotated "
+                    "over >= 1 GiB); algorithmic bytes = one read and one write of every element; HBM peak 8 TB/s.", "",
+                "| scan | N | inclusive us | exclusive us | excl/incl | inclusive GB/s | % of HBM peak |",
+                "|---|---|---|---|---|---|---|"]
+        for r in forms:
+            es = 8 if r["dtype"] == 2 else 4
+            f = r["forms_us"]
+            gbs = 2 * es * r["n"] * r["batch"] / f["incl"] / 1e3
+            out.append(f"| {DT[r['dtype']]} | {r['n']} | {f['incl']:.1f} | {f['excl']:.1f} | "
+                       f"{f['excl'] / f['incl']:.3f} | {gbs:.0f} | {100 * gbs / 8000:.1f} |")
     out += ["", "| group | sizes | Phi analytical | Phi learned | mean learned evals | geo-mean tuned/default |",
             "|---|---|---|---|---|---|"]
     for s in d["summary"]:

@@ -35,14 +35,46 @@ def sweeps(ops):
         for ln in range(4, 15):
             out.append(("fft", ppx.OP_FFT, ppx.C64, 1 << ln, (1 << 25) >> ln, -1))
     if "scan" in ops:
-        for code in (ppx.I32, ppx.F32):
+        for code in (ppx.I32, ppx.F32, ppx.F64):
             for ln in range(5, 14):
                 out.append(("scan", ppx.OP_SCAN, code, 1 << ln, (1 << 24) >> ln, -1))
     if "tridiag" in ops:
         for code in (ppx.F32, ppx.F64):
-            for algo in (ppx.TRI_CR, ppx.TRI_PCR):
+            for algo in (ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_WM):
                 for ln in range(5, 11):
                     out.append(("tridiag", ppx.OP_TRIDIAG, code, 1 << ln, (1 << 22) >> ln, algo))
+    return out
+
+
+def scan_forms_us(ppx, dtype, n, batch, cfg, reps, dev):
+    """Median microseconds of the inclusive and of the exclusive scan with one
+    configuration, each launch timed with events on the current stream and
+    reading a different input set (>= 1 GiB rotated, so no launch reads
+    cached data)."""
+    import statistics
+
+    import torch
+    t = {ppx.I32: torch.int32, ppx.F32: torch.float32, ppx.F64: torch.float64}[dtype]
+    set_bytes = 2 * n * batch * (8 if dtype == ppx.F64 else 4)
+    nsets = max(2, min(16, -(-(1 << 30) // set_bytes)))
+    xs = [torch.ones((batch, n), dtype=t, device=dev) for _ in range(nsets)]
+    ys = [torch.empty_like(x) for x in xs]
+    out = {}
+    for excl in (False, True):
+        f = ppx.scan_exclusive_batched if excl else ppx.scan_batched
+        for w in range(3):
+            f(xs[w % nsets], ys[w % nsets], n, batch, dtype, cfg)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for r in range(reps):
+            i = (r + 3) % nsets
+            ev[r][0].record()
+            f(xs[i], ys[i], n, batch, dtype, cfg)
+            ev[r][1].record()
+        torch.cuda.synchronize()
+        out["excl" if excl else "incl"] = statistics.median(a.elapsed_time(b) * 1e3 for a, b in ev)
+    del xs, ys
+    torch.cuda.empty_cache()
     return out
 
 
@@ -55,7 +87,7 @@ def plain_time_us(ppx, op, dtype, n, launches, dev):
         y = torch.empty_like(x)
         run = lambda i: ppx.fft_batched(x[i], y[i], n, 1, -1, cfg)  # noqa: E731
     elif op == ppx.OP_SCAN:
-        t = torch.int32 if dtype == ppx.I32 else torch.float32
+        t = {ppx.I32: torch.int32, ppx.F32: torch.float32, ppx.F64: torch.float64}[dtype]
         x = torch.zeros((launches, n), dtype=t, device=dev)
         y = torch.empty_like(x)
         run = lambda i: ppx.scan_batched(x[i], y[i], n, 1, dtype, cfg)  # noqa: E731
@@ -121,6 +153,10 @@ def main():
             rec["e_" + m + "_retimed"] = best / rec[m]["us"]
         rec["tuned_vs_default"] = rec["default"]["us"] / best
         rec["gelem_s"] = n * batch / best / 1e3
+        if op == ppx.OP_SCAN:
+            c = rec["exhaustive"]["cfg"]
+            cfg = ppx.make_config(c["radix"], c["threads_per_block"], c["problems_per_block"], c["algo"])
+            rec["forms_us"] = scan_forms_us(ppx, dtype, n, batch, cfg, args.reps, dev)
         if args.plain_launches > 0:
             k = min(args.plain_launches, batch)
             per = plain_time_us(ppx, op, dtype, n, k, dev)

@@ -144,6 +144,19 @@ def test_scan_float64_space():
         assert ppx.config_valid(ppx.OP_SCAN, ppx.F64, n, c)
 
 
+def test_tridiag_wm_space():
+    wm = ppx.TRI_WM
+    assert ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 1024, ppx.make_config(2, 64, 1, wm))       # P 16
+    assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 2048, ppx.make_config(2, 128, 1, wm))  # 128 lanes
+    assert ppx.config_valid(ppx.OP_TRIDIAG, ppx.F64, 64, ppx.make_config(2, 64, 2, wm | ppx.TRI_PIPE))
+    assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F64, 64, ppx.make_config(2, 64, 8, wm | ppx.TRI_PIPE))
+    assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 64, ppx.make_config(2, 64, 4, 6))
+    assert ppx.tri_family(wm | ppx.TRI_PIPE) == wm
+    cs = ppx.enumerate_configs(ppx.OP_TRIDIAG, ppx.F64, 256)
+    assert any(c.algo == wm for c in cs) and any(c.algo == wm | ppx.TRI_PIPE for c in cs)
+    assert not any(ppx.tri_family(c.algo) == wm for c in ppx.enumerate_configs(ppx.OP_TRIDIAG, ppx.F32, 4096))
+
+
 def test_fft_p32_thread_cap():
     assert ppx.config_valid(ppx.OP_FFT, ppx.C64, 16384, ppx.make_config(16, 512, 1))
     assert not ppx.config_valid(ppx.OP_FFT, ppx.C64, 16384, ppx.make_config(16, 1024, 2, 1))
