@@ -86,8 +86,13 @@ extern "C" {
                                equations form the first node), then radix 2
                                across lanes by broadcasts; S = 0, n / P <= 64,
                                P <= 16 */
+#define PPX_TRI_LF 6        /* Ladner-Fischer solver inside a wave (Sec. III):
+                               a prefix scan (Ladner-Fischer circuit) over
+                               elements of two equations, the first and last
+                               of a block, then one over the back-substitution
+                               maps; S = 0, n / P <= 64, P <= 16 */
 #define PPX_TRI_PIPE 8      /* flag, OR-ed onto PPX_TRI_CR_SHFL, _PCR_SHFL,
-                               _PCR_REG or _WM: persistent workgroups (as many as are
+                               _PCR_REG, _WM or _LF: persistent workgroups (as many as are
                                resident) that load the next group of systems
                                while solving the current one; needs
                                P * sizeof(element) <= 32 */

@@ -87,10 +87,11 @@ constexpr bool tri_in_wave(int algo) { return tri_base(algo) >= PPX_TRI_CR_SHFL;
 constexpr int tri_family(int algo) {
     return tri_base(algo) == PPX_TRI_CR || tri_base(algo) == PPX_TRI_CR_SHFL ? PPX_TRI_CR
            : tri_base(algo) == PPX_TRI_WM                                   ? PPX_TRI_WM
+           : tri_base(algo) == PPX_TRI_LF                                   ? PPX_TRI_LF
                                                                              : PPX_TRI_PCR;
 }
 // Largest variant code without the persistent flag.
-constexpr int kTriMaxBase = PPX_TRI_WM;
+constexpr int kTriMaxBase = PPX_TRI_LF;
 // Largest P * sizeof(element) of the persistent in-wave variants (the second
 // register set).
 constexpr int kTriPipeMaxBytes = 32;

@@ -49,6 +49,7 @@ static const void *wave_kernel(int base, int P) {
         case PPX_TRI_PCR_SHFL: return wave_kernel_p<T, PPX_TRI_PCR_SHFL, PIPE>(P);
         case PPX_TRI_PCR_REG: return wave_kernel_p<T, PPX_TRI_PCR_REG, PIPE>(P);
         case PPX_TRI_WM: return wave_kernel_p<T, PPX_TRI_WM, PIPE>(P);
+        case PPX_TRI_LF: return wave_kernel_p<T, PPX_TRI_LF, PIPE>(P);
         default: return nullptr;
     }
 }

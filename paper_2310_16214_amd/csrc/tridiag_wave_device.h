@@ -1,6 +1,6 @@
-// Tridiagonal CR, PCR and Wang & Mou inside one wave (the paper's "shuffle" variant of
-// Sec. V-A, where a problem small enough for one warp exchanges through
-// shuffles instead of shared memory; on gfx950 the wave has 64 lanes, so the
+// Tridiagonal CR, PCR, Wang & Mou and Ladner-Fischer solvers inside one wave
+// (the paper's "shuffle" variant of Sec. V-A, where a problem small enough for
+// one warp exchanges through shuffles instead of shared memory; on gfx950 the wave has 64 lanes, so the
 // condition is n / P <= 64).  Rows are kept at unit diagonal and eliminated by
 // unit_eliminate, as in the LDS kernels of tridiag_device.h.
 //
@@ -432,6 +432,123 @@ __device__ __forceinline__ void wave_wm(T (&a)[P], T (&c)[P], T (&d)[P], int t, 
     if (lps > 32) wm_lane_level<T, P, 5>(a, c, d, t);
 }
 
+// ---- Ladner-Fischer solver (PPX_TRI_LF)
+//
+// A block of consecutive equations is summarised by two equations, those of
+// its first and of its last unknown, each in terms of the two unknowns just
+// outside the block (the form of the Wang & Mou blocks above); two adjacent
+// summaries combine with one join.  This combination is associative, so the
+// summaries of the prefixes [0, i] follow from a scan with the
+// Ladner-Fischer circuit; the last equation of prefix [0, i] reads
+// x_i = d_i - c_i x_{i+1} (its a is 0: nothing lies before equation 0).  A
+// second Ladner-Fischer scan, over the affine maps x_{i+1} -> x_i from the
+// right, then gives every unknown.  In a lane:
+//   1. the summary of its P equations, serially;
+//   2. an inclusive scan of the lane summaries across the system's lanes
+//      (at level K a lane of the upper half of each 2^(K+1)-lane block
+//      combines the summary broadcast from the last lane of the lower half);
+//   3. from the last equation of the previous lane's prefix, the forward
+//      sweep over its own equations (one join each: the Thomas elimination);
+//   4. the composition of its P maps, an inclusive scan of the lane maps
+//      from the right (lower-half lanes take the upper half's first lane),
+//      and the back substitution from the next lane's first unknown.
+
+template <typename T>
+struct TriEq {
+    T a, c, d;
+};
+
+// Summary (f, l) of a block followed by (bf, bl) of the next: f takes the
+// join's x_{m+1} term, l = bl its x_m term.
+template <typename T>
+__device__ __forceinline__ void lf_combine(TriEq<T> &f, TriEq<T> &l, const TriEq<T> &bf, const TriEq<T> &bl) {
+    const WmJoin<T> j = wm_join(l.a, l.c, l.d, bf.a, bf.c, bf.d);
+    wm_left(f.a, f.c, f.d, j);
+    l = bl;
+    wm_right(l.a, l.c, l.d, j);
+}
+
+template <int K, bool FROM_LOW, typename T>
+__device__ __forceinline__ T lf_bcast(T v) {
+    if constexpr (K < 5) {
+        constexpr int AND = 0x1f & ~((2 << K) - 1);
+        return swz<AND, FROM_LOW ? (1 << K) - 1 : (1 << K)>(v);
+    } else {
+        return per_word(v, [](int w) { return __builtin_amdgcn_readlane(w, FROM_LOW ? 31 : 32); });
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void lf_prefix_level(TriEq<T> &f, TriEq<T> &l, int t) {
+    TriEq<T> sf, sl;
+    sf.a = lf_bcast<K, true>(f.a);
+    sf.c = lf_bcast<K, true>(f.c);
+    sf.d = lf_bcast<K, true>(f.d);
+    sl.a = lf_bcast<K, true>(l.a);
+    sl.c = lf_bcast<K, true>(l.c);
+    sl.d = lf_bcast<K, true>(l.d);
+    lf_combine(sf, sl, f, l);
+    if ((t >> K) & 1) {
+        f = sf;
+        l = sl;
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void lf_suffix_level(T &al, T &be, int t) {
+    const T sa = lf_bcast<K, false>(al), sb = lf_bcast<K, false>(be);
+    if (!((t >> K) & 1)) {  // own map after the upper half's: x = al - be * (sa - sb * Y)
+        al -= be * sa;
+        be = -(be * sb);
+    }
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void wave_lf(T (&a)[P], T (&c)[P], T (&d)[P], int t, int lps) {
+    // 1. the lane's summary
+    TriEq<T> f{a[0], c[0], d[0]}, l = f;
+#pragma unroll
+    for (int j = 1; j < P; ++j) lf_combine(f, l, TriEq<T>{a[j], c[j], d[j]}, TriEq<T>{a[j], c[j], d[j]});
+    // 2. prefix summaries of the lanes
+    if (lps > 1) lf_prefix_level<T, 0>(f, l, t);
+    if (lps > 2) lf_prefix_level<T, 1>(f, l, t);
+    if (lps > 4) lf_prefix_level<T, 2>(f, l, t);
+    if (lps > 8) lf_prefix_level<T, 3>(f, l, t);
+    if (lps > 16) lf_prefix_level<T, 4>(f, l, t);
+    if (lps > 32) lf_prefix_level<T, 5>(f, l, t);
+    // 3. forward sweep from the previous lane's prefix (none for the first)
+    T cq = sys_up(l.c, 1, lps), dq = sys_up(l.d, 1, lps);
+    if (t == 0) cq = dq = T(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const T r = rcp(T(1) - cq * a[j]);
+        dq = (d[j] - a[j] * dq) * r;
+        cq = c[j] * r;
+        c[j] = cq;
+        d[j] = dq;
+    }
+    // 4. maps from the right and back substitution
+    T al = d[P - 1], be = c[P - 1];
+#pragma unroll
+    for (int j = P - 2; j >= 0; --j) {
+        al = d[j] - c[j] * al;
+        be = -(c[j] * be);
+    }
+    if (lps > 1) lf_suffix_level<T, 0>(al, be, t);
+    if (lps > 2) lf_suffix_level<T, 1>(al, be, t);
+    if (lps > 4) lf_suffix_level<T, 2>(al, be, t);
+    if (lps > 8) lf_suffix_level<T, 3>(al, be, t);
+    if (lps > 16) lf_suffix_level<T, 4>(al, be, t);
+    if (lps > 32) lf_suffix_level<T, 5>(al, be, t);
+    T x = sys_down(al, 1, lps);  // first unknown of the next lane
+    if (t == lps - 1) x = T(0);
+#pragma unroll
+    for (int j = P - 1; j >= 0; --j) {
+        x = d[j] - c[j] * x;
+        d[j] = x;
+    }
+}
+
 // Boundary zeros, unit-diagonal scaling and the solve of the equations a
 // lane holds (b is consumed; x ends in d).
 template <typename T, int ALGO, int P>
@@ -449,6 +566,7 @@ __device__ __forceinline__ void tridiag_wave_solve(T (&a)[P], const T (&b)[P], T
     if constexpr (ALGO == PPX_TRI_CR_SHFL) wave_cr<T, P>(a, c, d, t, lps);
     else if constexpr (ALGO == PPX_TRI_PCR_SHFL) wave_pcr<T, P>(a, c, d, lps);
     else if constexpr (ALGO == PPX_TRI_WM) wave_wm<T, P>(a, c, d, t, lps);
+    else if constexpr (ALGO == PPX_TRI_LF) wave_lf<T, P>(a, c, d, t, lps);
     else wave_pcr_reg<T, P>(a, c, d, t, lps, smem + (threadIdx.x >> 6) * (3 * 64 * (P < 4 ? P : 4)));
 }
 

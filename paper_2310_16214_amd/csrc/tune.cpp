@@ -520,7 +520,7 @@ static int static_vgprs(int op, int dtype, int P, int algo) {
     if (op == PPX_OP_SCAN)
         return (dtype == PPX_F64 ? 2 : 1) * (P <= 2 ? 10 : P <= 4 ? 12 : P <= 8 ? 16 : P <= 16 ? 24 : 40);
     if (tri_in_wave(algo))
-        return (dtype == PPX_F64 ? 2 : 1) * (tri_base(algo) == PPX_TRI_CR_SHFL || tri_base(algo) == PPX_TRI_WM ? 5 : 6) * P *
+        return (dtype == PPX_F64 ? 2 : 1) * (tri_base(algo) == PPX_TRI_CR_SHFL || tri_base(algo) >= PPX_TRI_WM ? 5 : 6) * P *
                    ((algo & PPX_TRI_PIPE) ? 2 : 1) + 16;
     return dtype == PPX_F64 ? (algo == PPX_TRI_PCR ? 44 : 40) : (algo == PPX_TRI_PCR ? 32 : 28);
 }

@@ -25,14 +25,15 @@ I32, F32, F64, C64 = 0, 1, 2, 3
 OP_FFT, OP_SCAN, OP_TRIDIAG = 0, 1, 2
 FFT_LDS, FFT_LDS_SPLIT, FFT_LDS_PIPE, FFT_LDS_SPLIT_PIPE = 0, 1, 2, 3
 SCAN_KS, SCAN_LF, SCAN_KS_PIPE, SCAN_LF_PIPE = 0, 1, 2, 3
-TRI_CR, TRI_PCR, TRI_CR_SHFL, TRI_PCR_SHFL, TRI_PCR_REG, TRI_WM = 0, 1, 2, 3, 4, 5
+TRI_CR, TRI_PCR, TRI_CR_SHFL, TRI_PCR_SHFL, TRI_PCR_REG, TRI_WM, TRI_LF = 0, 1, 2, 3, 4, 5, 6
 TRI_PIPE = 8  # flag on an in-wave variant: persistent workgroups with prefetch
 
 
 def tri_family(algo):
-    """TRI_CR for the CR variants, TRI_WM for Wang & Mou, TRI_PCR for the PCR variants."""
+    """TRI_CR for the CR variants, TRI_WM / TRI_LF for Wang & Mou / Ladner-Fischer,
+    TRI_PCR for the PCR variants."""
     base = algo & ~TRI_PIPE
-    return TRI_CR if base in (TRI_CR, TRI_CR_SHFL) else TRI_WM if base == TRI_WM else TRI_PCR
+    return TRI_CR if base in (TRI_CR, TRI_CR_SHFL) else base if base in (TRI_WM, TRI_LF) else TRI_PCR
 TUNE_EXHAUSTIVE, TUNE_ANALYTICAL, TUNE_LEARNED = 0, 1, 2
 MIN_N, MAX_N = 16, 16384
 

@@ -10,7 +10,7 @@ import json
 import sys
 
 DT = {0: "int32", 1: "f32", 2: "f64", 3: "c64"}
-ALGO = {-1: "", 0: " CR", 1: " PCR", 5: " WM"}
+ALGO = {-1: "", 0: " CR", 1: " PCR", 5: " WM", 6: " LF"}
 
 
 def cfg_str(c):

@@ -40,7 +40,7 @@ def sweeps(ops):
                 out.append(("scan", ppx.OP_SCAN, code, 1 << ln, (1 << 24) >> ln, -1))
     if "tridiag" in ops:
         for code in (ppx.F32, ppx.F64):
-            for algo in (ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_WM):
+            for algo in (ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_WM, ppx.TRI_LF):
                 for ln in range(5, 11):
                     out.append(("tridiag", ppx.OP_TRIDIAG, code, 1 << ln, (1 << 22) >> ln, algo))
     return out
@@ -138,6 +138,12 @@ def main():
         if algo >= 0:
             dflt.algo = algo
             dflt.lds_elems = 0
+            if not ppx.config_valid(op, dtype, n, dflt):
+                # in-wave only (Wang & Mou): one system per workgroup with the
+                # fewest equations per lane
+                dflt = min((c for c in ppx.enumerate_configs(op, dtype, n)
+                            if c.algo == algo and c.problems_per_block == 1),
+                           key=lambda c: c.elems_per_thread)
         rec["default"] = dict(cfg=dflt.as_dict(), us=ppx.time_config(op, dtype, n, batch, dflt,
                                                                      args.reps))
         # efficiency as the paper defines it: performance of the method's

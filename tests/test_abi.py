@@ -150,8 +150,10 @@ def test_tridiag_wm_space():
     assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 2048, ppx.make_config(2, 128, 1, wm))  # 128 lanes
     assert ppx.config_valid(ppx.OP_TRIDIAG, ppx.F64, 64, ppx.make_config(2, 64, 2, wm | ppx.TRI_PIPE))
     assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F64, 64, ppx.make_config(2, 64, 8, wm | ppx.TRI_PIPE))
-    assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 64, ppx.make_config(2, 64, 4, 6))
+    assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 64, ppx.make_config(2, 64, 4, 7))
+    assert ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 64, ppx.make_config(2, 64, 4, ppx.TRI_LF))
     assert ppx.tri_family(wm | ppx.TRI_PIPE) == wm
+    assert ppx.tri_family(ppx.TRI_LF | ppx.TRI_PIPE) == ppx.TRI_LF
     cs = ppx.enumerate_configs(ppx.OP_TRIDIAG, ppx.F64, 256)
     assert any(c.algo == wm for c in cs) and any(c.algo == wm | ppx.TRI_PIPE for c in cs)
     assert not any(ppx.tri_family(c.algo) == wm for c in ppx.enumerate_configs(ppx.OP_TRIDIAG, ppx.F32, 4096))

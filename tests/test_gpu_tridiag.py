@@ -1,5 +1,5 @@
-"""GPU parity of the batched CR / PCR / Wang & Mou tridiagonal solvers against
-the FP64 Thomas oracle.
+"""GPU parity of the batched CR / PCR / Wang & Mou / Ladner-Fischer tridiagonal
+solvers against the FP64 Thomas oracle.
 
 Bar: per-system relative residual ||A x - d|| / ||d|| (float64, on the stored
 coefficients) <= 1e-4 for float32 and <= 1e-12 for float64; the forward error
@@ -45,7 +45,7 @@ def test_every_config(cuda, n, dtype):
           f"|x-oracle| {fe:.2e}, |x-x_true| {np.max(np.abs(x - xt)):.2e}")
 
 
-IN_WAVE = [ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL, ppx.TRI_PCR_REG, ppx.TRI_WM]
+IN_WAVE = [ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL, ppx.TRI_PCR_REG, ppx.TRI_WM, ppx.TRI_LF]
 ALL_ALGOS = [ppx.TRI_CR, ppx.TRI_PCR] + IN_WAVE + [a | ppx.TRI_PIPE for a in IN_WAVE]
 
 
@@ -105,7 +105,9 @@ PERSISTENT = [(64, np.float32, 64, 4, ppx.TRI_CR_SHFL | ppx.TRI_PIPE),
               (128, np.float32, 256, 16, ppx.TRI_CR_SHFL | ppx.TRI_PIPE),
               (128, np.float32, 128, 4, ppx.TRI_WM | ppx.TRI_PIPE),
               (64, np.float64, 64, 2, ppx.TRI_WM | ppx.TRI_PIPE),
-              (32, np.float32, 256, 64, ppx.TRI_WM | ppx.TRI_PIPE)]
+              (32, np.float32, 256, 64, ppx.TRI_WM | ppx.TRI_PIPE),
+              (256, np.float32, 256, 8, ppx.TRI_LF | ppx.TRI_PIPE),
+              (128, np.float64, 128, 2, ppx.TRI_LF | ppx.TRI_PIPE)]
 
 
 @pytest.mark.parametrize("n,dtype,L,G,algo", PERSISTENT)
@@ -121,18 +123,20 @@ def test_persistent_variants_loop_and_tail(cuda, n, dtype, L, G, algo):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-def test_wm_forward_error_matches_cr(cuda, dtype):
-    """Wang & Mou against CR on the same systems: both within the residual
-    bar, and forward errors against the oracle of the same order."""
+def test_wm_lf_forward_error_matches_cr(cuda, dtype):
+    """Wang & Mou and Ladner-Fischer against CR on the same systems: all
+    within the residual bar, and forward errors against the oracle of the
+    same order."""
     n, batch = 1024, 64
     a, b, c, d, _ = inputs.tridiag_input(n, batch, dtype, seed=41)
     dev = [to_dev(v, cuda) for v in (a, b, c, d)]
     ref = oracle.thomas(a, b, c, d)
     err = {}
-    for algo in (ppx.TRI_CR_SHFL, ppx.TRI_WM):
+    for algo in (ppx.TRI_CR_SHFL, ppx.TRI_WM, ppx.TRI_LF):
         cfg = ppx.make_config(2, 64, 1, algo)  # P = 16, one system per wave
         banner(f"tridiag wm vs cr {np.dtype(dtype).name} algo={algo}")
         x = _solve(dev, n, batch, dtype, cfg)
         assert oracle.tridiag_residual(a, b, c, d, x).max() <= TOL[dtype]
         err[algo] = np.max(np.abs(x - ref)) / np.max(np.abs(ref))
-    assert err[ppx.TRI_WM] <= 10 * max(err[ppx.TRI_CR_SHFL], np.finfo(dtype).eps)
+    for algo in (ppx.TRI_WM, ppx.TRI_LF):
+        assert err[algo] <= 10 * max(err[ppx.TRI_CR_SHFL], np.finfo(dtype).eps), err
