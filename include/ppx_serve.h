@@ -39,6 +39,16 @@ typedef struct ppx_server ppx_server;
 #define PPX_SERVE_PER_REQUEST 1  /* one single-call launch per job (baseline) */
 #define PPX_SERVE_NULL_DEVICE 2  /* OR-able: no GPU; launches complete at the
                                     next progress call (bookkeeping tests) */
+#define PPX_SERVE_ONLINE_TUNE 4  /* OR-able with PPX_SERVE_PER_REQUEST: online
+                                    learned tuning (ppx_online_* of
+                                    ppx_tune.h) per (op, dtype, n, tridiagonal
+                                    family); a job of >= 2^20 elements, when
+                                    its class awaits no other cost, launches
+                                    the session's next candidate and is timed
+                                    with events (cost: ns per element); every
+                                    other launch uses the class's current
+                                    choice.  Results do not depend on the
+                                    candidate beyond rounding. */
 
 typedef struct ppx_completion {
     int64_t id;
@@ -77,6 +87,10 @@ int ppx_server_release(ppx_server *s, int64_t id);
 int ppx_server_read(ppx_server *s, int64_t id, void *host_dst, int64_t bytes);
 
 int ppx_server_stats_get(ppx_server *s, ppx_server_stats *out);
+
+/* Online tuning (PPX_SERVE_ONLINE_TUNE): sessions (job classes) seen,
+ * evaluation launches so far, sessions whose search has stopped. */
+int ppx_server_online_stats(ppx_server *s, int *sessions, int64_t *evaluations, int *converged);
 
 /* A request of a replayed trace: the job and its arrival time (us after the
  * replay starts). */

@@ -140,7 +140,8 @@ typedef struct ppx_tune_report {
  * ppx_tune_ex -- tune() with an algorithm filter and a full report.  algo =
  * -1 searches every algorithm of the op; otherwise only that one (the cache
  * entry is then keyed by it); for the tridiagonal solvers the filter selects
- * a family, PPX_TRI_CR (CR through LDS or shuffles) or PPX_TRI_PCR.  reps = timed launches per candidate (<= 0:
+ * a family: PPX_TRI_CR (CR through LDS or shuffles), PPX_TRI_PCR (the PCR
+ * variants), PPX_TRI_WM or PPX_TRI_LF.  reps = timed launches per candidate (<= 0:
  * 100, the paper's count), each on a different buffer set so that no rep
  * reads data a previous rep left in the 256 MB Infinity Cache.  Synchronous;
  * needs a GPU.  Records the winner in the tune cache.
@@ -157,6 +158,39 @@ int ppx_tune_ex(int op, int dtype, int64_t n, int64_t batch, int method, int max
 int ppx_tune_large_trace(int64_t n, int64_t batch, int method, int max_evals, int reps, ppx_fft_plan *best,
                          double *best_us, int *evals_used, ppx_fft_plan *trace_plan, double *trace_us,
                          int trace_cap);
+
+/*
+ * Online tuning session -- the learned search of Sec. IV-B run one
+ * evaluation at a time, for callers (a request loop) that time candidates on
+ * their own launches and amortise the evaluations over repeated requests of
+ * one (op, dtype, n): the online use the paper's conclusion recommends the
+ * learned tuner for.  Candidates: as ppx_tune_ex (algo = -1: all, else one
+ * algorithm or tridiagonal family); the same BO state, seed and stopping rule
+ * as ppx_tune_ex's learned method, with max_evals (<= 0: no cap).  Costs are
+ * in any unit where lower is better.  Host-only bookkeeping: no GPU work.
+ * A session is not thread-safe.
+ *
+ * ppx_online_create   batch: a typical batch, for the analytical
+ *                     configuration used before any evaluation.
+ * ppx_online_next     *cfg receives the configuration for the next launch.
+ *                     Returns 1 when it is a candidate whose cost must be
+ *                     reported (ppx_online_report) before another is
+ *                     proposed; 0 when it is the session's current choice
+ *                     (best evaluated so far, else the analytical one):
+ *                     with explore == 0, while a cost is awaited, or once
+ *                     the search has stopped.  Negative on error.
+ * ppx_online_report   the pending candidate's cost (negative: it failed).
+ * ppx_online_status   evaluations so far, whether the search has stopped,
+ *                     the current choice and its cost (-1 before any).
+ */
+typedef struct ppx_online ppx_online;
+int ppx_online_create(int op, int dtype, int64_t n, int64_t batch, int algo, int max_evals,
+                      ppx_online **out);
+int ppx_online_next(ppx_online *o, int explore, ppx_config *cfg);
+int ppx_online_report(ppx_online *o, double cost);
+int ppx_online_status(const ppx_online *o, int *evals, int *converged, ppx_config *best,
+                      double *best_cost);
+int ppx_online_destroy(ppx_online *o);
 
 /* Median microseconds of `reps` launches of one explicit configuration, timed
  * like a tuning candidate (the default-vs-tuned baseline uses this). */

@@ -77,7 +77,15 @@ struct Launch {
     std::vector<int64_t> ids;
     hipEvent_t done = nullptr;
     int stream = 0;
+    // an online-tuning evaluation: timed by start -> done (both with timing)
+    ppx_online *session = nullptr;
+    hipEvent_t start = nullptr;
+    double elems = 0;
 };
+
+// Jobs smaller than this (elements) are not timed for online tuning: below
+// it a launch does not fill the GPU and its time is mostly fixed overhead.
+constexpr double kOnlineMinElems = double(1 << 20);
 
 }  // namespace
 }  // namespace ppx
@@ -95,10 +103,14 @@ struct ppx_server {
     std::deque<int64_t> completed;
     int64_t next_id = 1, submitted = 0, admitted = 0, ncompleted = 0, released = 0, launches = 0;
     int max_inflight_seen = 0, rr = 0;
+    int64_t online_evals = 0;
+    // online tuning sessions by (op, dtype, n, tridiagonal family or -1)
+    std::map<std::tuple<int, int, int64_t, int>, ppx_online *> sessions;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
     bool null_device() const { return flags & PPX_SERVE_NULL_DEVICE; }
     bool per_request() const { return flags & PPX_SERVE_PER_REQUEST; }
+    bool online() const { return flags & PPX_SERVE_ONLINE_TUNE; }
     double now_us() const {
         return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -119,7 +131,14 @@ hipEvent_t take_event(ppx_server *s) {
     return e;
 }
 
-int launch_single(const ppx_job &j, hipStream_t st) {
+int launch_single(const ppx_job &j, hipStream_t st, const ppx_config *cfg) {
+    if (cfg) {
+        switch (j.op) {
+            case PPX_OP_FFT: return fft_batched(j.in, j.out, j.n, j.batch, j.direction, cfg, st);
+            case PPX_OP_SCAN: return scan_batched(j.in, j.out, j.n, j.batch, j.dtype, cfg, st);
+            default: return tridiag_batched(j.in, j.b, j.c, j.d, j.out, j.n, j.batch, j.dtype, cfg, st);
+        }
+    }
     switch (j.op) {
         case PPX_OP_FFT: return fft_batched(j.in, j.out, j.n, j.batch, j.direction, nullptr, st);
         case PPX_OP_SCAN: return scan_batched(j.in, j.out, j.n, j.batch, j.dtype, nullptr, st);
@@ -148,6 +167,14 @@ void retire(ppx_server *s) {
         if (!done) {
             ++it;
             continue;
+        }
+        if (it->session) {  // an online-tuning evaluation: report its cost
+            float ms = -1.0f;
+            const bool timed = hipEventElapsedTime(&ms, it->start, it->done) == hipSuccess;
+            (void)ppx_online_report(it->session, timed ? ms * 1e6 / it->elems : -1.0);  // ns per element
+            (void)hipEventDestroy(it->start);
+            (void)hipEventDestroy(it->done);
+            it->done = nullptr;
         }
         for (int64_t id : it->ids) {
             Job &j = s->jobs[id];
@@ -190,6 +217,21 @@ std::vector<int64_t> admit(ppx_server *s, int64_t tile_cap, int job_cap) {
     return out;
 }
 
+// The online session of a job's class, created on first use (typical batch
+// for its analytical fallback: the job's own).
+int online_session(ppx_server *s, const ppx_job &j, ppx_online **out) {
+    const int fam = j.op == PPX_OP_TRIDIAG ? tri_family(j.algo) : -1;
+    const auto key = std::make_tuple(j.op, j.dtype, j.n, fam);
+    auto it = s->sessions.find(key);
+    if (it == s->sessions.end()) {
+        ppx_online *o = nullptr;
+        if (int rc = ppx_online_create(j.op, j.dtype, j.n, j.batch, fam, 0, &o)) return rc;
+        it = s->sessions.emplace(key, o).first;
+    }
+    *out = it->second;
+    return PPX_OK;
+}
+
 int progress(ppx_server *s, int *launched) {
     if (launched) *launched = 0;
     retire(s);
@@ -205,8 +247,28 @@ int progress(ppx_server *s, int *launched) {
             if (!l.done) return fail(PPX_EHIP, "event creation failed");
             hipStream_t st = s->streams[l.stream];
             int rc;
-            if (single) {
-                rc = launch_single(s->jobs[ids[0]].job, st);
+            if (single && s->online()) {
+                const ppx_job &j = s->jobs[ids[0]].job;
+                ppx_online *sess = nullptr;
+                if ((rc = online_session(s, j, &sess))) return rc;
+                const double elems = double(j.n) * double(j.batch);
+                ppx_config cfg{};
+                const int r = ppx_online_next(sess, elems >= kOnlineMinElems, &cfg);
+                if (r < 0) return r;
+                if (r == 1) {  // time this launch: swap in events that record time
+                    s->free_events.push_back(l.done);
+                    l.done = nullptr;
+                    if (hipEventCreate(&l.start) != hipSuccess || hipEventCreate(&l.done) != hipSuccess)
+                        return fail(PPX_EHIP, "event creation failed");
+                    l.session = sess;
+                    l.elems = elems;
+                    ++s->online_evals;
+                    if ((rc = fail_hip(hipEventRecord(l.start, st), "event record"))) return rc;
+                }
+                rc = launch_single(j, st, &cfg);
+                if (rc == PPX_OK) rc = fail_hip(hipEventRecord(l.done, st), "event record");
+            } else if (single) {
+                rc = launch_single(s->jobs[ids[0]].job, st, nullptr);
                 if (rc == PPX_OK) rc = fail_hip(hipEventRecord(l.done, st), "event record");
             } else {
                 std::vector<ppx_job> batch;
@@ -236,6 +298,8 @@ int ppx_server_create(int64_t budget, int max_inflight, int flags, ppx_server **
     *out = nullptr;
     if (budget < 1) return fail(PPX_EINVAL, "budget must be positive");
     if (max_inflight < 1 || max_inflight > 4) return fail(PPX_EINVAL, "max_inflight must be in 1..4");
+    if ((flags & PPX_SERVE_ONLINE_TUNE) && !(flags & PPX_SERVE_PER_REQUEST))
+        return fail(PPX_EINVAL, "online tuning applies to the per-request mode (the fused tiles have fixed shapes)");
     auto *s = new ppx_server();
     s->flags = flags;
     s->max_inflight = max_inflight;
@@ -266,13 +330,16 @@ int ppx_server_destroy(ppx_server *s) {
     if (!s->null_device()) {
         for (auto st : s->streams)
             if (st) (void)hipStreamSynchronize(st);
-        for (auto &l : s->inflight)
+        for (auto &l : s->inflight) {
             if (l.done) (void)hipEventDestroy(l.done);
+            if (l.start) (void)hipEventDestroy(l.start);
+        }
         for (auto e : s->free_events) (void)hipEventDestroy(e);
         for (auto st : s->streams)
             if (st) (void)hipStreamDestroy(st);
         if (s->arena_base) (void)hipFree(s->arena_base);
     }
+    for (auto &kv : s->sessions) ppx_online_destroy(kv.second);
     delete s;
     return PPX_OK;
 }
@@ -341,6 +408,20 @@ int ppx_server_stats_get(ppx_server *s, ppx_server_stats *o) {
     if (!s || !o) return fail(PPX_EINVAL, "null argument");
     *o = ppx_server_stats{s->submitted, s->admitted, s->ncompleted, s->released, s->launches,
                           s->budget, s->used, s->peak, s->max_inflight_seen, (int32_t)s->pending.size()};
+    return PPX_OK;
+}
+
+int ppx_server_online_stats(ppx_server *s, int *sessions, int64_t *evaluations, int *converged) {
+    if (!s) return fail(PPX_EINVAL, "null server");
+    int conv = 0;
+    for (auto &kv : s->sessions) {
+        int c = 0;
+        ppx_online_status(kv.second, nullptr, &c, nullptr, nullptr);
+        conv += c;
+    }
+    if (sessions) *sessions = (int)s->sessions.size();
+    if (evaluations) *evaluations = s->online_evals;
+    if (converged) *converged = conv;
     return PPX_OK;
 }
 

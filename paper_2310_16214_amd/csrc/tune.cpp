@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <random>
@@ -385,53 +386,38 @@ static void features(const ppx_config *c, int n, std::vector<double> &F, int &d)
     }
 }
 
-static int bo_search_impl(const ppx_config *c, int n, ppx_eval_fn fn, void *user, int max_evals,
-                          int n_init, int patience, double min_rel, uint64_t seed, int *order,
-                          double *values, int *evals_used, int *best_index) {
-    if (n <= 0) return fail(PPX_EINVAL, "empty candidate list");
-    if (n_init <= 0) n_init = std::max(3, (int)std::ceil(0.05 * n));
-    if (patience <= 0) patience = 5;
-    if (max_evals <= 0 || max_evals > n) max_evals = n;
-    n_init = std::min(n_init, max_evals);
-    std::vector<double> F;
-    int d;
-    features(c, n, F, d);
-    std::vector<char> done(n, 0);
-    std::vector<int> ord;
-    std::vector<double> val;  // recorded cost (penalised on failure)
-    std::vector<char> failed;
-    double worst = 0, best = 1e300;
-    int best_i = -1, last_improve = 0;
-    auto evaluate = [&](int i) {
-        const double v = fn(&c[i], user);
-        done[i] = 1;
-        ord.push_back(i);
-        const bool bad = !(v >= 0) || !std::isfinite(v);
-        failed.push_back(bad);
-        val.push_back(bad ? -1.0 : v);
-        if (!bad) worst = std::max(worst, v);
-        // re-penalise every failure at 10x the worst valid cost so far
-        for (size_t k = 0; k < val.size(); ++k)
-            if (failed[k]) val[k] = worst > 0 ? 10.0 * worst : 1e9;
-        if (!bad && v < best * (1.0 - min_rel)) last_improve = (int)ord.size();
-        if (!bad && v < best) {
-            best = v;
-            best_i = i;
-        }
-    };
-    std::mt19937_64 rng(seed);
-    std::vector<int> perm(n);
-    std::iota(perm.begin(), perm.end(), 0);
-    std::shuffle(perm.begin(), perm.end(), rng);
-    for (int k = 0; k < n_init; ++k) evaluate(perm[k]);
-    last_improve = std::max(last_improve, n_init);
-    while ((int)ord.size() < max_evals) {
-        if ((int)ord.size() - last_improve >= patience) break;
-        const int m = (int)ord.size();
-        std::vector<double> X((size_t)m * d), y(m);
+// The search of Sec. IV-B as an ask/tell state: ask() names the next
+// candidate to time (n_init random ones, then the Expected-Improvement
+// maximiser of a GP fitted to the log costs so far), tell() records its cost;
+// ask() returns -1 once max_evals candidates are timed, `patience`
+// evaluations pass without a relative improvement of min_rel, or no
+// candidate is left.  Used synchronously by the offline tuner and one
+// evaluation at a time by the online sessions of a request loop.
+class BoState {
+  public:
+    BoState(const ppx_config *c, int n, int max_evals, int n_init, int patience, double min_rel, uint64_t seed)
+        : n_(n), min_rel_(min_rel) {
+        if (n_init <= 0) n_init = std::max(3, (int)std::ceil(0.05 * n));
+        patience_ = patience > 0 ? patience : 5;
+        max_evals_ = max_evals <= 0 || max_evals > n ? n : max_evals;
+        n_init_ = std::min(n_init, max_evals_);
+        features(c, n, F_, d_);
+        done_.assign(n, 0);
+        std::mt19937_64 rng(seed);
+        perm_.resize(n);
+        std::iota(perm_.begin(), perm_.end(), 0);
+        std::shuffle(perm_.begin(), perm_.end(), rng);
+    }
+
+    int ask() {
+        const int m = (int)ord_.size();
+        if (m < n_init_) return perm_[m];
+        if (m >= max_evals_) return -1;
+        if (m - last_improve_ >= patience_) return -1;
+        std::vector<double> X((size_t)m * d_), y(m);
         for (int k = 0; k < m; ++k) {
-            std::copy(&F[ord[k] * d], &F[ord[k] * d] + d, &X[k * d]);
-            y[k] = std::log(std::max(val[k], 1e-30));
+            std::copy(&F_[ord_[k] * d_], &F_[ord_[k] * d_] + d_, &X[k * d_]);
+            y[k] = std::log(std::max(val_[k], 1e-30));
         }
         const double mean = std::accumulate(y.begin(), y.end(), 0.0) / m;
         double sd = 0;
@@ -440,36 +426,78 @@ static int bo_search_impl(const ppx_config *c, int n, ppx_eval_fn fn, void *user
         if (!(sd > 1e-12)) sd = 1.0;
         for (double &v : y) v = (v - mean) / sd;
         GP gp;
-        const bool ok = fit_gp(gp, X, y, m, d);
+        const bool ok = fit_gp(gp, X, y, m, d_);
         double ybest = 1e300;
         for (double v : y) ybest = std::min(ybest, v);
         int pick = -1;
         double pv = -1;
-        for (int i = 0; i < n; ++i) {
-            if (done[i]) continue;
-            double ei;
+        for (int i = 0; i < n_; ++i) {
+            if (done_[i]) continue;
+            double ei = 0.0;
             if (ok) {
                 double mu, var;
-                gp.predict(&F[i * d], &mu, &var);
+                gp.predict(&F_[i * d_], &mu, &var);
                 ei = expected_improvement(mu, std::sqrt(var), ybest);
-            } else {
-                ei = 0.0;
             }
             if (ei > pv) {
                 pv = ei;
                 pick = i;
             }
         }
-        if (pick < 0) break;
-        evaluate(pick);
+        return pick;
     }
+
+    // Cost v of candidate i (negative or non-finite: the run failed).
+    void tell(int i, double v) {
+        done_[i] = 1;
+        ord_.push_back(i);
+        const bool bad = !(v >= 0) || !std::isfinite(v);
+        failed_.push_back(bad);
+        val_.push_back(bad ? -1.0 : v);
+        if (!bad) worst_ = std::max(worst_, v);
+        // re-penalise every failure at 10x the worst valid cost so far
+        for (size_t k = 0; k < val_.size(); ++k)
+            if (failed_[k]) val_[k] = worst_ > 0 ? 10.0 * worst_ : 1e9;
+        if (!bad && v < best_ * (1.0 - min_rel_)) last_improve_ = (int)ord_.size();
+        if (!bad && v < best_) {
+            best_ = v;
+            best_i_ = i;
+        }
+        if ((int)ord_.size() == n_init_) last_improve_ = std::max(last_improve_, n_init_);
+    }
+
+    int evals() const { return (int)ord_.size(); }
+    int best_index() const { return best_i_; }
+    double best_cost() const { return best_; }
+    const std::vector<int> &order() const { return ord_; }
+    const std::vector<double> &values() const { return val_; }
+
+  private:
+    int n_, d_ = 0, n_init_, patience_, max_evals_;
+    double min_rel_;
+    std::vector<double> F_;
+    std::vector<char> done_, failed_;
+    std::vector<int> perm_, ord_;
+    std::vector<double> val_;
+    double worst_ = 0, best_ = 1e300;
+    int best_i_ = -1, last_improve_ = 0;
+};
+
+static int bo_search_impl(const ppx_config *c, int n, ppx_eval_fn fn, void *user, int max_evals,
+                          int n_init, int patience, double min_rel, uint64_t seed, int *order,
+                          double *values, int *evals_used, int *best_index) {
+    if (n <= 0) return fail(PPX_EINVAL, "empty candidate list");
+    BoState bo(c, n, max_evals, n_init, patience, min_rel, seed);
+    for (int i = bo.ask(); i >= 0; i = bo.ask()) bo.tell(i, fn(&c[i], user));
+    const auto &ord = bo.order();
+    const auto &val = bo.values();
     for (size_t k = 0; k < ord.size(); ++k) {
         if (order) order[k] = ord[k];
         if (values) values[k] = val[k];
     }
-    if (evals_used) *evals_used = (int)ord.size();
-    if (best_index) *best_index = best_i;
-    return best_i >= 0 ? PPX_OK : fail(PPX_ETIMEOUT, "every evaluated candidate failed");
+    if (evals_used) *evals_used = bo.evals();
+    if (best_index) *best_index = bo.best_index();
+    return bo.best_index() >= 0 ? PPX_OK : fail(PPX_ETIMEOUT, "every evaluated candidate failed");
 }
 
 // ============================================================ tune cache
@@ -836,29 +864,37 @@ double eval_gpu(const ppx_config *c, void *user) {
 }
 }  // namespace
 
+// The valid configurations a tuner searches: every algorithm (algo < 0), one
+// algorithm, or for the tridiagonal solvers one family.
+static int tune_candidates(int op, int dtype, int64_t n, int algo, std::vector<ppx_config> &cands) {
+    const int total = enumerate_configs(op, dtype, n, nullptr, 0);
+    if (total < 0) return total;
+    std::vector<ppx_config> all(total);
+    enumerate_configs(op, dtype, n, all.data(), total);
+    cands.clear();
+    for (const auto &c : all)
+        if (algo < 0 || (op == PPX_OP_TRIDIAG ? tri_family(c.algo) == tri_family(algo) : c.algo == algo))
+            cands.push_back(c);
+    if (cands.empty()) return fail(PPX_ECONFIG, "no valid configuration to tune");
+    return PPX_OK;
+}
+
 static int tune_impl(int op, int dtype, int64_t n, int64_t batch, int method, int max_evals,
                      int algo, int reps, ppx_tune_report *rep) {
     if (!rep) return fail(PPX_EINVAL, "null report");
     if (method < PPX_TUNE_EXHAUSTIVE || method > PPX_TUNE_LEARNED) return fail(PPX_EINVAL, "unknown tuning method");
     if (batch < 1) return fail(PPX_EINVAL, "batch must be >= 1");
     if (reps <= 0) reps = 100;
-    const int total = enumerate_configs(op, dtype, n, nullptr, 0);
-    if (total < 0) return total;
-    std::vector<ppx_config> all(total);
-    enumerate_configs(op, dtype, n, all.data(), total);
     std::vector<ppx_config> cands;
-    for (const auto &c : all)
-        if (algo < 0 || (op == PPX_OP_TRIDIAG ? tri_family(c.algo) == tri_family(algo) : c.algo == algo))
-            cands.push_back(c);
-    if (cands.empty()) return fail(PPX_ECONFIG, "no valid configuration to tune");
+    int rc = tune_candidates(op, dtype, n, algo, cands);
+    if (rc) return rc;
     if (!device_info()) return PPX_EDEVICE;
     Bench bench;
     bench.op = op;
     bench.dtype = dtype;
     bench.n = n;
     bench.batch = batch;
-    int rc = bench.init(reps);
-    if (rc) return rc;
+    if ((rc = bench.init(reps))) return rc;
     std::vector<std::pair<ppx_config, double>> trace;
     EvalCtx ctx{&bench, reps, &trace};
     const int nc = (int)cands.size();
@@ -1016,6 +1052,18 @@ static int tune_large_impl(int64_t n, int64_t batch, int method, int max_evals, 
     fail(PPX_OK, "");
     return PPX_OK;
 }
+
+// An online tuning session (include/ppx_tune.h): the learned search over
+// one (op, dtype, n, algorithm filter), one evaluation at a time.
+struct ppx_online {
+    int op = 0, dtype = 0, algo = -1;
+    int64_t n = 0;
+    std::vector<ppx_config> cands;
+    std::unique_ptr<ppx::BoState> bo;
+    int pending = -1;       // candidate whose cost is awaited
+    bool converged = false;
+    ppx_config fallback{};  // before any evaluation: the analytical choice
+};
 
 extern "C" {
 
@@ -1192,6 +1240,64 @@ int ppx_tuned_config(int op, int dtype, int64_t n, int algo, ppx_config *out) {
     auto it = g_cache.find({op, dtype, n, algo});
     if (it == g_cache.end()) return fail(PPX_EINVAL, "no tuned entry");
     *out = it->second.cfg;
+    return PPX_OK;
+}
+
+int ppx_online_create(int op, int dtype, int64_t n, int64_t batch, int algo, int max_evals,
+                      ppx_online **out) {
+    if (!out) return fail(PPX_EINVAL, "null output");
+    *out = nullptr;
+    if (batch < 1) return fail(PPX_EINVAL, "batch must be >= 1");
+    auto o = std::make_unique<ppx_online>();
+    o->op = op;
+    o->dtype = dtype;
+    o->n = n;
+    o->algo = algo;
+    if (int rc = tune_candidates(op, dtype, n, algo, o->cands)) return rc;
+    if (int rc = analytical_select(op, dtype, n, batch, o->cands, device_info() != nullptr, o->fallback))
+        return rc;
+    o->bo = std::make_unique<BoState>(o->cands.data(), (int)o->cands.size(), max_evals, 0, 5, 0.01,
+                                      0x2310'16214ULL);
+    *out = o.release();
+    return PPX_OK;
+}
+
+int ppx_online_next(ppx_online *o, int explore, ppx_config *cfg) {
+    if (!o || !cfg) return fail(PPX_EINVAL, "null argument");
+    if (explore && o->pending < 0 && !o->converged) {
+        const int i = o->bo->ask();
+        if (i >= 0) {
+            o->pending = i;
+            *cfg = o->cands[i];
+            return 1;
+        }
+        o->converged = true;
+    }
+    const int b = o->bo->best_index();
+    *cfg = b >= 0 ? o->cands[b] : o->fallback;
+    return 0;
+}
+
+int ppx_online_report(ppx_online *o, double cost) {
+    if (!o) return fail(PPX_EINVAL, "null session");
+    if (o->pending < 0) return fail(PPX_EINVAL, "no candidate awaits a cost");
+    o->bo->tell(o->pending, cost);
+    o->pending = -1;
+    return PPX_OK;
+}
+
+int ppx_online_status(const ppx_online *o, int *evals, int *converged, ppx_config *best, double *best_cost) {
+    if (!o) return fail(PPX_EINVAL, "null session");
+    if (evals) *evals = o->bo->evals();
+    if (converged) *converged = o->converged ? 1 : 0;
+    const int b = o->bo->best_index();
+    if (best) *best = b >= 0 ? o->cands[b] : o->fallback;
+    if (best_cost) *best_cost = b >= 0 ? o->bo->best_cost() : -1.0;
+    return PPX_OK;
+}
+
+int ppx_online_destroy(ppx_online *o) {
+    delete o;
     return PPX_OK;
 }
 

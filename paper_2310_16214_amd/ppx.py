@@ -300,12 +300,57 @@ _tune_sigs = {
 }
 
 
+_tune_sigs.update({
+    "ppx_online_create": ([ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                           ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "ppx_online_next": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Config)], ctypes.c_int),
+    "ppx_online_report": ([ctypes.c_void_p, ctypes.c_double], ctypes.c_int),
+    "ppx_online_status": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                           ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "ppx_online_destroy": ([ctypes.c_void_p], ctypes.c_int),
+})
+
+
 def _tl(name):
     f = getattr(lib(), name)
     if not getattr(f, "_ppx_typed", False):
         f.argtypes, f.restype = _tune_sigs[name]
         f._ppx_typed = True
     return f
+
+
+class OnlineTuner:
+    """Online learned-tuning session (ppx_online_* in include/ppx_tune.h)."""
+
+    def __init__(self, op, dtype, n, batch, algo=-1, max_evals=0):
+        self._h = ctypes.c_void_p()
+        _check(_tl("ppx_online_create")(op, dtype, n, batch, algo, max_evals, ctypes.byref(self._h)))
+
+    def next(self, explore=True):
+        """(config, is_candidate): is_candidate means report() its cost next."""
+        c = Config()
+        r = _check(_tl("ppx_online_next")(self._h, 1 if explore else 0, ctypes.byref(c)))
+        return c, r == 1
+
+    def report(self, cost):
+        _check(_tl("ppx_online_report")(self._h, float(cost)))
+
+    def status(self):
+        ev, conv, best, cost = ctypes.c_int(0), ctypes.c_int(0), Config(), ctypes.c_double(0)
+        _check(_tl("ppx_online_status")(self._h, ctypes.byref(ev), ctypes.byref(conv), ctypes.byref(best),
+                                         ctypes.byref(cost)))
+        return dict(evals=ev.value, converged=bool(conv.value), best=best, best_cost=cost.value)
+
+    def close(self):
+        if self._h:
+            _tl("ppx_online_destroy")(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fft_batched_large(inp, out, n, batch, direction=-1, plan=None, stream=None):
@@ -516,7 +561,7 @@ def mixed_tile_problems(op, dtype, n, algo=0):
 # ---------------------------------------------------------------- serving
 # (declared in include/ppx_serve.h)
 
-SERVE_FUSED, SERVE_PER_REQUEST, SERVE_NULL_DEVICE = 0, 1, 2
+SERVE_FUSED, SERVE_PER_REQUEST, SERVE_NULL_DEVICE, SERVE_ONLINE_TUNE = 0, 1, 2, 4
 
 
 class Completion(ctypes.Structure):
@@ -601,6 +646,14 @@ class Server:
         _check(_sl("ppx_server_stats_get", [ctypes.c_void_p, ctypes.POINTER(ServerStats)])(
             self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def online_stats(self):
+        """(sessions, evaluation launches, sessions whose search has stopped)."""
+        ses, ev, conv = ctypes.c_int(0), ctypes.c_int64(0), ctypes.c_int(0)
+        _check(_sl("ppx_server_online_stats", [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)])(
+            self._h, ctypes.byref(ses), ctypes.byref(ev), ctypes.byref(conv)))
+        return dict(sessions=ses.value, evaluations=ev.value, converged=conv.value)
 
     def replay(self, requests, auto_release=True):
         """requests: list of (Job, arrival_us) sorted by arrival; returns a list

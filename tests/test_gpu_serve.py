@@ -81,3 +81,53 @@ def test_backpressure_with_a_tight_budget(cuda):
     srv.close()
     assert st["completed"] == len(trace) and st["peak_used_bytes"] <= biggest
     assert all(c.complete_us >= c.admit_us >= c.arrival_us for c in comps)
+
+
+def test_online_tuning_serves_correct_results(cuda):
+    """Per-request serving with online learned tuning: three repeated job
+    classes large enough to be timed; every served output agrees with the
+    same job solved alone (and sampled problems with the oracle), whatever
+    candidate served it, and each class's search makes progress."""
+    import torch
+    pools = Pools(cuda, seed=6)
+    rng = np.random.default_rng(12)
+    trace = []
+    for k in range(90):
+        op = ("fft", "scan", "tridiag")[k % 3]
+        n, batch = {"fft": (1024, 1024), "scan": (1024, 1024), "tridiag": (256, 4096)}[op]
+        elems = n * batch
+        if op == "fft":
+            off = int(rng.integers(0, pools.fft.numel() - elems + 1)) & ~1
+            job = ppx.make_job(ppx.OP_FFT, ppx.C64, n, batch, pools.fft.data_ptr() + 8 * off, None)
+        elif op == "scan":
+            off = int(rng.integers(0, pools.scan.numel() - elems + 1)) & ~3
+            job = ppx.make_job(ppx.OP_SCAN, ppx.F32, n, batch, pools.scan.data_ptr() + 4 * off, None)
+        else:
+            off = int(rng.integers(0, pools.tri[0].numel() - elems + 1)) & ~3
+            p = [v.data_ptr() + 4 * off for v in pools.tri]
+            job = ppx.make_job(ppx.OP_TRIDIAG, ppx.F32, n, batch, p[0], None, algo=ppx.TRI_CR,
+                               b=p[1], c=p[2], d=p[3])
+        trace.append((job, 0.0, dict(op=op, n=n, batch=batch, offset=off)))
+    banner(f"serve online tuning jobs={len(trace)}")
+    srv = ppx.Server(1 << 32, max_inflight=2, flags=ppx.SERVE_PER_REQUEST | ppx.SERVE_ONLINE_TUNE)
+    comps = srv.replay([(j, t) for j, t, _ in trace], auto_release=False)
+    outs = [srv.read(c.id, _host_out(m)) for c, (_, _, m) in zip(comps, trace)]
+    st = srv.online_stats()
+    srv.close()
+    assert st["sessions"] == 3 and 9 <= st["evaluations"] <= len(trace)
+    for k, ((job, _, m), y) in enumerate(zip(trace, outs)):
+        n, batch, off = m["n"], m["batch"], m["offset"]
+        if m["op"] == "fft":
+            x = pools.fft[off:off + n * batch]
+            ref = torch.empty_like(x)
+            ppx.fft_batched(x, ref, n, batch, -1)
+            assert oracle.rel_l2(y, ref.cpu().numpy().reshape(batch, n)).max() <= 2 * fft_tol(n)
+            if k < 3:
+                xs = x.cpu().numpy().reshape(batch, n)[:2]
+                assert oracle.rel_l2(y[:2], oracle.dft(xs)).max() <= fft_tol(n)
+        elif m["op"] == "scan":
+            x = pools.scan[off:off + n * batch].cpu().numpy().reshape(batch, n)
+            assert np.all(np.abs(y.astype(np.float64) - oracle.scan(x)) <= scan_f32_bound(x))
+        else:
+            coeffs = [v[off:off + n * batch].cpu().numpy().reshape(batch, n) for v in pools.tri]
+            assert oracle.tridiag_residual(*coeffs, y).max() <= 1e-4

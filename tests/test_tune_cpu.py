@@ -243,3 +243,73 @@ def test_tune_cache_round_trip(tmp_path):
     assert ppx.load_tune_cache(str(q)) == 2
     assert ppx.tuned_config(ppx.OP_FFT, ppx.C64, 1024).as_tuple() == c.as_tuple()
     ppx.clear_tune_cache()
+
+
+# ---------------------------------------------------------------- online BO
+
+def _cost(c):
+    """A deterministic synthetic cost with structure in every feature."""
+    import math
+    return (1.0 + 0.3 * abs(math.log2(c.threads_per_block) - 8) + 0.2 * abs(math.log2(c.problems_per_block) - 2)
+            + 0.05 * c.algo + 0.01 * c.radix)
+
+
+def _drive(t):
+    order = []
+    c, cand = t.next()
+    while cand:
+        order.append(c.as_tuple())
+        t.report(_cost(c))
+        c, cand = t.next()
+    return order, c
+
+
+def test_online_session_replays_the_offline_search():
+    """One evaluation at a time, the online session proposes exactly the
+    candidates the offline learned search evaluates (same BO state, seed and
+    stopping rule) and ends on its best."""
+    for op, dt, n, algo in ((ppx.OP_SCAN, ppx.I32, 1024, -1), (ppx.OP_FFT, ppx.C64, 4096, -1),
+                            (ppx.OP_TRIDIAG, ppx.F32, 256, ppx.TRI_CR)):
+        cands = [c for c in ppx.enumerate_configs(op, dt, n)
+                 if algo < 0 or ppx.tri_family(c.algo) == ppx.tri_family(algo)]
+        best, order, _ = ppx.bo_search(cands, _cost, patience=5, min_rel=0.01, seed=0x231016214)
+        t = ppx.OnlineTuner(op, dt, n, 1 << 16, algo=algo)
+        got, final = _drive(t)
+        assert got == [cands[i].as_tuple() for i in order]
+        assert final.as_tuple() == cands[best].as_tuple()
+        st = t.status()
+        assert st["converged"] and st["evals"] == len(order) and st["best_cost"] == _cost(cands[best])
+        t.close()
+
+
+def test_online_session_protocol():
+    t = ppx.OnlineTuner(ppx.OP_SCAN, ppx.F32, 2048, 4096, max_evals=4)
+    c0, cand = t.next(explore=False)  # before any evaluation: the analytical choice
+    assert not cand and ppx.config_valid(ppx.OP_SCAN, ppx.F32, 2048, c0)
+    with pytest.raises(ppx.PpxError):
+        t.report(1.0)                  # nothing pending
+    c1, cand = t.next()
+    assert cand
+    c2, cand2 = t.next()               # a cost is awaited: the current choice
+    assert not cand2 and c2.as_tuple() == c0.as_tuple()
+    t.report(-1.0)                     # a failed run
+    for _ in range(3):
+        c, cand = t.next()
+        assert cand
+        t.report(2.0)
+    c, cand = t.next()                 # max_evals reached
+    assert not cand and t.status()["converged"] and t.status()["evals"] == 4
+    assert t.status()["best_cost"] == 2.0
+    t.close()
+
+
+def test_server_online_flag():
+    with pytest.raises(ppx.PpxError):
+        ppx.Server(1 << 20, flags=ppx.SERVE_ONLINE_TUNE)  # needs the per-request mode
+    s = ppx.Server(1 << 24, flags=ppx.SERVE_PER_REQUEST | ppx.SERVE_ONLINE_TUNE | ppx.SERVE_NULL_DEVICE)
+    ids = [s.submit(ppx.make_job(ppx.OP_SCAN, ppx.I32, 1024, 64, 1 << 20, None)) for _ in range(3)]
+    for _ in range(4):
+        s.progress()
+    assert sorted(c.id for c in s.poll()) == ids
+    assert s.online_stats() == dict(sessions=0, evaluations=0, converged=0)  # nothing is timed without a GPU
+    s.close()
