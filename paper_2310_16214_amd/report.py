@@ -66,6 +66,21 @@ def serving(path):
     b = d["backpressure_half_budget"]
     out.append(f"| {b['load']:.2f}, half budget | fused | {b['p50_ms']:.2f} | {b['p99_ms']:.2f} | "
                f"{b['gelem_s']:.1f} | {100 * b['hbm_frac']:.1f} | {b['launches']} |")
+    if "online" in d:
+        o = d["online"]
+        out += ["", f"Online learned tuning (one launch per request; {o['jobs']} jobs of the classes "
+                    f"{', '.join(o['classes'])}, batch giving 2^21..2^22 elements, all arriving at t = 0):", "",
+                "| configurations | pass | GElem/s | % HBM peak | p50 ms | p99 ms | evaluation launches so far |",
+                "|---|---|---|---|---|---|---|"]
+        rows = [("analytical model", 1, o["analytical"], "-")]
+        for k, p in enumerate(o["online"].get("passes", [o["online"]])):
+            rows.append(("online BO", k + 1, p, f"{p['online']['evaluations']} (converged "
+                                                f"{p['online']['converged']}/{p['online']['sessions']})"))
+        if "offline_exhaustive" in o:
+            rows.append(("offline exhaustive cache", 1, o["offline_exhaustive"], "-"))
+        for name, k, r, ev in rows:
+            out.append(f"| {name} | {k} | {r['gelem_s']:.1f} | {100 * r['hbm_frac']:.1f} | {r['p50_ms']:.2f} | "
+                       f"{r['p99_ms']:.2f} | {ev} |")
     print("\n".join(out))
 
 
