@@ -149,18 +149,20 @@ int fft_batched(const void *in, void *out, int64_t n, int64_t batch,
  * pass B over the n1 dimension, in place in `out`).  A plan fixes the split
  * and each pass's radix (= values per thread):
  *   log2_n1    log2 n1; both passes need a column length in the range their
- *              radix supports (radix 16: 2^6..2^10, radix 8: 2^5..2^9)
+ *              radix supports (pass A: radix 16 2^6..2^10, radix 8
+ *              2^5..2^9; pass B also 2^11..2^13 in narrow tiles)
  *   radix_a    radix of pass A (column length n2 = n / n1)
  *   radix_b    radix of pass B (column length n1)
- *   tile_a     columns per workgroup of pass A (16, 32 or 64)
- *   tile_b     columns per workgroup of pass B (16, 32 or 64)
+ *   tile_a     columns per workgroup of pass A (16, 32 or 64, >= radix_a)
+ *   tile_b     columns per workgroup of pass B (16, 32 or 64 for columns of
+ *              up to 1024 values; 2, 4 or 8 for longer ones)
  * A pass's workgroup transforms tile adjacent columns of length len with
  * tile * len / radix threads (64..1024) and tile * (len + 1) complex values
- * of LDS (<= 160 KiB); the tile must divide the pass's column count (n1 for
- * pass A, n2 for pass B).  Tuning the plan (tune_fft_large) is the
+ * of LDS (<= 160 KiB, with 2056 more for pass A's twiddle tables); the tile
+ * must divide the pass's column count (n1 for pass A, n2 for pass B).  Tuning the plan (tune_fft_large) is the
  * interdependent per-kernel search of the paper's learned tuner.
  */
-#define PPX_MAX_N_LARGE 1048576
+#define PPX_MAX_N_LARGE 8388608
 typedef struct ppx_fft_plan {
     int32_t log2_n1;
     int32_t radix_a;
@@ -191,8 +193,9 @@ int ppx_fft_plan_valid(int64_t n, const ppx_fft_plan *plan);
 int ppx_enumerate_fft_plans(int64_t n, ppx_fft_plan *out, int cap);
 
 /*
- * The untuned plan: the most even split (n1 <= n2) with radix 8 in both
- * passes where valid and 16-column tiles.  The analytical plan (tune_fft_large with
+ * The untuned plan: the most even valid split (n1 <= n2 on a tie) with
+ * radix 8 in both passes where valid and 16-column tiles (pass B's widest
+ * valid tile for columns of more than 1024 values).  The analytical plan (tune_fft_large with
  * PPX_TUNE_ANALYTICAL) is the gfx950 occupancy guideline applied per pass.
  */
 int ppx_default_fft_plan(int64_t n, ppx_fft_plan *out);

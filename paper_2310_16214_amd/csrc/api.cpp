@@ -89,7 +89,7 @@ const DeviceInfo *device_info() {
         return nullptr;
     }
     di->twiddles = dtw;
-    std::vector<float> lo(2 * 1024), hi(2 * 1024);
+    std::vector<float> lo(2 * 1024), hi(2 * (1024 + 8));
     fft_large_host_twiddles(lo.data(), hi.data());
     void *dlo = nullptr, *dhi = nullptr;
     if (hipMalloc(&dlo, lo.size() * sizeof(float)) != hipSuccess ||
@@ -173,7 +173,7 @@ int fft_batched_large(const void *in, void *out, int64_t n, int64_t batch, int d
     if (!aligned16(in) || !aligned16(out)) return fail(PPX_EINVAL, "pointers must be 16-byte aligned");
     if (direction != -1 && direction != 1) return fail(PPX_EINVAL, "direction must be -1 or +1");
     if (!is_pow2(n) || n <= PPX_MAX_N || n > PPX_MAX_N_LARGE)
-        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 1048576]");
+        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 8388608]");
     if (batch < 1) return fail(PPX_EINVAL, "batch must be >= 1");
     if (batch > (int64_t(1) << 40) / n) return fail(PPX_EINVAL, "batch * n is too large");
     const int64_t bytes = batch * n * 8;
@@ -199,7 +199,7 @@ int ppx_fft_plan_valid(int64_t n, const ppx_fft_plan *plan) {
 int ppx_enumerate_fft_plans(int64_t n, ppx_fft_plan *out, int cap) {
     t_err.clear();
     if (!is_pow2(n) || n <= PPX_MAX_N || n > PPX_MAX_N_LARGE)
-        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 1048576]");
+        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 8388608]");
     if (cap < 0 || (cap > 0 && !out)) return fail(PPX_EINVAL, "bad output buffer");
     const std::vector<ppx_fft_plan> all = fft_enumerate_plans(n);
     for (int i = 0; i < cap && i < (int)all.size(); ++i) out[i] = all[i];
@@ -210,7 +210,7 @@ int ppx_default_fft_plan(int64_t n, ppx_fft_plan *out) {
     t_err.clear();
     if (!out) return fail(PPX_EINVAL, "null plan");
     if (!is_pow2(n) || n <= PPX_MAX_N || n > PPX_MAX_N_LARGE)
-        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 1048576]");
+        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 8388608]");
     fft_default_plan(n, *out);
     return PPX_OK;
 }

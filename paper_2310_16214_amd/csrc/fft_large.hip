@@ -1,4 +1,4 @@
-// Large-N batched FFT (2^14 < n <= 2^20) in two passes of column FFTs -- the
+// Large-N batched FFT (2^14 < n <= 2^23) in two passes of column FFTs -- the
 // multi-kernel decomposition of Sec. IV-A for sizes beyond one workgroup.
 //
 // With n = n1 * n2 and input index j = j1 + n1 * j2 (j1 < n1, j2 < n2), the
@@ -11,19 +11,24 @@
 // where it lies.  So the output buffer holds Z and no workspace is needed,
 // but the input must be a different buffer.
 //
-// A workgroup takes a tile of TC = 16, 32 or 64 adjacent columns (a plan
-// parameter per pass): it reads them row by row (TC lanes on TC consecutive
-// values, runs of 128 to 512 bytes) into LDS,
-// transforms the 16 columns with the single-pass stage code (radix R = P,
-// T = len/P threads per column, exchanges in LDS), and writes the tile back
-// the same way (pass B) or row by row (pass A, 512-byte runs per wave).  The
-// LDS tile pads each column to len + 1 values, so that the TC values a row
-// read or write touches fall on different banks.
+// A workgroup takes a tile of TC adjacent columns (a plan parameter per
+// pass): it reads them row by row (TC lanes on TC consecutive values) into
+// LDS, transforms the TC columns with the single-pass stage code (radix
+// R = P, T = len/P threads per column, exchanges in LDS), and writes the tile
+// back the same way (pass B) or row by row (pass A, 512-byte runs per wave).
+// The LDS tile pads each column to len + 1 values, so that the TC values a
+// row read or write touches fall on different banks.  Columns of up to 1024
+// values take tiles of 16, 32 or 64 (runs of 128 to 512 bytes); pass B's
+// columns of 2048 to 8192 values (n > 2^20) fit LDS only in tiles of 2, 4 or
+// 8 (runs of 16 to 64 bytes).  Those narrow tiles number the workgroups so
+// that the tiles sharing a row's cache lines run on one XCD, whose L2 then
+// serves the lines to all of them (workgroups are dealt to the 8 XCDs in
+// turn).
 //
-// The pass-A twiddles w_n^m (m < n <= 2^20) are the product of two table
-// entries, w_{2^20}^{m' mod 1024} * w_{2^20}^{1024 (m' div 1024)} with
-// m' = m * 2^20 / n: 2 x 1024 values built on the host in double precision,
-// copied into LDS by every pass-A workgroup.
+// The pass-A twiddles w_n^m (m < n <= 2^23) are the product of three table
+// entries, w_{2^23}^{q mod 2^10} * w_{2^13}^{(q div 2^10) mod 2^10} *
+// w_8^{q div 2^20} with q = m * 2^23 / n: 1024 + 1024 + 8 values built on the
+// host in double precision, copied into LDS by every pass-A workgroup.
 #include "fft_device.h"
 
 #include <map>
@@ -35,11 +40,14 @@ __device__ __forceinline__ int tile_slot(int c, int e, int len) { return swz_c(c
 
 __device__ __forceinline__ int tw_swz(int j) { return j ^ ((j >> 5) & 31); }
 
+constexpr int kTwLargeVals = 1024 + 1024 + 8;  // the three pass-A tables
+constexpr int kLog2NLargeMax = 23;
+
 // float2 slots of a tile: TC padded columns, rounded up to whole 256-value
 // blocks (the swizzle permutes within aligned blocks of 256)
 __host__ __device__ constexpr int tile_vals(int log2len, int tc) { return (tc * ((1 << log2len) + 1) + 255) / 256 * 256; }
 
-// TC: columns per tile (16, 32 or 64: runs of 128, 256 or 512 bytes)
+// TC: columns per tile (2 to 64: runs of 16 to 512 bytes)
 template <int R, int LOG2LEN, bool PASS_A, int TC>
 __global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out, const float2 *__restrict__ tw,
                                                     const float2 *__restrict__ tw_lo,
@@ -52,23 +60,30 @@ __global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out
     constexpr int LTC = clog2(TC);
     extern __shared__ float4 lds_raw[];
     float2 *buf = reinterpret_cast<float2 *>(lds_raw);
-    const long long prob = blockIdx.x / tiles;
-    const int c0 = (int)(blockIdx.x % tiles) * TC;
+    long long blk = blockIdx.x;
+    if constexpr (TC < 16) {  // XCD x (= blk mod 8) takes the x-th eighth of the tiles, in order
+        const long long nb = gridDim.x;
+        if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    }
+    const long long prob = blk / tiles;
+    const int c0 = (int)(blk % tiles) * TC;
     const long long base = prob << log2n;
     const long long cols = 1LL << log2cols;
-    // pass A: both twiddle tables in LDS after the tile.  Read from global
+    // pass A: the twiddle tables in LDS after the tile.  Read from global
     // memory in the store loop, each table read would wait for the stores
     // issued before it (vector memory operations complete in issue order).
     // The lanes of the store loop read the low table at a stride of (column
-    // index) * n / 2^20 entries, often a multiple of 32; the tables are
-    // stored XOR-swizzled (bits 5..9 into 0..4) so that such strides spread
-    // over the banks.
-    float2 *tlo = buf + tile_vals(LOG2LEN, TC), *thi = tlo + 1024;
-    if constexpr (PASS_A)
+    // index) * 2^23 / n entries, often a multiple of 32; the two large
+    // tables are stored XOR-swizzled (bits 5..9 into 0..4) so that such
+    // strides spread over the banks.
+    float2 *tlo = buf + tile_vals(LOG2LEN, TC), *thi = tlo + 1024, *tht = thi + 1024;
+    if constexpr (PASS_A) {
         for (int j = threadIdx.x; j < 1024; j += blockDim.x) {
             tlo[tw_swz(j)] = tw_lo[j];
             thi[tw_swz(j)] = tw_hi[j];
         }
+        if (threadIdx.x < 8) tht[threadIdx.x] = tw_hi[1024 + threadIdx.x];
+    }
     for (int i = threadIdx.x; i < len * TC; i += blockDim.x) {
         const int c = i & (TC - 1), e = i >> LTC;
         buf[tile_slot(c, e, len)] = in[base + e * cols + c0 + c];
@@ -89,11 +104,12 @@ __global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out
         // k < R): its twiddles w^{(c0 + c) e} form a geometric sequence with
         // ratio w^{CS e}, started and stepped from the tables (R - 1 products,
         // so a few ulp of drift at most).
+        static_assert(TC >= R, "a pass-A thread stores R columns of one row");
         constexpr int CS = TC / R;
-        const int shift = 20 - log2n;
+        const int shift = kLog2NLargeMax - log2n;
         auto table_tw = [&](unsigned m) {  // w_n^m for m < n
-            const unsigned q = m << shift;  // < 2^20
-            return cmul(tlo[tw_swz((int)(q & 1023u))], thi[tw_swz((int)(q >> 10))]);
+            const unsigned q = m << shift;  // < 2^23
+            return cmul(cmul(tlo[tw_swz((int)(q & 1023u))], thi[tw_swz((int)((q >> 10) & 1023u))]), tht[q >> 20]);
         };
         const int e = threadIdx.x & (len - 1), ct = threadIdx.x >> LOG2LEN;
         float2 w = table_tw((unsigned)(c0 + ct) * (unsigned)e);
@@ -117,18 +133,23 @@ using TileKernel = void (*)(const float2 *, float2 *, const float2 *, const floa
                             long long, float);
 
 constexpr int kTileLdsMax = 160 * 1024;
-// LDS bytes of a pass: the tile, plus the twiddle tables (2 x 1024 values) in pass A
+// LDS bytes of a pass: the tile, plus the twiddle tables in pass A
 constexpr int64_t tile_lds(int log2len, int tc, bool pass_a) {
-    return ((int64_t)tile_vals(log2len, tc) + (pass_a ? 2048 : 0)) * (int64_t)sizeof(float2);
+    return ((int64_t)tile_vals(log2len, tc) + (pass_a ? kTwLargeVals : 0)) * (int64_t)sizeof(float2);
 }
-constexpr bool tile_ok(int radix, int log2len, int tc) {
+// Tile shapes: radix 8 or 16; 64 to 1024 threads; the LDS budget; pass A
+// stores R columns per thread (TC >= R) and keeps columns of at most 1024
+// values; tiles narrower than 16 columns only where wider ones do not fit
+// (columns of more than 1024 values).
+constexpr bool tile_ok(int radix, int log2len, int tc, bool pass_a) {
     return (radix == 8 || radix == 16) && log2len >= clog2(radix) && tc * ((1 << log2len) / radix) >= 64 &&
-           tc * ((1 << log2len) / radix) <= 1024 && tile_lds(log2len, tc, true) <= kTileLdsMax;
+           tc * ((1 << log2len) / radix) <= 1024 && tile_lds(log2len, tc, pass_a) <= kTileLdsMax &&
+           (!pass_a || (tc >= radix && log2len <= 10)) && (tc >= 16 || log2len > 10);
 }
 
 template <int R, int L, bool A, int TC>
 static TileKernel tile_entry() {
-    if constexpr (tile_ok(R, L, TC)) return &k_fft_tile<R, L, A, TC>;
+    if constexpr (tile_ok(R, L, TC, A)) return &k_fft_tile<R, L, A, TC>;
     else return nullptr;
 }
 template <int R, bool A, int TC>
@@ -140,15 +161,28 @@ static TileKernel tile_len(int log2len) {
         case 8: return tile_entry<R, 8, A, TC>();
         case 9: return tile_entry<R, 9, A, TC>();
         case 10: return tile_entry<R, 10, A, TC>();
+        case 11: return tile_entry<R, 11, A, TC>();
+        case 12: return tile_entry<R, 12, A, TC>();
+        case 13: return tile_entry<R, 13, A, TC>();
+        default: return nullptr;
+    }
+}
+template <int R, bool A>
+static TileKernel tile_tc(int log2len, int tc) {
+    switch (tc) {
+        case 2: return tile_len<R, A, 2>(log2len);
+        case 4: return tile_len<R, A, 4>(log2len);
+        case 8: return tile_len<R, A, 8>(log2len);
+        case 16: return tile_len<R, A, 16>(log2len);
+        case 32: return tile_len<R, A, 32>(log2len);
+        case 64: return tile_len<R, A, 64>(log2len);
         default: return nullptr;
     }
 }
 template <bool A>
 static TileKernel tile_lookup(int radix, int log2len, int tc) {
-    if (radix == 16) return tc == 16 ? tile_len<16, A, 16>(log2len) : tc == 32 ? tile_len<16, A, 32>(log2len)
-                                       : tc == 64 ? tile_len<16, A, 64>(log2len) : nullptr;
-    if (radix == 8) return tc == 16 ? tile_len<8, A, 16>(log2len) : tc == 32 ? tile_len<8, A, 32>(log2len)
-                                      : tc == 64 ? tile_len<8, A, 64>(log2len) : nullptr;
+    if (radix == 16) return tile_tc<16, A>(log2len, tc);
+    if (radix == 8) return tile_tc<8, A>(log2len, tc);
     return nullptr;
 }
 
@@ -157,8 +191,8 @@ const void *fft_tile_kernel(int radix, int log2len, int tc, bool pass_a) {
                                                  : tile_lookup<false>(radix, log2len, tc));
 }
 
-bool fft_tile_shape_valid(int radix, int log2len, int tc) {
-    return tile_lookup<true>(radix, log2len, tc) != nullptr;
+bool fft_tile_shape_valid(int radix, int log2len, int tc, bool pass_a) {
+    return (pass_a ? tile_lookup<true>(radix, log2len, tc) : tile_lookup<false>(radix, log2len, tc)) != nullptr;
 }
 
 int64_t fft_tile_lds_bytes(int log2len, int tc, bool pass_a) { return tile_lds(log2len, tc, pass_a); }
@@ -166,11 +200,16 @@ int64_t fft_tile_lds_bytes(int log2len, int tc, bool pass_a) { return tile_lds(l
 void fft_large_host_twiddles(float *lo2, float *hi2) {
     const double two_pi = 6.283185307179586476925286766559;
     for (int j = 0; j < 1024; ++j) {
-        const double a = two_pi * (double)j / (double)(1 << 20), b = two_pi * (double)j / 1024.0;
+        const double a = two_pi * (double)j / (double)(1 << kLog2NLargeMax), b = two_pi * (double)j / 8192.0;
         lo2[2 * j] = (float)cos(a);
         lo2[2 * j + 1] = (float)(-sin(a));
         hi2[2 * j] = (float)cos(b);
         hi2[2 * j + 1] = (float)(-sin(b));
+    }
+    for (int j = 0; j < 8; ++j) {  // w_8^j
+        const double c = two_pi * (double)j / 8.0;
+        hi2[2 * (1024 + j)] = (float)cos(c);
+        hi2[2 * (1024 + j) + 1] = (float)(-sin(c));
     }
 }
 
@@ -178,12 +217,12 @@ void fft_large_host_twiddles(float *lo2, float *hi2) {
 
 int fft_plan_check(int64_t n, const ppx_fft_plan &p) {
     if (!is_pow2(n) || n <= PPX_MAX_N || n > PPX_MAX_N_LARGE)
-        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 1048576]");
+        return fail(PPX_EINVAL, "large FFT: n must be a power of two in (16384, 8388608]");
     const int ln = ilog2(n);
     if (p.log2_n1 < 1 || p.log2_n1 >= ln) return fail(PPX_ECONFIG, "plan: log2_n1 out of range");
-    if (!fft_tile_shape_valid(p.radix_a, ln - p.log2_n1, p.tile_a))
+    if (!fft_tile_shape_valid(p.radix_a, ln - p.log2_n1, p.tile_a, true))
         return fail(PPX_ECONFIG, "plan: no pass-A tile kernel for this radix / tile width and column length n / n1");
-    if (!fft_tile_shape_valid(p.radix_b, p.log2_n1, p.tile_b))
+    if (!fft_tile_shape_valid(p.radix_b, p.log2_n1, p.tile_b, false))
         return fail(PPX_ECONFIG, "plan: no pass-B tile kernel for this radix / tile width and column length n1");
     if ((int64_t(1) << p.log2_n1) % p.tile_a || (n >> p.log2_n1) % p.tile_b)
         return fail(PPX_ECONFIG, "plan: tile width exceeds the number of columns");
@@ -197,24 +236,35 @@ std::vector<ppx_fft_plan> fft_enumerate_plans(int64_t n) {
     for (int l1 = 1; l1 < ln; ++l1)
         for (int ra : {8, 16})
             for (int rb : {8, 16})
-                for (int ta : {16, 32, 64})
-                    for (int tb : {16, 32, 64}) {
+                for (int ta : {2, 4, 8, 16, 32, 64})
+                    for (int tb : {2, 4, 8, 16, 32, 64}) {
                         const ppx_fft_plan p{l1, ra, rb, ta, tb};
-                        if (fft_tile_shape_valid(ra, ln - l1, ta) && fft_tile_shape_valid(rb, l1, tb) &&
+                        if (fft_tile_shape_valid(ra, ln - l1, ta, true) && fft_tile_shape_valid(rb, l1, tb, false) &&
                             (int64_t(1) << l1) % ta == 0 && (n >> l1) % tb == 0)
                             out.push_back(p);
                     }
     return out;
 }
 
+// The most even split (n1 <= n2 on a tie) with radix 8 where it exists and
+// 16-column tiles, narrower in pass B where its columns need it.
 void fft_default_plan(int64_t n, ppx_fft_plan &p) {
     const int ln = ilog2(n);
     p = ppx_fft_plan{0, 0, 0, 0, 0};
-    for (int l1 = ln / 2; l1 >= 1 && !p.log2_n1; --l1)  // the most even split with n1 <= n2
-        for (int ra : {8, 16})
+    int best = 1 << 30;
+    for (int l1 = 1; l1 < ln; ++l1) {
+        const int uneven = 2 * std::abs(2 * l1 - ln) + (2 * l1 > ln ? 1 : 0);
+        if (uneven >= best) continue;
+        for (int ra : {8, 16}) {
+            if (!fft_tile_shape_valid(ra, ln - l1, 16, true)) continue;
             for (int rb : {8, 16})
-                if (!p.log2_n1 && fft_tile_shape_valid(ra, ln - l1, 16) && fft_tile_shape_valid(rb, l1, 16))
-                    p = ppx_fft_plan{l1, ra, rb, 16, 16};
+                for (int tb : {16, 8, 4, 2})
+                    if (uneven < best && fft_tile_shape_valid(rb, l1, tb, false) && (n >> l1) % tb == 0) {
+                        p = ppx_fft_plan{l1, ra, rb, 16, tb};
+                        best = uneven;
+                    }
+        }
+    }
 }
 
 namespace {

@@ -39,7 +39,7 @@ struct DeviceInfo {
     int64_t l2_bytes = 0;
     std::string arch;
     const void *twiddles = nullptr;  // device table w[m] = exp(-2 pi i m/NMAX)
-    // large-N tables: w_{2^20}^j and w_{2^20}^{1024 j}, j < 1024
+    // large-N tables: w_{2^23}^j (j < 1024); w_{2^13}^j (j < 1024) then w_8^j (j < 8)
     const void *twiddles_large_lo = nullptr;
     const void *twiddles_large_hi = nullptr;
 };
@@ -120,9 +120,9 @@ const void *tridiag_kernel(int dtype, int algo, int P);
 void fft_host_twiddles(float *out2);
 
 // ---- large-N FFT (fft_large.hip) ----
-void fft_large_host_twiddles(float *lo2, float *hi2);  // 1024 pairs each
+void fft_large_host_twiddles(float *lo2, float *hi2);  // 1024 and 1032 pairs
 const void *fft_tile_kernel(int radix, int log2len, int tile, bool pass_a);
-bool fft_tile_shape_valid(int radix, int log2len, int tile);  // a pass of column length 2^log2len
+bool fft_tile_shape_valid(int radix, int log2len, int tile, bool pass_a);  // a pass of column length 2^log2len
 int64_t fft_tile_lds_bytes(int log2len, int tile, bool pass_a);
 int launch_fft_large(const void *in, void *out, int log2n, int64_t batch, const ppx_fft_plan &p, bool inverse,
                      hipStream_t s);

@@ -962,8 +962,8 @@ static int analytical_plan(int64_t n, int64_t batch, ppx_fft_plan &out) {
         std::vector<ppx_config> c;
         std::vector<ppx_resource> r;
         for (int radix : {8, 16})
-            for (int tile : {16, 32, 64}) {
-                if (!fft_tile_shape_valid(radix, l, tile) || ncols % tile) continue;
+            for (int tile : {2, 4, 8, 16, 32, 64}) {
+                if (!fft_tile_shape_valid(radix, l, tile, pass == 0) || ncols % tile) continue;
                 const int threads = tile * ((1 << l) / radix);
                 hipFuncAttributes a;
                 if (hipFuncGetAttributes(&a, fft_tile_kernel(radix, l, tile, pass == 0)) != hipSuccess)

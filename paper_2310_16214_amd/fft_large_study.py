@@ -1,5 +1,5 @@
 """Large-N FFT study on the current GPU: the two-pass plans of
-fft_batched_large for N = 2^15 .. 2^20 at 256 MiB per call (2^25 / N
+fft_batched_large for N = 2^15 .. 2^23 at 256 MiB per call (2^25 / N
 problems), each method of tune_fft_large (exhaustive, analytical, learned)
 against the exhaustive best, the Phi metric of Sec. VI over the sizes, the
 default plan, and the best plan's throughput against the 8 TB/s HBM peak and
@@ -78,7 +78,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=30)
     ap.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"))
-    ap.add_argument("--sizes", default="15,16,17,18,19,20")
+    ap.add_argument("--sizes", default="15,16,17,18,19,20,21,22,23")
     ap.add_argument("--report", nargs="+", default=None, metavar=("STUDY_JSON", "KERNEL_STATS_CSV"),
                     help="print the markdown summary of a study (no GPU)")
     ap.add_argument("--replay", default="",

@@ -253,7 +253,7 @@ class FftPlan(ctypes.Structure):
 
 
 MAX_N = 16384
-MAX_N_LARGE = 1 << 20
+MAX_N_LARGE = 1 << 23
 
 _tune_sigs = {
     "fft_batched_large": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
@@ -354,7 +354,7 @@ class OnlineTuner:
 
 
 def fft_batched_large(inp, out, n, batch, direction=-1, plan=None, stream=None):
-    """Two-pass FFT for 16384 < n <= 2^20 (see include/ppx.h); in and out must
+    """Two-pass FFT for 16384 < n <= 2^23 (see include/ppx.h); in and out must
     not overlap."""
     _check(_tl("fft_batched_large")(_ptr(inp), _ptr(out), n, batch, direction,
                                     ctypes.byref(plan) if plan is not None else None,

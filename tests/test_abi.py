@@ -29,7 +29,7 @@ BUF = 4096  # a fake, 16-byte aligned "device" address: never dereferenced
     ((BUF + 4, BUF, 1024, 1, -1), "aligned"),
     ((BUF, BUF, 1000, 1, -1), "power of two"),
     ((BUF, BUF, 8, 1, -1), "power of two"),
-    ((BUF, BUF, 1 << 21, 1, -1), "power of two"),
+    ((BUF, BUF, 1 << 24, 1, -1), "power of two"),
     ((BUF, BUF, 1024, 0, -1), "batch"),
     ((BUF, BUF, 1024, 1, 0), "direction"),
     ((BUF, BUF + 16, 1024, 4, -1), "overlap"),
@@ -45,7 +45,7 @@ def test_fft_argument_errors(args, msg):
     ((0, BUF, 1 << 16, 1, -1), "null"),
     ((BUF + 8, 1 << 30, 1 << 16, 1, -1), "aligned"),
     ((BUF, 1 << 30, 1 << 14, 1, -1), "power of two"),
-    ((BUF, 1 << 30, 1 << 21, 1, -1), "power of two"),
+    ((BUF, 1 << 40, 1 << 24, 1, -1), "power of two"),
     ((BUF, 1 << 30, 3 << 15, 1, -1), "power of two"),
     ((BUF, 1 << 30, 1 << 16, 0, -1), "batch"),
     ((BUF, 1 << 30, 1 << 16, 1, 2), "direction"),
@@ -67,32 +67,41 @@ def test_fft_batched_forwards_large_n_and_rejects_a_config():
 
 
 def test_fft_plans():
-    for ln in range(15, 21):
+    for ln in range(15, 24):
         n = 1 << ln
         plans = ppx.enumerate_fft_plans(n)
         assert plans, n
         for p in plans:
             assert ppx.fft_plan_valid(n, p)
             l2 = ln - p.log2_n1
-            for radix, length, tile, ncols in ((p.radix_a, l2, p.tile_a, 1 << p.log2_n1),
-                                               (p.radix_b, p.log2_n1, p.tile_b, 1 << l2)):
+            for radix, length, tile, ncols, extra in ((p.radix_a, l2, p.tile_a, 1 << p.log2_n1, 2056),
+                                                      (p.radix_b, p.log2_n1, p.tile_b, 1 << l2, 0)):
                 threads = tile * (1 << length) // radix
-                lds = -(-tile * ((1 << length) + 1) // 256) * 256 * 8
-                assert radix in (8, 16) and tile in (16, 32, 64) and ncols % tile == 0
+                lds = (-(-tile * ((1 << length) + 1) // 256) * 256 + extra) * 8
+                assert radix in (8, 16) and ncols % tile == 0
+                assert tile in ((16, 32, 64) if length <= 10 else (2, 4, 8))
                 assert 64 <= threads <= 1024 and lds <= 160 * 1024
+            assert l2 <= 10 and p.tile_a >= p.radix_a  # pass A: short columns, R columns per thread
         keys = [p.as_tuple() for p in plans]
         assert keys == sorted(keys) and len(set(keys)) == len(keys)
         d = ppx.default_fft_plan(n)
         assert d.as_tuple() in keys
-        assert d.log2_n1 <= ln - d.log2_n1  # n1 <= n2, the most even such split
-        assert not any(q[0] > d.log2_n1 and q[0] <= ln - q[0] for q in keys)
-    assert [p.as_tuple() for p in ppx.enumerate_fft_plans(1 << 20)] == [(10, 16, 16, 16, 16)]
+        # the most even split (n1 <= n2 on a tie)
+        uneven = lambda l1: (abs(2 * l1 - ln), 2 * l1 > ln)  # noqa: E731
+        assert all(uneven(d.log2_n1) <= uneven(q[0]) for q in keys)
+    assert ppx.default_fft_plan(1 << 20).as_tuple() == (10, 16, 16, 16, 16)
+    assert ppx.default_fft_plan(1 << 23).as_tuple() == (13, 16, 16, 16, 2)
+    assert [p.as_tuple() for p in ppx.enumerate_fft_plans(1 << 23)] == [(13, 16, 16, 16, 2)]
     assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 4, 16))      # radix 4
     assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(11, 16, 16))    # n1 = 2048 too long
     assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(6, 8, 16))      # n2 = 1024 with radix 8
     assert not ppx.fft_plan_valid(1 << 14, ppx.make_plan(7, 16, 16))     # not a large size
     assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 16, 16, 32, 128))  # tile 128
     assert not ppx.fft_plan_valid(1 << 20, ppx.make_plan(10, 16, 16, 32, 16))  # 32 x 1025 values of LDS
+    assert not ppx.fft_plan_valid(1 << 21, ppx.make_plan(10, 16, 16, 16, 16))  # pass A column of 2048
+    assert not ppx.fft_plan_valid(1 << 21, ppx.make_plan(11, 16, 16, 16, 16))  # 16 x 2049 values of LDS
+    assert ppx.fft_plan_valid(1 << 21, ppx.make_plan(11, 16, 16, 16, 8))
+    assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 16, 16, 16, 8))   # narrow tile on short columns
     assert ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 16, 16, 64, 64))
     with pytest.raises(ppx.PpxError):
         ppx.enumerate_fft_plans(1 << 14)

@@ -1,8 +1,9 @@
-"""GPU parity of the two-pass large-N FFT (16384 < N <= 2^20) against the
+"""GPU parity of the two-pass large-N FFT (16384 < N <= 2^23) against the
 oracle: every plan at N = 2^15 and 2^16 on whole problems (every bin by its
-definition),
-the default plan up to 2^20 on sampled bins (each bin by its definition),
-forward and inverse.  Bar: per-problem relative L2 <= 1e-5 * log2 N."""
+definition), every plan at 2^20 .. 2^23 (narrow pass-B tiles for columns of
+more than 1024 values) and the default plan at full size up to 2^23 on
+sampled bins (each bin by its definition) plus Parseval, forward and
+inverse.  Bar: per-problem relative L2 <= 1e-5 * log2 N."""
 import numpy as np
 import pytest
 
@@ -40,7 +41,42 @@ def test_every_plan_matches_oracle(cuda, n):
     print(f"n={n}: {len(plans)} plans, worst rel-L2 {worst:.3e}")
 
 
-@pytest.mark.parametrize("ln", [17, 18, 19, 20])
+def _sampled_bins(x, y, n, rng, problems, inverse=False):
+    ks = np.unique(np.concatenate([[0, 1, n // 2, n - 1], rng.integers(0, n, 44)]))
+    for b in problems:
+        ref = oracle.dft_bins(x[b:b + 1], ks, inverse=inverse)[0]
+        err = np.linalg.norm(y[b, ks] - ref) / np.linalg.norm(ref)
+        assert err <= fft_tol(n), (b, err)
+
+
+def _parseval(x, y, n):
+    px = np.sum(np.abs(x.astype(np.complex128)) ** 2, axis=1) * n
+    py = np.sum(np.abs(y.astype(np.complex128)) ** 2, axis=1)
+    assert np.max(np.abs(py - px) / px) <= 2 * fft_tol(n)
+
+
+@pytest.mark.parametrize("ln", [20, 21, 22, 23])
+def test_every_plan_sampled_bins(cuda, ln):
+    """Every plan, forward and inverse, two problems: 48 bins each by
+    definition, every bin through Parseval."""
+    n = 1 << ln
+    batch = 2
+    x = inputs.fft_input(n, batch, seed=ln + 40)
+    ks = np.unique(np.concatenate([[0, 1, n // 2, n - 1], np.random.default_rng(ln).integers(0, n, 44)]))
+    refs = {d: oracle.dft_bins(x, ks, inverse=d > 0) for d in (-1, +1)}  # [problem][bin]
+    plans = ppx.enumerate_fft_plans(n)
+    assert plans
+    for p in plans:
+        for direction in (-1, +1):
+            banner(f"fft large n={n} {p} dir={direction}")
+            y = _run(x, n, batch, p, direction)
+            err = np.linalg.norm(y[:, ks] - refs[direction], axis=1) / np.linalg.norm(refs[direction], axis=1)
+            assert err.max() <= fft_tol(n), (p, direction, err)
+            _parseval(x, y, n)
+    print(f"n={n}: {len(plans)} plans")
+
+
+@pytest.mark.parametrize("ln", [17, 18, 19, 20, 21, 22, 23])
 def test_default_plan_sampled_bins(cuda, ln):
     """Full 256 MiB call (2^25 / N problems); 3 problems checked on 48 bins
     each (their DFT by definition), the rest of the output through Parseval."""
@@ -49,16 +85,8 @@ def test_default_plan_sampled_bins(cuda, ln):
     banner(f"fft large n={n} batch={batch} default plan")
     x = inputs.fft_input(n, batch, seed=ln)
     y = _run(x, n, batch)
-    rng = np.random.default_rng(ln)
-    ks = np.unique(np.concatenate([[0, 1, n // 2, n - 1], rng.integers(0, n, 44)]))
-    for b in (0, batch // 2, batch - 1):
-        ref = oracle.dft_bins(x[b:b + 1], ks)[0]
-        err = np.linalg.norm(y[b, ks] - ref) / np.linalg.norm(ref)
-        assert err <= fft_tol(n), (b, err)
-    # Parseval on every problem: sum |X|^2 = N sum |x|^2
-    px = np.sum(np.abs(x.astype(np.complex128)) ** 2, axis=1) * n
-    py = np.sum(np.abs(y.astype(np.complex128)) ** 2, axis=1)
-    assert np.max(np.abs(py - px) / px) <= 2 * fft_tol(n)
+    _sampled_bins(x, y, n, np.random.default_rng(ln), (0, batch // 2, batch - 1))
+    _parseval(x, y, n)  # every problem: sum |X|^2 = N sum |x|^2
 
 
 def test_inverse_roundtrip_and_forwarding(cuda):
