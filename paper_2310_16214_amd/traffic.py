@@ -70,6 +70,10 @@ def main(fetch_csv, write_csv, detail_jsonl, out_json):
     copies = [(f, w) for f, w in zip(F, W) if "copyBuffer" in f[1]]
     if not copies:
         raise SystemExit("no reference copy in the counter runs (run bench.py --copy-ref)")
+    # the reference copies are the largest copy dispatches (small ones, such
+    # as table uploads, also use the copy kernel)
+    gmax = max(f[2] for f, _ in copies)
+    copies = [(f, w) for f, w in copies if f[2] == gmax]
     f_scale = COPY_BYTES / 1024 / (sum(f[4] for f, _ in copies) / len(copies))
     w_scale = COPY_BYTES / 1024 / (sum(w[4] for _, w in copies) / len(copies))
     detail = [json.loads(x) for x in open(detail_jsonl)]
