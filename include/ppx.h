@@ -149,13 +149,14 @@ int fft_batched(const void *in, void *out, int64_t n, int64_t batch,
  * pass B over the n1 dimension, in place in `out`).  A plan fixes the split
  * and each pass's radix (= values per thread):
  *   log2_n1    log2 n1; both passes need a column length in the range their
- *              radix supports (pass A: radix 16 2^6..2^10, radix 8
- *              2^5..2^9; pass B also 2^11..2^13 in narrow tiles)
+ *              radix and tile support (radix 16 from 2^6, radix 8 from
+ *              2^5; beyond 2^10 only narrow tiles, up to 2^12 in pass A
+ *              and 2^13 in pass B)
  *   radix_a    radix of pass A (column length n2 = n / n1)
  *   radix_b    radix of pass B (column length n1)
- *   tile_a     columns per workgroup of pass A (16, 32 or 64, >= radix_a)
- *   tile_b     columns per workgroup of pass B (16, 32 or 64 for columns of
- *              up to 1024 values; 2, 4 or 8 for longer ones)
+ *   tile_a     columns per workgroup of pass A
+ *   tile_b     columns per workgroup of pass B: 16, 32 or 64 for columns of
+ *              up to 1024 values, 2, 4 or 8 for longer ones
  * A pass's workgroup transforms tile adjacent columns of length len with
  * tile * len / radix threads (64..1024) and tile * (len + 1) complex values
  * of LDS (<= 160 KiB, with 2056 more for pass A's twiddle tables); the tile
@@ -193,9 +194,9 @@ int ppx_fft_plan_valid(int64_t n, const ppx_fft_plan *plan);
 int ppx_enumerate_fft_plans(int64_t n, ppx_fft_plan *out, int cap);
 
 /*
- * The untuned plan: the most even valid split (n1 <= n2 on a tie) with
- * radix 8 in both passes where valid and 16-column tiles (pass B's widest
- * valid tile for columns of more than 1024 values).  The analytical plan (tune_fft_large with
+ * The untuned plan: the most even valid split (n1 <= n2 on a tie) and, in
+ * each pass, the widest tile of at most 16 columns, with radix 8 where both
+ * radices allow it.  The analytical plan (tune_fft_large with
  * PPX_TUNE_ANALYTICAL) is the gfx950 occupancy guideline applied per pass.
  */
 int ppx_default_fft_plan(int64_t n, ppx_fft_plan *out);

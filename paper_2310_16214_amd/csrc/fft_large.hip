@@ -18,9 +18,9 @@
 // back the same way (pass B) or row by row (pass A, 512-byte runs per wave).
 // The LDS tile pads each column to len + 1 values, so that the TC values a
 // row read or write touches fall on different banks.  Columns of up to 1024
-// values take tiles of 16, 32 or 64 (runs of 128 to 512 bytes); pass B's
-// columns of 2048 to 8192 values (n > 2^20) fit LDS only in tiles of 2, 4 or
-// 8 (runs of 16 to 64 bytes).  Those narrow tiles number the workgroups so
+// values take tiles of 16, 32 or 64 (runs of 128 to 512 bytes); columns of
+// 2048 to 8192 values fit LDS only in tiles of 2, 4 or 8 (runs of 16 to 64
+// bytes; pass A with its tables up to 4096 values).  Those narrow tiles number the workgroups so
 // that the tiles sharing a row's cache lines run on one XCD, whose L2 then
 // serves the lines to all of them (workgroups are dealt to the 8 XCDs in
 // turn).
@@ -105,26 +105,45 @@ __global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out
     fft_stages_ct<R, P, false, LOG2LEN, 0, true>(v, buf, lp * (len + 1), nullptr, tid, true, sgn, tw);
     __syncthreads();
     if constexpr (PASS_A) {
-        // The workgroup has len * TC / R threads, so thread t stores element
-        // e = t mod len of columns ct + k * CS (ct = t div len, CS = TC / R,
-        // k < R): its twiddles w^{(c0 + c) e} form a geometric sequence with
-        // ratio w^{CS e}, started and stepped from the tables (R - 1 products,
-        // so a few ulp of drift at most).
-        static_assert(TC >= R, "a pass-A thread stores R columns of one row");
-        constexpr int CS = TC / R;
+        // Element (c, e) of the tile is stored at row c0 + c, position e, of
+        // the intermediate, times w^{(c0 + c) e}; consecutive threads take
+        // consecutive e (runs of 512 bytes per wave).  The workgroup has
+        // len * TC / R threads.  With TC >= R thread t takes e = t mod len
+        // and the R columns ct + k * CS (ct = t div len, CS = TC / R): its
+        // twiddles form a geometric sequence with ratio w^{CS e}.  With
+        // TC < R it takes the R / TC rows e = t + r * len * TC / R and all TC
+        // columns of each: one sequence of ratio w^e per row.  Sequences are
+        // started and stepped from the tables (at most R - 1 products, so a
+        // few ulp of drift at most).
         const int shift = kLog2NLargeMax - log2n;
         auto table_tw = [&](unsigned m) {  // w_n^m for m < n
             const unsigned q = m << shift;  // < 2^23
             return cmul(cmul(tlo[tw_swz((int)(q & 1023u))], thi[tw_swz((int)((q >> 10) & 1023u))]), tht[q >> 20]);
         };
-        const int e = threadIdx.x & (len - 1), ct = threadIdx.x >> LOG2LEN;
-        float2 w = table_tw((unsigned)(c0 + ct) * (unsigned)e);
-        const float2 step = table_tw((unsigned)CS * (unsigned)e);
+        if constexpr (TC >= R) {
+            constexpr int CS = TC / R;
+            const int e = threadIdx.x & (len - 1), ct = threadIdx.x >> LOG2LEN;
+            float2 w = table_tw((unsigned)(c0 + ct) * (unsigned)e);
+            const float2 step = table_tw((unsigned)CS * (unsigned)e);
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int c = ct + k * CS;
-            store_nt_any(out + base + (long long)(c0 + c) * len + e, cmul(buf[tile_slot(c, e, len)], w));
-            w = cmul(w, step);
+            for (int k = 0; k < R; ++k) {
+                const int c = ct + k * CS;
+                store_nt_any(out + base + (long long)(c0 + c) * len + e, cmul(buf[tile_slot(c, e, len)], w));
+                w = cmul(w, step);
+            }
+        } else {
+            constexpr int NT = len * TC / R;  // threads of the workgroup
+#pragma unroll
+            for (int r = 0; r < R / TC; ++r) {
+                const int e = (int)threadIdx.x + r * NT;
+                float2 w = table_tw((unsigned)c0 * (unsigned)e);
+                const float2 step = table_tw((unsigned)e);
+#pragma unroll
+                for (int c = 0; c < TC; ++c) {
+                    store_nt_any(out + base + (long long)(c0 + c) * len + e, cmul(buf[tile_slot(c, e, len)], w));
+                    w = cmul(w, step);
+                }
+            }
         }
     } else {
         for (int i = threadIdx.x; i < len * TC; i += blockDim.x) {
@@ -146,14 +165,13 @@ constexpr int kTileLdsMax = 160 * 1024;
 constexpr int64_t tile_lds(int log2len, int tc, bool pass_a) {
     return ((int64_t)tile_vals(log2len, tc) + (pass_a ? kTwLargeVals : 0)) * (int64_t)sizeof(float2);
 }
-// Tile shapes: radix 8 or 16; 64 to 1024 threads; the LDS budget; pass A
-// stores R columns per thread (TC >= R) and keeps columns of at most 1024
-// values; tiles narrower than 16 columns only where wider ones do not fit
-// (columns of more than 1024 values).
+// Tile shapes: radix 8 or 16; 64 to 1024 threads; the LDS budget (pass A
+// with its tables); tiles narrower than 16 columns only where wider ones do
+// not fit (columns of more than 1024 values).
 constexpr bool tile_ok(int radix, int log2len, int tc, bool pass_a) {
     return (radix == 8 || radix == 16) && log2len >= clog2(radix) && tc * ((1 << log2len) / radix) >= 64 &&
            tc * ((1 << log2len) / radix) <= 1024 && tile_lds(log2len, tc, pass_a) <= kTileLdsMax &&
-           (!pass_a || (tc >= radix && log2len <= 10)) && (tc >= 16 || log2len > 10);
+           (tc >= 16 || log2len > 10);
 }
 
 template <int R, int L, bool A, int TC>
@@ -255,23 +273,28 @@ std::vector<ppx_fft_plan> fft_enumerate_plans(int64_t n) {
     return out;
 }
 
-// The most even split (n1 <= n2 on a tie) with radix 8 where it exists and
-// 16-column tiles, narrower in pass B where its columns need it.
+// The most even valid split (n1 <= n2 on a tie) and, in each pass, the
+// widest tile of at most 16 columns, with radix 8 where both radices allow it.
 void fft_default_plan(int64_t n, ppx_fft_plan &p) {
     const int ln = ilog2(n);
     p = ppx_fft_plan{0, 0, 0, 0, 0};
+    auto pick = [&](int log2len, int64_t ncols, bool pass_a, int &radix, int &tile) {
+        for (int t : {16, 8, 4, 2})
+            for (int r : {8, 16})
+                if (fft_tile_shape_valid(r, log2len, t, pass_a) && ncols % t == 0) {
+                    radix = r;
+                    tile = t;
+                    return true;
+                }
+        return false;
+    };
     int best = 1 << 30;
     for (int l1 = 1; l1 < ln; ++l1) {
         const int uneven = 2 * std::abs(2 * l1 - ln) + (2 * l1 > ln ? 1 : 0);
-        if (uneven >= best) continue;
-        for (int ra : {8, 16}) {
-            if (!fft_tile_shape_valid(ra, ln - l1, 16, true)) continue;
-            for (int rb : {8, 16})
-                for (int tb : {16, 8, 4, 2})
-                    if (uneven < best && fft_tile_shape_valid(rb, l1, tb, false) && (n >> l1) % tb == 0) {
-                        p = ppx_fft_plan{l1, ra, rb, 16, tb};
-                        best = uneven;
-                    }
+        int ra, ta, rb, tb;
+        if (uneven < best && pick(ln - l1, int64_t(1) << l1, true, ra, ta) && pick(l1, n >> l1, false, rb, tb)) {
+            p = ppx_fft_plan{l1, ra, rb, ta, tb};
+            best = uneven;
         }
     }
 }
