@@ -158,7 +158,7 @@ def online_study(pools, njobs, seed, budget, max_inflight, cache):
     return res
 
 
-def run(njobs=2000, loads=(0.25, 0.5, 0.75, 0.9), budget=4 << 30, max_inflight=2, seed=0,
+def run(njobs=10000, loads=(0.25, 0.5, 0.75, 0.9), budget=4 << 30, max_inflight=2, seed=0,
         quick=False):
     import torch
 
@@ -201,7 +201,7 @@ def run(njobs=2000, loads=(0.25, 0.5, 0.75, 0.9), budget=4 << 30, max_inflight=2
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--jobs", type=int, default=2000)
+    ap.add_argument("--jobs", type=int, default=10000)
     ap.add_argument("--budget-gib", type=float, default=4.0)
     ap.add_argument("--max-inflight", type=int, default=2)
     ap.add_argument("--out", default="")
