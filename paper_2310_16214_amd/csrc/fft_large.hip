@@ -17,13 +17,14 @@
 // R = P, T = len/P threads per column, exchanges in LDS), and writes the tile
 // back the same way (pass B) or row by row (pass A, 512-byte runs per wave).
 // The LDS tile pads each column to len + 1 values, so that the TC values a
-// row read or write touches fall on different banks.  Columns of up to 1024
-// values take tiles of 16, 32 or 64 (runs of 128 to 512 bytes); columns of
-// 2048 to 8192 values fit LDS only in tiles of 2, 4 or 8 (runs of 16 to 64
-// bytes; pass A with its tables up to 4096 values).  Those narrow tiles number the workgroups so
-// that the tiles sharing a row's cache lines run on one XCD, whose L2 then
-// serves the lines to all of them (workgroups are dealt to the 8 XCDs in
-// turn).
+// row read or write touches fall on different banks.  Tiles of 16, 32 or 64
+// columns read and write runs of 128 to 512 bytes; tiles of 2, 4 or 8 (runs
+// of 16 to 64 bytes) are the only ones that fit LDS for columns of 2048 to
+// 8192 values (pass A, with its tables, up to 4096), and are also valid for
+// shorter columns, where they give more workgroups.  Narrow tiles number the
+// workgroups so that the tiles sharing a row's cache lines run on one XCD,
+// whose L2 then serves the lines to all of them (workgroups are dealt to the
+// 8 XCDs in turn).
 //
 // The pass-A twiddles w_n^m (m < n <= 2^23) are the product of three table
 // entries, w_{2^23}^{q mod 2^10} * w_{2^13}^{(q div 2^10) mod 2^10} *
@@ -166,12 +167,10 @@ constexpr int64_t tile_lds(int log2len, int tc, bool pass_a) {
     return ((int64_t)tile_vals(log2len, tc) + (pass_a ? kTwLargeVals : 0)) * (int64_t)sizeof(float2);
 }
 // Tile shapes: radix 8 or 16; 64 to 1024 threads; the LDS budget (pass A
-// with its tables); tiles narrower than 16 columns only where wider ones do
-// not fit (columns of more than 1024 values).
+// with its tables).
 constexpr bool tile_ok(int radix, int log2len, int tc, bool pass_a) {
     return (radix == 8 || radix == 16) && log2len >= clog2(radix) && tc * ((1 << log2len) / radix) >= 64 &&
-           tc * ((1 << log2len) / radix) <= 1024 && tile_lds(log2len, tc, pass_a) <= kTileLdsMax &&
-           (tc >= 16 || log2len > 10);
+           tc * ((1 << log2len) / radix) <= 1024 && tile_lds(log2len, tc, pass_a) <= kTileLdsMax;
 }
 
 template <int R, int L, bool A, int TC>

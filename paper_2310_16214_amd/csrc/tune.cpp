@@ -950,7 +950,11 @@ using namespace ppx;
 
 // The analytical plan: the most even split (as the default plan), and for
 // each pass the (radix, tile) that the occupancy guideline picks among the
-// tile kernels valid for its column length.
+// tile kernels valid for its column length.  Premise (i), coalescing, comes
+// first: the candidates are the tiles whose row runs are whole cache lines
+// (16 columns or more) where any is valid, else the widest valid tile; left
+// to itself the occupancy guideline prefers the narrowest tiles (more
+// workgroups), whose 16-byte runs waste most of each line.
 static int analytical_plan(int64_t n, int64_t batch, ppx_fft_plan &out) {
     fft_default_plan(n, out);
     if (!out.log2_n1) return fail(PPX_ECONFIG, "no valid plan");
@@ -961,9 +965,14 @@ static int analytical_plan(int64_t n, int64_t batch, ppx_fft_plan &out) {
         const int64_t ncols = int64_t(1) << (ln - l);
         std::vector<ppx_config> c;
         std::vector<ppx_resource> r;
+        int widest = 0;
+        for (int radix : {8, 16})
+            for (int tile : {2, 4, 8, 16, 32, 64})
+                if (fft_tile_shape_valid(radix, l, tile, pass == 0) && ncols % tile == 0) widest = std::max(widest, tile);
+        const int min_tile = std::min(widest, 16);
         for (int radix : {8, 16})
             for (int tile : {2, 4, 8, 16, 32, 64}) {
-                if (!fft_tile_shape_valid(radix, l, tile, pass == 0) || ncols % tile) continue;
+                if (tile < min_tile || !fft_tile_shape_valid(radix, l, tile, pass == 0) || ncols % tile) continue;
                 const int threads = tile * ((1 << l) / radix);
                 hipFuncAttributes a;
                 if (hipFuncGetAttributes(&a, fft_tile_kernel(radix, l, tile, pass == 0)) != hipSuccess)

@@ -383,8 +383,11 @@ def default_fft_plan(n):
     return p
 
 
-def tune_fft_large(n, batch, method, max_evals=0, reps=100, trace_cap=256):
-    """Returns (plan, best_us, evals_used, [(plan, us) timed in order])."""
+def tune_fft_large(n, batch, method, max_evals=0, reps=100, trace_cap=None):
+    """Returns (plan, best_us, evals_used, [(plan, us) timed in order]); the
+    trace holds every timed plan unless trace_cap is smaller."""
+    if trace_cap is None:
+        trace_cap = max(1, len(enumerate_fft_plans(n)))
     best = FftPlan()
     us = ctypes.c_double(0.0)
     ev = ctypes.c_int(0)

@@ -79,7 +79,7 @@ def test_fft_plans():
                 threads = tile * (1 << length) // radix
                 lds = (-(-tile * ((1 << length) + 1) // 256) * 256 + extra) * 8
                 assert radix in (8, 16) and ncols % tile == 0
-                assert tile in ((16, 32, 64) if length <= 10 else (2, 4, 8))
+                assert tile in ((2, 4, 8, 16, 32, 64) if length <= 10 else (2, 4, 8))
                 assert 64 <= threads <= 1024 and lds <= 160 * 1024
         keys = [p.as_tuple() for p in plans]
         assert keys == sorted(keys) and len(set(keys)) == len(keys)
@@ -100,7 +100,8 @@ def test_fft_plans():
     assert not ppx.fft_plan_valid(1 << 21, ppx.make_plan(10, 16, 16, 16, 16))  # pass A column of 2048
     assert not ppx.fft_plan_valid(1 << 21, ppx.make_plan(11, 16, 16, 16, 16))  # 16 x 2049 values of LDS
     assert ppx.fft_plan_valid(1 << 21, ppx.make_plan(11, 16, 16, 16, 8))
-    assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 16, 16, 16, 8))   # narrow tile on short columns
+    assert ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 16, 16, 16, 8))       # narrow tiles at any length
+    assert not ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 16, 16, 16, 1))   # tile 1
     assert ppx.fft_plan_valid(1 << 16, ppx.make_plan(8, 16, 16, 64, 64))
     with pytest.raises(ppx.PpxError):
         ppx.enumerate_fft_plans(1 << 14)

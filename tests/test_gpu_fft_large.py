@@ -64,15 +64,22 @@ def test_every_plan_sampled_bins(cuda, ln):
     x = inputs.fft_input(n, batch, seed=ln + 40)
     ks = np.unique(np.concatenate([[0, 1, n // 2, n - 1], np.random.default_rng(ln).integers(0, n, 44)]))
     refs = {d: oracle.dft_bins(x, ks, inverse=d > 0) for d in (-1, +1)}  # [problem][bin]
+    import torch
+    xd = to_dev(x, cuda)
+    yd = torch.empty_like(xd)
+    kd = torch.from_numpy(ks).to(cuda)
+    energy = np.sum(np.abs(x.astype(np.complex128)) ** 2, axis=1) * n  # Parseval: sum |X|^2
     plans = ppx.enumerate_fft_plans(n)
     assert plans
     for p in plans:
         for direction in (-1, +1):
             banner(f"fft large n={n} {p} dir={direction}")
-            y = _run(x, n, batch, p, direction)
-            err = np.linalg.norm(y[:, ks] - refs[direction], axis=1) / np.linalg.norm(refs[direction], axis=1)
+            ppx.fft_batched_large(xd, yd, n, batch, direction, p)
+            y_ks = to_host(yd[:, kd])
+            err = np.linalg.norm(y_ks - refs[direction], axis=1) / np.linalg.norm(refs[direction], axis=1)
             assert err.max() <= fft_tol(n), (p, direction, err)
-            _parseval(x, y, n)
+            e_gpu = (yd.to(torch.complex128).abs() ** 2).sum(dim=1).cpu().numpy()
+            assert np.max(np.abs(e_gpu - energy) / energy) <= 2 * fft_tol(n), (p, direction)
     print(f"n={n}: {len(plans)} plans")
 
 
