@@ -58,6 +58,27 @@ def test_tridiag_family_filter(cuda):
     ppx.clear_tune_cache()
 
 
+@pytest.mark.parametrize("family", [ppx.TRI_WM, ppx.TRI_LF])
+def test_tridiag_wm_lf_families(cuda, family):
+    """Each tuner restricted to the Wang & Mou or Ladner-Fischer family
+    returns a configuration of that family, recorded under it."""
+    for method in (ppx.TUNE_EXHAUSTIVE, ppx.TUNE_ANALYTICAL, ppx.TUNE_LEARNED):
+        banner(f"tune_ex tridiag family={family} method={method}")
+        rep, trace = ppx.tune_ex(ppx.OP_TRIDIAG, ppx.F64, 256, 1 << 12, method, algo=family, reps=5)
+        assert ppx.tri_family(rep.best.algo) == family and rep.best_us > 0
+        assert all(ppx.tri_family(c.algo) == family for c, _ in trace)
+        assert ppx.tri_family(ppx.tuned_config(ppx.OP_TRIDIAG, ppx.F64, 256, family).algo) == family
+    ppx.clear_tune_cache()
+
+
+def test_scan_float64_tuning(cuda):
+    for method in (ppx.TUNE_EXHAUSTIVE, ppx.TUNE_ANALYTICAL, ppx.TUNE_LEARNED):
+        banner(f"tune_ex scan f64 method={method}")
+        rep, _ = ppx.tune_ex(ppx.OP_SCAN, ppx.F64, 2048, 1 << 10, method, reps=5)
+        assert ppx.config_valid(ppx.OP_SCAN, ppx.F64, 2048, rep.best) and rep.best.elems_per_thread <= 16
+    ppx.clear_tune_cache()
+
+
 def test_time_config_and_resources(cuda):
     cfg = ppx.default_config(ppx.OP_FFT, ppx.C64, 1024)
     us = ppx.time_config(ppx.OP_FFT, ppx.C64, 1024, 1 << 12, cfg, reps=5)
