@@ -274,7 +274,9 @@ int tune(int op, int dtype, int64_t n, int64_t batch, int method, int max_evals,
  * One job of a mixed launch: a whole batched call of any operation.
  *   op, dtype, n, batch   as in the single calls
  *   direction             FFT only: -1 forward, +1 inverse
- *   algo                  tridiagonal only: PPX_TRI_CR or PPX_TRI_PCR
+ *   algo                  tridiagonal: PPX_TRI_CR or PPX_TRI_PCR; scan:
+ *                         PPX_JOB_SCAN_INCLUSIVE or PPX_JOB_SCAN_EXCLUSIVE
+ *                         (dtype PPX_I32, PPX_F32 or PPX_F64)
  *   in                    FFT / scan input; tridiagonal: a
  *   b, c, d               tridiagonal only (NULL otherwise)
  *   out                   FFT / scan output; tridiagonal: x
@@ -282,6 +284,8 @@ int tune(int op, int dtype, int64_t n, int64_t batch, int method, int max_evals,
  * calls.  Tridiagonal systems must fit one fused tile's 128 KiB of LDS
  * (float32 CR: n <= 8192; PCR or float64: n <= 4096; float64 PCR: n <= 2048).
  */
+#define PPX_JOB_SCAN_INCLUSIVE 0
+#define PPX_JOB_SCAN_EXCLUSIVE 1
 typedef struct ppx_job {
     int32_t op;
     int32_t dtype;

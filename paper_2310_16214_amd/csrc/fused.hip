@@ -37,7 +37,7 @@ constexpr int kMaxTilesPerLaunch = 1 << 18;
 constexpr int kSlots = 4;
 
 struct FusedJob {  // 64 bytes
-    int op, dtype, log2n, flags;  // flags: FFT 1 = inverse; tridiag = algo
+    int op, dtype, log2n, flags;  // flags: FFT 1 = inverse; scan 1 = exclusive; tridiag = algo
     long long batch;
     const void *p[4];
     void *out;
@@ -60,22 +60,28 @@ __global__ void k_fused_reset(FusedHeader *hdr) {
 
 // A scan tile is processed in sub-blocks of kFusedThreads * P elements (P = 4
 // up to n = 4096, then n / 1024), each a whole number of problems.
-template <typename T, int P>
+template <typename T, int P, bool EXCL>
 __device__ __forceinline__ void scan_tile_p(const FusedJob &j, const FusedTile &t, T *wave_tot) {
     const T *in = static_cast<const T *>(j.p[0]);
     T *out = static_cast<T *>(j.out);
     const int per = (kFusedThreads * P) >> j.log2n;  // problems per sub-block (>= 1)
     for (int s = 0; s < t.count; s += per) {
-        scan_block<T, P, PPX_SCAN_KS>(in, out, j.log2n, t.first + s, min(per, t.count - s), wave_tot);
+        scan_block<T, P, PPX_SCAN_KS, EXCL>(in, out, j.log2n, t.first + s, min(per, t.count - s), wave_tot);
         __syncthreads();  // wave totals are reused by the next sub-block
     }
 }
 
+template <typename T, bool EXCL>
+__device__ __forceinline__ void scan_tile_x(const FusedJob &j, const FusedTile &t, T *wave_tot) {
+    if (j.log2n <= 12) scan_tile_p<T, 4, EXCL>(j, t, wave_tot);
+    else if (j.log2n == 13) scan_tile_p<T, 8, EXCL>(j, t, wave_tot);
+    else scan_tile_p<T, 16, EXCL>(j, t, wave_tot);
+}
+
 template <typename T>
 __device__ __forceinline__ void scan_tile(const FusedJob &j, const FusedTile &t, T *wave_tot) {
-    if (j.log2n <= 12) scan_tile_p<T, 4>(j, t, wave_tot);
-    else if (j.log2n == 13) scan_tile_p<T, 8>(j, t, wave_tot);
-    else scan_tile_p<T, 16>(j, t, wave_tot);
+    if (j.flags & 1) scan_tile_x<T, true>(j, t, wave_tot);
+    else scan_tile_x<T, false>(j, t, wave_tot);
 }
 
 __global__ __launch_bounds__(kFusedThreads) void k_fused(const FusedJob *__restrict__ jobs,
@@ -84,8 +90,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(const FusedJob *__restr
                                                          const float2 *__restrict__ tw) {
     extern __shared__ float4 lds[];
     __shared__ int s_tile;
-    __shared__ float wave_tot_f[kFusedThreads / kWave];
-    __shared__ int wave_tot_i[kFusedThreads / kWave];
+    __shared__ double wave_tot_d[kFusedThreads / kWave];  // float and int totals alias its start
+    float *wave_tot_f = reinterpret_cast<float *>(wave_tot_d);
+    int *wave_tot_i = reinterpret_cast<int *>(wave_tot_d);
     const int ntiles = hdr->ntiles;
     for (;;) {
         if (threadIdx.x == 0) s_tile = (int)atomicAdd(&hdr->next_tile, 1u);
@@ -100,7 +107,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused(const FusedJob *__restr
                                      j.log2n, t.first, t.count, (j.flags & 1) ? -1.0f : 1.0f, lds);
         } else if (j.op == PPX_OP_SCAN) {
             if (j.dtype == PPX_I32) scan_tile<int>(j, t, wave_tot_i);
-            else scan_tile<float>(j, t, wave_tot_f);
+            else if (j.dtype == PPX_F32) scan_tile<float>(j, t, wave_tot_f);
+            else scan_tile<double>(j, t, wave_tot_d);
         } else if (j.dtype == PPX_F32) {
             const float *const *p = reinterpret_cast<const float *const *>(j.p);
             if (j.flags == PPX_TRI_PCR)
@@ -218,7 +226,10 @@ int check_job(const ppx_job &j) {
                 return fail(PPX_EINVAL, "job: FFT needs dtype PPX_C64 and direction -1/+1");
             break;
         case PPX_OP_SCAN:
-            if (j.dtype != PPX_I32 && j.dtype != PPX_F32) return fail(PPX_EINVAL, "job: scan dtype");
+            if (j.dtype != PPX_I32 && j.dtype != PPX_F32 && j.dtype != PPX_F64)
+                return fail(PPX_EINVAL, "job: scan dtype");
+            if (j.algo != PPX_JOB_SCAN_INCLUSIVE && j.algo != PPX_JOB_SCAN_EXCLUSIVE)
+                return fail(PPX_EINVAL, "job: scan algo must be PPX_JOB_SCAN_INCLUSIVE or _EXCLUSIVE");
             break;
         case PPX_OP_TRIDIAG: {
             if (j.dtype != PPX_F32 && j.dtype != PPX_F64) return fail(PPX_EINVAL, "job: tridiagonal dtype");
@@ -268,7 +279,7 @@ int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEve
         f.op = j.op;
         f.dtype = j.dtype;
         f.log2n = ilog2(j.n);
-        f.flags = j.op == PPX_OP_FFT ? (j.direction == 1 ? 1 : 0) : j.op == PPX_OP_TRIDIAG ? j.algo : 0;
+        f.flags = j.op == PPX_OP_FFT ? (j.direction == 1 ? 1 : 0) : j.algo;  // scan: exclusive; tridiag: algo
         f.batch = j.batch;
         f.p[0] = j.in;
         f.p[1] = j.b;

@@ -132,6 +132,8 @@ hipEvent_t take_event(ppx_server *s) {
 }
 
 int launch_single(const ppx_job &j, hipStream_t st, const ppx_config *cfg) {
+    if (j.op == PPX_OP_SCAN && j.algo == PPX_JOB_SCAN_EXCLUSIVE)
+        return scan_exclusive_batched(j.in, j.out, j.n, j.batch, j.dtype, cfg, st);
     if (cfg) {
         switch (j.op) {
             case PPX_OP_FFT: return fft_batched(j.in, j.out, j.n, j.batch, j.direction, cfg, st);

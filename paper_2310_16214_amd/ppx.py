@@ -565,6 +565,7 @@ def mixed_tile_problems(op, dtype, n, algo=0):
 # (declared in include/ppx_serve.h)
 
 SERVE_FUSED, SERVE_PER_REQUEST, SERVE_NULL_DEVICE, SERVE_ONLINE_TUNE = 0, 1, 2, 4
+JOB_SCAN_INCLUSIVE, JOB_SCAN_EXCLUSIVE = 0, 1  # the algo field of a scan job
 
 
 class Completion(ctypes.Structure):

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_2310_16214_amd import inputs, ppx
-from tests.gpu_util import banner, fft_tol, scan_f32_bound, to_dev, to_host
+from tests.gpu_util import banner, fft_tol, scan_bound, scan_f32_bound, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -15,7 +15,9 @@ pytestmark = pytest.mark.gpu
 MIX = [("fft", 16, 1000, -1), ("fft", 1024, 37, -1), ("fft", 16384, 3, 1), ("fft", 128, 129, 1),
        ("scan_i32", 32, 700, 0), ("scan_f32", 4096, 9, 0), ("scan_i32", 8192, 5, 0),
        ("scan_f32", 16384, 3, 0), ("tri_f32", 64, 300, ppx.TRI_CR), ("tri_f32", 1024, 7, ppx.TRI_PCR),
-       ("tri_f64", 256, 33, ppx.TRI_CR), ("tri_f32", 8192, 2, ppx.TRI_CR), ("fft", 2048, 1, -1)]
+       ("tri_f64", 256, 33, ppx.TRI_CR), ("tri_f32", 8192, 2, ppx.TRI_CR), ("fft", 2048, 1, -1),
+       ("scan_excl_i32", 256, 300, 1), ("scan_f64", 1024, 40, 0), ("scan_excl_f64", 16384, 3, 1),
+       ("scan_excl_f32", 2048, 20, 1)]
 
 
 def _build(cuda, seed=0):
@@ -30,12 +32,14 @@ def _build(cuda, seed=0):
             jobs.append(ppx.make_job(ppx.OP_FFT, ppx.C64, n, batch, xd, y, direction=extra))
             checks.append((kind, n, batch, (x, extra), (xd,), y))
         elif kind.startswith("scan"):
-            dt = np.int32 if kind.endswith("i32") else np.float32
-            x = inputs.scan_input(n, batch, dt, seed=s)
+            code = {"i32": ppx.I32, "f32": ppx.F32, "f64": ppx.F64}[kind[-3:]]
+            if code == ppx.F64:  # dyadic values: every partial sum exact
+                _, x = inputs.scan_input_dyadic(n, batch, seed=s)
+            else:
+                x = inputs.scan_input(n, batch, np.int32 if code == ppx.I32 else np.float32, seed=s)
             xd = to_dev(x, cuda)
             y = torch.empty_like(xd)
-            jobs.append(ppx.make_job(ppx.OP_SCAN, ppx.I32 if dt == np.int32 else ppx.F32, n, batch,
-                                     xd, y))
+            jobs.append(ppx.make_job(ppx.OP_SCAN, code, n, batch, xd, y, algo=extra))
             checks.append((kind, n, batch, (x,), (xd,), y))
         else:
             dt = np.float32 if kind.endswith("f32") else np.float64
@@ -53,11 +57,14 @@ def _check_oracle(kind, n, host, out):
         x, direction = host
         err = oracle.rel_l2(out, oracle.dft(x, inverse=direction == 1)).max()
         assert err <= fft_tol(n), (kind, n, err)
-    elif kind == "scan_i32":
-        assert np.array_equal(out, oracle.scan(host[0]))
-    elif kind == "scan_f32":
-        x = host[0]
-        assert np.all(np.abs(out.astype(np.float64) - oracle.scan(x)) <= scan_f32_bound(x))
+    elif kind.startswith("scan"):
+        x, excl = host[0], "excl" in kind
+        ref = oracle.scan(x, exclusive=excl)
+        if kind.endswith("f32"):
+            bound = scan_bound(x, 2.0 ** -24, exclusive=True) if excl else scan_f32_bound(x)
+            assert np.all(np.abs(out.astype(np.float64) - ref) <= bound), kind
+        else:  # int32, and float64 on dyadic values: exact
+            assert np.array_equal(out, ref), kind
     else:
         tol = 1e-4 if kind.endswith("f32") else 1e-12
         assert oracle.tridiag_residual(*host, out).max() <= tol
@@ -123,3 +130,5 @@ def test_mixed_rejects_bad_jobs(cuda):
         ppx.launch_mixed([bad])
     with pytest.raises(ppx.PpxError):
         ppx.launch_mixed([ppx.make_job(ppx.OP_FFT, ppx.C64, 100, 1, x, x)])
+    with pytest.raises(ppx.PpxError):  # scan form must be inclusive or exclusive
+        ppx.launch_mixed([ppx.make_job(ppx.OP_SCAN, ppx.F64, 64, 1, x, x, algo=2)])

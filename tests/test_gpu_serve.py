@@ -131,3 +131,27 @@ def test_online_tuning_serves_correct_results(cuda):
         else:
             coeffs = [v[off:off + n * batch].cpu().numpy().reshape(batch, n) for v in pools.tri]
             assert oracle.tridiag_residual(*coeffs, y).max() <= 1e-4
+
+
+@pytest.mark.parametrize("mode", [ppx.SERVE_FUSED, ppx.SERVE_PER_REQUEST])
+def test_served_exclusive_and_float64_scans(cuda, mode):
+    """Scan jobs of both forms in int32 and float64 (dyadic values, exact)
+    through either mode of the request loop, against the oracle exactly."""
+    from paper_2310_16214_amd import inputs
+    jobs, hosts = [], []
+    for k, (dt, form, n, batch) in enumerate([(ppx.I32, 1, 512, 40), (ppx.F64, 1, 4096, 9),
+                                               (ppx.F64, 0, 64, 500), (ppx.I32, 0, 16384, 2)]):
+        if dt == ppx.F64:
+            _, x = inputs.scan_input_dyadic(n, batch, seed=70 + k)
+        else:
+            x = inputs.scan_input(n, batch, np.int32, seed=70 + k)
+        xd = to_dev(x, cuda)
+        jobs.append((ppx.make_job(ppx.OP_SCAN, dt, n, batch, xd, None, algo=form), xd))
+        hosts.append((x, form))
+    banner(f"serve scans mode={mode}")
+    srv = ppx.Server(1 << 28, max_inflight=2, flags=mode)
+    comps = srv.replay([(j, 0.0) for j, _ in jobs], auto_release=False)
+    for c, (x, form) in zip(comps, hosts):
+        y = srv.read(c.id, np.empty_like(x))
+        assert np.array_equal(y, oracle.scan(x, exclusive=form == 1)), (x.dtype, form)
+    srv.close()

@@ -101,3 +101,15 @@ def test_replay_records_latencies_in_request_order():
     arr = [c.arrival_us for c in comps]
     assert arr == sorted(arr)
     assert s.stats()["released"] == 20 and s.stats()["used_bytes"] == 0
+
+
+def test_scan_job_forms_are_validated():
+    s = ppx.Server(1 << 24, flags=ppx.SERVE_NULL_DEVICE)
+    for dt in (ppx.I32, ppx.F32, ppx.F64):
+        for form in (ppx.JOB_SCAN_INCLUSIVE, ppx.JOB_SCAN_EXCLUSIVE):
+            s.submit(ppx.make_job(ppx.OP_SCAN, dt, 256, 4, ADDR, None, algo=form))
+    with pytest.raises(ppx.PpxError):
+        s.submit(ppx.make_job(ppx.OP_SCAN, ppx.F32, 256, 4, ADDR, None, algo=2))
+    with pytest.raises(ppx.PpxError):
+        s.submit(ppx.make_job(ppx.OP_SCAN, ppx.C64, 256, 4, ADDR, None))
+    s.close()
