@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_2310_16214_amd import ppx
 from paper_2310_16214_amd.serve_bench import Pools, make_trace
-from tests.gpu_util import banner, fft_tol, scan_f32_bound
+from tests.gpu_util import banner, fft_tol, scan_f32_bound, to_dev
 
 pytestmark = pytest.mark.gpu
 
