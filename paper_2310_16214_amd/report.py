@@ -18,14 +18,25 @@ def cfg_str(c):
            + (f" a{c['algo']}" if c['algo'] else "")
 
 
+def paper_unit(r):
+    """The paper's own figure for the record: GFlop/s for the FFT (5 N log2 N
+    flops per problem), MData/s for the scan and MRows/s for the tridiagonal
+    solvers (N * batch * 1e-6 / t)."""
+    import math
+    elems_per_us = r["n"] * r["batch"] / r["exhaustive"]["us"]
+    if r["op"] == "fft":
+        return f"{5 * math.log2(r['n']) * elems_per_us / 1e3:.0f} GFlop/s"
+    return f"{elems_per_us:.0f} {'MData/s' if r['op'] == 'scan' else 'MRows/s'}"
+
+
 def tuning(path):
     d = json.load(open(path))
-    out = ["| op | N | exhaustive best | us | GElem/s | analytical (e) | learned (e, evals/space) | default us | tuned/default | batched/plain |",
-           "|---|---|---|---|---|---|---|---|---|---|"]
+    out = ["| op | N | exhaustive best | us | GElem/s | paper unit | analytical (e) | learned (e, evals/space) | default us | tuned/default | batched/plain |",
+           "|---|---|---|---|---|---|---|---|---|---|---|"]
     for r in d["records"]:
         name = r["op"] + " " + DT[r["dtype"]] + ALGO[r["algo"]]
         out.append(f"| {name} | {r['n']} | {cfg_str(r['exhaustive']['cfg'])} | {r['exhaustive']['us']:.1f} | "
-                   f"{r['gelem_s']:.0f} | {cfg_str(r['analytical']['cfg'])} ({r['e_analytical']:.2f}) | "
+                   f"{r['gelem_s']:.0f} | {paper_unit(r)} | {cfg_str(r['analytical']['cfg'])} ({r['e_analytical']:.2f}) | "
                    f"{cfg_str(r['learned']['cfg'])} ({r['e_learned']:.2f}, {r['learned']['evals']}/{r['exhaustive']['space']}) | "
                    f"{r['default']['us']:.1f} | {r['tuned_vs_default']:.2f} | {r.get('batched_vs_plain', float('nan')):.0f} |")
     forms = [r for r in d["records"] if "forms_us" in r]
