@@ -184,6 +184,28 @@ def test_persistent_variants_loop_and_tail(cuda, n, radix, L, G, algo):
         assert d.max() <= fft_tol(n)
 
 
+@pytest.mark.parametrize("batch", [1, 7, 300, 1500, 2600, 4100, 6001])
+def test_persistent_radix8_every_exit(cuda, batch):
+    """Batches that end after one, two, three or more iterations per
+    workgroup of the persistent kernel (every early exit of its peeled and
+    unrolled loop), each problem against the plain kernel and a few against
+    the oracle."""
+    import torch
+    n = 4096
+    cfg = ppx.make_config(8, 512, 1, ppx.FFT_LDS_PIPE)
+    plain = ppx.make_config(8, 512, 1, 0)
+    x = inputs.fft_input(n, batch, seed=batch)
+    xd = to_dev(x, cuda)
+    banner(f"fft persistent radix 8 n={n} batch={batch}")
+    y, y2 = torch.empty_like(xd), torch.empty_like(xd)
+    ppx.fft_batched(xd, y, n, batch, -1, cfg)
+    ppx.fft_batched(xd, y2, n, batch, -1, plain)
+    assert oracle.rel_l2(to_host(y), to_host(y2)).max() <= fft_tol(n)
+    idx = np.unique(np.array([0, batch // 2, batch - 1]))
+    ys = to_host(y[torch.from_numpy(idx).to(cuda)])
+    assert oracle.rel_l2(ys, oracle.dft(x[idx])).max() <= fft_tol(n)
+
+
 def test_persistent_needs_radix_equal_p(cuda):
     import torch
     x = torch.zeros(1024, dtype=torch.complex64, device=cuda)
