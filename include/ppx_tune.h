@@ -216,15 +216,22 @@ int ppx_stream_reference(const void *const *in, int k, void *out, int64_t bytes,
 
 /*
  * Tune cache: tuned configurations keyed by (op, dtype, n, algo filter) for
- * the running device architecture.  Text file, one entry per line:
+ * the running device architecture, and tuned large-FFT plans keyed by n.
+ * Text file, one entry per line:
  *   arch op dtype n algo radix P L G_b S algo_cfg us method
- * load merges the file into memory; save writes every entry.
+ *   arch plan n log2_n1 radix_a radix_b tile_a tile_b us method
+ * load merges the file into memory (returns the number of entries taken;
+ * entries no longer valid are skipped); save writes every entry; clear
+ * empties both kinds.
  */
 int ppx_tune_cache_load(const char *path);
 int ppx_tune_cache_save(const char *path);
 int ppx_tune_cache_clear(void);
 /* Cached entry for (op, dtype, n, algo filter); PPX_EINVAL if none. */
 int ppx_tuned_config(int op, int dtype, int64_t n, int algo, ppx_config *out);
+/* Tuned large-FFT plan for n (fft_batched_large's plan == NULL uses it);
+ * PPX_EINVAL if none. */
+int ppx_tuned_fft_plan(int64_t n, ppx_fft_plan *out);
 
 #ifdef __cplusplus
 }

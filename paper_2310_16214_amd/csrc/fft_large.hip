@@ -316,6 +316,16 @@ void fft_record_plan(int64_t n, const ppx_fft_plan &p) {
     g_plans[n] = p;
 }
 
+std::vector<std::pair<int64_t, ppx_fft_plan>> fft_recorded_plans() {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    return std::vector<std::pair<int64_t, ppx_fft_plan>>(g_plans.begin(), g_plans.end());
+}
+
+void fft_clear_plans() {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plans.clear();
+}
+
 int launch_fft_large(const void *in, void *out, int log2n, int64_t batch, const ppx_fft_plan &p, bool inverse,
                      hipStream_t s) {
     const DeviceInfo *di = device_info();

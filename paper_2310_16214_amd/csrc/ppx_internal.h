@@ -127,6 +127,8 @@ int64_t fft_tile_lds_bytes(int log2len, int tile, bool pass_a);
 int launch_fft_large(const void *in, void *out, int log2n, int64_t batch, const ppx_fft_plan &p, bool inverse,
                      hipStream_t s);
 int fft_plan_check(int64_t n, const ppx_fft_plan &p);  // PPX_OK or a failure with reason
+std::vector<std::pair<int64_t, ppx_fft_plan>> fft_recorded_plans();  // tuned plans by n
+void fft_clear_plans();
 void fft_default_plan(int64_t n, ppx_fft_plan &p);
 std::vector<ppx_fft_plan> fft_enumerate_plans(int64_t n);
 bool fft_tuned_plan(int64_t n, ppx_fft_plan &p);

@@ -1184,6 +1184,20 @@ int ppx_tune_cache_load(const char *path) {
         if (line.empty() || line[0] == '#') continue;
         std::istringstream is(line);
         std::string arch;
+        if (line.compare(0, 12, "gfx950 plan ") == 0) {  // a tuned large-FFT plan
+            std::string tag;
+            int64_t n;
+            ppx_fft_plan p{};
+            double us;
+            int method;
+            if (!(is >> arch >> tag >> n >> p.log2_n1 >> p.radix_a >> p.radix_b >> p.tile_a >> p.tile_b >> us >>
+                  method))
+                return fail(PPX_EINVAL, "malformed tune cache line: " + line);
+            if (fft_plan_check(n, p) != PPX_OK) continue;  // stale entry
+            fft_record_plan(n, p);
+            ++count;
+            continue;
+        }
         int op, dtype, algo, method;
         int64_t n;
         ppx_config c{};
@@ -1215,12 +1229,27 @@ int ppx_tune_cache_save(const char *path) {
           << c.elems_per_thread << ' ' << c.threads_per_block << ' ' << c.problems_per_block << ' '
           << c.lds_elems << ' ' << c.algo << ' ' << kv.second.us << ' ' << kv.second.method << '\n';
     }
+    f << "# arch plan n log2_n1 radix_a radix_b tile_a tile_b us method (tuned large-FFT plans)\n";
+    for (const auto &np : fft_recorded_plans()) {
+        const ppx_fft_plan &p = np.second;
+        f << "gfx950 plan " << np.first << ' ' << p.log2_n1 << ' ' << p.radix_a << ' ' << p.radix_b << ' '
+          << p.tile_a << ' ' << p.tile_b << " 0 -1\n";
+    }
     return f ? PPX_OK : fail(PPX_EINVAL, "write failed");
 }
 
 int ppx_tune_cache_clear(void) {
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    g_cache.clear();
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_cache.clear();
+    }
+    fft_clear_plans();
+    return PPX_OK;
+}
+
+int ppx_tuned_fft_plan(int64_t n, ppx_fft_plan *out) {
+    if (!out) return fail(PPX_EINVAL, "null output");
+    if (!fft_tuned_plan(n, *out)) return fail(PPX_EINVAL, "no tuned plan for this n");
     return PPX_OK;
 }
 

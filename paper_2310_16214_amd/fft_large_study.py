@@ -81,9 +81,16 @@ def main():
     ap.add_argument("--sizes", default="15,16,17,18,19,20,21,22,23")
     ap.add_argument("--report", nargs="+", default=None, metavar=("STUDY_JSON", "KERNEL_STATS_CSV"),
                     help="print the markdown summary of a study (no GPU)")
+    ap.add_argument("--plans", default="", metavar="STUDY_JSON",
+                    help="print the exhaustive-best plans of a study as tune-cache lines")
     ap.add_argument("--replay", default="",
                     help="a study JSON: only run each size's exhaustive-best plan 10 times (for a kernel trace)")
     args = ap.parse_args()
+    if args.plans:
+        for r in json.load(open(args.plans))["records"]:
+            p = r["exhaustive"]["plan"]
+            print(f"gfx950 plan {r['n']} {p[0]} {p[1]} {p[2]} {p[3]} {p[4]} {r['exhaustive']['us']:.3f} 0")
+        return
     if args.report:
         report(*args.report)
         return

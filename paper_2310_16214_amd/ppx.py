@@ -507,6 +507,14 @@ def clear_tune_cache():
     _tl("ppx_tune_cache_clear")()
 
 
+def tuned_fft_plan(n):
+    """The tuned large-FFT plan recorded for n, or None."""
+    p = FftPlan()
+    f = lib().ppx_tuned_fft_plan
+    f.argtypes, f.restype = [ctypes.c_int64, ctypes.POINTER(FftPlan)], ctypes.c_int
+    return p if f(n, ctypes.byref(p)) == OK else None
+
+
 def tuned_config(op, dtype, n, algo=-1):
     c = Config()
     if _tl("ppx_tuned_config")(op, dtype, n, algo, ctypes.byref(c)) != OK:

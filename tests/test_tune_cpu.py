@@ -245,6 +245,25 @@ def test_tune_cache_round_trip(tmp_path):
     ppx.clear_tune_cache()
 
 
+def test_tune_cache_keeps_large_fft_plans(tmp_path):
+    ppx.clear_tune_cache()
+    p = tmp_path / "plans.txt"
+    p.write_text("gfx950 plan 1048576 8 16 8 4 16 304.3 0\n"
+                 "gfx950 plan 8388608 11 16 16 4 8 373.5 0\n"
+                 "gfx950 plan 65536 8 4 16 16 16 1.0 0\n"       # radix 4: not a valid plan, skipped
+                 "gfx950 plan 16384 7 16 16 16 16 1.0 0\n")     # not a large size: skipped
+    assert ppx.load_tune_cache(str(p)) == 2
+    assert ppx.tuned_fft_plan(1 << 20).as_tuple() == (8, 16, 8, 4, 16)
+    assert ppx.tuned_fft_plan(1 << 16) is None
+    q = tmp_path / "saved.txt"
+    ppx.save_tune_cache(str(q))
+    ppx.clear_tune_cache()
+    assert ppx.tuned_fft_plan(1 << 20) is None
+    assert ppx.load_tune_cache(str(q)) == 2
+    assert ppx.tuned_fft_plan(1 << 23).as_tuple() == (11, 16, 16, 4, 8)
+    ppx.clear_tune_cache()
+
+
 # ---------------------------------------------------------------- online BO
 
 def _cost(c):
