@@ -24,7 +24,8 @@
 // shorter columns, where they give more workgroups.  Narrow tiles number the
 // workgroups so that the tiles sharing a row's cache lines run on one XCD,
 // whose L2 then serves the lines to all of them (workgroups are dealt to the
-// 8 XCDs in turn).
+// 8 XCDs in turn).  Pass-A tiles that leave room for one workgroup per CU
+// run persistent, loading the next tile while transforming the current one.
 //
 // The pass-A twiddles w_n^m (m < n <= 2^23) are the product of three table
 // entries, w_{2^23}^{q mod 2^10} * w_{2^13}^{(q div 2^10) mod 2^10} *
@@ -32,6 +33,7 @@
 // host in double precision, copied into LDS by every pass-A workgroup.
 #include "fft_device.h"
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -54,17 +56,131 @@ constexpr int kLog2NLargeMax = 23;
 // blocks (the swizzle permutes within aligned blocks of 256)
 __host__ __device__ constexpr int tile_vals(int log2len, int tc) { return (tc * ((1 << log2len) + 1) + 255) / 256 * 256; }
 
-// TC: columns per tile (2 to 64: runs of 16 to 512 bytes)
-template <int R, int LOG2LEN, bool PASS_A, int TC>
-__global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out, const float2 *__restrict__ tw,
-                                                    const float2 *__restrict__ tw_lo,
-                                                    const float2 *__restrict__ tw_hi, int log2n,
-                                                    int log2cols, long long tiles, float sgn) {
-    constexpr int len = 1 << LOG2LEN;  // column length: the sub-transform size
+// Pass-A workgroups whose tile and tables take more than half of the LDS run
+// one per CU; such tile shapes are launched persistent (k_fft_tile_p).  Pass
+// B keeps one workgroup per tile: its persistent form (radix 16 only, at
+// these sizes) needs more than the 128 registers of a 1024-thread workgroup
+// and spilled, and measured slower at n = 2^23.
+__host__ __device__ constexpr bool tile_persistent(int log2len, int tc, bool pass_a) {
+    return pass_a && ((int64_t)tile_vals(log2len, tc) + kTwLargeVals) * (int64_t)sizeof(float2) > 80 * 1024;
+}
+
+// Pass A: the three twiddle tables into LDS after the tile.  Read from global
+// memory in the store loop, each table read would wait for the stores issued
+// before it (vector memory operations complete in issue order).  The lanes
+// of the store loop read the low table at a stride of (column index) * 2^23 /
+// n entries, often a multiple of 32; the two large tables are stored
+// XOR-swizzled (bits 5..9 into 0..4) so that such strides spread over the
+// banks.
+__device__ __forceinline__ void tile_tables_to_lds(float2 *tlo, float2 *thi, float2 *tht, const float2 *__restrict__ tw_lo,
+                                                   const float2 *__restrict__ tw_hi) {
+    for (int j = threadIdx.x; j < 1024; j += blockDim.x) {
+        tlo[tw_swz(j)] = tw_lo[j];
+        thi[tw_swz(j)] = tw_hi[j];
+    }
+    if (threadIdx.x < 8) tht[threadIdx.x] = tw_hi[1024 + threadIdx.x];
+}
+
+// The tile in LDS (written by the caller, no barrier yet): transform its TC
+// columns and write them out.  NT = len * TC / R threads; tx is the thread's
+// index in the workgroup.  PERSIST (pass A only) stores through a descriptor
+// of the problem's output, with the column step in the scalar operand.
+template <int R, int LOG2LEN, bool PASS_A, int TC, bool PERSIST>
+__device__ __forceinline__ void tile_transform_store(float2 *buf, const float2 *tlo, const float2 *thi, const float2 *tht,
+                                                     float2 *out, long long base, int c0, long long cols, int log2n,
+                                                     float sgn, const float2 *__restrict__ tw, int tx) {
+    constexpr int len = 1 << LOG2LEN;
     constexpr int P = R;
     constexpr int lT = LOG2LEN - clog2(P);
     constexpr int T = 1 << lT;
     constexpr int LTC = clog2(TC);
+    constexpr int NT = len * TC / R;
+    // the problem's n values of the output (offsets below 2^26 bytes)
+    const __amdgpu_buffer_rsrc_t orsrc = __builtin_amdgcn_make_buffer_rsrc(
+        out + base, (short)0, (int)((1LL << log2n) * (long long)sizeof(float2)), kBufferFlags);
+    __syncthreads();
+    const int lp = tx >> lT;  // column of the tile
+    const int tid = tx & (T - 1);
+    float2 v[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) v[j] = buf[tile_slot(lp, tid + j * T, len)];
+    __syncthreads();
+    if constexpr (PASS_A) fft_conj<P>(v, sgn);  // the inverse: conjugated in pass A, out in pass B
+    fft_stages_ct<R, P, false, LOG2LEN, 0, true>(v, buf, lp * (len + 1), nullptr, tid, true, sgn, tw);
+    __syncthreads();
+    if constexpr (PASS_A) {
+        // Element (c, e) of the tile is stored at row c0 + c, position e, of
+        // the intermediate, times w^{(c0 + c) e}; consecutive threads take
+        // consecutive e (runs of 512 bytes per wave).  With TC >= R thread t
+        // takes e = t mod len and the R columns ct + k * CS (ct = t div len,
+        // CS = TC / R): its twiddles form a geometric sequence with ratio
+        // w^{CS e}.  With TC < R it takes the R / TC rows e = t + r * NT and
+        // all TC columns of each: one sequence of ratio w^e per row.
+        // Sequences are started and stepped from the tables (at most R - 1
+        // products, so a few ulp of drift at most).
+        const int shift = kLog2NLargeMax - log2n;
+        auto table_tw = [&](unsigned m) {  // w_n^m for m < n
+            const unsigned q = m << shift;  // < 2^23
+            return cmul(cmul(tlo[tw_swz((int)(q & 1023u))], thi[tw_swz((int)((q >> 10) & 1023u))]), tht[q >> 20]);
+        };
+        if constexpr (TC >= R) {
+            constexpr int CS = TC / R;
+            const int e = tx & (len - 1), ct = tx >> LOG2LEN;
+            float2 w = table_tw((unsigned)(c0 + ct) * (unsigned)e);
+            const float2 step = table_tw((unsigned)CS * (unsigned)e);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int c = ct + k * CS;
+                const float2 y = cmul(buf[tile_slot(c, e, len)], w);
+                if constexpr (PERSIST)  // one vector offset, the column step in the scalar operand
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, y), orsrc,
+                                                          ((c0 + ct) * len + e) * (int)sizeof(float2),
+                                                          k * CS * len * (int)sizeof(float2), kStoreNT);
+                else
+                    store_nt_any(out + base + (long long)(c0 + c) * len + e, y);
+                w = cmul(w, step);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R / TC; ++r) {
+                const int e = tx + r * NT;
+                float2 w = table_tw((unsigned)c0 * (unsigned)e);
+                const float2 step = table_tw((unsigned)e);
+#pragma unroll
+                for (int c = 0; c < TC; ++c) {
+                    const float2 y = cmul(buf[tile_slot(c, e, len)], w);
+                    if constexpr (PERSIST)
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, y), orsrc,
+                                                              (c0 * len + tx) * (int)sizeof(float2),
+                                                              (c * len + r * NT) * (int)sizeof(float2), kStoreNT);
+                    else
+                        store_nt_any(out + base + (long long)(c0 + c) * len + e, y);
+                    w = cmul(w, step);
+                }
+            }
+        }
+    } else {
+        for (int i = tx; i < len * TC; i += NT) {
+            const int c = i & (TC - 1), e = i >> LTC;
+            const float2 y = buf[tile_slot(c, e, len)];
+            if constexpr (TC * (int)sizeof(float2) >= kTileNtRun)
+                store_nt_any(out + base + e * cols + c0 + c, make_float2(y.x, sgn * y.y));
+            else
+                out[base + e * cols + c0 + c] = make_float2(y.x, sgn * y.y);
+        }
+    }
+}
+
+// TC: columns per tile (2 to 64: runs of 16 to 512 bytes).  One workgroup
+// per tile; `total` (the tiles of the batch) is unused.
+template <int R, int LOG2LEN, bool PASS_A, int TC>
+__global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out, const float2 *__restrict__ tw,
+                                                    const float2 *__restrict__ tw_lo,
+                                                    const float2 *__restrict__ tw_hi, int log2n,
+                                                    int log2cols, long long tiles, long long, float sgn) {
+    constexpr int len = 1 << LOG2LEN;  // column length: the sub-transform size
+    constexpr int LTC = clog2(TC);
+    constexpr int NT = len * TC / R;
     extern __shared__ float4 lds_raw[];
     float2 *buf = reinterpret_cast<float2 *>(lds_raw);
     long long blk = blockIdx.x;
@@ -76,90 +192,102 @@ __global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out
     const int c0 = (int)(blk % tiles) * TC;
     const long long base = prob << log2n;
     const long long cols = 1LL << log2cols;
-    // pass A: the twiddle tables in LDS after the tile.  Read from global
-    // memory in the store loop, each table read would wait for the stores
-    // issued before it (vector memory operations complete in issue order).
-    // The lanes of the store loop read the low table at a stride of (column
-    // index) * 2^23 / n entries, often a multiple of 32; the two large
-    // tables are stored XOR-swizzled (bits 5..9 into 0..4) so that such
-    // strides spread over the banks.
     float2 *tlo = buf + tile_vals(LOG2LEN, TC), *thi = tlo + 1024, *tht = thi + 1024;
-    if constexpr (PASS_A) {
-        for (int j = threadIdx.x; j < 1024; j += blockDim.x) {
-            tlo[tw_swz(j)] = tw_lo[j];
-            thi[tw_swz(j)] = tw_hi[j];
-        }
-        if (threadIdx.x < 8) tht[threadIdx.x] = tw_hi[1024 + threadIdx.x];
-    }
-    for (int i = threadIdx.x; i < len * TC; i += blockDim.x) {
+    if constexpr (PASS_A) tile_tables_to_lds(tlo, thi, tht, tw_lo, tw_hi);
+    for (int i = threadIdx.x; i < len * TC; i += NT) {
         const int c = i & (TC - 1), e = i >> LTC;
         buf[tile_slot(c, e, len)] = in[base + e * cols + c0 + c];
     }
-    __syncthreads();
-    const int lp = threadIdx.x >> lT;  // column of the tile
-    const int tid = threadIdx.x & (T - 1);
-    float2 v[P];
+    tile_transform_store<R, LOG2LEN, PASS_A, TC, false>(buf, tlo, thi, tht, out, base, c0, cols, log2n, sgn, tw,
+                                                        (int)threadIdx.x);
+}
+
+// Buffer descriptor of tile t's rows (the problem from column c0 on); no
+// records (loads return zero, no memory access) for t >= total.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const float2 *in, long long t, long long total,
+                                                            long long tiles, int tc, int log2n) {
+    const bool ok = t < total;
+    const long long prob = ok ? t / tiles : 0;
+    const int c0 = ok ? (int)(t % tiles) * tc : 0;
+    const char *p = reinterpret_cast<const char *>(in + (prob << log2n) + c0);
+    const int bytes = ok ? (int)(((1LL << log2n) - c0) * (long long)sizeof(float2)) : 0;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, bytes, kBufferFlags);
+}
+
+// The thread's R values of a tile's rows: element i = tx + k * NT, column
+// i mod TC (= tx mod TC), row i div TC (= tx div TC + k * len / R).  Byte
+// offsets stay below 2^26 (n <= 2^23 values).
+template <int R, int LOG2LEN, int TC>
+__device__ __forceinline__ void tile_load_rows(float2 (&pre)[R], __amdgpu_buffer_rsrc_t r, int cols, int tx) {
+    constexpr int LTC = clog2(TC);
+    const int voff = ((tx >> LTC) * cols + (tx & (TC - 1))) * (int)sizeof(float2);
+    const int rstride = ((1 << LOG2LEN) / R) * cols * (int)sizeof(float2);
 #pragma unroll
-    for (int j = 0; j < P; ++j) v[j] = buf[tile_slot(lp, tid + j * T, len)];
-    __syncthreads();
-    if constexpr (PASS_A) fft_conj<P>(v, sgn);  // the inverse: conjugated in pass A, out in pass B
-    fft_stages_ct<R, P, false, LOG2LEN, 0, true>(v, buf, lp * (len + 1), nullptr, tid, true, sgn, tw);
-    __syncthreads();
-    if constexpr (PASS_A) {
-        // Element (c, e) of the tile is stored at row c0 + c, position e, of
-        // the intermediate, times w^{(c0 + c) e}; consecutive threads take
-        // consecutive e (runs of 512 bytes per wave).  The workgroup has
-        // len * TC / R threads.  With TC >= R thread t takes e = t mod len
-        // and the R columns ct + k * CS (ct = t div len, CS = TC / R): its
-        // twiddles form a geometric sequence with ratio w^{CS e}.  With
-        // TC < R it takes the R / TC rows e = t + r * len * TC / R and all TC
-        // columns of each: one sequence of ratio w^e per row.  Sequences are
-        // started and stepped from the tables (at most R - 1 products, so a
-        // few ulp of drift at most).
-        const int shift = kLog2NLargeMax - log2n;
-        auto table_tw = [&](unsigned m) {  // w_n^m for m < n
-            const unsigned q = m << shift;  // < 2^23
-            return cmul(cmul(tlo[tw_swz((int)(q & 1023u))], thi[tw_swz((int)((q >> 10) & 1023u))]), tht[q >> 20]);
-        };
-        if constexpr (TC >= R) {
-            constexpr int CS = TC / R;
-            const int e = threadIdx.x & (len - 1), ct = threadIdx.x >> LOG2LEN;
-            float2 w = table_tw((unsigned)(c0 + ct) * (unsigned)e);
-            const float2 step = table_tw((unsigned)CS * (unsigned)e);
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const int c = ct + k * CS;
-                store_nt_any(out + base + (long long)(c0 + c) * len + e, cmul(buf[tile_slot(c, e, len)], w));
-                w = cmul(w, step);
-            }
-        } else {
-            constexpr int NT = len * TC / R;  // threads of the workgroup
-#pragma unroll
-            for (int r = 0; r < R / TC; ++r) {
-                const int e = (int)threadIdx.x + r * NT;
-                float2 w = table_tw((unsigned)c0 * (unsigned)e);
-                const float2 step = table_tw((unsigned)e);
-#pragma unroll
-                for (int c = 0; c < TC; ++c) {
-                    store_nt_any(out + base + (long long)(c0 + c) * len + e, cmul(buf[tile_slot(c, e, len)], w));
-                    w = cmul(w, step);
-                }
-            }
-        }
-    } else {
-        for (int i = threadIdx.x; i < len * TC; i += blockDim.x) {
-            const int c = i & (TC - 1), e = i >> LTC;
-            const float2 y = buf[tile_slot(c, e, len)];
-            if constexpr (TC * (int)sizeof(float2) >= kTileNtRun)
-                store_nt_any(out + base + e * cols + c0 + c, make_float2(y.x, sgn * y.y));
-            else
-                out[base + e * cols + c0 + c] = make_float2(y.x, sgn * y.y);
-        }
+    for (int k = 0; k < R; ++k)
+        pre[k] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, k * rstride, 0));
+}
+
+// Persistent form for tiles that leave room for one workgroup per CU: a grid
+// of at most one workgroup per CU walks the tiles and loads the next tile's
+// values into registers while it transforms and stores the current one, so
+// that a CU's loads overlap its own stages (one workgroup per CU otherwise
+// alternates between loading and computing).  The loads of a tile that does
+// not exist go through a descriptor without records, so no branch surrounds
+// them; the first tile is peeled, so the loop is entered only after a whole
+// tile (loads, then stores), the same history as its back edge, and the
+// compiler's wait before the LDS writes covers the prefetch only, not the
+// stores issued after it.  With the grid and the tile count multiples of 8,
+// XCD x (= blockIdx mod 8) walks the x-th eighth of the tiles, and its
+// workgroups take consecutive tiles at each step, so the tiles sharing a
+// row's cache lines are in flight on one XCD together.  Every thread of a
+// workgroup runs the same iterations, so all reach every barrier.
+template <int R, int LOG2LEN, bool PASS_A, int TC>
+__global__ __launch_bounds__(1024) void k_fft_tile_p(const float2 *in, float2 *out, const float2 *__restrict__ tw,
+                                                      const float2 *__restrict__ tw_lo,
+                                                      const float2 *__restrict__ tw_hi, int log2n,
+                                                      int log2cols, long long tiles, long long total, float sgn) {
+    static_assert(PASS_A, "pass A only");
+    constexpr int len = 1 << LOG2LEN;
+    constexpr int LTC = clog2(TC);
+    extern __shared__ float4 lds_raw[];
+    float2 *buf = reinterpret_cast<float2 *>(lds_raw);
+    const long long cols = 1LL << log2cols;
+    float2 *tlo = buf + tile_vals(LOG2LEN, TC), *thi = tlo + 1024, *tht = thi + 1024;
+    if constexpr (PASS_A) tile_tables_to_lds(tlo, thi, tht, tw_lo, tw_hi);
+    // this workgroup's tiles: t = first, first + step, ... < end (first < end:
+    // the grid never exceeds the tiles)
+    const long long G = gridDim.x, b = blockIdx.x;
+    long long t = b, step = G, end = total;
+    if ((G & 7) == 0 && (total & 7) == 0) {
+        const long long eighth = total >> 3;
+        t = (b & 7) * eighth + (b >> 3);
+        step = G >> 3;
+        end = t - (b >> 3) + eighth;
     }
+    float2 pre[R];
+    tile_load_rows<R, LOG2LEN, TC>(pre, tile_rsrc(in, t, end, tiles, TC, log2n), (int)cols, (int)threadIdx.x);
+    auto one_tile = [&](long long cur) {
+        // an empty asm that claims to change tx keeps the compiler from
+        // hoisting every tx-derived address out of the tile loop and keeping
+        // it live (which spills)
+        int tx = (int)threadIdx.x;
+        asm volatile("" : "+v"(tx));
+        __syncthreads();  // the previous tile's LDS reads (or the tables' writes) are done
+        const int c = tx & (TC - 1), e0 = tx >> LTC;
+#pragma unroll
+        for (int k = 0; k < R; ++k) buf[tile_slot(c, e0 + k * (len / R), len)] = pre[k];
+        tile_load_rows<R, LOG2LEN, TC>(pre, tile_rsrc(in, cur + step, end, tiles, TC, log2n), (int)cols, tx);
+        const long long prob = cur / tiles;
+        const int c0 = (int)(cur % tiles) * TC;
+        tile_transform_store<R, LOG2LEN, PASS_A, TC, true>(buf, tlo, thi, tht, out, prob << log2n, c0, cols, log2n,
+                                                           sgn, tw, tx);
+    };
+    one_tile(t);
+    for (t += step; t < end; t += step) one_tile(t);
 }
 
 using TileKernel = void (*)(const float2 *, float2 *, const float2 *, const float2 *, const float2 *, int, int,
-                            long long, float);
+                            long long, long long, float);
 
 constexpr int kTileLdsMax = 160 * 1024;
 // LDS bytes of a pass: the tile, plus the twiddle tables in pass A
@@ -175,8 +303,9 @@ constexpr bool tile_ok(int radix, int log2len, int tc, bool pass_a) {
 
 template <int R, int L, bool A, int TC>
 static TileKernel tile_entry() {
-    if constexpr (tile_ok(R, L, TC, A)) return &k_fft_tile<R, L, A, TC>;
-    else return nullptr;
+    if constexpr (!tile_ok(R, L, TC, A)) return nullptr;
+    else if constexpr (tile_persistent(L, TC, A)) return &k_fft_tile_p<R, L, A, TC>;
+    else return &k_fft_tile<R, L, A, TC>;
 }
 template <int R, bool A, int TC>
 static TileKernel tile_len(int log2len) {
@@ -339,15 +468,20 @@ int launch_fft_large(const void *in, void *out, int log2n, int64_t batch, const 
     const float2 *hi = static_cast<const float2 *>(di->twiddles_large_hi);
     // pass A: columns of length n2 of the [n2][n1] input, tiles of the n1 columns
     const long long tiles_a = (1LL << l1) / p.tile_a, tiles_b = (1LL << l2) / p.tile_b;
-    hipLaunchKernelGGL(ka, dim3((unsigned)(batch * tiles_a)), dim3(p.tile_a * ((1 << l2) / p.radix_a)),
+    const long long total_a = batch * tiles_a, total_b = batch * tiles_b;
+    // persistent shapes: one workgroup per CU at most
+    auto grid = [&](long long total, int log2len, int tc, bool pass_a) {
+        return tile_persistent(log2len, tc, pass_a) ? std::min<long long>(total, std::max(di->cus, 1)) : total;
+    };
+    hipLaunchKernelGGL(ka, dim3((unsigned)grid(total_a, l2, p.tile_a, true)), dim3(p.tile_a * ((1 << l2) / p.radix_a)),
                        (size_t)tile_lds(l2, p.tile_a, true), s, static_cast<const float2 *>(in), static_cast<float2 *>(out),
-                       tw, lo, hi, log2n, l1, tiles_a, sgn);
+                       tw, lo, hi, log2n, l1, tiles_a, total_a, sgn);
     int rc = fail_hip(hipGetLastError(), "large FFT pass A launch");
     if (rc) return rc;
     // pass B: columns of length n1 of the [n1][n2] intermediate, in place
-    hipLaunchKernelGGL(kb, dim3((unsigned)(batch * tiles_b)), dim3(p.tile_b * ((1 << l1) / p.radix_b)),
+    hipLaunchKernelGGL(kb, dim3((unsigned)grid(total_b, l1, p.tile_b, false)), dim3(p.tile_b * ((1 << l1) / p.radix_b)),
                        (size_t)tile_lds(l1, p.tile_b, false), s, static_cast<const float2 *>(out), static_cast<float2 *>(out),
-                       tw, lo, hi, log2n, l2, tiles_b, sgn);
+                       tw, lo, hi, log2n, l2, tiles_b, total_b, sgn);
     return fail_hip(hipGetLastError(), "large FFT pass B launch");
 }
 

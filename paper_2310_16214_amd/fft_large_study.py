@@ -84,7 +84,8 @@ def main():
     ap.add_argument("--plans", default="", metavar="STUDY_JSON",
                     help="print the exhaustive-best plans of a study as tune-cache lines")
     ap.add_argument("--replay", default="",
-                    help="a study JSON: only run each size's exhaustive-best plan 10 times (for a kernel trace)")
+                    help="a study JSON: only run the exhaustive-best plan of each size in --sizes 10 times, "
+                         "after one 256 MiB copy (for a kernel trace or counter runs)")
     args = ap.parse_args()
     if args.plans:
         for r in json.load(open(args.plans))["records"]:
@@ -99,8 +100,18 @@ def main():
     dev = torch.device("cuda:0")
     torch.zeros(1, device=dev)
     if args.replay:
+        # a plain 256 MiB device copy first: the calibration dispatch for
+        # FETCH_SIZE / WRITE_SIZE counter runs of the replay
+        a = torch.zeros(1 << 25, dtype=torch.complex64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        sizes = {int(v) for v in args.sizes.split(",")}
         for rec in json.load(open(args.replay))["records"]:
             n, batch = rec["n"], rec["batch"]
+            if n.bit_length() - 1 not in sizes:
+                continue
             plan = ppx.make_plan(*rec["exhaustive"]["plan"])
             x = torch.zeros(n * batch, dtype=torch.complex64, device=dev)
             y = torch.empty_like(x)
