@@ -273,10 +273,17 @@ __global__ __launch_bounds__(fft_max_threads(P)) void k_fft(const float2 *in, fl
 constexpr int clog2(int x) { return x <= 1 ? 0 : 1 + clog2(x / 2); }
 
 // With STAGED the last stage leaves its results in the LDS buffer, at their
-// output positions, instead of storing them (see k_fft_n).
-template <int R, int P, bool SPLIT, int LOG2N, int LNS, bool STAGED = false>
+// output positions, instead of storing them (see k_fft_n).  After the
+// exchange that follows stage s (0-based), hook.template at<s>() runs: a
+// caller's work to place between the stages (none by default).
+struct NoStageHook {
+    template <int S>
+    __device__ __forceinline__ void at() const {}
+};
+template <int R, int P, bool SPLIT, int LOG2N, int LNS, bool STAGED = false, typename Hook = NoStageHook>
 __device__ __forceinline__ void fft_stages_ct(float2 (&v)[P], void *lds, int poff, float2 *dst, int tid,
-                                              bool active, float sgn, const float2 *__restrict__ tw) {
+                                              bool active, float sgn, const float2 *__restrict__ tw,
+                                              const Hook &hook = Hook{}) {
     constexpr int REM = LOG2N % clog2(R);
     constexpr int RS = (LNS == 0 && REM != 0) ? (1 << REM) : R;  // mixed-radix first stage
     constexpr int LRS = clog2(RS);
@@ -295,7 +302,10 @@ __device__ __forceinline__ void fft_stages_ct(float2 (&v)[P], void *lds, int pof
         }
     } else {
         stage_exchange<RS, P, SPLIT>(v, lds, poff, tid, T, LNS);
-        fft_stages_ct<R, P, SPLIT, LOG2N, LNS + LRS, STAGED>(v, lds, poff, dst, tid, active, sgn, tw);
+        // index of the stage just done: the first spans REM or log2 R bits
+        constexpr int S = LNS == 0 ? 0 : 1 + (LNS - (REM ? REM : clog2(R))) / clog2(R);
+        hook.template at<S>();
+        fft_stages_ct<R, P, SPLIT, LOG2N, LNS + LRS, STAGED, Hook>(v, lds, poff, dst, tid, active, sgn, tw, hook);
     }
 }
 

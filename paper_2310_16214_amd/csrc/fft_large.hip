@@ -65,6 +65,18 @@ __host__ __device__ constexpr bool tile_persistent(int log2len, int tc, bool pas
     return pass_a && ((int64_t)tile_vals(log2len, tc) + kTwLargeVals) * (int64_t)sizeof(float2) > 80 * 1024;
 }
 
+// float2 entries of a column transform's stage twiddle bases (every stage but
+// the first: w^k, w^{4k} and, radix 16, w^{8k} for k below the stage's span),
+// which the persistent pass A keeps in LDS after the tables.
+__host__ __device__ constexpr int tile_stage_tw_vals(int radix, int log2len) {
+    const int lr = radix == 16 ? 4 : 3;
+    const int nst = (log2len + lr - 1) / lr;
+    const int first = log2len % lr ? log2len % lr : lr;
+    int e = 0;
+    for (int i = 0; i < nst - 1; ++i) e += (radix == 16 ? 3 : 2) << (first + i * lr);
+    return e;
+}
+
 // Pass A: the three twiddle tables into LDS after the tile.  Read from global
 // memory in the store loop, each table read would wait for the stores issued
 // before it (vector memory operations complete in issue order).  The lanes
@@ -81,14 +93,60 @@ __device__ __forceinline__ void tile_tables_to_lds(float2 *tlo, float2 *thi, flo
     if (threadIdx.x < 8) tht[threadIdx.x] = tw_hi[1024 + threadIdx.x];
 }
 
+// The stages of a tile's columns with the twiddle bases read from LDS (twl,
+// laid out by fft_tw_to_lds), the form the persistent pass A uses: the stage
+// code of the single-pass kernels reads them from global memory, and such a
+// read, issued after the next tile's loads, waits for those loads too
+// (vector memory operations complete in issue order).  Radix R = P: one
+// butterfly per thread and stage after a first stage of the remaining bits.
+// The last stage leaves its results in LDS at their output positions.
+template <int R, int LOG2LEN, int LNS, int IDX, typename Hook>
+__device__ __forceinline__ void tile_stages_twl(float2 (&v)[R], float2 *buf, int poff, int tid, const float2 *twl,
+                                                const Hook &hook) {
+    constexpr int P = R;
+    constexpr int REM = LOG2LEN % clog2(R);
+    constexpr int RS = (LNS == 0 && REM != 0) ? (1 << REM) : R;
+    constexpr int LRS = clog2(RS);
+    constexpr int T = 1 << (LOG2LEN - clog2(P));
+    if constexpr (LNS == 0) {
+        stage_butterflies<RS, P, true>(v, tid, T, 0, nullptr);
+    } else {
+        constexpr int OFF = fft_tw_offset<R, LOG2LEN>(IDX);
+        const int k = tid & ((1 << LNS) - 1);
+        TwBase b;
+        b.w1 = twl[OFF + k];
+        if constexpr (RS >= 8) b.w4 = twl[OFF + (1 << LNS) + k];
+        if constexpr (RS >= 16) b.w8 = twl[OFF + (2 << LNS) + k];
+        float2 w[RS];
+        stage_twiddles_from<RS>(w, b);
+#pragma unroll
+        for (int q = 1; q < RS; ++q) v[q] = cmul(v[q], w[q]);
+        RegDFT<RS>::run(v);
+    }
+    if constexpr (LNS + LRS == LOG2LEN) {
+        constexpr int NB = P / RS;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int q = 0; q < RS; ++q) buf[swz_c(poff + stage_out_pos<RS>(tid + i * T, LNS, q))] = v[i + q * NB];
+    } else {
+        stage_exchange<RS, P, false>(v, buf, poff, tid, T, LNS);
+        constexpr int S = LNS == 0 ? 0 : 1 + (LNS - (REM ? REM : clog2(R))) / clog2(R);
+        hook.template at<S>();
+        tile_stages_twl<R, LOG2LEN, LNS + LRS, LNS == 0 ? IDX : IDX + 1, Hook>(v, buf, poff, tid, twl, hook);
+    }
+}
+
 // The tile in LDS (written by the caller, no barrier yet): transform its TC
 // columns and write them out.  NT = len * TC / R threads; tx is the thread's
-// index in the workgroup.  PERSIST (pass A only) stores through a descriptor
-// of the problem's output, with the column step in the scalar operand.
-template <int R, int LOG2LEN, bool PASS_A, int TC, bool PERSIST>
+// index in the workgroup.  PERSIST (pass A only) takes the stage twiddle
+// bases from LDS (tw then points there) and stores through a descriptor of
+// the problem's output, with the column step in the scalar operand.
+template <int R, int LOG2LEN, bool PASS_A, int TC, bool PERSIST, typename Hook = NoStageHook>
 __device__ __forceinline__ void tile_transform_store(float2 *buf, const float2 *tlo, const float2 *thi, const float2 *tht,
                                                      float2 *out, long long base, int c0, long long cols, int log2n,
-                                                     float sgn, const float2 *__restrict__ tw, int tx) {
+                                                     float sgn, const float2 *__restrict__ tw, int tx,
+                                                     const Hook &hook = Hook{}) {
     constexpr int len = 1 << LOG2LEN;
     constexpr int P = R;
     constexpr int lT = LOG2LEN - clog2(P);
@@ -106,7 +164,10 @@ __device__ __forceinline__ void tile_transform_store(float2 *buf, const float2 *
     for (int j = 0; j < P; ++j) v[j] = buf[tile_slot(lp, tid + j * T, len)];
     __syncthreads();
     if constexpr (PASS_A) fft_conj<P>(v, sgn);  // the inverse: conjugated in pass A, out in pass B
-    fft_stages_ct<R, P, false, LOG2LEN, 0, true>(v, buf, lp * (len + 1), nullptr, tid, true, sgn, tw);
+    if constexpr (PERSIST)  // tw: the stage twiddle bases in LDS
+        tile_stages_twl<R, LOG2LEN, 0, 0, Hook>(v, buf, lp * (len + 1), tid, tw, hook);
+    else
+        fft_stages_ct<R, P, false, LOG2LEN, 0, true, Hook>(v, buf, lp * (len + 1), nullptr, tid, true, sgn, tw, hook);
     __syncthreads();
     if constexpr (PASS_A) {
         // Element (c, e) of the tile is stored at row c0 + c, position e, of
@@ -217,15 +278,36 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const float2 *in, lo
 // The thread's R values of a tile's rows: element i = tx + k * NT, column
 // i mod TC (= tx mod TC), row i div TC (= tx div TC + k * len / R).  Byte
 // offsets stay below 2^26 (n <= 2^23 values).
-template <int R, int LOG2LEN, int TC>
+// Chunk C of NC: the loads k with k * NC / R == C (the chunks partition them).
+template <int R, int LOG2LEN, int TC, int C = 0, int NC = 1>
 __device__ __forceinline__ void tile_load_rows(float2 (&pre)[R], __amdgpu_buffer_rsrc_t r, int cols, int tx) {
     constexpr int LTC = clog2(TC);
     const int voff = ((tx >> LTC) * cols + (tx & (TC - 1))) * (int)sizeof(float2);
     const int rstride = ((1 << LOG2LEN) / R) * cols * (int)sizeof(float2);
 #pragma unroll
     for (int k = 0; k < R; ++k)
-        pre[k] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, k * rstride, 0));
+        if (k * NC / R == C)
+            pre[k] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, k * rstride, 0));
 }
+
+// The persistent pass A's next-tile loads, spread over the stages: chunk 0
+// before the first stage, chunk s after the exchange that follows stage
+// s - 1, NC = (stages - 1) chunks, so none is issued in the last stage, just
+// before the stores.  (A burst of every load at the tile's start, on the
+// heels of the previous tile's stores, leaves the memory system idle during
+// the later stages.)
+template <int R, int LOG2LEN, int TC>
+struct TilePrefetch {
+    static constexpr int NST = (LOG2LEN + clog2(R) - 1) / clog2(R);
+    static constexpr int NC = NST > 2 ? NST - 1 : 1;
+    float2 (&pre)[R];
+    __amdgpu_buffer_rsrc_t r;
+    int cols, tx;
+    template <int S>
+    __device__ __forceinline__ void at() const {
+        if constexpr (S + 1 < NC) tile_load_rows<R, LOG2LEN, TC, S + 1, NC>(pre, r, cols, tx);
+    }
+};
 
 // Persistent form for tiles that leave room for one workgroup per CU: a grid
 // of at most one workgroup per CU walks the tiles and loads the next tile's
@@ -253,7 +335,10 @@ __global__ __launch_bounds__(1024) void k_fft_tile_p(const float2 *in, float2 *o
     float2 *buf = reinterpret_cast<float2 *>(lds_raw);
     const long long cols = 1LL << log2cols;
     float2 *tlo = buf + tile_vals(LOG2LEN, TC), *thi = tlo + 1024, *tht = thi + 1024;
-    if constexpr (PASS_A) tile_tables_to_lds(tlo, thi, tht, tw_lo, tw_hi);
+    float2 *twl = tht + 8;  // the stage twiddle bases
+    static_assert(fft_tw_entries<R, LOG2LEN>() == tile_stage_tw_vals(R, LOG2LEN), "stage base count");
+    tile_tables_to_lds(tlo, thi, tht, tw_lo, tw_hi);
+    fft_tw_to_lds<R, LOG2LEN>(twl, tw);
     // this workgroup's tiles: t = first, first + step, ... < end (first < end:
     // the grid never exceeds the tiles)
     const long long G = gridDim.x, b = blockIdx.x;
@@ -276,11 +361,12 @@ __global__ __launch_bounds__(1024) void k_fft_tile_p(const float2 *in, float2 *o
         const int c = tx & (TC - 1), e0 = tx >> LTC;
 #pragma unroll
         for (int k = 0; k < R; ++k) buf[tile_slot(c, e0 + k * (len / R), len)] = pre[k];
-        tile_load_rows<R, LOG2LEN, TC>(pre, tile_rsrc(in, cur + step, end, tiles, TC, log2n), (int)cols, tx);
+        const TilePrefetch<R, LOG2LEN, TC> nxt{pre, tile_rsrc(in, cur + step, end, tiles, TC, log2n), (int)cols, tx};
+        tile_load_rows<R, LOG2LEN, TC, 0, TilePrefetch<R, LOG2LEN, TC>::NC>(pre, nxt.r, nxt.cols, tx);
         const long long prob = cur / tiles;
         const int c0 = (int)(cur % tiles) * TC;
         tile_transform_store<R, LOG2LEN, PASS_A, TC, true>(buf, tlo, thi, tht, out, prob << log2n, c0, cols, log2n,
-                                                           sgn, tw, tx);
+                                                           sgn, twl, tx, nxt);
     };
     one_tile(t);
     for (t += step; t < end; t += step) one_tile(t);
@@ -290,15 +376,18 @@ using TileKernel = void (*)(const float2 *, float2 *, const float2 *, const floa
                             long long, long long, float);
 
 constexpr int kTileLdsMax = 160 * 1024;
-// LDS bytes of a pass: the tile, plus the twiddle tables in pass A
-constexpr int64_t tile_lds(int log2len, int tc, bool pass_a) {
-    return ((int64_t)tile_vals(log2len, tc) + (pass_a ? kTwLargeVals : 0)) * (int64_t)sizeof(float2);
+// LDS bytes of a pass: the tile, plus the twiddle tables in pass A, plus the
+// stage twiddle bases in the persistent pass A
+constexpr int64_t tile_lds(int radix, int log2len, int tc, bool pass_a) {
+    return ((int64_t)tile_vals(log2len, tc) + (pass_a ? kTwLargeVals : 0) +
+            (tile_persistent(log2len, tc, pass_a) ? tile_stage_tw_vals(radix, log2len) : 0)) *
+           (int64_t)sizeof(float2);
 }
 // Tile shapes: radix 8 or 16; 64 to 1024 threads; the LDS budget (pass A
 // with its tables).
 constexpr bool tile_ok(int radix, int log2len, int tc, bool pass_a) {
     return (radix == 8 || radix == 16) && log2len >= clog2(radix) && tc * ((1 << log2len) / radix) >= 64 &&
-           tc * ((1 << log2len) / radix) <= 1024 && tile_lds(log2len, tc, pass_a) <= kTileLdsMax;
+           tc * ((1 << log2len) / radix) <= 1024 && tile_lds(radix, log2len, tc, pass_a) <= kTileLdsMax;
 }
 
 template <int R, int L, bool A, int TC>
@@ -350,7 +439,7 @@ bool fft_tile_shape_valid(int radix, int log2len, int tc, bool pass_a) {
     return (pass_a ? tile_lookup<true>(radix, log2len, tc) : tile_lookup<false>(radix, log2len, tc)) != nullptr;
 }
 
-int64_t fft_tile_lds_bytes(int log2len, int tc, bool pass_a) { return tile_lds(log2len, tc, pass_a); }
+int64_t fft_tile_lds_bytes(int radix, int log2len, int tc, bool pass_a) { return tile_lds(radix, log2len, tc, pass_a); }
 
 void fft_large_host_twiddles(float *lo2, float *hi2) {
     const double two_pi = 6.283185307179586476925286766559;
@@ -474,13 +563,13 @@ int launch_fft_large(const void *in, void *out, int log2n, int64_t batch, const 
         return tile_persistent(log2len, tc, pass_a) ? std::min<long long>(total, std::max(di->cus, 1)) : total;
     };
     hipLaunchKernelGGL(ka, dim3((unsigned)grid(total_a, l2, p.tile_a, true)), dim3(p.tile_a * ((1 << l2) / p.radix_a)),
-                       (size_t)tile_lds(l2, p.tile_a, true), s, static_cast<const float2 *>(in), static_cast<float2 *>(out),
+                       (size_t)tile_lds(p.radix_a, l2, p.tile_a, true), s, static_cast<const float2 *>(in), static_cast<float2 *>(out),
                        tw, lo, hi, log2n, l1, tiles_a, total_a, sgn);
     int rc = fail_hip(hipGetLastError(), "large FFT pass A launch");
     if (rc) return rc;
     // pass B: columns of length n1 of the [n1][n2] intermediate, in place
     hipLaunchKernelGGL(kb, dim3((unsigned)grid(total_b, l1, p.tile_b, false)), dim3(p.tile_b * ((1 << l1) / p.radix_b)),
-                       (size_t)tile_lds(l1, p.tile_b, false), s, static_cast<const float2 *>(out), static_cast<float2 *>(out),
+                       (size_t)tile_lds(p.radix_b, l1, p.tile_b, false), s, static_cast<const float2 *>(out), static_cast<float2 *>(out),
                        tw, lo, hi, log2n, l2, tiles_b, total_b, sgn);
     return fail_hip(hipGetLastError(), "large FFT pass B launch");
 }

@@ -123,7 +123,7 @@ void fft_host_twiddles(float *out2);
 void fft_large_host_twiddles(float *lo2, float *hi2);  // 1024 and 1032 pairs
 const void *fft_tile_kernel(int radix, int log2len, int tile, bool pass_a);
 bool fft_tile_shape_valid(int radix, int log2len, int tile, bool pass_a);  // a pass of column length 2^log2len
-int64_t fft_tile_lds_bytes(int log2len, int tile, bool pass_a);
+int64_t fft_tile_lds_bytes(int radix, int log2len, int tile, bool pass_a);
 int launch_fft_large(const void *in, void *out, int log2n, int64_t batch, const ppx_fft_plan &p, bool inverse,
                      hipStream_t s);
 int fft_plan_check(int64_t n, const ppx_fft_plan &p);  // PPX_OK or a failure with reason

@@ -981,7 +981,7 @@ static int analytical_plan(int64_t n, int64_t batch, ppx_fft_plan &out) {
                 // grid-fill term then sees the pass's workgroup count
                 c.push_back(ppx_config{radix, radix, threads, tile, 0, 0});
                 r.push_back(ppx_resource{threads, a.numRegs,
-                                         (int32_t)(fft_tile_lds_bytes(l, tile, pass == 0) + a.sharedSizeBytes)});
+                                         (int32_t)(fft_tile_lds_bytes(radix, l, tile, pass == 0) + a.sharedSizeBytes)});
             }
         if (c.empty()) return fail(PPX_ECONFIG, "no pass kernel");
         const int k = analytical_pick_impl(m, c.data(), r.data(), (int)c.size(), batch * ncols,
