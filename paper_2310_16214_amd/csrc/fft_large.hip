@@ -313,7 +313,10 @@ struct TilePrefetch {
 // of at most one workgroup per CU walks the tiles and loads the next tile's
 // values into registers while it transforms and stores the current one, so
 // that a CU's loads overlap its own stages (one workgroup per CU otherwise
-// alternates between loading and computing).  The loads of a tile that does
+// alternates between loading and computing).  The loads go out in chunks
+// between the stages (TilePrefetch), and the stages read their twiddle bases
+// from LDS (tile_stages_twl), so no global read inside a tile waits for the
+// prefetch.  The loads of a tile that does
 // not exist go through a descriptor without records, so no branch surrounds
 // them; the first tile is peeled, so the loop is entered only after a whole
 // tile (loads, then stores), the same history as its back edge, and the
