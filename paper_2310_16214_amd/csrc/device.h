@@ -192,6 +192,14 @@ __device__ __forceinline__ T per_word(T v, F f) {
     }
 }
 
+// Value of lane (lane - 1) across the whole wave (DPP wave_shr:1); lane 0
+// receives 0.  Must be called with all 64 lanes active.
+constexpr int kDppWaveShr1 = 0x138;
+template <typename T>
+__device__ __forceinline__ T dpp_wave_shr1(T v) {
+    return per_word(v, [](int x) { return __builtin_amdgcn_update_dpp(0, x, kDppWaveShr1, 0xf, 0xf, false); });
+}
+
 // Value of lane (lane - D) within the same 16-lane row, 0 where that lane is
 // outside the row.
 template <int D, typename T>

@@ -13,7 +13,9 @@
 //   3. when a problem spans several waves (T > 64), each wave's total goes to
 //      one LDS slot and every thread adds the totals of the earlier waves of
 //      its problem (the paper's per-problem shared-memory slots, one per wave);
-//   4. add the exclusive prefix to the P values and store.
+//   4. add the exclusive prefix to the P values and store; the thread's
+//      prefix is the inclusive lane result of the lane before it, so every
+//      term of an output is a sum of elements at or before that output.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -90,9 +92,15 @@ __device__ __forceinline__ void scan_values(U (&v)[P], int lT, T *wave_tot) {
     // 2. lane network over the problem's segment of the wave
     const int lane = threadIdx.x & (kWave - 1);
     const int seg = lT >= 6 ? kWave : (1 << lT);
-    U incl = ALGO == PPX_SCAN_LF ? lanes_scan_lf<U>(total, seg, lane)
-                                 : lanes_scan_ks<U>(total, seg, lane);
-    U prefix = incl - total;  // exclusive prefix of this thread within the wave segment
+    const U incl = ALGO == PPX_SCAN_LF ? lanes_scan_lf<U>(total, seg, lane)
+                                       : lanes_scan_ks<U>(total, seg, lane);
+    // Exclusive prefix of this thread within the segment: the previous lane's
+    // inclusive value (0 at the segment's first lane), moved by a one-lane
+    // shift.  Forming it as incl - total instead would cancel: every output
+    // would then carry rounding on the scale of the thread's whole chunk and
+    // of the elements after it, not of the sum the output is defined by.
+    const U prev = dpp_wave_shr1(incl);
+    U prefix = (lane & (seg - 1)) == 0 ? U(0) : prev;
 
     // 3. earlier waves of the same problem
     if (lT > 6) {

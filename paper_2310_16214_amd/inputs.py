@@ -45,6 +45,28 @@ def scan_input(n: int, batch: int, dtype, seed: int = 0) -> np.ndarray:
     raise TypeError(f"unsupported scan dtype {dtype}")
 
 
+def scan_input_spiked(n: int, batch: int, dtype, seed: int = 0, spike: float = 1.0e6) -> np.ndarray:
+    """float32 or float64 uniform [0, 1), shape [batch][n], with one value per
+    row replaced by ``spike`` at a position p with (p + 1) % 32 == 0, i.e. at
+    the end of a 32-element block (hence of every aligned chunk of 2..32
+    elements that contains it).  Draw order: the uniform array, then the
+    block index of each row (integers on [0, n/32), or 0 when n < 32, where
+    the spike goes at n - 1)."""
+    rng = np.random.default_rng(seed)
+    dtype = np.dtype(dtype)
+    x = rng.random(size=(batch, n), dtype=dtype)
+    blocks = max(1, n // 32)
+    pos = rng.integers(0, blocks, size=batch) * 32 + min(32, n) - 1
+    x[np.arange(batch), pos] = spike
+    return x
+
+
+def scan_input_normal(n: int, batch: int, dtype, seed: int = 0) -> np.ndarray:
+    """Standard-normal values (mixed signs) drawn in float64 and rounded to
+    float32 or float64, shape [batch][n]."""
+    return np.random.default_rng(seed).standard_normal(size=(batch, n)).astype(np.dtype(dtype))
+
+
 def scan_input_dyadic(n: int, batch: int, seed: int = 0):
     """float64 values k * 2^-20, integer k uniform on [0, 2^20), shape
     [batch][n]; returns (k as int64, values).  Every partial sum of up to 2^33

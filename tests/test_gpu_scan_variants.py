@@ -48,7 +48,7 @@ def test_float64_uniform_every_config(cuda, n):
     xd = to_dev(x, cuda)
     for e in (False, True):
         ref = oracle.scan(x, exclusive=e)
-        bound = scan_bound(x, U64, exclusive=e, oracle_rounds=True)
+        bound = scan_bound(x, U64, exclusive=e, oracle_unit=U64)
         for cfg in ppx.enumerate_configs(ppx.OP_SCAN, ppx.F64, n):
             banner(f"scan f64 n={n} excl={e} {cfg}")
             y = _run(xd, n, batch, ppx.F64, cfg, exclusive=e)
