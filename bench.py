@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip tuned-vs-default, the small case, batched-vs-plain and the serving point")
     p.add_argument("--ops", default="fft,scan,tridiag")
     p.add_argument("--tune-cache", default=os.path.join(
         ROOT, "paper_2310_16214_amd", "tuned", "mi355x.txt"))
@@ -67,7 +69,9 @@ def build_workload(ops, dev):
             cfg = ppx.resolve_config(ppx.OP_FFT, ppx.C64, n, batch)
             calls.append(dict(op="fft", dtype="c64", n=n, batch=batch, bpe=16, cfg=cfg,
                               run=(lambda x=x, y=y, n=n, b=batch, c=cfg:
-                                   ppx.fft_batched(x, y, n, b, -1, c))))
+                                   ppx.fft_batched(x, y, n, b, -1, c)),
+                              run_cfg=(lambda c, x=x, y=y, n=n, b=batch:
+                                       (lambda: ppx.fft_batched(x, y, n, b, -1, c)))))
     if "scan" in ops:
         for dt, code in ((np.int32, ppx.I32), (np.float32, ppx.F32)):
             base = inputs.scan_input(1 << 13, (1 << 24) >> 13, dt, seed=1).reshape(-1)
@@ -79,7 +83,9 @@ def build_workload(ops, dev):
                 cfg = ppx.resolve_config(ppx.OP_SCAN, code, n, batch)
                 calls.append(dict(op="scan", dtype=np.dtype(dt).name, n=n, batch=batch, bpe=8,
                                   cfg=cfg, run=(lambda x=x, y=y, n=n, b=batch, c=cfg, k=code:
-                                                ppx.scan_batched(x, y, n, b, k, c))))
+                                                ppx.scan_batched(x, y, n, b, k, c)),
+                                  run_cfg=(lambda c, x=x, y=y, n=n, b=batch, k=code:
+                                           (lambda: ppx.scan_batched(x, y, n, b, k, c)))))
     if "tridiag" in ops:
         for dt, code in ((np.float32, ppx.F32), (np.float64, ppx.F64)):
             for ln in range(5, 11):
@@ -96,7 +102,9 @@ def build_workload(ops, dev):
                     calls.append(dict(op="tridiag_" + name, dtype=np.dtype(dt).name, n=n,
                                       batch=batch, bpe=5 * es, cfg=cfg,
                                       run=(lambda n=n, bt=batch, cf=cfg, k=code, t=(ad, bd, cd, dd, xo):
-                                           ppx.tridiag_batched(*t, n, bt, k, cf))))
+                                           ppx.tridiag_batched(*t, n, bt, k, cf)),
+                                      run_cfg=(lambda cf, n=n, bt=batch, k=code, t=(ad, bd, cd, dd, xo):
+                                               (lambda: ppx.tridiag_batched(*t, n, bt, k, cf)))))
     return calls
 
 
@@ -161,6 +169,138 @@ def stream_ceiling(ppx, dom, dev, stream, reps=10):
         ts.append(e0.elapsed_time(e1) * 1e3)
     del sets
     return (k + 1) * nbytes / float(np.median(ts)) / 1e3  # GB/s
+
+
+def _event_us(stream, fn, reps):
+    """Median duration (us) of fn() between two events on `stream`."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3)
+    return float(np.median(ts))
+
+
+def tuned_vs_default(ppx, calls, per, stream, steps=2):
+    """Every call of the step with the plain default configuration (one
+    problem per workgroup, radix 2), timed the way the step's per-call pass
+    times the tuned ones (an event pair per call, the calls back to back, so a
+    call's data was last touched a step earlier); per operation the geometric
+    mean of tuned / default speed-ups and the smallest one."""
+    import torch
+    runs = []
+    for c in calls:
+        op = c["op"]
+        code = {"fft": ppx.C64, "int32": ppx.I32, "float32": ppx.F32, "float64": ppx.F64}[
+            "fft" if op == "fft" else c["dtype"]]
+        opc = ppx.OP_FFT if op == "fft" else ppx.OP_SCAN if op == "scan" else ppx.OP_TRIDIAG
+        d = ppx.default_config(opc, code, c["n"])
+        if opc == ppx.OP_TRIDIAG:  # the plain kernel of the call's family
+            d.algo = ppx.TRI_CR if op == "tridiag_cr" else ppx.TRI_PCR
+            d.lds_elems = 0
+        runs.append(c["run_cfg"](d))
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in calls]
+          for _ in range(steps)]
+    for r in runs:  # warm-up: code objects
+        r()
+    torch.cuda.synchronize()
+    for s in range(steps):
+        for r, (e0, e1) in zip(runs, ev[s]):
+            e0.record(stream)
+            r()
+            e1.record(stream)
+    torch.cuda.synchronize()
+    out = {}
+    for i, c in enumerate(calls):
+        us = float(np.mean([ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(steps)])) * 1e3
+        key = "fft" if c["op"] == "fft" else "scan" if c["op"] == "scan" else "tridiag"
+        out.setdefault(key, []).append(us / per[i]["us"])
+    res = {k: {"geomean": round(float(np.exp(np.mean(np.log(v)))), 3), "min": round(float(min(v)), 3),
+               "calls": len(v)} for k, v in out.items()}
+    res["default"] = "radix 2, one problem per workgroup, L = min(n/2, 1024) (tridiagonal: plain CR/PCR)"
+    return res
+
+
+def c1_and_batched(ppx, dev, stream, nthreads):
+    """The small case: 64 signals of N = 1024 (seed 0), plain radix-2 kernel.
+    Kernel-only time (event pair, median of 200), time with the launch (host
+    clock around launch + synchronisation, median of 200), the CPU oracle's
+    time for the same 64 signals, and batched vs plain: the one batched call
+    against 64 launches of one problem each, same configuration."""
+    import torch
+
+    import oracle
+    from paper_2310_16214_amd import inputs
+    n, batch = 1024, 64
+    x = inputs.fft_input(n, batch, seed=0)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty_like(xd)
+    cfg = ppx.default_config(ppx.OP_FFT, ppx.C64, n)
+    run = lambda: ppx.fft_batched(xd, y, n, batch, -1, cfg, stream)  # noqa: E731
+    for _ in range(20):
+        run()
+    torch.cuda.synchronize()
+    kernel_us = _event_us(stream, run, 200)
+    wall = []
+    for _ in range(200):
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        wall.append((time.perf_counter() - t0) * 1e6)
+    rows = [(xd[i], y[i]) for i in range(batch)]
+
+    def per_problem():
+        for a, b in rows:
+            ppx.fft_batched(a, b, n, 1, -1, cfg, stream)
+    per_problem()
+    plain_us = _event_us(stream, per_problem, 20)
+    tuned = ppx.resolve_config(ppx.OP_FFT, ppx.C64, n, batch)
+    run_t = lambda: ppx.fft_batched(xd, y, n, batch, -1, tuned, stream)  # noqa: E731
+    run_t()
+    tuned_us = _event_us(stream, run_t, 200)
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.dft(x, nthreads=nthreads)
+    oracle_s = time.perf_counter() - t0
+    return ({"workload": "fft 64 x n=1024 c64, plain radix-2 (L=512, one problem per workgroup)",
+             "kernel_us": round(kernel_us, 2), "with_launch_us": round(float(np.median(wall)), 2),
+             "oracle_ms": round(oracle_s * 1e3, 2), "oracle_cores": nthreads,
+             "tuned_config_kernel_us": round(tuned_us, 2)},
+            {"workload": "fft 64 x n=1024 c64, plain radix-2 configuration",
+             "batched_us": round(kernel_us, 2), "one_launch_per_problem_us": round(plain_us, 2),
+             "ratio": round(plain_us / kernel_us, 2)})
+
+
+def serving_point(dev, njobs=2000, load=0.75):
+    """The request loop on a mixed trace (FFT c64, scan f32, CR f32; log2 N
+    uniform 4..14, tridiagonal 4..13; batch uniform 1..4096): saturation of
+    the fused continuous batching and of one launch per request (all jobs
+    arriving at once), then Poisson arrivals at `load` x the fused saturation
+    rate for both modes; p50 / p99 latency (arrival to completion) and
+    GElem/s."""
+    from paper_2310_16214_amd import serve_bench as sb
+    pools = sb.Pools(dev, 0)
+    budget, inflight = 4 << 30, 2
+    warm = sb.make_trace(50, float("inf"), 99, pools)
+    for m in ("fused", "per_request"):
+        sb.run_trace(warm, m, budget, inflight)
+    burst = sb.make_trace(njobs, float("inf"), 0, pools)
+    sat = {m: sb.run_trace(burst, m, budget, inflight) for m in ("fused", "per_request")}
+    rate = njobs / (sat["fused"]["span_ms"] / 1e3)
+    trace = sb.make_trace(njobs, load * rate, 1, pools)
+    pt = {m: sb.run_trace(trace, m, budget, inflight) for m in ("fused", "per_request")}
+    keep = ("p50_ms", "p99_ms", "gelem_s", "hbm_frac", "launches")
+    r = {"jobs": njobs, "mix": "fft c64 / scan f32 / CR f32, log2 N 4..14 (CR 4..13), batch 1..4096",
+         "saturation": {m: {k: round(v[k], 4) for k in ("gelem_s", "hbm_frac", "launches")}
+                        for m, v in sat.items()},
+         "load": load, "offered_jobs_per_s": round(load * rate, 1),
+         "at_load": {m: {k: round(v[k], 4) for k in keep} for m, v in pt.items()}}
+    del pools
+    return r
 
 
 def cpu_baseline(calls_meta, nthreads, budget_s=20.0):
@@ -308,12 +448,22 @@ def main():
                      "stream_ref_gbs": round(ref_gbs, 1),
                      "frac_of_stream_ref": round(dom["gb_s"] / ref_gbs, 4)},
     }
+    # the rest of the metric, each measured on resident buffers outside the
+    # timed steps: tuned vs default, batched vs plain and the small case, and
+    # one serving load point
+    nthreads = len(os.sched_getaffinity(0))
+    if not args.no_extras:
+        out["tuned_vs_default"] = tuned_vs_default(ppx, calls, per, stream)
+        out["c1"], out["batched_vs_plain"] = c1_and_batched(ppx, dev, stream, nthreads)
+        del calls
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["serving"] = serving_point(dev)
     if args.detail:
         with open(args.detail, "w") as f:
             for r in per:
                 f.write(json.dumps(r) + "\n")
     if not args.no_cpu_baseline:
-        nthreads = len(os.sched_getaffinity(0))
         v, est, sampled = cpu_baseline(per, nthreads)
         out["cpu_baseline"] = {"value": round(v, 6), "unit": "GElem/s", "cores": nthreads,
                                "kind": "oracle",

@@ -274,14 +274,15 @@ int tune(int op, int dtype, int64_t n, int64_t batch, int method, int max_evals,
  * One job of a mixed launch: a whole batched call of any operation.
  *   op, dtype, n, batch   as in the single calls
  *   direction             FFT only: -1 forward, +1 inverse
- *   algo                  tridiagonal: PPX_TRI_CR or PPX_TRI_PCR; scan:
+ *   algo                  tridiagonal: the solver family, PPX_TRI_CR,
+ *                         PPX_TRI_PCR, PPX_TRI_WM or PPX_TRI_LF; scan:
  *                         PPX_JOB_SCAN_INCLUSIVE or PPX_JOB_SCAN_EXCLUSIVE
  *                         (dtype PPX_I32, PPX_F32 or PPX_F64)
  *   in                    FFT / scan input; tridiagonal: a
  *   b, c, d               tridiagonal only (NULL otherwise)
  *   out                   FFT / scan output; tridiagonal: x
  * Device pointers, 16-byte aligned, caller-owned; aliasing as in the single
- * calls.  Tridiagonal systems must fit one fused tile's 128 KiB of LDS
+ * calls.  Tridiagonal systems solved through LDS (n > 1024) must fit 128 KiB
  * (float32 CR: n <= 8192; PCR or float64: n <= 4096; float64 PCR: n <= 2048).
  */
 #define PPX_JOB_SCAN_INCLUSIVE 0
@@ -302,18 +303,33 @@ typedef struct ppx_job {
 
 /*
  * launch_mixed -- Sec. IV-A's batched invocation extended to a batch of
- * uneven jobs (different operations, sizes and batch counts) in ONE
- * persistent launch.  Every job is cut into tiles whose shape depends only on
- * (op, dtype, n, algo), so each job's output is bit-identical whatever else
- * shares the launch.  Asynchronous and stream-ordered; allocates nothing
- * (device tables are created on a device's first mixed launch).  At most
- * 16384 jobs and 262144 tiles per launch (PPX_EINVAL beyond).  Each job's
- * result equals the single call's within that call's tolerance.
+ * uneven jobs (different operations, sizes and batch counts) in one launch
+ * of persistent kernels.  Each job is cut into tiles of the shape its
+ * single call uses with cfg == NULL (the tuned configuration, else the
+ * analytical one; tridiagonal: of the job's family): the same radix, values
+ * per thread and solver, so each job's output equals that single call's and
+ * does not depend on what else shares the launch.  The tiles run in
+ * persistent kernels, one per family of tile shapes (FFT, scan and
+ * tridiagonal by block size and register demand), replayed as one hipGraph.
+ * Asynchronous and stream-ordered; allocates nothing after a device's first
+ * mixed launch, which creates the launch tables (4 ring slots) and captures
+ * graphs as new family sets appear.  At most 16384 jobs and 2^20 tiles per
+ * launch (PPX_EINVAL beyond).
  */
 int launch_mixed(const ppx_job *jobs, int njobs, void *stream);
 
-/* Problems per tile the mixed launch uses for a job of (op, dtype, n, algo). */
-int ppx_mixed_tile_problems(int op, int dtype, int64_t n, int algo);
+/*
+ * ppx_mixed_tile_config -- how launch_mixed cuts *job: returns the problems
+ * per tile (> 0) or a negative PPX_E* code, and writes to *cfg (if not
+ * NULL) the single-call configuration whose arithmetic the tiles follow:
+ * the configuration of the job's call with cfg == NULL, with the persistent
+ * flag cleared (a launch strategy, not arithmetic); for an FFT whose tuned
+ * shape is not radix = P in {8, 16} (or 4 with n <= 1024), the radix = P
+ * shape used instead.  A single call with that configuration gives the same
+ * bits as the job in a mixed launch.  Needs no GPU when the configuration
+ * comes from the tune cache or the static resource table.
+ */
+int ppx_mixed_tile_config(const ppx_job *job, ppx_config *cfg);
 
 /* ---------------------------------------------------------------------- */
 /* Helpers                                                                 */

@@ -323,10 +323,11 @@ constexpr bool fft_staged_io() {
     return !SPLIT && LOG2N <= 6 && LOG2N > clog2(R) && (1 << (LOG2N - clog2(P))) <= 16;
 }
 
-// Words [0, total/2) of the block into the buffer (swizzled float2 slots).
-__device__ __forceinline__ void fft_stage_in(float2 *buf, const float2 *src, int total) {
+// Words [0, total/2) of the block into the buffer (swizzled float2 slots);
+// tx is the thread's index in the workgroup, nt the workgroup's threads.
+__device__ __forceinline__ void fft_stage_in(float2 *buf, const float2 *src, int total, int tx, int nt) {
     const float4 *src4 = reinterpret_cast<const float4 *>(src);
-    for (int e = threadIdx.x; 2 * e < total; e += blockDim.x) {
+    for (int e = tx; 2 * e < total; e += nt) {
         const float4 w = src4[e];
         buf[swz_c(2 * e)] = make_float2(w.x, w.y);
         buf[swz_c(2 * e + 1)] = make_float2(w.z, w.w);
@@ -335,9 +336,10 @@ __device__ __forceinline__ void fft_stage_in(float2 *buf, const float2 *src, int
 
 // The buffer's first total values to dst as 16-byte words (conjugated for the
 // inverse transform), with non-temporal stores.
-__device__ __forceinline__ void fft_stage_out(const float2 *buf, float2 *dst, int total, float sgn) {
+__device__ __forceinline__ void fft_stage_out(const float2 *buf, float2 *dst, int total, float sgn, int tx,
+                                              int nt) {
     u32x4 *dst4 = reinterpret_cast<u32x4 *>(dst);
-    for (int e = threadIdx.x; 2 * e < total; e += blockDim.x) {
+    for (int e = tx; 2 * e < total; e += nt) {
         const float2 a = buf[swz_c(2 * e)], b = buf[swz_c(2 * e + 1)];
         store_nt(dst4 + e, __builtin_bit_cast(u32x4, make_float4(a.x, sgn * a.y, b.x, sgn * b.y)));
     }
@@ -364,18 +366,20 @@ __device__ __forceinline__ void fft_conj(float2 (&v)[P], float sgn) {
     for (int j = 0; j < P; ++j) v[j].y *= sgn;
 }
 
-// Same arguments as k_fft (log2n is implied by LOG2N).
+// One workgroup's share with the log2 n-specialised stage sequence:
+// problems [p0, p0 + nprob), laid out as in fft_block (T = n/P threads per
+// problem; threads of problems beyond nprob only take part in the barriers).
+// Used by k_fft_n and by the mixed launch's FFT tiles, so both compute the
+// same values.  tx is the thread's index in the workgroup and nt the
+// workgroup's threads (passed in, so that a caller's loop can keep the
+// addresses derived from them from being hoisted and held in registers).
 template <int R, int P, bool SPLIT, int LOG2N>
-__global__ __launch_bounds__(fft_max_threads(P)) void k_fft_n(const float2 *in, float2 *out,
-                                                               const float2 *__restrict__ tw, int,
-                                                               long long batch, int gb, float sgn) {
-    extern __shared__ float4 lds_raw[];
+__device__ __forceinline__ void fft_group_ct(const float2 *in, float2 *out, const float2 *__restrict__ tw,
+                                             long long p0, int nprob, float sgn, void *lds_raw, int tx, int nt) {
     constexpr int n = 1 << LOG2N;
     constexpr int lT = LOG2N - clog2(P);
-    const long long p0 = (long long)blockIdx.x * gb;
-    const int nprob = (int)min((long long)gb, batch - p0);
-    const int lp = threadIdx.x >> lT;
-    const int tid = threadIdx.x & ((1 << lT) - 1);
+    const int lp = tx >> lT;
+    const int tid = tx & ((1 << lT) - 1);
     const long long prob = p0 + lp;
     const bool active = lp < nprob;
     float2 v[P];
@@ -385,7 +389,7 @@ __global__ __launch_bounds__(fft_max_threads(P)) void k_fft_n(const float2 *in, 
         constexpr int T = 1 << lT;
         float2 *buf = reinterpret_cast<float2 *>(lds_raw);
         const int total = nprob * n;
-        fft_stage_in(buf, in + p0 * n, total);
+        fft_stage_in(buf, in + p0 * n, total, tx, nt);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < P; ++j) v[j] = buf[swz_c(lp * n + tid + j * T)];
@@ -393,7 +397,7 @@ __global__ __launch_bounds__(fft_max_threads(P)) void k_fft_n(const float2 *in, 
         fft_conj<P>(v, sgn);
         fft_stages_ct<R, P, SPLIT, LOG2N, 0, true>(v, lds_raw, lp * n, nullptr, tid, active, sgn, tw);
         __syncthreads();
-        fft_stage_out(buf, out + p0 * n, total, sgn);
+        fft_stage_out(buf, out + p0 * n, total, sgn, tx, nt);
     } else {
         fft_load_raw_ct<P, LOG2N>(v, in + prob * n, tid, active);
         // keep the scheduler from interleaving the loads with their first use,
@@ -402,6 +406,17 @@ __global__ __launch_bounds__(fft_max_threads(P)) void k_fft_n(const float2 *in, 
         fft_conj<P>(v, sgn);
         fft_stages_ct<R, P, SPLIT, LOG2N, 0>(v, lds_raw, lp * n, out + prob * n, tid, active, sgn, tw);
     }
+}
+
+// Same arguments as k_fft (log2n is implied by LOG2N).
+template <int R, int P, bool SPLIT, int LOG2N>
+__global__ __launch_bounds__(fft_max_threads(P)) void k_fft_n(const float2 *in, float2 *out,
+                                                               const float2 *__restrict__ tw, int,
+                                                               long long batch, int gb, float sgn) {
+    extern __shared__ float4 lds_raw[];
+    const long long p0 = (long long)blockIdx.x * gb;
+    const int nprob = (int)min((long long)gb, batch - p0);
+    fft_group_ct<R, P, SPLIT, LOG2N>(in, out, tw, p0, nprob, sgn, lds_raw, threadIdx.x, blockDim.x);
 }
 
 // --- persistent variant

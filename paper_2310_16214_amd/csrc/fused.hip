@@ -1,223 +1,146 @@
-// Mixed batched launch: jobs of different operations, sizes and batch counts
-// processed by one persistent kernel.
+// Mixed batched launch, host side: planning each job's tiles from its tuned
+// configuration, the launch tables, and the per-slot hipGraphs that replay
+// the table expansion and the family kernels (see mixed.h).
 //
-// Every job is cut into tiles of whole problems, one tile being what one
-// 1024-thread workgroup processes at once with the tile shape of its
-// operation: FFT radix 16 with 16 values per thread (16384 complex values
-// per tile, 16384/n problems), scan with 4 values per thread for n <= 4096
-// (sub-blocks of 4096 elements, up to 16384 per tile) and n/1024 above, CR or
-// PCR with as many systems as the 128 KiB LDS budget holds.  The tile shape
-// depends only on (op, dtype, n), so a job's result is the same bits whatever
-// else shares the launch.  Workgroups are persistent -- as many as can be
-// resident -- and pull tile indices from a device counter until the tile
-// table is exhausted, so every workgroup exits once the table is drained.
-// The counter reset and the kernel are captured once per ring slot in a
-// hipGraph; a launch writes the slot's job/tile table (one host-to-device
-// copy of the used part) and replays the graph.
+// A launch copies one table (header and job records) from pinned memory to
+// the device and replays a graph captured for the set of families that have
+// tiles: [expand the tile lists] -> [family kernel] -> [family kernel] ...
+// Each family kernel is persistent (as many workgroups as are resident) and
+// drains its family's tiles, so every workgroup exits once they are done.
+// Graphs are captured on first use of a (ring slot, family set) and kept.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
-#include "fft_device.h"
-#include "ppx_internal.h"
-#include "scan_device.h"
+#include "mixed.h"
 #include "tridiag_device.h"
 
 namespace ppx {
 
-constexpr int kFusedThreads = 1024;
-constexpr int kFusedLds = 128 * 1024;
-constexpr int kFusedFftElems = 16384;       // complex values per FFT tile
-constexpr int kFusedScanElems = 16384;      // elements per scan tile
-constexpr int kMaxJobsPerLaunch = 1 << 14;
-constexpr int kMaxTilesPerLaunch = 1 << 18;
 constexpr int kSlots = 4;
 
-struct FusedJob {  // 64 bytes
-    int op, dtype, log2n, flags;  // flags: FFT 1 = inverse; scan 1 = exclusive; tridiag = algo
-    long long batch;
-    const void *p[4];
-    void *out;
-};
-struct FusedTile {  // 16 bytes
-    int job, count;
-    long long first;
-};
-struct FusedHeader {
-    unsigned next_tile;  // work counter
-    int ntiles;
-};
-
-static_assert(sizeof(FusedJob) == 64, "job layout");
-static_assert(sizeof(FusedTile) == 16, "tile layout");
-
-__global__ void k_fused_reset(FusedHeader *hdr) {
-    if (threadIdx.x == 0) hdr->next_tile = 0u;
-}
-
-// A scan tile is processed in sub-blocks of kFusedThreads * P elements (P = 4
-// up to n = 4096, then n / 1024), each a whole number of problems.
-template <typename T, int P, bool EXCL>
-__device__ __forceinline__ void scan_tile_p(const FusedJob &j, const FusedTile &t, T *wave_tot) {
-    const T *in = static_cast<const T *>(j.p[0]);
-    T *out = static_cast<T *>(j.out);
-    const int per = (kFusedThreads * P) >> j.log2n;  // problems per sub-block (>= 1)
-    for (int s = 0; s < t.count; s += per) {
-        scan_block<T, P, PPX_SCAN_KS, EXCL>(in, out, j.log2n, t.first + s, min(per, t.count - s), wave_tot);
-        __syncthreads();  // wave totals are reused by the next sub-block
+int64_t mix_lds_bytes(int fam) {
+    switch (fam) {
+        case kFamFft256: return 256 * 16 * 8;    // complex exchange, P = 16
+        case kFamFft1024: return 1024 * 16 * 8;  // complex exchange, P = 16
+        case kFamTriW32:
+        case kFamTriW32H: return 4 * 3 * 64 * 4 * 4;  // PCR LDS exchange: 4 waves, 3 * 64 * 4 floats each
+        case kFamTriW64:
+        case kFamTriW64H: return 4 * 3 * 64 * 4 * 8;
+        case kFamTriLds: return kMixTriLdsBudget;
+        default: return 0;  // scan: static wave-total slots only
     }
 }
 
-template <typename T, bool EXCL>
-__device__ __forceinline__ void scan_tile_x(const FusedJob &j, const FusedTile &t, T *wave_tot) {
-    if (j.log2n <= 12) scan_tile_p<T, 4, EXCL>(j, t, wave_tot);
-    else if (j.log2n == 13) scan_tile_p<T, 8, EXCL>(j, t, wave_tot);
-    else scan_tile_p<T, 16, EXCL>(j, t, wave_tot);
+static const void *mix_kernel(int fam) {
+    if (fam == kFamFft256 || fam == kFamFft1024) return mix_fft_kernel(fam);
+    if (fam == kFamScan256 || fam == kFamScan1024) return mix_scan_kernel(fam);
+    return mix_tri_kernel(fam);
 }
 
-template <typename T>
-__device__ __forceinline__ void scan_tile(const FusedJob &j, const FusedTile &t, T *wave_tot) {
-    if (j.flags & 1) scan_tile_x<T, true>(j, t, wave_tot);
-    else scan_tile_x<T, false>(j, t, wave_tot);
-}
-
-__global__ __launch_bounds__(kFusedThreads) void k_fused(const FusedJob *__restrict__ jobs,
-                                                         const FusedTile *__restrict__ tiles,
-                                                         FusedHeader *hdr,
-                                                         const float2 *__restrict__ tw) {
-    extern __shared__ float4 lds[];
-    __shared__ int s_tile;
-    __shared__ double wave_tot_d[kFusedThreads / kWave];  // float and int totals alias its start
-    float *wave_tot_f = reinterpret_cast<float *>(wave_tot_d);
-    int *wave_tot_i = reinterpret_cast<int *>(wave_tot_d);
-    const int ntiles = hdr->ntiles;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&hdr->next_tile, 1u);
-        __syncthreads();
-        const int ti = s_tile;
-        __syncthreads();
-        if (ti >= ntiles) break;  // uniform: every wave of the workgroup leaves
-        const FusedTile t = tiles[ti];
-        const FusedJob j = jobs[t.job];
-        if (j.op == PPX_OP_FFT) {
-            fft_block<16, 16, false>(static_cast<const float2 *>(j.p[0]), static_cast<float2 *>(j.out), tw,
-                                     j.log2n, t.first, t.count, (j.flags & 1) ? -1.0f : 1.0f, lds);
-        } else if (j.op == PPX_OP_SCAN) {
-            if (j.dtype == PPX_I32) scan_tile<int>(j, t, wave_tot_i);
-            else if (j.dtype == PPX_F32) scan_tile<float>(j, t, wave_tot_f);
-            else scan_tile<double>(j, t, wave_tot_d);
-        } else if (j.dtype == PPX_F32) {
-            const float *const *p = reinterpret_cast<const float *const *>(j.p);
-            if (j.flags == PPX_TRI_PCR)
-                tridiag_block<float, PPX_TRI_PCR>(p[0], p[1], p[2], p[3], static_cast<float *>(j.out),
-                                                  j.log2n, t.first, t.count, reinterpret_cast<float *>(lds));
-            else
-                tridiag_block<float, PPX_TRI_CR>(p[0], p[1], p[2], p[3], static_cast<float *>(j.out),
-                                                 j.log2n, t.first, t.count, reinterpret_cast<float *>(lds));
-        } else {
-            const double *const *p = reinterpret_cast<const double *const *>(j.p);
-            if (j.flags == PPX_TRI_PCR)
-                tridiag_block<double, PPX_TRI_PCR>(p[0], p[1], p[2], p[3], static_cast<double *>(j.out),
-                                                   j.log2n, t.first, t.count, reinterpret_cast<double *>(lds));
-            else
-                tridiag_block<double, PPX_TRI_CR>(p[0], p[1], p[2], p[3], static_cast<double *>(j.out),
-                                                  j.log2n, t.first, t.count, reinterpret_cast<double *>(lds));
-        }
-        __syncthreads();  // LDS and the tile index are reused by the next tile
+// Writes each job's run of its family's tile list: entry first_tile + k of
+// the job's family is the job's index, k < the job's tile count.
+__global__ __launch_bounds__(kMixExpandThreads) void k_mix_expand(char *tables) {
+    const MixHeader *h = reinterpret_cast<const MixHeader *>(tables);
+    const MixJob *jobs = reinterpret_cast<const MixJob *>(tables + kMixHeaderBytes);
+    unsigned *tiles = reinterpret_cast<unsigned *>(tables + h->tiles_off);
+    const unsigned njobs = h->njobs;
+    for (unsigned jb = blockIdx.x; jb < njobs; jb += gridDim.x) {
+        const MixJob &j = jobs[jb];
+        const unsigned nt = (unsigned)((j.batch + j.per_tile - 1) / j.per_tile);
+        unsigned *dst = tiles + h->tile_base[j.family] + j.first_tile;
+        for (unsigned k = threadIdx.x; k < nt; k += blockDim.x) dst[k] = jb;
     }
 }
 
-// ------------------------------------------------------------------- host
+const void *mix_expand_kernel() { return reinterpret_cast<const void *>(&k_mix_expand); }
 
-// Problems per tile of a job: a pure function of (op, dtype, n, algo).
-int64_t fused_tile_problems(int op, int dtype, int64_t n, int algo) {
-    if (op == PPX_OP_FFT) return std::max<int64_t>(1, kFusedFftElems / n);
-    if (op == PPX_OP_SCAN) return std::max<int64_t>(1, kFusedScanElems / n);
-    const int64_t per_sys = tri_lds_arrays(algo) * (dtype == PPX_F64 ? 8 : 4) * n;
-    const int64_t by_lds = kFusedLds / per_sys;
-    const int64_t by_threads = 2 * kFusedThreads / n > 0 ? 2 * kFusedThreads / n : 1;
-    return std::min(by_lds, std::max<int64_t>(1, by_threads));
-}
+// ------------------------------------------------------------- planning
 
-namespace {
-struct Slot {
-    FusedJob *d_jobs = nullptr;
-    FusedTile *d_tiles = nullptr;
-    FusedHeader *d_hdr = nullptr;
-    char *h_stage = nullptr;  // pinned: header | jobs | tiles
-    hipEvent_t done = nullptr;
-    hipGraphExec_t exec = nullptr;
-    bool used = false;
-};
-struct MixedCtx {
-    int device = -1;
-    int grid = 0;
-    Slot slots[kSlots];
-    int next = 0;
-};
-std::mutex g_mixed_mu;
-std::vector<MixedCtx *> g_mixed;  // per device ordinal, never freed
-
-constexpr size_t kStageBytes = 256 + sizeof(FusedJob) * kMaxJobsPerLaunch + sizeof(FusedTile) * kMaxTilesPerLaunch;
-
-int init_ctx(MixedCtx *m, const DeviceInfo *di) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fused),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kFusedLds);
-    (void)e;  // not every runtime needs it; the occupancy query below decides
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused, kFusedThreads, kFusedLds) != hipSuccess ||
-        per_cu < 1)
-        return fail(PPX_EHIP, "fused kernel cannot be resident");
-    m->grid = per_cu * di->cus;
-    hipStream_t cap;
-    if (hipStreamCreate(&cap) != hipSuccess) return fail(PPX_EHIP, "stream creation failed");
-    for (auto &s : m->slots) {
-        if (hipMalloc(&s.d_hdr, 256) != hipSuccess ||
-            hipMalloc(&s.d_jobs, sizeof(FusedJob) * kMaxJobsPerLaunch) != hipSuccess ||
-            hipMalloc(&s.d_tiles, sizeof(FusedTile) * kMaxTilesPerLaunch) != hipSuccess ||
-            hipHostMalloc(&s.h_stage, kStageBytes, hipHostMallocDefault) != hipSuccess ||
-            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
-            return fail(PPX_ENOMEM, "could not allocate the mixed-launch tables");
-        // capture: counter reset, then the persistent kernel, reading this
-        // slot's tables at fixed addresses
-        hipGraph_t g;
-        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
-            return fail(PPX_EHIP, "graph capture failed");
-        hipLaunchKernelGGL(k_fused_reset, dim3(1), dim3(64), 0, cap, s.d_hdr);
-        hipLaunchKernelGGL(k_fused, dim3(m->grid), dim3(kFusedThreads), kFusedLds, cap, s.d_jobs,
-                           s.d_tiles, s.d_hdr, static_cast<const float2 *>(di->twiddles));
-        if (hipStreamEndCapture(cap, &g) != hipSuccess) return fail(PPX_EHIP, "graph capture failed");
-        const hipError_t ie = hipGraphInstantiate(&s.exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) return fail(PPX_EHIP, "graph instantiation failed");
-    }
-    (void)hipStreamDestroy(cap);
+// The configuration the single call with cfg == NULL uses for this job: the
+// tuned (or analytical) one for (op, dtype, n); for a tridiagonal job, the
+// one of its family (the job's algo).
+int job_config(const ppx_job &j, ppx_config &c) {
+    if (j.op == PPX_OP_TRIDIAG) return family_config(j.dtype, j.n, j.batch, j.algo, c);
+    const int dtype = j.op == PPX_OP_FFT ? PPX_C64 : j.dtype;
+    if (ppx_resolve_config(j.op, dtype, j.n, j.batch, &c) != PPX_OK) return PPX_ECONFIG;
     return PPX_OK;
 }
 
-MixedCtx *mixed_ctx() {
-    const DeviceInfo *di = device_info();
-    if (!di) return nullptr;
-    std::lock_guard<std::mutex> lk(g_mixed_mu);
-    if ((int)g_mixed.size() <= di->device) g_mixed.resize(di->device + 1, nullptr);
-    if (!g_mixed[di->device]) {
-        auto *m = new MixedCtx();
-        m->device = di->device;
-        if (init_ctx(m, di) != PPX_OK) return nullptr;  // leaks the partial context on purpose
-        g_mixed[di->device] = m;
-    }
-    return g_mixed[di->device];
+// Radix = P = 8 or 16, or 4 up to n = 1024: the shapes the FFT families hold.
+static bool fft_mix_shape(int radix, int P, int64_t n) {
+    return radix == P && (P == 8 || P == 16 || (P == 4 && n <= 1024));
 }
-}  // namespace
 
-// Validates one job against the single-call rules and the fused limits.
-int check_job(const ppx_job &j) {
+int mix_plan(const ppx_job &j, MixPlan &m) {
+    ppx_config c;
+    if (int rc = job_config(j, c)) return rc;
+    const int log2n = ilog2(j.n);
+    m.flags = 0;
+    if (j.op == PPX_OP_FFT) {
+        c.algo &= ~PPX_FFT_LDS_PIPE;  // the launch is persistent itself
+        if (!fft_mix_shape(c.radix, c.elems_per_thread, j.n)) {
+            // a shape the families do not hold: the nearest radix = P one, at
+            // one problem per 64-thread group at least
+            const int P = (c.elems_per_thread <= 8 && j.n / 8 <= kMaxThreadsPerBlock) ? 8 : 16;
+            const int64_t T = j.n / P;
+            c.radix = P;
+            c.elems_per_thread = P;
+            c.problems_per_block = (int)std::max<int64_t>(1, kWave / T);
+            c.threads_per_block = (int)(T * c.problems_per_block);
+            c.lds_elems = 0;
+            complete_config(PPX_OP_FFT, PPX_C64, j.n, c);
+            if (validate_config(PPX_OP_FFT, PPX_C64, j.n, c)) return fail(PPX_ECONFIG, "job: no FFT tile shape");
+        }
+        const int P = c.elems_per_thread;
+        const int64_t T = j.n / P;
+        m.family = T <= 256 ? kFamFft256 : kFamFft1024;
+        const bool split = (c.algo & PPX_FFT_LDS_SPLIT) != 0;
+        m.shape = mix_fft_shape(log2n, P, split);
+        m.per_tile = (int)(mix_block(m.family) / T);
+        m.flags = j.direction == 1 ? 1 : 0;
+    } else if (j.op == PPX_OP_SCAN) {
+        c.algo &= PPX_SCAN_LF;  // KS or LF; the persistent flag cleared
+        const int P = c.elems_per_thread;
+        const int64_t T = j.n / P;
+        m.family = T <= 256 ? kFamScan256 : kFamScan1024;
+        m.shape = mix_scan_shape(j.dtype, ilog2(P), c.algo == PPX_SCAN_LF);
+        m.per_tile = (int)(mix_block(m.family) / T);
+        m.flags = j.algo == PPX_JOB_SCAN_EXCLUSIVE ? 1 : 0;
+    } else {
+        c.algo = tri_base(c.algo);
+        const bool f64 = j.dtype == PPX_F64;
+        if (tri_in_wave(c.algo)) {
+            const int P = c.elems_per_thread;
+            m.family = mix_triw_family(f64, c.algo, P);
+            m.shape = mix_triw_shape(c.algo, ilog2(P));
+            m.per_tile = (int)(256 * P / j.n);
+        } else {
+            const int64_t per_sys = tri_lds_arrays(c.algo) * (f64 ? 8 : 4) * j.n;
+            if (per_sys > kMixTriLdsBudget)
+                return fail(PPX_EINVAL, "job: tridiagonal system too large for a mixed-launch tile (128 KiB of LDS)");
+            const int64_t scaled = (int64_t)c.problems_per_block * 1024 / c.threads_per_block;
+            m.family = kFamTriLds;
+            m.shape = mix_tril_shape(f64, c.algo == PPX_TRI_PCR);
+            m.per_tile = (int)std::max<int64_t>(1, std::min<int64_t>(scaled, kMixTriLdsBudget / per_sys));
+        }
+    }
+    m.cfg = c;
+    m.ntiles = (j.batch + m.per_tile - 1) / m.per_tile;
+    return PPX_OK;
+}
+
+// Validates one job against the single-call rules and the mixed-launch
+// limits, and plans its tiles.
+int check_job(const ppx_job &j, MixPlan *plan) {
     if (!j.in || !j.out) return fail(PPX_EINVAL, "job: null pointer");
     if (!is_pow2(j.n) || j.n < PPX_MIN_N || j.n > PPX_MAX_N) return fail(PPX_EINVAL, "job: bad n");
     if (j.batch < 1) return fail(PPX_EINVAL, "job: batch must be >= 1");
+    if (j.batch > (int64_t(1) << 40) / j.n) return fail(PPX_EINVAL, "job: batch * n is too large");
     auto al = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
     if (!al(j.in) || !al(j.out)) return fail(PPX_EINVAL, "job: pointers must be 16-byte aligned");
     switch (j.op) {
@@ -231,77 +154,209 @@ int check_job(const ppx_job &j) {
             if (j.algo != PPX_JOB_SCAN_INCLUSIVE && j.algo != PPX_JOB_SCAN_EXCLUSIVE)
                 return fail(PPX_EINVAL, "job: scan algo must be PPX_JOB_SCAN_INCLUSIVE or _EXCLUSIVE");
             break;
-        case PPX_OP_TRIDIAG: {
+        case PPX_OP_TRIDIAG:
             if (j.dtype != PPX_F32 && j.dtype != PPX_F64) return fail(PPX_EINVAL, "job: tridiagonal dtype");
-            if (j.algo != PPX_TRI_CR && j.algo != PPX_TRI_PCR) return fail(PPX_EINVAL, "job: tridiagonal algo");
+            if (j.algo != PPX_TRI_CR && j.algo != PPX_TRI_PCR && j.algo != PPX_TRI_WM && j.algo != PPX_TRI_LF)
+                return fail(PPX_EINVAL, "job: tridiagonal algo must be a family: PPX_TRI_CR, _PCR, _WM or _LF");
             if (!j.b || !j.c || !j.d || !al(j.b) || !al(j.c) || !al(j.d))
                 return fail(PPX_EINVAL, "job: tridiagonal coefficient pointers");
-            const int64_t per_sys = tri_lds_arrays(j.algo) * (j.dtype == PPX_F64 ? 8 : 4) * j.n;
-            if (per_sys > kFusedLds) return fail(PPX_EINVAL, "job: tridiagonal system too large for a fused tile");
             break;
-        }
         default:
             return fail(PPX_EINVAL, "job: unknown op");
     }
+    MixPlan m;
+    if (int rc = mix_plan(j, m)) return rc;
+    if (m.ntiles > kMixMaxTiles) return fail(PPX_EINVAL, "job: more tiles than one mixed launch holds");
+    if (plan) *plan = m;
     return PPX_OK;
 }
 
 int64_t mixed_tile_count(const ppx_job *jobs, int njobs) {
     int64_t tiles = 0;
     for (int i = 0; i < njobs; ++i) {
-        const int64_t per = fused_tile_problems(jobs[i].op, jobs[i].dtype, jobs[i].n, jobs[i].algo);
-        tiles += (jobs[i].batch + per - 1) / per;
+        MixPlan m;
+        if (mix_plan(jobs[i], m) != PPX_OK) return -1;
+        tiles += m.ntiles;
     }
     return tiles;
 }
 
+// Plans every job and writes the header and job records into `buf` (at
+// least mix_table_bytes(njobs, 0) bytes).  Returns the family mask, or a
+// negative error.  ntiles_out receives the total tile count.
+int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_out) {
+    if (!jobs || njobs < 1) return fail(PPX_EINVAL, "no jobs");
+    if (njobs > kMixMaxJobs) return fail(PPX_EINVAL, "too many jobs for one mixed launch");
+    auto *h = reinterpret_cast<MixHeader *>(buf);
+    auto *rec = reinterpret_cast<MixJob *>(buf + kMixHeaderBytes);
+    std::memset(h, 0, kMixHeaderBytes);
+    int64_t fam_tiles[kMixFamilies] = {};
+    for (int i = 0; i < njobs; ++i) {
+        MixPlan m;
+        if (int rc = check_job(jobs[i], &m)) return rc;
+        const ppx_job &j = jobs[i];
+        MixJob &r = rec[i];
+        r.shape = m.shape;
+        r.flags = m.flags;
+        r.log2n = ilog2(j.n);
+        r.per_tile = m.per_tile;
+        r.batch = j.batch;
+        r.first_tile = (unsigned)fam_tiles[m.family];
+        r.family = m.family;
+        r.p[0] = j.in;
+        r.p[1] = j.b;
+        r.p[2] = j.c;
+        r.p[3] = j.d;
+        r.out = j.out;
+        fam_tiles[m.family] += m.ntiles;
+    }
+    int64_t total = 0;
+    int mask = 0;
+    for (int f = 0; f < kMixFamilies; ++f) {
+        h->tile_base[f] = (unsigned)total;
+        h->ntiles[f] = (unsigned)fam_tiles[f];
+        total += fam_tiles[f];
+        if (fam_tiles[f]) mask |= 1 << f;
+    }
+    if (total > kMixMaxTiles) return fail(PPX_EINVAL, "too many tiles for one mixed launch");
+    h->njobs = (unsigned)njobs;
+    h->tiles_off = (unsigned)((kMixHeaderBytes + (int64_t)njobs * sizeof(MixJob) + 15) & ~int64_t(15));
+    *ntiles_out = total;
+    return mask;
+}
+
+// ------------------------------------------------------- device context
+namespace {
+struct Slot {
+    char *d_tables = nullptr;
+    char *h_stage = nullptr;  // pinned: header | jobs
+    hipEvent_t done = nullptr;
+    bool used = false;
+    std::map<int, hipGraphExec_t> graphs;  // by family mask
+};
+struct MixedCtx {
+    int device = -1;
+    hipStream_t capture = nullptr;
+    Slot slots[kSlots];
+    int next = 0;
+};
+std::mutex g_mixed_mu;
+std::vector<MixedCtx *> g_mixed;  // per device ordinal, never freed
+
+constexpr size_t kTableBytes = (size_t)mix_table_bytes(kMixMaxJobs, kMixMaxTiles) + 16;
+constexpr size_t kStageBytes = (size_t)mix_table_bytes(kMixMaxJobs, 0);
+
+int init_ctx(MixedCtx *m) {
+    if (int rc = mix_prepare_kernels()) return rc;
+    if (hipStreamCreate(&m->capture) != hipSuccess) return fail(PPX_EHIP, "stream creation failed");
+    for (auto &s : m->slots) {
+        if (hipMalloc(&s.d_tables, kTableBytes) != hipSuccess ||
+            hipHostMalloc(&s.h_stage, kStageBytes, hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+            return fail(PPX_ENOMEM, "could not allocate the mixed-launch tables");
+    }
+    return PPX_OK;
+}
+
+MixedCtx *mixed_ctx() {
+    const DeviceInfo *di = device_info();
+    if (!di) return nullptr;
+    if ((int)g_mixed.size() <= di->device) g_mixed.resize(di->device + 1, nullptr);
+    if (!g_mixed[di->device]) {
+        auto *m = new MixedCtx();
+        m->device = di->device;
+        if (init_ctx(m) != PPX_OK) return nullptr;  // leaks the partial context on purpose
+        g_mixed[di->device] = m;
+    }
+    return g_mixed[di->device];
+}
+
+// The graph of a slot for a family mask: expansion, then each family's
+// persistent kernel, in family order.
+int slot_graph(MixedCtx *m, Slot &s, int mask, hipGraphExec_t *out) {
+    auto it = s.graphs.find(mask);
+    if (it != s.graphs.end()) {
+        *out = it->second;
+        return PPX_OK;
+    }
+    const DeviceInfo *di = device_info();
+    hipGraph_t g;
+    if (hipStreamBeginCapture(m->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(PPX_EHIP, "graph capture failed");
+    int rc = mix_enqueue(s.d_tables, mask, nullptr, static_cast<const float2 *>(di->twiddles), m->capture);
+    const hipError_t ce = hipStreamEndCapture(m->capture, &g);
+    if (rc) return rc;
+    if (ce != hipSuccess) return fail(PPX_EHIP, "graph capture failed");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(PPX_EHIP, "graph instantiation failed");
+    s.graphs[mask] = exec;
+    *out = exec;
+    return PPX_OK;
+}
+}  // namespace
+
+// Resident workgroups of each family's kernel on the current device (from
+// the occupancy query at its block size and LDS), set up once per process.
+static int g_resident[kMixFamilies];
+static bool g_prepared = false;
+static std::mutex g_prep_mu;
+
+int mix_prepare_kernels() {
+    std::lock_guard<std::mutex> lk(g_prep_mu);
+    if (g_prepared) return PPX_OK;
+    const DeviceInfo *di = device_info();
+    if (!di) return PPX_EDEVICE;
+    for (int f = 0; f < kMixFamilies; ++f) {
+        const void *k = mix_kernel(f);
+        const int64_t lds = mix_lds_bytes(f);
+        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, mix_block(f), (size_t)lds) != hipSuccess ||
+            per_cu < 1)
+            return fail(PPX_EHIP, "a mixed-launch kernel cannot be resident");
+        g_resident[f] = per_cu * di->cus;
+    }
+    g_prepared = true;
+    return PPX_OK;
+}
+
+// Enqueues the expansion and the kernels of the families in `mask` on
+// stream s, reading the tables at d_tables.  ntiles (per family, may be
+// NULL) caps each grid at the family's tile count; NULL launches the
+// resident count (a captured graph serves any tile count).
+int mix_enqueue(char *d_tables, int mask, const int64_t *ntiles, const float2 *tw, hipStream_t s) {
+    hipLaunchKernelGGL(k_mix_expand, dim3(kMixExpandBlocks), dim3(kMixExpandThreads), 0, s, d_tables);
+    hipError_t e = hipGetLastError();
+    for (int f = 0; f < kMixFamilies && e == hipSuccess; ++f) {
+        if (!(mask & (1 << f))) continue;
+        int64_t grid = g_resident[f];
+        if (ntiles) grid = std::min<int64_t>(grid, std::max<int64_t>(1, ntiles[f]));
+        hipLaunchKernelGGL(reinterpret_cast<mix_kernel_t>(const_cast<void *>(mix_kernel(f))), dim3((unsigned)grid),
+                           dim3(mix_block(f)), (size_t)mix_lds_bytes(f), s, static_cast<const char *>(d_tables), tw);
+        e = hipGetLastError();
+    }
+    return fail_hip(e, "mixed launch");
+}
+
 int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEvent_t done_event) {
     if (!jobs || njobs < 1) return fail(PPX_EINVAL, "no jobs");
-    if (njobs > kMaxJobsPerLaunch) return fail(PPX_EINVAL, "too many jobs for one mixed launch");
-    for (int i = 0; i < njobs; ++i)
-        if (int rc = check_job(jobs[i])) return rc;
-    const int64_t ntiles = mixed_tile_count(jobs, njobs);
-    if (ntiles > kMaxTilesPerLaunch) return fail(PPX_EINVAL, "too many tiles for one mixed launch");
+    if (njobs > kMixMaxJobs) return fail(PPX_EINVAL, "too many jobs for one mixed launch");
+    std::unique_lock<std::mutex> lk(g_mixed_mu);
     MixedCtx *m = mixed_ctx();
     if (!m) return PPX_EHIP;
-    std::unique_lock<std::mutex> lk(g_mixed_mu);
     Slot &s = m->slots[m->next];
-    m->next = (m->next + 1) % kSlots;
     if (s.used && hipEventSynchronize(s.done) != hipSuccess) return fail(PPX_EHIP, "slot wait failed");
-    // host tables in the slot's pinned staging buffer
-    auto *hdr = reinterpret_cast<FusedHeader *>(s.h_stage);
-    auto *hj = reinterpret_cast<FusedJob *>(s.h_stage + 256);
-    auto *ht = reinterpret_cast<FusedTile *>(s.h_stage + 256 + sizeof(FusedJob) * kMaxJobsPerLaunch);
-    int64_t k = 0;
-    for (int i = 0; i < njobs; ++i) {
-        const ppx_job &j = jobs[i];
-        FusedJob &f = hj[i];
-        f.op = j.op;
-        f.dtype = j.dtype;
-        f.log2n = ilog2(j.n);
-        f.flags = j.op == PPX_OP_FFT ? (j.direction == 1 ? 1 : 0) : j.algo;  // scan: exclusive; tridiag: algo
-        f.batch = j.batch;
-        f.p[0] = j.in;
-        f.p[1] = j.b;
-        f.p[2] = j.c;
-        f.p[3] = j.d;
-        f.out = j.out;
-        const int64_t per = fused_tile_problems(j.op, j.dtype, j.n, j.algo);
-        for (int64_t p = 0; p < j.batch; p += per) {
-            ht[k].job = i;
-            ht[k].count = (int)std::min<int64_t>(per, j.batch - p);
-            ht[k].first = p;
-            ++k;
-        }
-    }
-    hdr->next_tile = 0;
-    hdr->ntiles = (int)ntiles;
-    hipError_t e = hipMemcpyAsync(s.d_hdr, hdr, sizeof(FusedHeader), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(s.d_jobs, hj, sizeof(FusedJob) * njobs, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(s.d_tiles, ht, sizeof(FusedTile) * ntiles, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipGraphLaunch(s.exec, stream);
+    int64_t ntiles = 0;
+    const int mask = mix_build_tables(jobs, njobs, s.h_stage, &ntiles);
+    if (mask < 0) return mask;
+    m->next = (m->next + 1) % kSlots;
+    hipGraphExec_t exec = nullptr;
+    if (int rc = slot_graph(m, s, mask, &exec)) return rc;
+    hipError_t e = hipMemcpyAsync(s.d_tables, s.h_stage, kMixHeaderBytes + (size_t)njobs * sizeof(MixJob),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, stream);
     if (e == hipSuccess) e = hipEventRecord(s.done, stream);
     if (e == hipSuccess && done_event) e = hipEventRecord(done_event, stream);
     s.used = true;
@@ -315,6 +370,11 @@ extern "C" int launch_mixed(const ppx_job *jobs, int njobs, void *stream) {
     return ppx::launch_mixed_impl(jobs, njobs, static_cast<hipStream_t>(stream), nullptr);
 }
 
-extern "C" int ppx_mixed_tile_problems(int op, int dtype, int64_t n, int algo) {
-    return (int)ppx::fused_tile_problems(op, dtype, n, algo);
+extern "C" int ppx_mixed_tile_config(const ppx_job *job, ppx_config *cfg) {
+    ppx::fail(PPX_OK, "");
+    if (!job) return ppx::fail(PPX_EINVAL, "null job");
+    ppx::MixPlan m;
+    if (int rc = ppx::check_job(*job, &m)) return rc;
+    if (cfg) *cfg = m.cfg;
+    return m.per_tile;
 }

@@ -1,0 +1,180 @@
+// Mixed batched launch: the device-side tables and the kernel families.
+//
+// A mixed launch takes jobs of different operations, sizes and batch counts.
+// Each job's problems are cut into tiles; a tile is what one workgroup of
+// the job's kernel family processes at once, and its shape is the tuned
+// single-call configuration of the job (the tune cache's entry for (op,
+// dtype, n), else the analytical model's choice): the same radix, values per
+// thread and exchange algorithm, with the problems per workgroup scaled from
+// the tuned block size to the family's.  Those are the quantities a
+// problem's arithmetic depends on, so every job computes the same values as
+// the single call with that configuration.
+//
+// Families group the tile shapes by block size and register demand, because
+// a kernel's VGPR count and LDS size are the maxima over the code it
+// contains and set its occupancy for every tile it runs:
+//   FFT, T = n/P <= 256 threads per problem: 256-thread workgroups;
+//   FFT, T > 256: 1024-thread workgroups;
+//   scan, likewise by T;
+//   tridiagonal inside a wave (n/P <= 64), float32 / float64, each in a
+//   light and a heavy register tier (mix_triw_family);
+//   tridiagonal through LDS (CR and PCR of larger systems).
+// One persistent kernel per family pulls tile indices from the family's
+// counter until its tiles are drained.  A launch runs, in one stream, the
+// table expansion and then the kernels of the families that have tiles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ppx_internal.h"
+
+namespace ppx {
+
+enum MixFamily : int {
+    kFamFft256 = 0,
+    kFamFft1024,
+    kFamScan256,
+    kFamScan1024,
+    kFamTriW32,    // in-wave, float32: CR, WM, LF with P <= 8
+    kFamTriW32H,   // in-wave, float32: P = 16, and the PCR variants
+    kFamTriW64,    // in-wave, float64, P <= 8
+    kFamTriW64H,   // in-wave, float64, P = 16
+    kFamTriLds,    // LDS CR / PCR, float32 and float64
+    kMixFamilies
+};
+
+// One job as the kernels see it (72 bytes).
+struct MixJob {
+    int shape;            // family-specific code of the tile's kernel instantiation
+    int flags;            // FFT: 1 = inverse; scan: 1 = exclusive
+    int log2n;
+    int per_tile;         // problems per tile
+    long long batch;
+    unsigned first_tile;  // index of the job's first tile in its family's list
+    int family;
+    const void *p[4];     // FFT / scan input; tridiagonal a, b, c, d
+    void *out;            // FFT / scan output; tridiagonal x
+};
+static_assert(sizeof(MixJob) == 72, "job record layout");
+
+// Header of a launch's tables; the jobs follow at byte kMixHeaderBytes, the
+// tile lists (one 32-bit job index per tile, family after family) at
+// tiles_off.
+struct MixHeader {
+    unsigned next[kMixFamilies];      // tile counters (0 at launch)
+    unsigned ntiles[kMixFamilies];    // tiles per family
+    unsigned tile_base[kMixFamilies]; // first entry of each family's list
+    unsigned njobs;
+    unsigned tiles_off;               // byte offset of the tile lists
+};
+constexpr int kMixHeaderBytes = 256;
+static_assert(sizeof(MixHeader) <= kMixHeaderBytes, "header layout");
+
+constexpr int kMixMaxJobs = 1 << 14;
+constexpr int kMixMaxTiles = 1 << 20;
+
+// Bytes of the tables of a launch with njobs jobs and ntiles tiles.
+constexpr int64_t mix_table_bytes(int64_t njobs, int64_t ntiles) {
+    return kMixHeaderBytes + njobs * (int64_t)sizeof(MixJob) + ntiles * 4;
+}
+
+// ---- shape codes
+// FFT (radix = P in {4, 8, 16}): ((log2n * 3 + pidx) * 2 + split).
+constexpr int fft_pidx(int P) { return P == 4 ? 0 : P == 8 ? 1 : 2; }
+constexpr int mix_fft_shape(int log2n, int P, bool split) { return (log2n * 3 + fft_pidx(P)) * 2 + (split ? 1 : 0); }
+constexpr int kMixFftShapes = (kFftLog2NMax + 1) * 6;
+// Scan: ((dtype * 5 + log2(P) - 1) * 2 + lf) with dtype PPX_I32/F32/F64.
+constexpr int mix_scan_shape(int dtype, int lp, bool lf) { return (dtype * 5 + lp - 1) * 2 + (lf ? 1 : 0); }
+constexpr int kMixScanShapes = 3 * 5 * 2;
+// In-wave tridiagonal: (variant - PPX_TRI_CR_SHFL) * 4 + log2(P) - 1.
+constexpr int mix_triw_shape(int base, int lp) { return (base - PPX_TRI_CR_SHFL) * 4 + lp - 1; }
+constexpr int kMixTriwShapes = 5 * 4;
+// Family of an in-wave tridiagonal shape (variant without the persistent
+// flag, P).
+constexpr int mix_triw_family(bool f64, int algo, int P) {
+    return f64 ? (P == 16 ? kFamTriW64H : kFamTriW64)
+               : (P == 16 || algo == PPX_TRI_PCR_SHFL || algo == PPX_TRI_PCR_REG ? kFamTriW32H : kFamTriW32);
+}
+// LDS tridiagonal: dtype_is_f64 * 2 + (algo == PPX_TRI_PCR).
+constexpr int mix_tril_shape(bool f64, bool pcr) { return (f64 ? 2 : 0) + (pcr ? 1 : 0); }
+
+// Block size and dynamic LDS bytes of each family's kernel.
+constexpr int mix_block(int fam) {
+    return fam == kFamFft1024 || fam == kFamScan1024 || fam == kFamTriLds ? 1024 : 256;
+}
+constexpr int kMixTriLdsBudget = 128 * 1024;
+int64_t mix_lds_bytes(int fam);
+
+// Kernel of a family (signature mix_kernel_t), from the translation unit
+// that instantiates it.
+typedef void (*mix_kernel_t)(const char *tables, const float2 *tw);
+const void *mix_fft_kernel(int fam);
+const void *mix_scan_kernel(int fam);
+const void *mix_tri_kernel(int fam);
+// Writes every family's tile list from the job records (one launch).
+const void *mix_expand_kernel();
+constexpr int kMixExpandBlocks = 512;
+constexpr int kMixExpandThreads = 256;
+
+// ---- host side (fused.hip)
+// How a job is cut into tiles: its family, the kernel shape code, problems
+// per tile, flags, tile count, and the single-call configuration whose
+// arithmetic the tiles follow (the tuned one with the persistent flag
+// cleared; a radix = P substitute where the tuned FFT shape is not one the
+// families hold).
+struct MixPlan {
+    int family, shape, per_tile, flags;
+    int64_t ntiles;
+    ppx_config cfg;
+};
+// The single-call configuration of a job with cfg == NULL (tridiagonal: the
+// job's family).
+int job_config(const ppx_job &j, ppx_config &c);
+int mix_plan(const ppx_job &j, MixPlan &m);
+// Plans every job and writes the header and job records into buf; returns
+// the mask of families with tiles or a negative error.
+int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_out);
+// Occupancy of every family kernel on the current device (once).
+int mix_prepare_kernels();
+// Expansion plus the family kernels of `mask`, on stream s.
+int mix_enqueue(char *d_tables, int mask, const int64_t *ntiles, const float2 *tw, hipStream_t s);
+
+// ---- the persistent tile loop shared by the families
+// Claims tile indices of family FAM from its counter until they run out and
+// calls body(job, first problem, problem count, tx) for each, tx being the
+// thread's index in the workgroup passed through an empty asm that claims
+// to change it: without it the compiler hoists every address derived from
+// the thread index out of the loop, for every shape a family holds, and
+// keeps them all live (the FFT families then spilled).  The next index is
+// claimed while the current tile is processed.  Every thread of the
+// workgroup runs the same iterations, so all reach every barrier.
+template <int FAM, typename Body>
+__device__ __forceinline__ void mix_tile_loop(const char *tables, Body &&body) {
+    __shared__ unsigned s_tile;
+    const MixHeader *h = reinterpret_cast<const MixHeader *>(tables);
+    const MixJob *jobs = reinterpret_cast<const MixJob *>(tables + kMixHeaderBytes);
+    const unsigned *tiles = reinterpret_cast<const unsigned *>(tables + h->tiles_off) + h->tile_base[FAM];
+    unsigned *ctr = const_cast<unsigned *>(&h->next[FAM]);
+    const unsigned ntiles = h->ntiles[FAM];
+    if (threadIdx.x == 0) s_tile = atomicAdd(ctr, 1u);
+    __syncthreads();
+    unsigned t = __builtin_amdgcn_readfirstlane(s_tile);
+    while (t < ntiles) {
+        unsigned next = 0;
+        if (threadIdx.x == 0) next = atomicAdd(ctr, 1u);
+        const MixJob j = jobs[__builtin_amdgcn_readfirstlane(tiles[t])];
+        const long long first = (long long)(t - j.first_tile) * j.per_tile;
+        const int count = (int)min((long long)j.per_tile, j.batch - first);
+        int tx = threadIdx.x;
+        asm volatile("" : "+v"(tx));
+        body(j, first, count, tx);
+        __syncthreads();  // every thread is done with s_tile and the tile's LDS
+        if (threadIdx.x == 0) s_tile = next;
+        __syncthreads();
+        t = __builtin_amdgcn_readfirstlane(s_tile);
+    }
+}
+
+}  // namespace ppx

@@ -135,8 +135,10 @@ bool fft_tuned_plan(int64_t n, ppx_fft_plan &p);
 void fft_record_plan(int64_t n, const ppx_fft_plan &p);
 
 // ---- mixed launch (fused.hip) ----
-int check_job(const ppx_job &j);
-int64_t fused_tile_problems(int op, int dtype, int64_t n, int algo);
+struct MixPlan;
+// Validates a job for the mixed launch and plans its tiles (plan may be NULL).
+int check_job(const ppx_job &j, MixPlan *plan = nullptr);
+// Tiles of the jobs' mixed launch, or -1 if a job cannot be planned.
 int64_t mixed_tile_count(const ppx_job *jobs, int njobs);
 // launch_mixed with an optional extra event recorded after the launch.
 int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEvent_t done_event);
@@ -147,6 +149,9 @@ void complete_config(int op, int dtype, int64_t n, ppx_config &c);
 int default_config(int op, int dtype, int64_t n, ppx_config &c);
 int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap);
 int analytical_config(int op, int dtype, int64_t n, int64_t batch, ppx_config &c);
+// The configuration of a tridiagonal call restricted to one family (tuned
+// entry of the family, else the analytical choice within it).
+int family_config(int dtype, int64_t n, int64_t batch, int family, ppx_config &c);
 // tune cache (tune.cpp): entry recorded for (op, dtype, n, any algorithm)
 bool cached_config(int op, int dtype, int64_t n, ppx_config &c);
 void store_cached_config(int op, int dtype, int64_t n, const ppx_config &c);

@@ -70,8 +70,9 @@ __device__ __forceinline__ void store_chunk(T *dst, const T (&v)[P]) {
 // there is one barrier, which every thread of the workgroup must reach.
 // EXCL: the exclusive scan (each output the sum of the inputs before it):
 // step 1 is then the thread-serial exclusive scan, the rest is unchanged.
+// tx: the thread's index in the workgroup.
 template <typename T, int P, int ALGO, bool EXCL = false, typename U>
-__device__ __forceinline__ void scan_values(U (&v)[P], int lT, T *wave_tot) {
+__device__ __forceinline__ void scan_values(U (&v)[P], int lT, T *wave_tot, int tx) {
     // 1. serial scan within the thread
     U total;
     if constexpr (EXCL) {
@@ -90,7 +91,7 @@ __device__ __forceinline__ void scan_values(U (&v)[P], int lT, T *wave_tot) {
     }
 
     // 2. lane network over the problem's segment of the wave
-    const int lane = threadIdx.x & (kWave - 1);
+    const int lane = tx & (kWave - 1);
     const int seg = lT >= 6 ? kWave : (1 << lT);
     const U incl = ALGO == PPX_SCAN_LF ? lanes_scan_lf<U>(total, seg, lane)
                                        : lanes_scan_ks<U>(total, seg, lane);
@@ -104,7 +105,7 @@ __device__ __forceinline__ void scan_values(U (&v)[P], int lT, T *wave_tot) {
 
     // 3. earlier waves of the same problem
     if (lT > 6) {
-        const int w = threadIdx.x >> 6;
+        const int w = tx >> 6;
         if (lane == kWave - 1) wave_tot[w] = __builtin_bit_cast(T, incl);
         __syncthreads();
         const int w0 = w & ~((1 << (lT - 6)) - 1);
@@ -122,17 +123,17 @@ using ScanArith = typename std::conditional<std::is_same<T, int>::value, unsigne
 
 // One workgroup's share: problems [p0, p0 + nprob), T = n/P threads per
 // problem (threads of problems beyond nprob compute on zeros and store
-// nothing).  `wave_tot` holds blockDim.x / 64 values.  Used by k_scan and by
-// the fused kernel.
+// nothing).  `wave_tot` holds blockDim.x / 64 values; tx is the thread's
+// index in the workgroup.  Used by k_scan and by the mixed launch's tiles.
 template <typename T, int P, int ALGO, bool EXCL = false>
 __device__ __forceinline__ void scan_block(const T *in, T *out, int log2n, long long p0, int nprob,
-                                           T *wave_tot) {
+                                           T *wave_tot, int tx) {
     constexpr int LP = P == 2 ? 1 : P == 4 ? 2 : P == 8 ? 3 : P == 16 ? 4 : 5;
     using U = ScanArith<T>;
     const int lT = log2n - LP;  // log2 threads per problem
-    const int lp = threadIdx.x >> lT;
+    const int lp = tx >> lT;
     const bool active = lp < nprob;
-    const long long off = p0 * (1LL << log2n) + (long long)threadIdx.x * P;
+    const long long off = p0 * (1LL << log2n) + (long long)tx * P;
 
     U v[P];
     if (active) {
@@ -141,7 +142,7 @@ __device__ __forceinline__ void scan_block(const T *in, T *out, int log2n, long 
 #pragma unroll
         for (int j = 0; j < P; ++j) v[j] = U(0);
     }
-    scan_values<T, P, ALGO, EXCL>(v, lT, wave_tot);
+    scan_values<T, P, ALGO, EXCL>(v, lT, wave_tot, tx);
     if (active) store_chunk<U, P>(reinterpret_cast<U *>(out) + off, v);
 }
 
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(1024) void k_scan(const T *in, T *out, int log2n, l
                                                int gb) {
     __shared__ T wave_tot[kMaxThreadsPerBlock / kWave];
     const long long p0 = (long long)blockIdx.x * gb;
-    scan_block<T, P, ALGO, EXCL>(in, out, log2n, p0, (int)min((long long)gb, batch - p0), wave_tot);
+    scan_block<T, P, ALGO, EXCL>(in, out, log2n, p0, (int)min((long long)gb, batch - p0), wave_tot, threadIdx.x);
 }
 
 // Persistent variant: a grid of resident workgroups (at most one per group)
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(1024) void k_scan_pipe(const T *in, T *out, int log
     auto iteration = [&](long long grp, int parity, U (&cur)[P], U (&nxt)[P]) {
         buf_load<U, P>(nxt, group_rsrc(in, grp + G, gb, n, sizeof(T), batch), voff);
         __builtin_amdgcn_sched_barrier(0);
-        scan_values<T, P, ALGO, EXCL>(cur, lT, wave_tot[parity]);
+        scan_values<T, P, ALGO, EXCL>(cur, lT, wave_tot[parity], threadIdx.x);
         buf_store<U, P>(cur, group_rsrc(out, grp, gb, n, sizeof(T), batch), voff);
     };
     long long g = blockIdx.x;  // < ngroups: the grid never exceeds the groups

@@ -14,10 +14,14 @@
 
 #include "../../include/ppx_serve.h"
 #include "../../include/ppx_tune.h"
-#include "ppx_internal.h"
+#include "mixed.h"
 
 namespace ppx {
 namespace {
+
+// Admission caps of one mixed launch.
+constexpr int64_t kMixLaunchTiles = kMixMaxTiles;
+constexpr int kMixLaunchJobs = kMixMaxJobs;
 
 int64_t elem_bytes(int dtype) { return dtype == PPX_C64 || dtype == PPX_F64 ? 8 : 4; }
 
@@ -145,16 +149,10 @@ int launch_single(const ppx_job &j, hipStream_t st, const ppx_config *cfg) {
         case PPX_OP_FFT: return fft_batched(j.in, j.out, j.n, j.batch, j.direction, nullptr, st);
         case PPX_OP_SCAN: return scan_batched(j.in, j.out, j.n, j.batch, j.dtype, nullptr, st);
         default: {
+            // the job's family: its tuned entry, else the analytical choice
+            // within it (the configuration the mixed launch's tiles follow)
             ppx_config c{};
-            if (ppx_resolve_config(PPX_OP_TRIDIAG, j.dtype, j.n, j.batch, &c) != PPX_OK) return PPX_EINVAL;
-            if (tri_family(c.algo) != tri_family(j.algo)) {
-                // the tuned entry of the requested algorithm, else the plain default
-                if (ppx_tuned_config(PPX_OP_TRIDIAG, j.dtype, j.n, j.algo, &c) != PPX_OK) {
-                    if (default_config(PPX_OP_TRIDIAG, j.dtype, j.n, c) != PPX_OK) return PPX_EINVAL;
-                    c.algo = j.algo;
-                    c.lds_elems = 0;
-                }
-            }
+            if (int rc = job_config(j, c)) return rc;
             return tridiag_batched(j.in, j.b, j.c, j.d, j.out, j.n, j.batch, j.dtype, &c, st);
         }
     }
@@ -199,7 +197,7 @@ std::vector<int64_t> admit(ppx_server *s, int64_t tile_cap, int job_cap) {
     while (!s->pending.empty() && (int)out.size() < job_cap) {
         Job &j = s->jobs[s->pending.front()];
         if (s->used + j.footprint > s->budget) break;
-        const int64_t jt = mixed_tile_count(&j.job, 1);
+        const int64_t jt = mixed_tile_count(&j.job, 1);  // planned at submit: >= 1
         if (!out.empty() && tiles + jt > tile_cap) break;
         if (!j.job.out) {
             const int64_t off = s->arena.alloc(job_out_bytes(j.job));
@@ -234,51 +232,90 @@ int online_session(ppx_server *s, const ppx_job &j, ppx_online **out) {
     return PPX_OK;
 }
 
+// Undoes the admission of jobs whose launch failed: they go back to the
+// front of the queue in their order, their budget and arena space are
+// returned, and so are the launch's events.
+void unadmit(ppx_server *s, const std::vector<int64_t> &ids, Launch &l) {
+    for (auto it = ids.rbegin(); it != ids.rend(); ++it) {
+        Job &j = s->jobs[*it];
+        s->used -= j.footprint;
+        if (j.arena_off >= 0) {
+            s->arena.release(j.arena_off, job_out_bytes(j.job));
+            j.arena_off = -1;
+            j.job.out = nullptr;
+        }
+        j.admit_us = 0;
+        s->pending.push_front(*it);
+        --s->admitted;
+    }
+    if (l.start) (void)hipEventDestroy(l.start);
+    if (l.session) {  // a timed evaluation: its events were its own
+        if (l.done) (void)hipEventDestroy(l.done);
+        (void)ppx_online_report(l.session, -1.0);  // the candidate counts as failed
+        --s->online_evals;
+    } else if (l.done) {
+        s->free_events.push_back(l.done);
+    }
+    l.done = l.start = nullptr;
+    l.session = nullptr;
+}
+
+// Launches the admitted jobs `ids` as l (one job alone in the per-request
+// mode, as a candidate of its online session when that mode tunes online; a
+// mixed launch otherwise).  On failure nothing of l is in flight.
+int launch_admitted(ppx_server *s, const std::vector<int64_t> &ids, Launch &l) {
+    l.done = take_event(s);
+    if (!l.done) return fail(PPX_EHIP, "event creation failed");
+    hipStream_t st = s->streams[l.stream];
+    const bool single = s->per_request();
+    int rc;
+    if (single && s->online()) {
+        const ppx_job &j = s->jobs[ids[0]].job;
+        ppx_online *sess = nullptr;
+        if ((rc = online_session(s, j, &sess))) return rc;
+        const double elems = double(j.n) * double(j.batch);
+        ppx_config cfg{};
+        const int r = ppx_online_next(sess, elems >= kOnlineMinElems, &cfg);
+        if (r < 0) return r;
+        if (r == 1) {  // time this launch: swap in events that record time
+            s->free_events.push_back(l.done);
+            l.done = nullptr;
+            l.session = sess;  // from here on a failure reports the candidate as failed
+            l.elems = elems;
+            ++s->online_evals;
+            if (hipEventCreate(&l.start) != hipSuccess || hipEventCreate(&l.done) != hipSuccess)
+                return fail(PPX_EHIP, "event creation failed");
+            if ((rc = fail_hip(hipEventRecord(l.start, st), "event record"))) return rc;
+        }
+        rc = launch_single(j, st, &cfg);
+        if (rc == PPX_OK) rc = fail_hip(hipEventRecord(l.done, st), "event record");
+    } else if (single) {
+        rc = launch_single(s->jobs[ids[0]].job, st, nullptr);
+        if (rc == PPX_OK) rc = fail_hip(hipEventRecord(l.done, st), "event record");
+    } else {
+        std::vector<ppx_job> batch;
+        batch.reserve(ids.size());
+        for (int64_t id : ids) batch.push_back(s->jobs[id].job);
+        rc = launch_mixed_impl(batch.data(), (int)batch.size(), st, l.done);
+    }
+    return rc;
+}
+
 int progress(ppx_server *s, int *launched) {
     if (launched) *launched = 0;
     retire(s);
     while ((int)s->inflight.size() < s->max_inflight && !s->pending.empty()) {
         const bool single = s->per_request();
-        std::vector<int64_t> ids = admit(s, int64_t(1) << 18, single ? 1 : (1 << 14));
+        std::vector<int64_t> ids = admit(s, kMixLaunchTiles, single ? 1 : kMixLaunchJobs);
         if (ids.empty()) break;
         Launch l;
         l.ids = ids;
         l.stream = s->rr++ % (int)std::max<size_t>(1, s->streams.size());
         if (!s->null_device()) {
-            l.done = take_event(s);
-            if (!l.done) return fail(PPX_EHIP, "event creation failed");
-            hipStream_t st = s->streams[l.stream];
-            int rc;
-            if (single && s->online()) {
-                const ppx_job &j = s->jobs[ids[0]].job;
-                ppx_online *sess = nullptr;
-                if ((rc = online_session(s, j, &sess))) return rc;
-                const double elems = double(j.n) * double(j.batch);
-                ppx_config cfg{};
-                const int r = ppx_online_next(sess, elems >= kOnlineMinElems, &cfg);
-                if (r < 0) return r;
-                if (r == 1) {  // time this launch: swap in events that record time
-                    s->free_events.push_back(l.done);
-                    l.done = nullptr;
-                    if (hipEventCreate(&l.start) != hipSuccess || hipEventCreate(&l.done) != hipSuccess)
-                        return fail(PPX_EHIP, "event creation failed");
-                    l.session = sess;
-                    l.elems = elems;
-                    ++s->online_evals;
-                    if ((rc = fail_hip(hipEventRecord(l.start, st), "event record"))) return rc;
-                }
-                rc = launch_single(j, st, &cfg);
-                if (rc == PPX_OK) rc = fail_hip(hipEventRecord(l.done, st), "event record");
-            } else if (single) {
-                rc = launch_single(s->jobs[ids[0]].job, st, nullptr);
-                if (rc == PPX_OK) rc = fail_hip(hipEventRecord(l.done, st), "event record");
-            } else {
-                std::vector<ppx_job> batch;
-                batch.reserve(ids.size());
-                for (int64_t id : ids) batch.push_back(s->jobs[id].job);
-                rc = launch_mixed_impl(batch.data(), (int)batch.size(), st, l.done);
+            if (int rc = launch_admitted(s, ids, l)) {
+                unadmit(s, ids, l);
+                return rc;
             }
-            if (rc != PPX_OK) return rc;
         }
         s->inflight.push_back(l);
         ++s->launches;

@@ -550,10 +550,11 @@ __device__ __forceinline__ void wave_lf(T (&a)[P], T (&c)[P], T (&d)[P], int t, 
 }
 
 // Boundary zeros, unit-diagonal scaling and the solve of the equations a
-// lane holds (b is consumed; x ends in d).
+// lane holds (b is consumed; x ends in d).  tx: the thread's index in the
+// workgroup (it selects the wave's LDS exchange buffer).
 template <typename T, int ALGO, int P>
 __device__ __forceinline__ void tridiag_wave_solve(T (&a)[P], const T (&b)[P], T (&c)[P], T (&d)[P], int t,
-                                                   int lps, T *smem) {
+                                                   int lps, T *smem, int tx) {
     if (t == 0) a[0] = T(0);            // multiplies the absent x_{-1}
     if (t == lps - 1) c[P - 1] = T(0);  // multiplies the absent x_n
 #pragma unroll
@@ -567,19 +568,20 @@ __device__ __forceinline__ void tridiag_wave_solve(T (&a)[P], const T (&b)[P], T
     else if constexpr (ALGO == PPX_TRI_PCR_SHFL) wave_pcr<T, P>(a, c, d, lps);
     else if constexpr (ALGO == PPX_TRI_WM) wave_wm<T, P>(a, c, d, t, lps);
     else if constexpr (ALGO == PPX_TRI_LF) wave_lf<T, P>(a, c, d, t, lps);
-    else wave_pcr_reg<T, P>(a, c, d, t, lps, smem + (threadIdx.x >> 6) * (3 * 64 * (P < 4 ? P : 4)));
+    else wave_pcr_reg<T, P>(a, c, d, t, lps, smem + (tx >> 6) * (3 * 64 * (P < 4 ? P : 4)));
 }
 
 // One workgroup's share: systems [first, first + nsys) of size n = P * lps,
 // lps = n / P <= 64 lanes each; every lane owns P equations.  Lanes of
-// systems beyond nsys solve identity rows and store nothing.
+// systems beyond nsys solve identity rows and store nothing.  tx: the
+// thread's index in the workgroup.
 template <typename T, int ALGO, int P>
 __device__ __forceinline__ void tridiag_wave_block(const T *A, const T *B, const T *C, const T *D,
-                                                   T *X, int log2n, long long first, int nsys, T *smem) {
+                                                   T *X, int log2n, long long first, int nsys, T *smem, int tx) {
     const int n = 1 << log2n;
     const int lps = n / P;
-    const int sys_local = threadIdx.x / lps;
-    const int t = threadIdx.x % lps;
+    const int sys_local = tx / lps;
+    const int t = tx % lps;
     const bool active = sys_local < nsys;
     const long long base = (first + sys_local) * n + (long long)t * P;
     T a[P], b[P], c[P], d[P];
@@ -595,7 +597,7 @@ __device__ __forceinline__ void tridiag_wave_block(const T *A, const T *B, const
             b[j] = T(1);
         }
     }
-    tridiag_wave_solve<T, ALGO, P>(a, b, c, d, t, lps, smem);
+    tridiag_wave_solve<T, ALGO, P>(a, b, c, d, t, lps, smem, tx);
     if (active) wave_store<T, P>(X + base, d);
 }
 
@@ -615,7 +617,7 @@ __global__ __launch_bounds__(256, (tri_wave_min_waves<T, ALGO, P>())) void k_tri
     extern __shared__ float4 smem_raw[];  // PPX_TRI_PCR_REG: 3 * 64 * min(P, 4) values per wave
     const long long first = (long long)blockIdx.x * gb;
     const int nsys = (int)min((long long)gb, batch - first);
-    tridiag_wave_block<T, ALGO, P>(a, b, c, d, x, log2n, first, nsys, reinterpret_cast<T *>(smem_raw));
+    tridiag_wave_block<T, ALGO, P>(a, b, c, d, x, log2n, first, nsys, reinterpret_cast<T *>(smem_raw), threadIdx.x);
 }
 
 // Persistent variant (algo | PPX_TRI_PIPE): a grid of resident workgroups
@@ -654,7 +656,7 @@ __global__ __launch_bounds__(256) void k_tridiag_wave_pipe(const T *A, const T *
                          T (&nc)[P], T (&nd)[P]) {
         load(grp + G, na, nb, nc, nd);
         __builtin_amdgcn_sched_barrier(0);
-        tridiag_wave_solve<T, ALGO, P>(a, b, c, d, t, lps, smem);
+        tridiag_wave_solve<T, ALGO, P>(a, b, c, d, t, lps, smem, threadIdx.x);
         buf_store<T, P>(d, group_rsrc(X, grp, gb, n, es, batch), voff);
     };
     long long g = blockIdx.x;  // < ngroups: the grid never exceeds the groups

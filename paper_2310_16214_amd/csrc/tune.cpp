@@ -879,6 +879,46 @@ static int tune_candidates(int op, int dtype, int64_t n, int algo, std::vector<p
     return PPX_OK;
 }
 
+// The configuration a call with cfg == NULL uses, restricted to one
+// tridiagonal family (CR, PCR, WM or LF): the tune cache's entry recorded for
+// that family, else the entry for every algorithm if it belongs to the family,
+// else the analytical model's choice among the family's configurations.
+int family_config(int dtype, int64_t n, int64_t batch, int family, ppx_config &c) {
+    family = tri_family(family);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.find({PPX_OP_TRIDIAG, dtype, n, family});
+        if (it != g_cache.end()) {
+            c = it->second.cfg;
+            return PPX_OK;
+        }
+        auto jt = g_cache.find({PPX_OP_TRIDIAG, dtype, n, -1});
+        if (jt != g_cache.end() && tri_family(jt->second.cfg.algo) == family) {
+            c = jt->second.cfg;
+            return PPX_OK;
+        }
+    }
+    static std::mutex memo_mu;
+    static std::map<std::tuple<int, int64_t, int64_t, int, bool>, ppx_config> memo;
+    const bool have_device = device_info() != nullptr;
+    const auto key = std::make_tuple(dtype, n, batch, family, have_device);
+    {
+        std::lock_guard<std::mutex> lk(memo_mu);
+        auto it = memo.find(key);
+        if (it != memo.end()) {
+            c = it->second;
+            return PPX_OK;
+        }
+    }
+    std::vector<ppx_config> cands;
+    if (int rc = tune_candidates(PPX_OP_TRIDIAG, dtype, n, family, cands)) return rc;
+    if (int rc = analytical_select(PPX_OP_TRIDIAG, dtype, n, batch, cands, have_device, c)) return rc;
+    std::lock_guard<std::mutex> lk(memo_mu);
+    memo[key] = c;
+    fail(PPX_OK, "");
+    return PPX_OK;
+}
+
 static int tune_impl(int op, int dtype, int64_t n, int64_t batch, int method, int max_evals,
                      int algo, int reps, ppx_tune_report *rep) {
     if (!rep) return fail(PPX_EINVAL, "null report");

@@ -562,11 +562,17 @@ def launch_mixed(jobs, stream=None):
     _check(f(arr, len(jobs), stream))
 
 
-def mixed_tile_problems(op, dtype, n, algo=0):
-    f = lib().ppx_mixed_tile_problems
-    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
-    f.restype = ctypes.c_int
-    return f(op, dtype, n, algo)
+def mixed_tile_config(job):
+    """How launch_mixed cuts a Job: (problems per tile, Config whose
+    arithmetic the tiles follow)."""
+    f = lib().ppx_mixed_tile_config
+    if not getattr(f, "_ppx_typed", False):
+        f.argtypes = [ctypes.POINTER(Job), ctypes.POINTER(Config)]
+        f.restype = ctypes.c_int
+        f._ppx_typed = True
+    c = Config()
+    per = _check(f(ctypes.byref(job), ctypes.byref(c)))
+    return per, c
 
 
 # ---------------------------------------------------------------- serving

@@ -1,0 +1,93 @@
+"""CPU tests of the mixed launch's tile planning (no GPU: configurations come
+from the shipped tune cache, or the analytical model's static resource table).
+
+Each job's tiles must follow the configuration its single call uses with a
+NULL config (the tuned shape, persistent flag cleared), with the problems per
+tile scaled from the tuned block size to the family's, and a valid
+single-call configuration reported for it."""
+import os
+
+import pytest
+
+from paper_2310_16214_amd import ppx
+
+CACHE = os.path.join(os.path.dirname(ppx.__file__), "tuned", "mi355x.txt")
+PIPE = {ppx.OP_FFT: 2, ppx.OP_SCAN: 2, ppx.OP_TRIDIAG: 8}
+
+
+@pytest.fixture(scope="module")
+def tuned():
+    ppx.clear_tune_cache()
+    ppx.load_tune_cache(CACHE)
+    yield
+    ppx.clear_tune_cache()
+
+
+def _job(op, dtype, n, batch, algo=0, direction=-1):
+    p = 1 << 12  # 16-byte aligned placeholders: planning never touches memory
+    return ppx.make_job(op, dtype, n, batch, p, p, direction=direction, algo=algo, b=p, c=p, d=p)
+
+
+def _cases():
+    out = []
+    for k in range(4, 15):
+        out.append((ppx.OP_FFT, ppx.C64, 1 << k, 0))
+        out.append((ppx.OP_SCAN, ppx.F32, 1 << k, ppx.JOB_SCAN_INCLUSIVE))
+        out.append((ppx.OP_SCAN, ppx.I32, 1 << k, ppx.JOB_SCAN_EXCLUSIVE))
+        out.append((ppx.OP_SCAN, ppx.F64, 1 << k, ppx.JOB_SCAN_INCLUSIVE))
+    for k in range(5, 11):
+        for fam in (ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_WM, ppx.TRI_LF):
+            out.append((ppx.OP_TRIDIAG, ppx.F32, 1 << k, fam))
+            out.append((ppx.OP_TRIDIAG, ppx.F64, 1 << k, fam))
+    return out
+
+
+@pytest.mark.parametrize("op,dtype,n,algo", _cases())
+def test_tiles_follow_the_tuned_configuration(tuned, op, dtype, n, algo):
+    batch = max(1, (1 << 22) // n)
+    per, cfg = ppx.mixed_tile_config(_job(op, dtype, n, batch, algo))
+    if op == ppx.OP_TRIDIAG:
+        ref = ppx.tuned_config(op, dtype, n, algo)
+    else:
+        ref = ppx.resolve_config(op, ppx.C64 if op == ppx.OP_FFT else dtype, n, batch)
+    want = ref.as_tuple()[:5] + (ref.algo & ~PIPE[op],)
+    assert cfg.as_tuple() == want, (cfg, ref)
+    assert ppx.config_valid(op, ppx.C64 if op == ppx.OP_FFT else dtype, n, cfg)
+    # problems per tile: the tuned workgroup's share scaled to the family's
+    # block (256 or 1024 threads)
+    T = n // cfg.elems_per_thread
+    block = 256 if T <= 256 else 1024
+    assert per == block // T
+
+
+def test_untuned_fft_shape_gets_a_radix_equal_p_substitute(tmp_path):
+    # a radix-2 plain configuration recorded as the tuned one: not a shape
+    # the FFT families hold
+    plain = ppx.default_config(ppx.OP_FFT, ppx.C64, 1024)
+    path = tmp_path / "cache.txt"
+    path.write_text("# arch op dtype n algo_filter radix P L G_b S algo us method\n"
+                    "gfx950 %d %d 1024 -1 %d %d %d %d %d %d 100.0 0\n"
+                    % ((ppx.OP_FFT, ppx.C64) + plain.as_tuple()))
+    ppx.clear_tune_cache()
+    try:
+        ppx.load_tune_cache(str(path))
+        assert ppx.resolve_config(ppx.OP_FFT, ppx.C64, 1024, 100).as_tuple() == plain.as_tuple()
+        per, cfg = ppx.mixed_tile_config(_job(ppx.OP_FFT, ppx.C64, 1024, 100))
+        assert cfg.radix == cfg.elems_per_thread and cfg.radix in (8, 16)
+        assert ppx.config_valid(ppx.OP_FFT, ppx.C64, 1024, cfg)
+        assert per == 256 // (1024 // cfg.elems_per_thread)
+    finally:
+        ppx.clear_tune_cache()
+
+
+def test_job_errors():
+    p = 1 << 12
+    bad = [ppx.make_job(ppx.OP_FFT, ppx.F32, 64, 1, p, p),  # FFT needs c64
+           ppx.make_job(ppx.OP_SCAN, ppx.F32, 64, 1, p, p, algo=3),
+           ppx.make_job(ppx.OP_TRIDIAG, ppx.F32, 64, 1, p, p, algo=ppx.TRI_CR_SHFL, b=p, c=p, d=p),
+           ppx.make_job(ppx.OP_TRIDIAG, ppx.F64, 8192, 1, p, p, algo=ppx.TRI_CR, b=p, c=p, d=p),
+           ppx.make_job(ppx.OP_SCAN, ppx.F32, 100, 1, p, p),
+           ppx.make_job(ppx.OP_SCAN, ppx.F32, 64, 1, p + 8, p)]
+    for j in bad:
+        with pytest.raises(ppx.PpxError):
+            ppx.mixed_tile_config(j)
