@@ -319,6 +319,27 @@ typedef struct ppx_job {
 int launch_mixed(const ppx_job *jobs, int njobs, void *stream);
 
 /*
+ * launch_mixed_noalloc -- launch_mixed for callers that cannot allocate
+ * device or pinned memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same jobs, tiles, kernels and results
+ * as launch_mixed (bit-identical outputs); the launch tables live in a
+ * static device array of about 1 MiB that the library holds on each device
+ * until the process ends.  At most PPX_NOALLOC_MAX_JOBS jobs and
+ * PPX_NOALLOC_MAX_TILES tiles per call (PPX_EINVAL beyond; the tile count of
+ * a job is its batch over ppx_mixed_tile_config's problems per tile).  The
+ * caller passes the inputs and outputs.  The first call on a device sets it
+ * up (device state, occupancy queries, the array's address) without
+ * allocating; later calls only plan on the host and enqueue: a few table
+ * copy kernels, the tile-list expansion and the family kernels, on `stream`.
+ * Every call on a device shares that device's array, so calls whose work
+ * overlaps on one device (different streams, or host threads) race and must
+ * be ordered by the caller.  Asynchronous and stream-ordered.
+ */
+#define PPX_NOALLOC_MAX_JOBS 256
+#define PPX_NOALLOC_MAX_TILES 262144
+int launch_mixed_noalloc(const ppx_job *jobs, int njobs, void *stream);
+
+/*
  * ppx_mixed_tile_config -- how launch_mixed cuts *job: returns the problems
  * per tile (> 0) or a negative PPX_E* code, and writes to *cfg (if not
  * NULL) the single-call configuration whose arithmetic the tiles follow:

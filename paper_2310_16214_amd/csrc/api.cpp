@@ -27,8 +27,20 @@ int fail_hip(hipError_t e, const char *what) {
 }
 
 // ------------------------------------------------------------ device state
+// The FFT twiddle tables live in static device arrays, filled once per device
+// when it is first used: setting a device up allocates no device memory.
+// w[m] = exp(-2 pi i m / 2^14); the large-N tables w_{2^23}^j (j < 1024) and
+// w_{2^13}^j (j < 1024) followed by w_8^j (j < 8).
+static __device__ float2 g_tw_small[1 << kFftLog2NMax];
+static __device__ float2 g_tw_large_lo[1024];
+static __device__ float2 g_tw_large_hi[1024 + 8];
+
 namespace {
 std::mutex g_dev_mu;
+// host images of the tables (filled under g_dev_mu)
+float g_tw_host[2 << kFftLog2NMax];
+float g_tw_lo_host[2 * 1024];
+float g_tw_hi_host[2 * (1024 + 8)];
 std::vector<DeviceInfo *> g_devices;  // indexed by device ordinal; never freed
 bool g_any_device = false;
 int64_t g_lds_limit = kStaticLdsPerBlock;
@@ -77,29 +89,23 @@ const DeviceInfo *device_info() {
     di->clock_khz = prop.clockRate;
     di->l2_bytes = prop.l2CacheSize;
     di->arch = prop.gcnArchName;
-    // Twiddle table for the largest supported FFT; every smaller size
-    // indexes it with a stride.
-    std::vector<float> tw(2 * (size_t(1) << kFftLog2NMax));
-    fft_host_twiddles(tw.data());
-    void *dtw = nullptr;
-    if (hipMalloc(&dtw, tw.size() * sizeof(float)) != hipSuccess ||
-        hipMemcpy(dtw, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-        fail(PPX_ENOMEM, "could not create the FFT twiddle table");
+    // Twiddle tables: the largest supported FFT's (every smaller size indexes
+    // it with a stride) and the large-N tables, copied into this device's
+    // static arrays.
+    fft_host_twiddles(g_tw_host);
+    fft_large_host_twiddles(g_tw_lo_host, g_tw_hi_host);
+    void *dtw = nullptr, *dlo = nullptr, *dhi = nullptr;
+    if (hipGetSymbolAddress(&dtw, HIP_SYMBOL(g_tw_small)) != hipSuccess ||
+        hipGetSymbolAddress(&dlo, HIP_SYMBOL(g_tw_large_lo)) != hipSuccess ||
+        hipGetSymbolAddress(&dhi, HIP_SYMBOL(g_tw_large_hi)) != hipSuccess ||
+        hipMemcpy(dtw, g_tw_host, sizeof g_tw_host, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dlo, g_tw_lo_host, sizeof g_tw_lo_host, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dhi, g_tw_hi_host, sizeof g_tw_hi_host, hipMemcpyHostToDevice) != hipSuccess) {
+        fail(PPX_EDEVICE, "could not set up the FFT twiddle tables");
         delete di;
         return nullptr;
     }
     di->twiddles = dtw;
-    std::vector<float> lo(2 * 1024), hi(2 * (1024 + 8));
-    fft_large_host_twiddles(lo.data(), hi.data());
-    void *dlo = nullptr, *dhi = nullptr;
-    if (hipMalloc(&dlo, lo.size() * sizeof(float)) != hipSuccess ||
-        hipMalloc(&dhi, hi.size() * sizeof(float)) != hipSuccess ||
-        hipMemcpy(dlo, lo.data(), lo.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(dhi, hi.data(), hi.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-        fail(PPX_ENOMEM, "could not create the large-FFT twiddle tables");
-        delete di;
-        return nullptr;
-    }
     di->twiddles_large_lo = dlo;
     di->twiddles_large_hi = dhi;
     if ((int)g_devices.size() <= dev) g_devices.resize(dev + 1, nullptr);

@@ -363,7 +363,92 @@ int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEve
     return fail_hip(e, "mixed launch");
 }
 
+// ------------------------------------------------ the allocation-free launch
+// The same launch for callers that cannot allocate (code under graph capture,
+// tight serving loops): its tables live in `scratch`, a file-scope device
+// array holding at most kNoAllocJobs jobs and kNoAllocTiles tiles, whose
+// address on each device is taken once at set-up (hipGetSymbolAddress; in
+// host code the array's name is not a device address).  The table reaches the
+// device through the kernel arguments of a few copy launches (the runtime
+// copies kernel arguments when a launch is enqueued), so no host buffer
+// outlives the call and no copy is issued from host memory; the tile
+// counters are part of that table and start at zero with it.  Every call on
+// a device shares its array: calls that overlap on one device race.
+constexpr int kNoAllocJobs = PPX_NOALLOC_MAX_JOBS;
+constexpr int kNoAllocTiles = PPX_NOALLOC_MAX_TILES;
+constexpr int64_t kNoAllocBytes = mix_table_bytes(kNoAllocJobs, kNoAllocTiles) + 16;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kTableChunk = 2048;  // table bytes per copy launch
+struct TableChunk {
+    unsigned offset, bytes;
+    unsigned char data[kTableChunk];
+};
+
+__global__ __launch_bounds__(256) void k_mix_table_copy(char *tables, TableChunk c) {
+    for (unsigned i = threadIdx.x; i < c.bytes; i += blockDim.x) tables[c.offset + i] = (char)c.data[i];
+}
+
+namespace {
+std::mutex g_noalloc_mu;
+std::vector<char *> g_scratch;  // per device ordinal: the array's device address
+}  // namespace
+
+// Set-up of the current device for the allocation-free launch: the device
+// state and twiddle tables (static arrays), the family kernels' occupancy,
+// and the address of `scratch` on this device.
+static char *noalloc_scratch() {
+    const DeviceInfo *di = device_info();
+    if (!di) return nullptr;
+    if (mix_prepare_kernels() != PPX_OK) return nullptr;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if ((int)g_scratch.size() <= di->device) g_scratch.resize(di->device + 1, nullptr);
+    if (!g_scratch[di->device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            fail_hip(e == hipSuccess ? hipErrorInvalidSymbol : e, "scratch address");
+            return nullptr;
+        }
+        g_scratch[di->device] = static_cast<char *>(p);
+    }
+    return g_scratch[di->device];
+}
+
+int launch_mixed_noalloc_impl(const ppx_job *jobs, int njobs, hipStream_t stream) {
+    if (!jobs || njobs < 1) return fail(PPX_EINVAL, "no jobs");
+    if (njobs > kNoAllocJobs)
+        return fail(PPX_EINVAL, "launch_mixed_noalloc takes at most PPX_NOALLOC_MAX_JOBS (256) jobs");
+    // header and job records, built on the stack
+    alignas(16) char table[kMixHeaderBytes + sizeof(MixJob) * kNoAllocJobs];
+    int64_t ntiles = 0;
+    const int mask = mix_build_tables(jobs, njobs, table, &ntiles);
+    if (mask < 0) return mask;
+    if (ntiles > kNoAllocTiles)
+        return fail(PPX_EINVAL, "launch_mixed_noalloc takes at most PPX_NOALLOC_MAX_TILES (262144) tiles");
+    char *d = noalloc_scratch();
+    if (!d) return PPX_EDEVICE;
+    const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
+    const unsigned bytes = (unsigned)(kMixHeaderBytes + sizeof(MixJob) * (size_t)njobs);
+    TableChunk c;
+    for (unsigned off = 0; off < bytes; off += kTableChunk) {
+        c.offset = off;
+        c.bytes = std::min<unsigned>(kTableChunk, bytes - off);
+        std::memcpy(c.data, table + off, c.bytes);
+        hipLaunchKernelGGL(k_mix_table_copy, dim3(1), dim3(256), 0, stream, d, c);
+        if (int rc = fail_hip(hipGetLastError(), "table copy")) return rc;
+    }
+    int64_t fam_tiles[kMixFamilies];
+    for (int f = 0; f < kMixFamilies; ++f) fam_tiles[f] = h->ntiles[f];
+    return mix_enqueue(d, mask, fam_tiles, static_cast<const float2 *>(device_info()->twiddles), stream);
+}
+
 }  // namespace ppx
+
+extern "C" int launch_mixed_noalloc(const ppx_job *jobs, int njobs, void *stream) {
+    ppx::fail(PPX_OK, "");
+    return ppx::launch_mixed_noalloc_impl(jobs, njobs, static_cast<hipStream_t>(stream));
+}
 
 extern "C" int launch_mixed(const ppx_job *jobs, int njobs, void *stream) {
     ppx::fail(PPX_OK, "");

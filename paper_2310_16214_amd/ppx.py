@@ -562,6 +562,26 @@ def launch_mixed(jobs, stream=None):
     _check(f(arr, len(jobs), stream))
 
 
+NOALLOC_MAX_JOBS, NOALLOC_MAX_TILES = 256, 262144
+
+
+def launch_mixed_noalloc(jobs, stream=None):
+    """launch_mixed with its tables in the library's static device array (no
+    allocation; see include/ppx.h)."""
+    f = lib().launch_mixed_noalloc
+    if not getattr(f, "_ppx_typed", False):
+        f.argtypes = [ctypes.POINTER(Job), ctypes.c_int, ctypes.c_void_p]
+        f.restype = ctypes.c_int
+        f._ppx_typed = True
+    arr = (Job * len(jobs))(*jobs)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    elif hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    _check(f(arr, len(jobs), stream))
+
+
 def mixed_tile_config(job):
     """How launch_mixed cuts a Job: (problems per tile, Config whose
     arithmetic the tiles follow)."""

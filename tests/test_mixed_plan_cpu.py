@@ -91,3 +91,19 @@ def test_job_errors():
     for j in bad:
         with pytest.raises(ppx.PpxError):
             ppx.mixed_tile_config(j)
+
+
+def test_noalloc_refuses_oversize_calls_before_any_gpu_work():
+    # planning runs on the host before the device is touched, so these are
+    # refused here without a GPU (pointers are never dereferenced)
+    p = 1 << 12
+    many = [ppx.make_job(ppx.OP_SCAN, ppx.F32, 64, 1, p, p)] * (ppx.NOALLOC_MAX_JOBS + 1)
+    with pytest.raises(ppx.PpxError) as e:
+        ppx.launch_mixed_noalloc(many, stream=0)
+    assert e.value.code == ppx.EINVAL and "PPX_NOALLOC_MAX_JOBS" in str(e.value)
+    job = ppx.make_job(ppx.OP_SCAN, ppx.F32, 16384, 1, p, p)
+    per, _ = ppx.mixed_tile_config(job)
+    big = ppx.make_job(ppx.OP_SCAN, ppx.F32, 16384, (ppx.NOALLOC_MAX_TILES + 1) * per, p, p)
+    with pytest.raises(ppx.PpxError) as e:
+        ppx.launch_mixed_noalloc([big], stream=0)
+    assert e.value.code == ppx.EINVAL and "PPX_NOALLOC_MAX_TILES" in str(e.value)
