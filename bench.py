@@ -92,7 +92,7 @@ def build_workload(ops, dev):
                 n = 1 << ln
                 batch = (1 << 22) // n
                 a, b, c, d, _ = inputs.tridiag_input(n, batch, dt, seed=2)
-                for algo, name in ((ppx.TRI_CR, "cr"), (ppx.TRI_PCR, "pcr")):
+                for algo, name in ((ppx.TRI_CR, "cr"), (ppx.TRI_PCR, "pcr"), (ppx.TRI_CR_PCR, "cr_pcr")):
                     # separate copies per algorithm: no call reads data another
                     # call of the same step has just touched
                     ad, bd, cd, dd = (torch.from_numpy(v).to(dev) for v in (a, b, c, d))
@@ -200,7 +200,7 @@ def tuned_vs_default(ppx, calls, per, stream, steps=2):
         opc = ppx.OP_FFT if op == "fft" else ppx.OP_SCAN if op == "scan" else ppx.OP_TRIDIAG
         d = ppx.default_config(opc, code, c["n"])
         if opc == ppx.OP_TRIDIAG:  # the plain kernel of the call's family
-            d.algo = ppx.TRI_CR if op == "tridiag_cr" else ppx.TRI_PCR
+            d.algo = ppx.TRI_PCR if op == "tridiag_pcr" else ppx.TRI_CR
             d.lds_elems = 0
         runs.append(c["run_cfg"](d))
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in calls]
@@ -221,7 +221,8 @@ def tuned_vs_default(ppx, calls, per, stream, steps=2):
         out.setdefault(key, []).append(us / per[i]["us"])
     res = {k: {"geomean": round(float(np.exp(np.mean(np.log(v)))), 3), "min": round(float(min(v)), 3),
                "calls": len(v)} for k, v in out.items()}
-    res["default"] = "radix 2, one problem per workgroup, L = min(n/2, 1024) (tridiagonal: plain CR/PCR)"
+    res["default"] = ("radix 2, one problem per workgroup, L = min(n/2, 1024) (tridiagonal: the plain LDS PCR "
+                      "for the PCR family, the plain LDS CR for the others)")
     return res
 
 
@@ -437,7 +438,7 @@ def main():
         "data": "synthetic (seeded uniform inputs of the paper's workload shapes)",
         "config": {"workload": "batched FFT sweep N=2^4..2^14 (256 MiB/call) + inclusive scan "
                                "sweep N=2^5..2^13 (2^24 elem/call, int32+f32) + tridiagonal "
-                               "CR/PCR sweep N=2^5..2^10 (2^22 unknowns/call, f32+f64)",
+                               "CR/PCR/CR-PCR-hybrid sweep N=2^5..2^10 (2^22 unknowns/call, f32+f64)",
                    "calls_per_step": len(calls), "elements_per_step": elems,
                    "algorithmic_bytes_per_step": bytes_step,
                    "hbm_frac_step": round(bytes_step / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},

@@ -72,30 +72,35 @@ extern "C" {
 #define PPX_SCAN_LF_PIPE 3  /* PPX_SCAN_LF, persistent as above */
 #define PPX_TRI_CR 0        /* cyclic reduction (Sec. III), LDS exchange */
 #define PPX_TRI_PCR 1       /* parallel cyclic reduction (Sec. III), LDS exchange */
-#define PPX_TRI_CR_SHFL 2   /* CR inside a wave: registers + lane shuffles, no
+#define PPX_TRI_CR_PCR 2    /* CR -> PCR hybrid inside a wave (S = 0): the CR
+                               levels inside each lane reduce its P equations
+                               to one, PCR solves the n / P remaining ones
+                               across the lanes, back substitution inside the
+                               lane recovers the rest; n / P <= 64, P <= 16 */
+#define PPX_TRI_CR_SHFL 3   /* CR inside a wave: registers + lane shuffles, no
                                LDS (S = 0); valid when n / P <= 64, P <= 16 */
-#define PPX_TRI_PCR_SHFL 3  /* PCR inside a wave (S = 0); n / P <= 64, P <= 16 */
-#define PPX_TRI_PCR_REG 4   /* PCR inside a wave, the cross-lane exchange through
+#define PPX_TRI_PCR_SHFL 4  /* PCR inside a wave (S = 0); n / P <= 64, P <= 16 */
+#define PPX_TRI_PCR_REG 5   /* PCR inside a wave, the cross-lane exchange through
                                a per-wave LDS buffer of 3 * 64 * min(P, 4)
                                values (16-byte accesses) instead of shuffles;
                                S = 0, n / P <= 64, P <= 16 */
-#define PPX_TRI_WM 5        /* Wang & Mou divide and conquer inside a wave
+#define PPX_TRI_WM 6        /* Wang & Mou divide and conquer inside a wave
                                (Sec. III): blocks of equations merge in pairs,
                                each equation kept solved in terms of its
                                block's two outer unknowns; radix P (a lane's P
                                equations form the first node), then radix 2
                                across lanes by broadcasts; S = 0, n / P <= 64,
                                P <= 16 */
-#define PPX_TRI_LF 6        /* Ladner-Fischer solver inside a wave (Sec. III):
+#define PPX_TRI_LF 7        /* Ladner-Fischer solver inside a wave (Sec. III):
                                a prefix scan (Ladner-Fischer circuit) over
                                elements of two equations, the first and last
                                of a block, then one over the back-substitution
                                maps; S = 0, n / P <= 64, P <= 16 */
-#define PPX_TRI_PIPE 8      /* flag, OR-ed onto PPX_TRI_CR_SHFL, _PCR_SHFL,
-                               _PCR_REG, _WM or _LF: persistent workgroups (as many as are
+#define PPX_TRI_PIPE 8      /* flag, OR-ed onto an in-wave variant (PPX_TRI_CR_PCR,
+                               _CR_SHFL, _PCR_SHFL, _PCR_REG, _WM or _LF):
+                               persistent workgroups (as many as are
                                resident) that load the next group of systems
-                               while solving the current one; needs
-                               P * sizeof(element) <= 32 */
+                               while solving the current one */
 
 /* ---- tuning methods ---- */
 #define PPX_TUNE_EXHAUSTIVE 0 /* time every valid configuration (Sec. VI) */

@@ -89,6 +89,18 @@ int ppx_analytical_pick(const ppx_device_model *m, const ppx_config *cands,
                         const ppx_resource *res, int ncands, int64_t batch, int flags,
                         int *chosen);
 
+/*
+ * The library's analytical choice (what tune() with PPX_TUNE_ANALYTICAL
+ * picks: the gfx950 candidate rules, the occupancy guideline with grid fill
+ * and the 50% window, and the persistent twin of a choice that keeps at most
+ * two workgroups resident) restricted to a caller's candidate list, e.g. a
+ * smaller search space.  Each candidate must be valid for (op, dtype, n);
+ * *chosen receives the index of the choice.  Resources come from the device
+ * when one is initialised, else from the static table.
+ */
+int ppx_analytical_select(int op, int dtype, int64_t n, int64_t batch, const ppx_config *cands,
+                          int ncands, int *chosen);
+
 /* Evaluator: the cost (e.g. median microseconds) of a candidate; a negative
  * value marks a failed or timed-out run. */
 typedef double (*ppx_eval_fn)(const ppx_config *cfg, void *user);
@@ -141,7 +153,7 @@ typedef struct ppx_tune_report {
  * -1 searches every algorithm of the op; otherwise only that one (the cache
  * entry is then keyed by it); for the tridiagonal solvers the filter selects
  * a family: PPX_TRI_CR (CR through LDS or shuffles), PPX_TRI_PCR (the PCR
- * variants), PPX_TRI_WM or PPX_TRI_LF.  reps = timed launches per candidate (<= 0:
+ * variants), PPX_TRI_CR_PCR (the hybrid), PPX_TRI_WM or PPX_TRI_LF.  reps = timed launches per candidate (<= 0:
  * 100, the paper's count), each on a different buffer set so that no rep
  * reads data a previous rep left in the 256 MB Infinity Cache.  Synchronous;
  * needs a GPU.  Records the winner in the tune cache.

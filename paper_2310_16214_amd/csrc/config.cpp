@@ -92,10 +92,10 @@ int validate_config(int op, int dtype, int64_t n, const ppx_config &c) {
             if (c.radix != 0 && c.radix != 2) return fail(PPX_ECONFIG, "tridiagonal radix must be 2");
             if (tri_base(c.algo) < PPX_TRI_CR || tri_base(c.algo) > kTriMaxBase ||
                 (c.algo & ~(PPX_TRI_PIPE | 7)) != 0)
-                return fail(PPX_ECONFIG, "tridiagonal algo must be PPX_TRI_CR, _PCR, _CR_SHFL, _PCR_SHFL, _PCR_REG, _WM or _LF (the last five optionally | PPX_TRI_PIPE)");
+                return fail(PPX_ECONFIG, "tridiagonal algo must be PPX_TRI_CR, _PCR, _CR_PCR, _CR_SHFL, _PCR_SHFL, _PCR_REG, _WM or _LF (the in-wave ones optionally | PPX_TRI_PIPE)");
             if ((c.algo & PPX_TRI_PIPE) &&
                 (!tri_in_wave(c.algo) || P * (dtype == PPX_F64 ? 8 : 4) > kTriPipeMaxBytes))
-                return fail(PPX_ECONFIG, "PPX_TRI_PIPE needs an in-wave variant and P * element size <= 32 bytes");
+                return fail(PPX_ECONFIG, "PPX_TRI_PIPE needs an in-wave variant and P * element size <= 128 bytes");
             if (tri_in_wave(c.algo)) {
                 if (n / P > kWave) return fail(PPX_ECONFIG, "shuffle variant needs n / P <= 64 (a system within a wave)");
                 if (P > tri_wave_max_p(c.algo, dtype)) return fail(PPX_ECONFIG, "shuffle variant: too many elements per thread");
@@ -136,8 +136,9 @@ int enumerate_configs(int op, int dtype, int64_t n, ppx_config *out, int cap) {
     const int *radices = op == PPX_OP_FFT ? radices_fft : radix_two;
     const int nr = op == PPX_OP_FFT ? 4 : 1;
     static const int algos_two[] = {0, 1, 2, 3};
-    static const int algos_tri[] = {PPX_TRI_CR, PPX_TRI_PCR, PPX_TRI_CR_SHFL, PPX_TRI_PCR_SHFL, PPX_TRI_PCR_REG,
-                                    PPX_TRI_WM, PPX_TRI_LF, PPX_TRI_CR_SHFL | PPX_TRI_PIPE,
+    static const int algos_tri[] = {PPX_TRI_CR, PPX_TRI_PCR, PPX_TRI_CR_PCR, PPX_TRI_CR_SHFL, PPX_TRI_PCR_SHFL,
+                                    PPX_TRI_PCR_REG, PPX_TRI_WM, PPX_TRI_LF, PPX_TRI_CR_PCR | PPX_TRI_PIPE,
+                                    PPX_TRI_CR_SHFL | PPX_TRI_PIPE,
                                     PPX_TRI_PCR_SHFL | PPX_TRI_PIPE, PPX_TRI_PCR_REG | PPX_TRI_PIPE,
                                     PPX_TRI_WM | PPX_TRI_PIPE, PPX_TRI_LF | PPX_TRI_PIPE};
     const int *algos = op == PPX_OP_TRIDIAG ? algos_tri : algos_two;

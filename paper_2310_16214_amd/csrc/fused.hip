@@ -156,8 +156,8 @@ int check_job(const ppx_job &j, MixPlan *plan) {
             break;
         case PPX_OP_TRIDIAG:
             if (j.dtype != PPX_F32 && j.dtype != PPX_F64) return fail(PPX_EINVAL, "job: tridiagonal dtype");
-            if (j.algo != PPX_TRI_CR && j.algo != PPX_TRI_PCR && j.algo != PPX_TRI_WM && j.algo != PPX_TRI_LF)
-                return fail(PPX_EINVAL, "job: tridiagonal algo must be a family: PPX_TRI_CR, _PCR, _WM or _LF");
+            if (!tri_is_family(j.algo))
+                return fail(PPX_EINVAL, "job: tridiagonal algo must be a family: PPX_TRI_CR, _PCR, _CR_PCR, _WM or _LF");
             if (!j.b || !j.c || !j.d || !al(j.b) || !al(j.c) || !al(j.d))
                 return fail(PPX_EINVAL, "job: tridiagonal coefficient pointers");
             break;

@@ -88,9 +88,10 @@ constexpr int kMixFftShapes = (kFftLog2NMax + 1) * 6;
 // Scan: ((dtype * 5 + log2(P) - 1) * 2 + lf) with dtype PPX_I32/F32/F64.
 constexpr int mix_scan_shape(int dtype, int lp, bool lf) { return (dtype * 5 + lp - 1) * 2 + (lf ? 1 : 0); }
 constexpr int kMixScanShapes = 3 * 5 * 2;
-// In-wave tridiagonal: (variant - PPX_TRI_CR_SHFL) * 4 + log2(P) - 1.
-constexpr int mix_triw_shape(int base, int lp) { return (base - PPX_TRI_CR_SHFL) * 4 + lp - 1; }
-constexpr int kMixTriwShapes = 5 * 4;
+// In-wave tridiagonal: (variant - PPX_TRI_CR_PCR) * 4 + log2(P) - 1 (the
+// in-wave variants are the codes PPX_TRI_CR_PCR .. PPX_TRI_LF).
+constexpr int mix_triw_shape(int base, int lp) { return (base - PPX_TRI_CR_PCR) * 4 + lp - 1; }
+constexpr int kMixTriwShapes = (PPX_TRI_LF - PPX_TRI_CR_PCR + 1) * 4;
 // Family of an in-wave tridiagonal shape (variant without the persistent
 // flag, P).
 constexpr int mix_triw_family(bool f64, int algo, int P) {

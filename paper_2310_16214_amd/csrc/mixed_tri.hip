@@ -1,7 +1,8 @@
 // Tridiagonal families of the mixed launch: persistent kernels whose tiles
 // run the job's tuned solver.  Systems that fit a wave (n / P <= 64) run the
-// in-wave variants (CR, PCR with shuffles or with the LDS exchange, Wang &
-// Mou, Ladner-Fischer) in 256-thread workgroups, one kernel per dtype and per
+// in-wave variants (the CR -> PCR hybrid, CR, PCR with shuffles or with the
+// LDS exchange, Wang & Mou, Ladner-Fischer) in 256-thread workgroups, one
+// kernel per dtype and per
 // register tier: a kernel's VGPR count is the maximum over its shapes, and
 // the P = 16 solvers (and in float32 also the PCR ones, 94-100 VGPRs against
 // 56-62 for CR, WM and LF) would otherwise halve the others' occupancy.
@@ -25,7 +26,7 @@ template <int FAM, int ID>
 __device__ __forceinline__ void mix_triw_dispatch(const MixJob &j, long long first, int count, void *smem, int tx) {
     if constexpr (ID < kMixTriwShapes) {
         using T = TriwType<FAM>;
-        constexpr int ALGO = PPX_TRI_CR_SHFL + ID / 4;
+        constexpr int ALGO = PPX_TRI_CR_PCR + ID / 4;
         constexpr int LP = ID % 4 + 1;
         constexpr int P = 1 << LP;
         if constexpr (triw_member<FAM>(ALGO, P)) {

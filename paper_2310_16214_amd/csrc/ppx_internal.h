@@ -83,18 +83,28 @@ constexpr int tri_wave_max_p(int, int) { return 16; }
 // The variant without the persistent flag, in-wave variants (registers +
 // lane exchange) and the algorithm family.
 constexpr int tri_base(int algo) { return algo & ~PPX_TRI_PIPE; }
-constexpr bool tri_in_wave(int algo) { return tri_base(algo) >= PPX_TRI_CR_SHFL; }
+constexpr bool tri_in_wave(int algo) { return tri_base(algo) >= PPX_TRI_CR_PCR; }
 constexpr int tri_family(int algo) {
     return tri_base(algo) == PPX_TRI_CR || tri_base(algo) == PPX_TRI_CR_SHFL ? PPX_TRI_CR
-           : tri_base(algo) == PPX_TRI_WM                                   ? PPX_TRI_WM
-           : tri_base(algo) == PPX_TRI_LF                                   ? PPX_TRI_LF
-                                                                             : PPX_TRI_PCR;
+           : tri_base(algo) == PPX_TRI_PCR || tri_base(algo) == PPX_TRI_PCR_SHFL ||
+                   tri_base(algo) == PPX_TRI_PCR_REG
+               ? PPX_TRI_PCR
+               : tri_base(algo);  // the hybrid, WM and LF are families of one variant
+}
+// Families a tridiagonal tuning or job may name.
+constexpr bool tri_is_family(int algo) {
+    return algo == PPX_TRI_CR || algo == PPX_TRI_PCR || algo == PPX_TRI_CR_PCR || algo == PPX_TRI_WM ||
+           algo == PPX_TRI_LF;
 }
 // Largest variant code without the persistent flag.
 constexpr int kTriMaxBase = PPX_TRI_LF;
 // Largest P * sizeof(element) of the persistent in-wave variants (the second
-// register set).
-constexpr int kTriPipeMaxBytes = 32;
+// register set): every in-wave P.  With 16 values per lane and array the two
+// register sets need 135-218 VGPRs in float32 (two or three waves per SIMD)
+// and, in float64, AGPRs as well (one wave per SIMD); a persistent grid needs
+// no more waves than that, and the tuners weigh the prefetch against the
+// lower occupancy.
+constexpr int kTriPipeMaxBytes = 128;
 int launch_fft(const void *in, void *out, int log2n, int64_t batch,
                const ppx_config &c, bool inverse, hipStream_t s);
 // exclusive: each output is the sum of the inputs before it (0 first).

@@ -45,6 +45,7 @@ static const void *wave_kernel_p(int P) {
 template <typename T, bool PIPE>
 static const void *wave_kernel(int base, int P) {
     switch (base) {
+        case PPX_TRI_CR_PCR: return wave_kernel_p<T, PPX_TRI_CR_PCR, PIPE>(P);
         case PPX_TRI_CR_SHFL: return wave_kernel_p<T, PPX_TRI_CR_SHFL, PIPE>(P);
         case PPX_TRI_PCR_SHFL: return wave_kernel_p<T, PPX_TRI_PCR_SHFL, PIPE>(P);
         case PPX_TRI_PCR_REG: return wave_kernel_p<T, PPX_TRI_PCR_REG, PIPE>(P);

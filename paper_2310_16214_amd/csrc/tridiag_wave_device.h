@@ -91,13 +91,15 @@ __device__ __forceinline__ void wave_store(T *dst, const T (&v)[P]) {
     }
 }
 
-// CR on the registers of one lane group; t = lane index within the system,
-// lps = lanes per system, n = P * lps.
+// CR forward levels inside the lane (2s <= P, and 2s <= n/4 so that the last
+// level leaves two equations): equation r = 2s*m + 2s - 1 eliminates r - s and
+// r + s; only the right neighbour of the lane's last active equation can be
+// equation s - 1 of the next lane (one shuffle of three values).  After them
+// each lane's last equation couples the last equations of the lanes beside it.
 template <typename T, int P>
-__device__ __forceinline__ void wave_cr(T (&a)[P], T (&c)[P], T (&d)[P], int t, int lps) {
+__device__ __forceinline__ void cr_inlane_forward(T (&a)[P], T (&c)[P], T (&d)[P], int t, int lps) {
     const int n = P * lps;
     const bool last_lane = t + 1 == lps;
-    // ---- forward levels inside the lane (2s <= P)
 #pragma unroll
     for (int s = 1; 2 * s <= P; s *= 2) {
         if (2 * s > n / 2) break;  // the last level leaves two equations
@@ -111,6 +113,49 @@ __device__ __forceinline__ void wave_cr(T (&a)[P], T (&c)[P], T (&d)[P], int t, 
                            local ? c[(r + s) % P] : nc, local ? d[(r + s) % P] : nd);
         }
     }
+}
+
+// CR back substitution inside the lane (s < P), once every lane's last
+// unknown is in d[P - 1]: equation r = 2s*m + s - 1 gets x_r = d_r - a_r
+// x_{r-s} - c_r x_{r+s}, where x_{r-s} for the lane's first such equation is
+// the previous lane's last unknown.
+template <typename T, int P>
+__device__ __forceinline__ void cr_inlane_backward(T (&a)[P], T (&c)[P], T (&d)[P], int t, int lps) {
+    const int n = P * lps;
+#pragma unroll
+    for (int s = P / 2; s >= 1; s /= 2) {
+        if (2 * s > n / 2) continue;
+        const T xl = shfl_up(d[P - 1], 1);  // x of the previous lane's last equation
+#pragma unroll
+        for (int r = s - 1; r < P; r += 2 * s) {
+            T x = d[r];
+            if (r >= s) x -= a[r] * d[r - s];
+            else if (t > 0) x -= a[r] * xl;
+            x -= c[r] * d[r + s];  // r + s <= P - 1: always local
+            d[r] = x;
+        }
+    }
+}
+
+// The 2x2 system of one lane's equations P/2 - 1 and P - 1 (a system held by
+// a single lane, after the in-lane levels).
+template <typename T, int P>
+__device__ __forceinline__ void cr_solve_pair_inlane(T (&a)[P], T (&c)[P], T (&d)[P]) {
+    constexpr int i1 = P / 2 - 1, i2 = P - 1;
+    const T r = rcp(T(1) - c[i1] * a[i2]);
+    const T x1 = (d[i1] - c[i1] * d[i2]) * r;
+    const T x2 = (d[i2] - a[i2] * d[i1]) * r;
+    d[i1] = x1;
+    d[i2] = x2;
+}
+
+// CR on the registers of one lane group; t = lane index within the system,
+// lps = lanes per system, n = P * lps.
+template <typename T, int P>
+__device__ __forceinline__ void wave_cr(T (&a)[P], T (&c)[P], T (&d)[P], int t, int lps) {
+    const int n = P * lps;
+    const bool last_lane = t + 1 == lps;
+    cr_inlane_forward<T, P>(a, c, d, t, lps);
     // ---- forward levels across lanes (s >= P): last equation of each lane
     for (int s = P; s <= n / 4; s *= 2) {
         const int dl = s / P;
@@ -122,12 +167,7 @@ __device__ __forceinline__ void wave_cr(T (&a)[P], T (&c)[P], T (&d)[P], int t, 
     }
     // ---- the 2x2 system of equations n/2 - 1 and n - 1
     if (lps == 1) {
-        constexpr int i1 = P / 2 - 1, i2 = P - 1;
-        const T r = rcp(T(1) - c[i1] * a[i2]);
-        const T x1 = (d[i1] - c[i1] * d[i2]) * r;
-        const T x2 = (d[i2] - a[i2] * d[i1]) * r;
-        d[i1] = x1;
-        d[i2] = x2;
+        cr_solve_pair_inlane<T, P>(a, c, d);
     } else {
         const int h = lps / 2;  // lanes h-1 and lps-1 hold the two equations
         const T oa = shfl_down(a[P - 1], h), od = shfl_down(d[P - 1], h);
@@ -149,20 +189,34 @@ __device__ __forceinline__ void wave_cr(T (&a)[P], T (&c)[P], T (&d)[P], int t, 
             d[P - 1] = x;
         }
     }
-    // ---- back substitution inside the lane (s < P)
-#pragma unroll
-    for (int s = P / 2; s >= 1; s /= 2) {
-        if (2 * s > n / 2) continue;
-        const T xl = shfl_up(d[P - 1], 1);  // x of the previous lane's last equation
-#pragma unroll
-        for (int r = s - 1; r < P; r += 2 * s) {
-            T x = d[r];
-            if (r >= s) x -= a[r] * d[r - s];
-            else if (t > 0) x -= a[r] * xl;
-            x -= c[r] * d[r + s];  // r + s <= P - 1: always local
-            d[r] = x;
+    cr_inlane_backward<T, P>(a, c, d, t, lps);
+}
+
+// CR -> PCR hybrid (PPX_TRI_CR_PCR): the CR levels inside the lane reduce
+// each lane's P equations to its last one; PCR then solves that reduced
+// system of lps equations (one per lane, stride P in the original indices)
+// in log2(lps) steps, every lane active, with shuffles confined to the
+// system's lanes (an out-of-system neighbour meets an exact zero coefficient,
+// as in wave_pcr: lane 0's reduced a and the last lane's reduced c are
+// products with the zeroed boundary coefficients); back substitution inside
+// the lane then recovers the other equations.  Work per lane: P - 1
+// eliminations, log2(lps) eliminations and P - 1 substitutions, against
+// PCR's P log2(n) eliminations and CR's 2 log2(lps) cross-lane levels with
+// most lanes idle.
+template <typename T, int P>
+__device__ __forceinline__ void wave_cr_pcr(T (&a)[P], T (&c)[P], T (&d)[P], int t, int lps) {
+    cr_inlane_forward<T, P>(a, c, d, t, lps);
+    if (lps == 1) {
+        cr_solve_pair_inlane<T, P>(a, c, d);
+    } else {
+        for (int dl = 1; dl < lps; dl *= 2) {
+            const T la = sys_up(a[P - 1], dl, lps), lc = sys_up(c[P - 1], dl, lps), ld = sys_up(d[P - 1], dl, lps);
+            const T ra = sys_down(a[P - 1], dl, lps), rc = sys_down(c[P - 1], dl, lps),
+                    rd = sys_down(d[P - 1], dl, lps);
+            unit_eliminate(a[P - 1], c[P - 1], d[P - 1], la, lc, ld, ra, rc, rd);
         }
     }
+    cr_inlane_backward<T, P>(a, c, d, t, lps);
 }
 
 // PCR steps with stride S < P, unrolled: the left neighbours of equations
@@ -565,6 +619,7 @@ __device__ __forceinline__ void tridiag_wave_solve(T (&a)[P], const T (&b)[P], T
         d[j] *= r;
     }
     if constexpr (ALGO == PPX_TRI_CR_SHFL) wave_cr<T, P>(a, c, d, t, lps);
+    else if constexpr (ALGO == PPX_TRI_CR_PCR) wave_cr_pcr<T, P>(a, c, d, t, lps);
     else if constexpr (ALGO == PPX_TRI_PCR_SHFL) wave_pcr<T, P>(a, c, d, lps);
     else if constexpr (ALGO == PPX_TRI_WM) wave_wm<T, P>(a, c, d, t, lps);
     else if constexpr (ALGO == PPX_TRI_LF) wave_lf<T, P>(a, c, d, t, lps);

@@ -548,7 +548,8 @@ static int static_vgprs(int op, int dtype, int P, int algo) {
     if (op == PPX_OP_SCAN)
         return (dtype == PPX_F64 ? 2 : 1) * (P <= 2 ? 10 : P <= 4 ? 12 : P <= 8 ? 16 : P <= 16 ? 24 : 40);
     if (tri_in_wave(algo))
-        return (dtype == PPX_F64 ? 2 : 1) * (tri_base(algo) == PPX_TRI_CR_SHFL || tri_base(algo) >= PPX_TRI_WM ? 5 : 6) * P *
+        return (dtype == PPX_F64 ? 2 : 1) *
+                   (tri_base(algo) == PPX_TRI_PCR_SHFL || tri_base(algo) == PPX_TRI_PCR_REG ? 6 : 5) * P *
                    ((algo & PPX_TRI_PIPE) ? 2 : 1) + 16;
     return dtype == PPX_F64 ? (algo == PPX_TRI_PCR ? 44 : 40) : (algo == PPX_TRI_PCR ? 32 : 28);
 }
@@ -880,7 +881,7 @@ static int tune_candidates(int op, int dtype, int64_t n, int algo, std::vector<p
 }
 
 // The configuration a call with cfg == NULL uses, restricted to one
-// tridiagonal family (CR, PCR, WM or LF): the tune cache's entry recorded for
+// tridiagonal family (CR, PCR, the CR -> PCR hybrid, WM or LF): the tune cache's entry recorded for
 // that family, else the entry for every algorithm if it belongs to the family,
 // else the analytical model's choice among the family's configurations.
 int family_config(int dtype, int64_t n, int64_t batch, int family, ppx_config &c) {
@@ -1137,6 +1138,20 @@ int ppx_analytical_pick(const ppx_device_model *m, const ppx_config *cands, cons
     const int k = analytical_pick_impl(*m, cands, res, ncands, batch, flags);
     *chosen = k;
     return k >= 0 ? PPX_OK : fail(PPX_ECONFIG, "no candidate can be resident");
+}
+
+int ppx_analytical_select(int op, int dtype, int64_t n, int64_t batch, const ppx_config *cands,
+                          int ncands, int *chosen) {
+    if (!cands || !chosen || ncands <= 0 || batch < 1) return fail(PPX_EINVAL, "bad argument");
+    std::vector<ppx_config> v(cands, cands + ncands);
+    for (const auto &c : v)
+        if (int rc = validate_config(op, dtype, n, c)) return rc;
+    ppx_config pick{};
+    if (int rc = analytical_select(op, dtype, n, batch, v, device_info_if_ready() != nullptr, pick)) return rc;
+    *chosen = -1;
+    for (int i = 0; i < ncands; ++i)
+        if (std::memcmp(&v[i], &pick, sizeof pick) == 0) *chosen = i;
+    return *chosen >= 0 ? PPX_OK : fail(PPX_ECONFIG, "analytical choice not among the candidates");
 }
 
 int ppx_bo_search(const ppx_config *cands, int ncands, ppx_eval_fn fn, void *user, int max_evals,

@@ -25,15 +25,16 @@ I32, F32, F64, C64 = 0, 1, 2, 3
 OP_FFT, OP_SCAN, OP_TRIDIAG = 0, 1, 2
 FFT_LDS, FFT_LDS_SPLIT, FFT_LDS_PIPE, FFT_LDS_SPLIT_PIPE = 0, 1, 2, 3
 SCAN_KS, SCAN_LF, SCAN_KS_PIPE, SCAN_LF_PIPE = 0, 1, 2, 3
-TRI_CR, TRI_PCR, TRI_CR_SHFL, TRI_PCR_SHFL, TRI_PCR_REG, TRI_WM, TRI_LF = 0, 1, 2, 3, 4, 5, 6
+TRI_CR, TRI_PCR, TRI_CR_PCR, TRI_CR_SHFL, TRI_PCR_SHFL, TRI_PCR_REG, TRI_WM, TRI_LF = 0, 1, 2, 3, 4, 5, 6, 7
 TRI_PIPE = 8  # flag on an in-wave variant: persistent workgroups with prefetch
 
 
 def tri_family(algo):
-    """TRI_CR for the CR variants, TRI_WM / TRI_LF for Wang & Mou / Ladner-Fischer,
-    TRI_PCR for the PCR variants."""
+    """TRI_CR for the CR variants, TRI_PCR for the PCR variants; the CR -> PCR
+    hybrid, Wang & Mou and Ladner-Fischer are families of their own."""
     base = algo & ~TRI_PIPE
-    return TRI_CR if base in (TRI_CR, TRI_CR_SHFL) else base if base in (TRI_WM, TRI_LF) else TRI_PCR
+    return (TRI_CR if base in (TRI_CR, TRI_CR_SHFL) else TRI_PCR if base in (TRI_PCR, TRI_PCR_SHFL, TRI_PCR_REG)
+            else base)
 TUNE_EXHAUSTIVE, TUNE_ANALYTICAL, TUNE_LEARNED = 0, 1, 2
 MIN_N, MAX_N = 16, 16384
 
@@ -272,6 +273,8 @@ _tune_sigs = {
     "ppx_analytical_pick": ([ctypes.POINTER(DeviceModel), ctypes.POINTER(Config),
                              ctypes.POINTER(Resource), ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                              ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "ppx_analytical_select": ([ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(Config),
+                               ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "ppx_bo_search": ([ctypes.POINTER(Config), ctypes.c_int, EVAL_FN, ctypes.c_void_p, ctypes.c_int,
                        ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
@@ -417,6 +420,14 @@ def analytical_pick(model, cands, resources, batch, flags=0):
     ra = (Resource * n)(*resources)
     k = ctypes.c_int(-1)
     _check(_tl("ppx_analytical_pick")(ctypes.byref(model), ca, ra, n, batch, flags, ctypes.byref(k)))
+    return k.value
+
+
+def analytical_select(op, dtype, n, batch, cands):
+    """Index of the library's analytical choice among cands (ppx_tune.h)."""
+    ca = (Config * len(cands))(*cands)
+    k = ctypes.c_int(-1)
+    _check(_tl("ppx_analytical_select")(op, dtype, n, batch, ca, len(cands), ctypes.byref(k)))
     return k.value
 
 

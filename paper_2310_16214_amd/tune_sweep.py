@@ -40,7 +40,7 @@ def sweeps(ops):
                 out.append(("scan", ppx.OP_SCAN, code, 1 << ln, (1 << 24) >> ln, -1))
     if "tridiag" in ops:
         for code in (ppx.F32, ppx.F64):
-            for algo in (ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_WM, ppx.TRI_LF):
+            for algo in (ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_CR_PCR, ppx.TRI_WM, ppx.TRI_LF):
                 for ln in range(5, 11):
                     out.append(("tridiag", ppx.OP_TRIDIAG, code, 1 << ln, (1 << 22) >> ln, algo))
     return out
@@ -107,6 +107,41 @@ def plain_time_us(ppx, op, dtype, n, launches, dev):
     return (time.perf_counter() - t0) * 1e6 / launches
 
 
+def restricted_study(ppx, records, max_gb):
+    """The three methods over a smaller search space, from the exhaustive
+    run's timings: candidates with at most max_gb problems per workgroup
+    (the benchmark configuration's "problems/block 1..16").  Exhaustive is
+    the best timed candidate of the subset; analytical the library's
+    selection rule applied to the subset (ppx_analytical_select); learned the
+    library's Bayesian search (same stopping rule, seed and features as
+    tune()) run over the subset with the measured times as its evaluations.
+    Returns per-size records and Phi per group."""
+    out, groups = [], {}
+    for r in records:
+        sub = [(c, us) for c, us in r["all"] if c[3] <= max_gb]
+        if not sub:
+            continue
+        cands = [ppx.Config(*c) for c, _ in sub]
+        times = {tuple(c): us for c, us in sub}
+        best = min(times.values())
+        ka = ppx.analytical_select(r["op_code"], r["dtype"], r["n"], r["batch"], cands)
+        kb, order, _ = ppx.bo_search(cands, lambda c: times[tuple(c.as_tuple())], patience=5,
+                                     min_rel=0.01, seed=0x231016214)
+        rec = dict(op=r["op"], dtype=r["dtype"], algo=r["algo"], n=r["n"], space=len(sub),
+                   best_cfg=min(sub, key=lambda t: t[1])[0], best_us=best,
+                   analytical_cfg=sub[ka][0], e_analytical=best / sub[ka][1],
+                   learned_cfg=sub[kb][0], e_learned=best / sub[kb][1], learned_evals=len(order),
+                   e_full_space_best=r["exhaustive"]["us"] / best)
+        out.append(rec)
+        groups.setdefault((r["op"], r["dtype"], r["algo"]), []).append(rec)
+    summary = [dict(op=k[0], dtype=k[1], algo=k[2], max_problems_per_block=max_gb,
+                    sizes=[x["n"] for x in v], phi_analytical=ppx.phi([x["e_analytical"] for x in v]),
+                    phi_learned=ppx.phi([x["e_learned"] for x in v]),
+                    evals_learned=[x["learned_evals"] for x in v])
+               for k, v in groups.items()]
+    return out, summary
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--ops", default="fft,scan,tridiag")
@@ -115,6 +150,9 @@ def main():
     ap.add_argument("--cache", default=os.path.join(ROOT, "paper_2310_16214_amd", "tuned",
                                                      "mi355x.txt"))
     ap.add_argument("--plain-launches", type=int, default=2000)
+    ap.add_argument("--max-gb", type=int, default=16,
+                    help="also report the methods over candidates with at most this many problems "
+                         "per workgroup (0: skip)")
     args = ap.parse_args()
     import torch
 
@@ -126,7 +164,7 @@ def main():
         ppx.load_tune_cache(args.cache)
     records = []
     for name, op, dtype, n, batch, algo in sweeps(ops):
-        rec = dict(op=name, dtype=dtype, n=n, batch=batch, algo=algo)
+        rec = dict(op=name, op_code=op, dtype=dtype, n=n, batch=batch, algo=algo)
         t0 = time.time()
         for method in (ppx.TUNE_ANALYTICAL, ppx.TUNE_LEARNED, ppx.TUNE_EXHAUSTIVE):
             rep, trace = ppx.tune_ex(op, dtype, n, batch, method, algo=algo, reps=args.reps)
@@ -187,10 +225,16 @@ def main():
                             tuned_vs_default=[r["tuned_vs_default"] for r in rs],
                             batched_vs_plain=[r.get("batched_vs_plain") for r in rs]))
         print(json.dumps(summary[-1]), flush=True)
+    restricted = None
+    if args.max_gb > 0:
+        rrec, rsum = restricted_study(ppx, records, args.max_gb)
+        for x in rsum:
+            print(json.dumps(x), flush=True)
+        restricted = dict(records=rrec, summary=rsum)
     os.makedirs(args.out_dir, exist_ok=True)
     tag = "_".join(sorted(ops))
     with open(os.path.join(args.out_dir, f"tuning_{tag}.json"), "w") as f:
-        json.dump(dict(records=records, summary=summary, reps=args.reps), f)
+        json.dump(dict(records=records, summary=summary, reps=args.reps, restricted=restricted), f)
 
 
 if __name__ == "__main__":

@@ -158,8 +158,12 @@ def test_tridiag_wm_space():
     assert ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 1024, ppx.make_config(2, 64, 1, wm))       # P 16
     assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 2048, ppx.make_config(2, 128, 1, wm))  # 128 lanes
     assert ppx.config_valid(ppx.OP_TRIDIAG, ppx.F64, 64, ppx.make_config(2, 64, 2, wm | ppx.TRI_PIPE))
-    assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F64, 64, ppx.make_config(2, 64, 8, wm | ppx.TRI_PIPE))
-    assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 64, ppx.make_config(2, 64, 4, 7))
+    assert ppx.config_valid(ppx.OP_TRIDIAG, ppx.F64, 64, ppx.make_config(2, 64, 8, wm | ppx.TRI_PIPE))  # P 8
+    assert ppx.config_valid(ppx.OP_TRIDIAG, ppx.F64, 1024, ppx.make_config(2, 64, 1, wm | ppx.TRI_PIPE))  # P 16
+    assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F64, 2048, ppx.make_config(2, 64, 1, wm | ppx.TRI_PIPE))
+    assert not ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 64, ppx.make_config(2, 64, 4, 16))
+    assert ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 64, ppx.make_config(2, 64, 4, ppx.TRI_CR_PCR))
+    assert ppx.tri_family(ppx.TRI_CR_PCR | ppx.TRI_PIPE) == ppx.TRI_CR_PCR
     assert ppx.config_valid(ppx.OP_TRIDIAG, ppx.F32, 64, ppx.make_config(2, 64, 4, ppx.TRI_LF))
     assert ppx.tri_family(wm | ppx.TRI_PIPE) == wm
     assert ppx.tri_family(ppx.TRI_LF | ppx.TRI_PIPE) == ppx.TRI_LF

@@ -1,5 +1,5 @@
-"""GPU parity of the batched CR / PCR / Wang & Mou / Ladner-Fischer tridiagonal
-solvers against the FP64 Thomas oracle.
+"""GPU parity of the batched CR / PCR / CR -> PCR hybrid / Wang & Mou /
+Ladner-Fischer tridiagonal solvers against the FP64 Thomas oracle.
 
 Bar: per-system relative residual ||A x - d|| / ||d|| (float64, on the stored
 coefficients) <= 1e-4 for float32 and <= 1e-12 for float64, and the forward
@@ -51,7 +51,7 @@ def test_every_config(cuda, n, dtype):
           f"worst |x-oracle| {worst_fe:.2e}, |x-x_true| {np.max(np.abs(x - xt)):.2e}")
 
 
-IN_WAVE = [ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL, ppx.TRI_PCR_REG, ppx.TRI_WM, ppx.TRI_LF]
+IN_WAVE = [ppx.TRI_CR_PCR, ppx.TRI_CR_SHFL, ppx.TRI_PCR_SHFL, ppx.TRI_PCR_REG, ppx.TRI_WM, ppx.TRI_LF]
 ALL_ALGOS = [ppx.TRI_CR, ppx.TRI_PCR] + IN_WAVE + [a | ppx.TRI_PIPE for a in IN_WAVE]
 
 
@@ -82,7 +82,7 @@ def test_x_may_alias_d(cuda):
 def _full_size_cases():
     """(n, dtype, algo) of the full-size test: every variant at the sweep's
     smallest and largest size where a configuration of it exists (the in-wave
-    variants need n / P <= 64, the persistent ones P * element size <= 32)."""
+    variants need n / P <= 64)."""
     cases = []
     for n in (32, 1024):
         for dtype in (np.float32, np.float64):
@@ -147,11 +147,11 @@ def test_wm_lf_forward_error_matches_cr(cuda, dtype):
     dev = [to_dev(v, cuda) for v in (a, b, c, d)]
     ref = oracle.thomas(a, b, c, d)
     err = {}
-    for algo in (ppx.TRI_CR_SHFL, ppx.TRI_WM, ppx.TRI_LF):
+    for algo in (ppx.TRI_CR_SHFL, ppx.TRI_WM, ppx.TRI_LF, ppx.TRI_CR_PCR):
         cfg = ppx.make_config(2, 64, 1, algo)  # P = 16, one system per wave
         banner(f"tridiag wm vs cr {np.dtype(dtype).name} algo={algo}")
         x = _solve(dev, n, batch, dtype, cfg)
         assert oracle.tridiag_residual(a, b, c, d, x).max() <= TOL[dtype]
         err[algo] = np.max(np.abs(x - ref)) / np.max(np.abs(ref))
-    for algo in (ppx.TRI_WM, ppx.TRI_LF):
+    for algo in (ppx.TRI_WM, ppx.TRI_LF, ppx.TRI_CR_PCR):
         assert err[algo] <= 10 * max(err[ppx.TRI_CR_SHFL], np.finfo(dtype).eps), err

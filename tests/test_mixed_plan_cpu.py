@@ -36,7 +36,7 @@ def _cases():
         out.append((ppx.OP_SCAN, ppx.I32, 1 << k, ppx.JOB_SCAN_EXCLUSIVE))
         out.append((ppx.OP_SCAN, ppx.F64, 1 << k, ppx.JOB_SCAN_INCLUSIVE))
     for k in range(5, 11):
-        for fam in (ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_WM, ppx.TRI_LF):
+        for fam in (ppx.TRI_CR, ppx.TRI_PCR, ppx.TRI_CR_PCR, ppx.TRI_WM, ppx.TRI_LF):
             out.append((ppx.OP_TRIDIAG, ppx.F32, 1 << k, fam))
             out.append((ppx.OP_TRIDIAG, ppx.F64, 1 << k, fam))
     return out
@@ -50,8 +50,11 @@ def test_tiles_follow_the_tuned_configuration(tuned, op, dtype, n, algo):
         ref = ppx.tuned_config(op, dtype, n, algo)
     else:
         ref = ppx.resolve_config(op, ppx.C64 if op == ppx.OP_FFT else dtype, n, batch)
-    want = ref.as_tuple()[:5] + (ref.algo & ~PIPE[op],)
-    assert cfg.as_tuple() == want, (cfg, ref)
+    if ref is None:  # no tuned entry: the family's analytical choice
+        assert op == ppx.OP_TRIDIAG and ppx.tri_family(cfg.algo) == algo
+    else:
+        want = ref.as_tuple()[:5] + (ref.algo & ~PIPE[op],)
+        assert cfg.as_tuple() == want, (cfg, ref)
     assert ppx.config_valid(op, ppx.C64 if op == ppx.OP_FFT else dtype, n, cfg)
     # problems per tile: the tuned workgroup's share scaled to the family's
     # block (256 or 1024 threads)
