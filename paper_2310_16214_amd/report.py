@@ -10,7 +10,7 @@ import json
 import sys
 
 DT = {0: "int32", 1: "f32", 2: "f64", 3: "c64"}
-ALGO = {-1: "", 0: " CR", 1: " PCR", 5: " WM", 6: " LF"}
+ALGO = {-1: "", 0: " CR", 1: " PCR", 2: " CR-PCR", 6: " WM", 7: " LF"}
 
 
 def cfg_str(c):
@@ -59,6 +59,21 @@ def tuning(path):
         out.append(f"| {s['op']} {DT[s['dtype']]}{ALGO[s['algo']]} | {s['sizes'][0]}..{s['sizes'][-1]} | "
                    f"{s['phi_analytical']:.3f} | {s['phi_learned']:.3f} | "
                    f"{sum(s['evals_learned']) / len(s['evals_learned']):.1f} | {g:.2f} |")
+    rs = d.get("restricted")
+    if rs:
+        gb = rs["summary"][0]["max_problems_per_block"] if rs["summary"] else 16
+        out += ["", f"Restricted space: candidates with at most {gb} problems per workgroup (the benchmark "
+                    "configuration's problems/block 1..16), from the same exhaustive timings; analytical = the "
+                    "library's selection rule over the subset, learned = its Bayesian search over the subset "
+                    "with the measured times as evaluations.", "",
+                "| group | sizes | Phi analytical | Phi learned | mean learned evals | subset best / full-space best |",
+                "|---|---|---|---|---|---|"]
+        for sm in rs["summary"]:
+            recs = [x for x in rs["records"] if (x["op"], x["dtype"], x["algo"]) == (sm["op"], sm["dtype"], sm["algo"])]
+            worst = min(x["e_full_space_best"] for x in recs)
+            out.append(f"| {sm['op']} {DT[sm['dtype']]}{ALGO[sm['algo']]} | {sm['sizes'][0]}..{sm['sizes'][-1]} | "
+                       f"{sm['phi_analytical']:.3f} | {sm['phi_learned']:.3f} | "
+                       f"{sum(sm['evals_learned']) / len(sm['evals_learned']):.1f} | min {worst:.3f} |")
     print("\n".join(out))
 
 
