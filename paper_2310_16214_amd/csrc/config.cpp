@@ -40,6 +40,7 @@ static int lds_elems(int op, int64_t n, const ppx_config &c) {
             return T > kWave ? c.threads_per_block / kWave : 0;
         }
         default:
+            if (tri_blk(c.algo, n, c.elems_per_thread)) return 2 * c.threads_per_block;  // lane slots, two sets
             if (tri_in_wave(c.algo)) return 0;
             return (int)((c.algo == PPX_TRI_PCR ? 2 : 1) * c.problems_per_block * n);
     }
@@ -96,7 +97,13 @@ int validate_config(int op, int dtype, int64_t n, const ppx_config &c) {
             if ((c.algo & PPX_TRI_PIPE) &&
                 (!tri_in_wave(c.algo) || P * (dtype == PPX_F64 ? 8 : 4) > kTriPipeMaxBytes))
                 return fail(PPX_ECONFIG, "PPX_TRI_PIPE needs an in-wave variant and P * element size <= 128 bytes");
-            if (tri_in_wave(c.algo)) {
+            if (tri_blk(c.algo, n, P)) {  // the hybrid across waves
+                if (c.algo & PPX_TRI_PIPE) return fail(PPX_ECONFIG, "the multi-wave hybrid has no persistent form");
+                if (n / P > kTriBlkMaxLanes) return fail(PPX_ECONFIG, "the hybrid needs n / P <= 1024");
+                if (P > 16) return fail(PPX_ECONFIG, "the hybrid holds at most 16 equations per lane");
+                if (L > tri_blk_max_threads(dtype == PPX_F64 ? 8 : 4, (int)P))
+                    return fail(PPX_ECONFIG, "the multi-wave hybrid with 16 doubles per lane allows at most 512 threads");
+            } else if (tri_in_wave(c.algo)) {
                 if (n / P > kWave) return fail(PPX_ECONFIG, "shuffle variant needs n / P <= 64 (a system within a wave)");
                 if (P > tri_wave_max_p(c.algo, dtype)) return fail(PPX_ECONFIG, "shuffle variant: too many elements per thread");
                 if (L > kTriWaveMaxThreads) return fail(PPX_ECONFIG, "shuffle variant allows at most 256 threads");

@@ -98,6 +98,17 @@ constexpr bool tri_is_family(int algo) {
 }
 // Largest variant code without the persistent flag.
 constexpr int kTriMaxBase = PPX_TRI_LF;
+// The CR -> PCR hybrid also runs systems that span several waves (64 < n / P
+// <= 1024) in one workgroup, the lanes exchanging through LDS.  Workgroup
+// size bound of that kernel: 16 doubles per lane and array need more than the
+// 128 VGPRs a 1024-thread workgroup leaves per lane (it spilled), so those
+// shapes take at most 512 threads.
+constexpr int tri_blk_max_threads(int elem_bytes, int P) { return elem_bytes * P > 64 ? 512 : 1024; }
+constexpr int kTriBlkMaxLanes = 1024;
+// Whether a configuration is the multi-wave hybrid.
+constexpr bool tri_blk(int algo, int64_t n, int64_t P) {
+    return (algo & ~PPX_TRI_PIPE) == PPX_TRI_CR_PCR && P > 0 && n / P > kWave;
+}
 // Largest P * sizeof(element) of the persistent in-wave variants (the second
 // register set): every in-wave P.  With 16 values per lane and array the two
 // register sets need 135-218 VGPRs in float32 (two or three waves per SIMD)
@@ -123,7 +134,9 @@ const void *fft_spec4_kernel(int log2n, bool split);  // radix = P = 4, n = 16..
 // The persistent FFT variants exist for radix = P = 8 or 16.
 constexpr bool fft_pipe_available(int radix, int P) { return radix == P && (P == 8 || P == 16); }
 const void *scan_kernel(int dtype, int P, int algo, bool exclusive = false);
-const void *tridiag_kernel(int dtype, int algo, int P);
+// The kernel of a tridiagonal configuration (n selects the multi-wave
+// hybrid for PPX_TRI_CR_PCR with n / P > 64).
+const void *tridiag_kernel(int dtype, int algo, int P, int64_t n);
 
 // Builds the forward twiddle table for NMAX = 2^kFftLog2NMax in host memory
 // (float pairs from double-precision sincos).

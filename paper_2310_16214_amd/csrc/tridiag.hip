@@ -13,6 +13,9 @@ namespace ppx {
 
 int64_t tridiag_lds_bytes(int n, const ppx_config &c, int dtype) {
     const int64_t es = dtype == PPX_F64 ? 8 : 4;
+    const int64_t P = c.elems_per_thread > 0 ? c.elems_per_thread
+                                             : (int64_t)n * c.problems_per_block / c.threads_per_block;
+    if (tri_blk(c.algo, n, P)) return 6 * (int64_t)c.threads_per_block * es;  // two sets of a, c, d slots
     if (tri_base(c.algo) == PPX_TRI_PCR_REG) {  // exchange buffer: 3 * 64 * min(P, 4) values per wave
         const int64_t waves = (c.threads_per_block + 63) / 64;
         const int64_t P = c.elems_per_thread > 0 ? c.elems_per_thread
@@ -58,9 +61,24 @@ static const void *wave_kernel(int base, int P) {
 template <typename T>
 using TriKernel = void (*)(const T *, const T *, const T *, const T *, T *, int, long long, int);
 
-const void *tridiag_kernel(int dtype, int algo, int P) {
+template <typename T>
+static const void *blk_kernel(int P) {
+    switch (P) {
+        case 2: return reinterpret_cast<const void *>(&k_tridiag_blk<T, 2>);
+        case 4: return reinterpret_cast<const void *>(&k_tridiag_blk<T, 4>);
+        case 8: return reinterpret_cast<const void *>(&k_tridiag_blk<T, 8>);
+        case 16: return reinterpret_cast<const void *>(&k_tridiag_blk<T, 16>);
+        default: return nullptr;
+    }
+}
+
+const void *tridiag_kernel(int dtype, int algo, int P, int64_t n) {
     const int base = tri_base(algo);
     const bool pipe = (algo & PPX_TRI_PIPE) != 0;
+    if (tri_blk(algo, n, P)) {
+        if (pipe) return nullptr;
+        return dtype == PPX_F64 ? blk_kernel<double>(P) : dtype == PPX_F32 ? blk_kernel<float>(P) : nullptr;
+    }
     if (tri_in_wave(algo)) {
         if (dtype == PPX_F64) return pipe ? wave_kernel<double, true>(base, P) : wave_kernel<double, false>(base, P);
         if (dtype == PPX_F32) return pipe ? wave_kernel<float, true>(base, P) : wave_kernel<float, false>(base, P);
@@ -111,7 +129,7 @@ int launch_tridiag(const void *a, const void *b, const void *c, const void *d, v
                    int64_t batch, int dtype, const ppx_config &cfg, hipStream_t s) {
     const DeviceInfo *di = device_info();
     if (!di) return PPX_EDEVICE;
-    const void *k = tridiag_kernel(dtype, cfg.algo, cfg.elems_per_thread);
+    const void *k = tridiag_kernel(dtype, cfg.algo, cfg.elems_per_thread, int64_t(1) << log2n);
     if (!k) return fail(PPX_ECONFIG, "no tridiagonal kernel for this dtype / algo");
     const int64_t lds = tridiag_lds_bytes(1 << log2n, cfg, dtype);
     if (lds > di->lds_per_block)

@@ -656,6 +656,136 @@ __device__ __forceinline__ void tridiag_wave_block(const T *A, const T *B, const
     if (active) wave_store<T, P>(X + base, d);
 }
 
+// ---- the CR -> PCR hybrid for systems spanning several waves
+// (PPX_TRI_CR_PCR with 64 < n / P <= 1024)
+//
+// The same three phases as wave_cr_pcr, one system per n / P consecutive
+// threads of the workgroup, but the lanes of a system cross waves, so every
+// exchange between lanes goes through LDS slots indexed by the thread (xs:
+// two sets of three arrays of L values, L = the workgroup's threads).  Each
+// exchange writes one set, waits at a barrier and reads it; consecutive
+// exchanges alternate sets, so a set is rewritten only after the barrier of
+// the exchange in between, which every thread reaches after its reads of the
+// set.  An absent neighbour (outside the system) is an identity row (zeros).
+// Barriers: log2 P forward levels, log2(n / P) PCR steps, one for the
+// previous lane's unknown.  Every thread of the workgroup reaches each of
+// them (threads of absent systems solve identity rows).
+template <typename T, int P>
+__device__ __forceinline__ void block_cr_pcr(T (&a)[P], T (&c)[P], T (&d)[P], int t, int lps, int tx, int L,
+                                             T *xs) {
+    int set = 0;
+    auto slots = [&]() {
+        T *w = xs + (set & 1) * 3 * L;
+        ++set;
+        return w;
+    };
+    // ---- CR forward levels inside the lane
+#pragma unroll
+    for (int s = 1; 2 * s <= P; s *= 2) {
+        T *w = slots();
+        w[tx] = a[s - 1];
+        w[L + tx] = c[s - 1];
+        w[2 * L + tx] = d[s - 1];
+        __syncthreads();
+        T na = T(0), nc = T(0), nd = T(0);  // equation s - 1 of the next lane
+        if (t + 1 < lps) {
+            na = w[tx + 1];
+            nc = w[L + tx + 1];
+            nd = w[2 * L + tx + 1];
+        }
+#pragma unroll
+        for (int r = 2 * s - 1; r < P; r += 2 * s) {
+            const bool local = r + s < P;
+            unit_eliminate(a[r], c[r], d[r], a[r - s], c[r - s], d[r - s], local ? a[(r + s) % P] : na,
+                           local ? c[(r + s) % P] : nc, local ? d[(r + s) % P] : nd);
+        }
+    }
+    // ---- PCR on the lanes' last equations
+    for (int dl = 1; dl < lps; dl *= 2) {
+        T *w = slots();
+        w[tx] = a[P - 1];
+        w[L + tx] = c[P - 1];
+        w[2 * L + tx] = d[P - 1];
+        __syncthreads();
+        T la = T(0), lc = T(0), ld = T(0), ra = T(0), rc = T(0), rd = T(0);
+        if (t >= dl) {
+            la = w[tx - dl];
+            lc = w[L + tx - dl];
+            ld = w[2 * L + tx - dl];
+        }
+        if (t + dl < lps) {
+            ra = w[tx + dl];
+            rc = w[L + tx + dl];
+            rd = w[2 * L + tx + dl];
+        }
+        unit_eliminate(a[P - 1], c[P - 1], d[P - 1], la, lc, ld, ra, rc, rd);
+    }
+    // ---- the previous lane's last unknown, then back substitution in the lane
+    T *w = slots();
+    w[tx] = d[P - 1];
+    __syncthreads();
+    const T xl = t > 0 ? w[tx - 1] : T(0);
+#pragma unroll
+    for (int s = P / 2; s >= 1; s /= 2) {
+#pragma unroll
+        for (int r = s - 1; r < P; r += 2 * s) {
+            T x = d[r];
+            if (r >= s) x -= a[r] * d[r - s];
+            else x -= a[r] * xl;  // xl = 0 in the first lane, where a[0] = 0 too
+            x -= c[r] * d[r + s];
+            d[r] = x;
+        }
+    }
+}
+
+// One workgroup's share of the multi-wave hybrid: systems [first, first +
+// nsys), lps = n / P > 64 lanes each (several waves), L = the workgroup's
+// threads (a multiple of lps); xs holds 6 * L values.
+template <typename T, int P>
+__device__ __forceinline__ void tridiag_blk_block(const T *A, const T *B, const T *C, const T *D, T *X,
+                                                  int log2n, long long first, int nsys, T *xs, int tx, int L) {
+    const int n = 1 << log2n;
+    const int lps = n / P;
+    const int sys_local = tx / lps;
+    const int t = tx % lps;
+    const bool active = sys_local < nsys;
+    const long long base = (first + sys_local) * n + (long long)t * P;
+    T a[P], b[P], c[P], d[P];
+    if (active) {
+        wave_load<T, P>(A + base, a);
+        wave_load<T, P>(B + base, b);
+        wave_load<T, P>(C + base, c);
+        wave_load<T, P>(D + base, d);
+    } else {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            a[j] = c[j] = d[j] = T(0);
+            b[j] = T(1);
+        }
+    }
+    if (t == 0) a[0] = T(0);            // multiplies the absent x_{-1}
+    if (t == lps - 1) c[P - 1] = T(0);  // multiplies the absent x_n
+#pragma unroll
+    for (int j = 0; j < P; ++j) {  // scale every row to unit diagonal
+        const T r = rcp(b[j]);
+        a[j] *= r;
+        c[j] *= r;
+        d[j] *= r;
+    }
+    block_cr_pcr<T, P>(a, c, d, t, lps, tx, L, xs);
+    if (active) wave_store<T, P>(X + base, d);
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(tri_blk_max_threads(sizeof(T), P)) void k_tridiag_blk(const T *a, const T *b, const T *c, const T *d, T *x,
+                                                      int log2n, long long batch, int gb) {
+    extern __shared__ float4 smem_raw[];  // 6 * blockDim.x values
+    const long long first = (long long)blockIdx.x * gb;
+    const int nsys = (int)min((long long)gb, batch - first);
+    tridiag_blk_block<T, P>(a, b, c, d, x, log2n, first, nsys, reinterpret_cast<T *>(smem_raw), threadIdx.x,
+                            blockDim.x);
+}
+
 // Minimum waves per SIMD the compiler must leave room for: 3 for 16 doubles
 // per lane and array with CR or the LDS-exchange PCR (left alone it allocated
 // up to 253 VGPRs there, two waves per SIMD, so the 16 systems per CU of an

@@ -558,7 +558,7 @@ static const void *kernel_for(int op, int dtype, int64_t n, const ppx_config &c)
     switch (op) {
         case PPX_OP_FFT: return fft_kernel(c.radix, c.elems_per_thread, c.algo, ilog2(n));
         case PPX_OP_SCAN: return scan_kernel(dtype, c.elems_per_thread, c.algo);
-        default: return tridiag_kernel(dtype, c.algo, c.elems_per_thread);
+        default: return tridiag_kernel(dtype, c.algo, c.elems_per_thread, n);
     }
 }
 

@@ -30,14 +30,16 @@ def _solve(arrs_dev, n, batch, dtype, cfg=None, x=None):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048, 4096])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384])
 def test_every_config(cuda, n, dtype):
-    batch = 37 if n <= 1024 else 3
+    batch = 37 if n <= 1024 else 5 if n <= 4096 else 3
     a, b, c, d, xt = inputs.tridiag_input(n, batch, dtype, seed=n)
     dev = [to_dev(v, cuda) for v in (a, b, c, d)]
     ref = oracle.thomas(a, b, c, d)
     cfgs = ppx.enumerate_configs(ppx.OP_TRIDIAG, CODE[dtype], n)
-    assert cfgs
+    if not cfgs:
+        assert dtype == np.float64 and n == 16384  # the only size with no configuration
+        return
     worst_fe = 0.0
     for cfg in cfgs:
         banner(f"tridiag n={n} {np.dtype(dtype).name} {cfg}")
