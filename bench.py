@@ -277,8 +277,8 @@ def c1_and_batched(ppx, dev, stream, nthreads):
 
 
 def serving_point(dev, njobs=2000, load=0.75):
-    """The request loop on a mixed trace (FFT c64, scan f32, CR f32; log2 N
-    uniform 4..14, tridiagonal 4..13; batch uniform 1..4096): saturation of
+    """The request loop on a mixed trace (FFT c64, scan f32, tridiagonal f32
+    with the CR -> PCR hybrid; log2 N uniform 4..14; batch uniform 1..4096): saturation of
     the fused continuous batching and of one launch per request (all jobs
     arriving at once), then Poisson arrivals at `load` x the fused saturation
     rate for both modes; p50 / p99 latency (arrival to completion) and
@@ -295,7 +295,8 @@ def serving_point(dev, njobs=2000, load=0.75):
     trace = sb.make_trace(njobs, load * rate, 1, pools)
     pt = {m: sb.run_trace(trace, m, budget, inflight) for m in ("fused", "per_request")}
     keep = ("p50_ms", "p99_ms", "gelem_s", "hbm_frac", "launches")
-    r = {"jobs": njobs, "mix": "fft c64 / scan f32 / CR f32, log2 N 4..14 (CR 4..13), batch 1..4096",
+    r = {"jobs": njobs, "mix": "fft c64 / scan f32 / tridiagonal f32 (CR->PCR hybrid), log2 N 4..14, "
+                               "batch 1..4096",
          "saturation": {m: {k: round(v[k], 4) for k in ("gelem_s", "hbm_frac", "launches")}
                         for m, v in sat.items()},
          "load": load, "offered_jobs_per_s": round(load * rate, 1),

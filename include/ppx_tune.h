@@ -101,6 +101,13 @@ int ppx_analytical_pick(const ppx_device_model *m, const ppx_config *cands,
 int ppx_analytical_select(int op, int dtype, int64_t n, int64_t batch, const ppx_config *cands,
                           int ncands, int *chosen);
 
+/*
+ * Consistency check of the mixed launch (launch_mixed): PPX_OK if every
+ * family of tile shapes has its persistent kernel in the library, else
+ * PPX_EINVAL naming the first family without one.  Needs no GPU.
+ */
+int ppx_mixed_families_complete(void);
+
 /* Evaluator: the cost (e.g. median microseconds) of a candidate; a negative
  * value marks a failed or timed-out run. */
 typedef double (*ppx_eval_fn)(const ppx_config *cfg, void *user);

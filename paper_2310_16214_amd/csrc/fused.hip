@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "mixed.h"
@@ -27,18 +28,24 @@ int64_t mix_lds_bytes(int fam) {
     switch (fam) {
         case kFamFft256: return 256 * 16 * 8;    // complex exchange, P = 16
         case kFamFft1024: return 1024 * 16 * 8;  // complex exchange, P = 16
+        case kFamFft1024P8: return 1024 * 8 * 8;  // complex exchange, P = 8
         case kFamTriW32:
         case kFamTriW32H: return 4 * 3 * 64 * 4 * 4;  // PCR LDS exchange: 4 waves, 3 * 64 * 4 floats each
         case kFamTriW64:
         case kFamTriW64H: return 4 * 3 * 64 * 4 * 8;
         case kFamTriLds: return kMixTriLdsBudget;
+        case kFamTriBlk32:
+        case kFamTriBlk32H: return 6 * 1024 * 4;  // two sets of a, c, d lane slots
+        case kFamTriBlk64: return 6 * 1024 * 8;
+        case kFamTriBlk64H: return 6 * 512 * 8;
         default: return 0;  // scan: static wave-total slots only
     }
 }
 
+// The family's kernel, from whichever translation unit instantiates it.
 static const void *mix_kernel(int fam) {
-    if (fam == kFamFft256 || fam == kFamFft1024) return mix_fft_kernel(fam);
-    if (fam == kFamScan256 || fam == kFamScan1024) return mix_scan_kernel(fam);
+    if (const void *k = mix_fft_kernel(fam)) return k;
+    if (const void *k = mix_scan_kernel(fam)) return k;
     return mix_tri_kernel(fam);
 }
 
@@ -98,7 +105,7 @@ int mix_plan(const ppx_job &j, MixPlan &m) {
         }
         const int P = c.elems_per_thread;
         const int64_t T = j.n / P;
-        m.family = T <= 256 ? kFamFft256 : kFamFft1024;
+        m.family = T <= 256 ? kFamFft256 : P == 8 ? kFamFft1024P8 : kFamFft1024;
         const bool split = (c.algo & PPX_FFT_LDS_SPLIT) != 0;
         m.shape = mix_fft_shape(log2n, P, split);
         m.per_tile = (int)(mix_block(m.family) / T);
@@ -114,7 +121,12 @@ int mix_plan(const ppx_job &j, MixPlan &m) {
     } else {
         c.algo = tri_base(c.algo);
         const bool f64 = j.dtype == PPX_F64;
-        if (tri_in_wave(c.algo)) {
+        if (tri_blk(c.algo, j.n, c.elems_per_thread)) {  // the hybrid across waves
+            const int P = c.elems_per_thread;
+            m.family = !f64 ? (P == 16 ? kFamTriBlk32H : kFamTriBlk32) : P == 16 ? kFamTriBlk64H : kFamTriBlk64;
+            m.shape = ilog2(P) - 1;
+            m.per_tile = (int)(mix_block(m.family) / (j.n / P));
+        } else if (tri_in_wave(c.algo)) {
             const int P = c.elems_per_thread;
             m.family = mix_triw_family(f64, c.algo, P);
             m.shape = mix_triw_shape(c.algo, ilog2(P));
@@ -310,12 +322,13 @@ int mix_prepare_kernels() {
     if (!di) return PPX_EDEVICE;
     for (int f = 0; f < kMixFamilies; ++f) {
         const void *k = mix_kernel(f);
+        if (!k) return fail(PPX_EHIP, "mixed launch: no kernel for family " + std::to_string(f));
         const int64_t lds = mix_lds_bytes(f);
         (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, mix_block(f), (size_t)lds) != hipSuccess ||
             per_cu < 1)
-            return fail(PPX_EHIP, "a mixed-launch kernel cannot be resident");
+            return fail(PPX_EHIP, "mixed launch: the kernel of family " + std::to_string(f) + " cannot be resident");
         g_resident[f] = per_cu * di->cus;
     }
     g_prepared = true;
@@ -453,6 +466,12 @@ extern "C" int launch_mixed_noalloc(const ppx_job *jobs, int njobs, void *stream
 extern "C" int launch_mixed(const ppx_job *jobs, int njobs, void *stream) {
     ppx::fail(PPX_OK, "");
     return ppx::launch_mixed_impl(jobs, njobs, static_cast<hipStream_t>(stream), nullptr);
+}
+
+extern "C" int ppx_mixed_families_complete(void) {
+    for (int f = 0; f < ppx::kMixFamilies; ++f)
+        if (!ppx::mix_kernel(f)) return ppx::fail(PPX_EINVAL, "mixed launch: no kernel for family " + std::to_string(f));
+    return PPX_OK;
 }
 
 extern "C" int ppx_mixed_tile_config(const ppx_job *job, ppx_config *cfg) {

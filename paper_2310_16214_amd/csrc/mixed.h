@@ -18,7 +18,8 @@
 //   scan, likewise by T;
 //   tridiagonal inside a wave (n/P <= 64), float32 / float64, each in a
 //   light and a heavy register tier (mix_triw_family);
-//   tridiagonal through LDS (CR and PCR of larger systems).
+//   tridiagonal through LDS (CR and PCR of larger systems);
+//   the CR -> PCR hybrid of systems spanning several waves.
 // One persistent kernel per family pulls tile indices from the family's
 // counter until its tiles are drained.  A launch runs, in one stream, the
 // table expansion and then the kernels of the families that have tiles.
@@ -34,7 +35,8 @@ namespace ppx {
 
 enum MixFamily : int {
     kFamFft256 = 0,
-    kFamFft1024,
+    kFamFft1024,   // P = 16
+    kFamFft1024P8, // P = 8: half the LDS and fewer registers, two workgroups per CU
     kFamScan256,
     kFamScan1024,
     kFamTriW32,    // in-wave, float32: CR, WM, LF with P <= 8
@@ -42,6 +44,10 @@ enum MixFamily : int {
     kFamTriW64,    // in-wave, float64, P <= 8
     kFamTriW64H,   // in-wave, float64, P = 16
     kFamTriLds,    // LDS CR / PCR, float32 and float64
+    kFamTriBlk32,  // the CR -> PCR hybrid across waves, float32, P <= 8
+    kFamTriBlk32H, // the same, float32, P = 16
+    kFamTriBlk64,  // the same, float64, P <= 8
+    kFamTriBlk64H, // the same, float64, P = 16 (512-thread workgroups)
     kMixFamilies
 };
 
@@ -103,7 +109,11 @@ constexpr int mix_tril_shape(bool f64, bool pcr) { return (f64 ? 2 : 0) + (pcr ?
 
 // Block size and dynamic LDS bytes of each family's kernel.
 constexpr int mix_block(int fam) {
-    return fam == kFamFft1024 || fam == kFamScan1024 || fam == kFamTriLds ? 1024 : 256;
+    return fam == kFamFft1024 || fam == kFamFft1024P8 || fam == kFamScan1024 || fam == kFamTriLds ||
+                   fam == kFamTriBlk32 || fam == kFamTriBlk32H || fam == kFamTriBlk64
+               ? 1024
+           : fam == kFamTriBlk64H ? 512
+                                  : 256;
 }
 constexpr int kMixTriLdsBudget = 128 * 1024;
 int64_t mix_lds_bytes(int fam);

@@ -88,6 +88,34 @@ __global__ __launch_bounds__(1024) void k_mix_tril(const char *tables, const flo
     });
 }
 
+// The hybrid across waves: a tile is mix_block(FAM) / (n / P) systems, the
+// lanes exchanging through LDS slots (two sets of a, c, d per thread).
+template <int FAM, int LP>
+__device__ __forceinline__ void mix_trib_dispatch(const MixJob &j, long long first, int count, void *smem, int tx) {
+    if constexpr (LP <= 4) {
+        using T = typename std::conditional<FAM == kFamTriBlk32 || FAM == kFamTriBlk32H, float, double>::type;
+        constexpr int P = 1 << LP;
+        if constexpr ((FAM == kFamTriBlk32H || FAM == kFamTriBlk64H) == (P == 16)) {
+            if (j.shape == LP - 1) {
+                tridiag_blk_block<T, P>(static_cast<const T *>(j.p[0]), static_cast<const T *>(j.p[1]),
+                                        static_cast<const T *>(j.p[2]), static_cast<const T *>(j.p[3]),
+                                        static_cast<T *>(j.out), j.log2n, first, count, static_cast<T *>(smem), tx,
+                                        mix_block(FAM));
+                return;
+            }
+        }
+        mix_trib_dispatch<FAM, LP + 1>(j, first, count, smem, tx);
+    }
+}
+
+template <int FAM>
+__global__ __launch_bounds__(mix_block(FAM)) void k_mix_trib(const char *tables, const float2 *) {
+    extern __shared__ float4 smem[];
+    mix_tile_loop<FAM>(tables, [&](const MixJob &j, long long first, int count, int tx) {
+        mix_trib_dispatch<FAM, 1>(j, first, count, smem, tx);
+    });
+}
+
 const void *mix_tri_kernel(int fam) {
     switch (fam) {
         case kFamTriW32: return reinterpret_cast<const void *>(&k_mix_triw<kFamTriW32>);
@@ -95,6 +123,10 @@ const void *mix_tri_kernel(int fam) {
         case kFamTriW64: return reinterpret_cast<const void *>(&k_mix_triw<kFamTriW64>);
         case kFamTriW64H: return reinterpret_cast<const void *>(&k_mix_triw<kFamTriW64H>);
         case kFamTriLds: return reinterpret_cast<const void *>(&k_mix_tril);
+        case kFamTriBlk32: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk32>);
+        case kFamTriBlk32H: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk32H>);
+        case kFamTriBlk64: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk64>);
+        case kFamTriBlk64H: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk64H>);
         default: return nullptr;
     }
 }

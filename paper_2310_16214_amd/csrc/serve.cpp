@@ -190,13 +190,21 @@ void retire(ppx_server *s) {
 
 // Admits pending jobs in arrival order while they fit; stops at the first
 // that does not (no overtaking), so a large job is delayed, never starved.
+// One launch takes at most budget / max_inflight bytes of footprint (a job
+// larger than that goes alone): with every job pending at once, one launch
+// would otherwise take the whole budget, the next could be admitted only
+// after it completed, and the GPU would idle while the host retires,
+// admits and launches; with the cap a launch is always queued behind the
+// running one.
 std::vector<int64_t> admit(ppx_server *s, int64_t tile_cap, int job_cap) {
     std::vector<int64_t> out;
-    int64_t tiles = 0;
+    int64_t tiles = 0, bytes = 0;
+    const int64_t launch_cap = s->budget / std::max(1, s->max_inflight);
     const double t = s->now_us();
     while (!s->pending.empty() && (int)out.size() < job_cap) {
         Job &j = s->jobs[s->pending.front()];
         if (s->used + j.footprint > s->budget) break;
+        if (!out.empty() && bytes + j.footprint > launch_cap) break;
         const int64_t jt = mixed_tile_count(&j.job, 1);  // planned at submit: >= 1
         if (!out.empty() && tiles + jt > tile_cap) break;
         if (!j.job.out) {
@@ -207,6 +215,7 @@ std::vector<int64_t> admit(ppx_server *s, int64_t tile_cap, int job_cap) {
                                          : static_cast<void *>(s->arena_base + off);
         }
         s->used += j.footprint;
+        bytes += j.footprint;
         s->peak = std::max(s->peak, s->used);
         j.admit_us = t;
         tiles += jt;

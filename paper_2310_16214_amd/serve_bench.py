@@ -2,9 +2,9 @@
 launch per request, on the same GPU and the same arrival trace.
 
 Requests are whole batched jobs: operation FFT (complex FP32), inclusive scan
-(FP32) or tridiagonal CR (FP32), equiprobable; per-job N log-uniform on
-2^4..2^14 (tridiagonal 2^4..2^13, the largest system one fused tile's LDS
-holds); batch count uniform on 1..4096; Poisson arrivals.  Job inputs are
+(FP32) or tridiagonal solve (FP32, the CR -> PCR hybrid family, which holds
+every size in registers), equiprobable; per-job N log-uniform on 2^4..2^14;
+batch count uniform on 1..4096; Poisson arrivals.  Job inputs are
 windows into resident, seeded device pools; outputs are allocated by the
 server from its HBM budget and released when the job completes.
 
@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 OPS = ("fft", "scan", "tridiag")
+TRI_FAMILY = 2  # PPX_TRI_CR_PCR, the CR -> PCR hybrid family
 
 
 class Pools:
@@ -46,7 +47,7 @@ class Pools:
         self.fft = torch.from_numpy(inputs.fft_input(1 << 14, 4096, seed=seed).reshape(-1)).to(dev)
         self.scan = torch.from_numpy(inputs.scan_input(1 << 14, 4096, np.float32, seed=seed + 1)
                                      .reshape(-1)).to(dev)
-        a, b, c, d, _ = inputs.tridiag_input(1 << 13, 4096, np.float32, seed=seed + 2)
+        a, b, c, d, _ = inputs.tridiag_input(1 << 14, 4096, np.float32, seed=seed + 2)
         self.tri = [torch.from_numpy(v.reshape(-1)).to(dev) for v in (a, b, c, d)]
 
 
@@ -65,7 +66,7 @@ def _make_job(op, n, batch, rng, pools):
     else:
         off = int(rng.integers(0, pools.tri[0].numel() - elems + 1)) & ~3
         p = [v.data_ptr() + 4 * off for v in pools.tri]
-        job = ppx.make_job(ppx.OP_TRIDIAG, ppx.F32, n, batch, p[0], None, algo=ppx.TRI_CR,
+        job = ppx.make_job(ppx.OP_TRIDIAG, ppx.F32, n, batch, p[0], None, algo=TRI_FAMILY,
                            b=p[1], c=p[2], d=p[3])
         bpe = 20
     return job, dict(op=op, n=n, batch=batch, elems=elems, bytes=bpe * elems, offset=off)
@@ -78,7 +79,7 @@ def make_trace(njobs, rate_per_s, seed, pools):
     t = 0.0
     for _ in range(njobs):
         op = OPS[rng.integers(0, 3)]
-        ln = int(rng.integers(4, 15 if op != "tridiag" else 14))
+        ln = int(rng.integers(4, 15))
         n = 1 << ln
         batch = int(rng.integers(1, 4097))
         if np.isfinite(rate_per_s):
@@ -194,9 +195,8 @@ def run(njobs=10000, loads=(0.25, 0.5, 0.75, 0.9), budget=4 << 30, max_inflight=
     print(json.dumps(online), flush=True)
     return dict(online=online, saturation=sat, saturation_jobs_per_s=jobs_per_s, points=points,
                 backpressure_half_budget=back, budget_bytes=budget, max_inflight=max_inflight,
-                njobs=njobs, mix="ops equiprobable {fft c64, scan f32, tridiag CR f32}; "
-                               "log2 N uniform 4..14 (tridiag 4..13); batch uniform 1..4096; "
-                               "Poisson arrivals")
+                njobs=njobs, mix="ops equiprobable {fft c64, scan f32, tridiag f32 (CR->PCR hybrid family)}; "
+                               "log2 N uniform 4..14; batch uniform 1..4096; Poisson arrivals")
 
 
 def main():

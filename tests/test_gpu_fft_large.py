@@ -1,6 +1,7 @@
 """GPU parity of the two-pass large-N FFT (16384 < N <= 2^23) against the
 oracle: every plan at N = 2^15 and 2^16 on whole problems (every bin by its
-definition), every plan at 2^20 .. 2^23 (narrow pass-B tiles for columns of
+definition), the tuned and the default plan on one whole problem at 2^17 and
+2^18, every plan at 2^20 .. 2^23 (narrow pass-B tiles for columns of
 more than 1024 values) and the default plan at full size up to 2^23 on
 sampled bins (each bin by its definition) plus Parseval, forward and
 inverse.  Bar: per-problem relative L2 <= 1e-5 * log2 N."""
@@ -39,6 +40,20 @@ def test_every_plan_matches_oracle(cuda, n):
         worst = max(worst, err, erri)
         assert err <= fft_tol(n) and erri <= fft_tol(n), (p, err, erri)
     print(f"n={n}: {len(plans)} plans, worst rel-L2 {worst:.3e}")
+
+
+@pytest.mark.parametrize("ln", [17, 18])
+def test_tuned_plan_every_bin(cuda, ln):
+    """One problem at 2^17 and 2^18, the tuned (NULL) and the default plan,
+    forward: every bin against its O(N) definition."""
+    n = 1 << ln
+    x = inputs.fft_input(n, 1, seed=ln + 60)
+    ref = oracle.dft_bins(x, np.arange(n))
+    for plan in (None, ppx.default_fft_plan(n)):
+        banner(f"fft large n={n} every bin, plan {plan}")
+        err = oracle.rel_l2(_run(x, n, 1, plan), ref).max()
+        print(f"n={n} plan {plan}: rel-L2 {err:.3e} (bound {fft_tol(n):.1e})")
+        assert err <= fft_tol(n), (plan, err)
 
 
 def _sampled_bins(x, y, n, rng, problems, inverse=False):

@@ -29,7 +29,8 @@ MIX = ([("fft", ppx.C64, 1 << k, b, d) for k, b, d in
           [(ppx.F32, 5, 999, ppx.TRI_CR), (ppx.F32, 7, 201, ppx.TRI_PCR), (ppx.F32, 10, 37, ppx.TRI_CR),
            (ppx.F32, 10, 23, ppx.TRI_PCR), (ppx.F64, 6, 300, ppx.TRI_WM), (ppx.F64, 9, 41, ppx.TRI_LF),
            (ppx.F64, 10, 17, ppx.TRI_CR), (ppx.F32, 8, 61, ppx.TRI_LF), (ppx.F32, 12, 3, ppx.TRI_CR),
-           (ppx.F64, 11, 5, ppx.TRI_PCR)]])
+           (ppx.F64, 11, 5, ppx.TRI_PCR), (ppx.F32, 13, 3, ppx.TRI_CR_PCR), (ppx.F64, 12, 3, ppx.TRI_CR_PCR),
+           (ppx.F32, 10, 37, ppx.TRI_CR_PCR), (ppx.F32, 14, 2, ppx.TRI_CR_PCR)]])
 
 
 @pytest.fixture(scope="module")

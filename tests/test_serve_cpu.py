@@ -16,9 +16,9 @@ def test_admission_respects_budget_and_fifo():
     # each job: 1024 * 64 int32 in + out = 512 KiB; budget holds three
     s = ppx.Server(3 * 512 * 1024, max_inflight=4, flags=ppx.SERVE_NULL_DEVICE)
     ids = [s.submit(_job(1024, 64)) for _ in range(5)]
-    assert s.progress() == 3                      # three fit, in one launch
-    st = s.stats()
-    assert st["admitted"] == 3 and st["pending"] == 2 and st["launches"] == 1
+    assert s.progress() == 3                      # three fit (one per launch: each launch
+    st = s.stats()                                # takes at most budget / max_inflight)
+    assert st["admitted"] == 3 and st["pending"] == 2 and st["launches"] == 3
     assert st["used_bytes"] == 3 * 512 * 1024
     assert s.progress() == 0                      # the launch completes; no room yet
     done = s.poll()
@@ -29,6 +29,23 @@ def test_admission_respects_budget_and_fifo():
     s.release(ids[2])
     assert s.progress() == 1
     assert s.stats()["peak_used_bytes"] <= 3 * 512 * 1024
+
+
+def test_launch_takes_its_share_of_the_budget():
+    # budget for four jobs, two launches in flight: two launches of two jobs
+    # each, so one is queued behind the other instead of one taking it all
+    s = ppx.Server(4 * 512 * 1024, max_inflight=2, flags=ppx.SERVE_NULL_DEVICE)
+    for _ in range(6):
+        s.submit(_job(1024, 64))
+    assert s.progress() == 4
+    st = s.stats()
+    assert st["launches"] == 2 and st["admitted"] == 4 and st["max_inflight_seen"] == 2
+    # a job larger than the share still goes, alone
+    s2 = ppx.Server(2 * 512 * 1024, max_inflight=4, flags=ppx.SERVE_NULL_DEVICE)
+    big = s2.submit(_job(1024, 96))               # 768 KiB > 256 KiB share
+    assert s2.progress() == 1 and s2.stats()["launches"] == 1
+    s2.progress()
+    assert [c.id for c in s2.poll()] == [big]
 
 
 def test_large_job_is_delayed_not_overtaken():
