@@ -322,6 +322,13 @@ typedef struct ppx_job {
  * launch (PPX_EINVAL beyond).
  */
 int launch_mixed(const ppx_job *jobs, int njobs, void *stream);
+/* A job of at least this many elements (n * batch) whose configuration with
+ * cfg == NULL is a persistent variant runs, inside launch_mixed, as that
+ * single call, after the tiled jobs: it fills the GPU by itself, and the
+ * persistent kernel prefetches its next group while computing the current
+ * one, which a tile of the shared loop cannot.  Still a pure function of the
+ * job, so its output is the same alone or in any mix. */
+#define PPX_MIXED_DIRECT_ELEMS (1LL << 22)
 
 /*
  * launch_mixed_noalloc -- launch_mixed for callers that cannot allocate
@@ -349,7 +356,9 @@ int launch_mixed_noalloc(const ppx_job *jobs, int njobs, void *stream);
  * per tile (> 0) or a negative PPX_E* code, and writes to *cfg (if not
  * NULL) the single-call configuration whose arithmetic the tiles follow:
  * the configuration of the job's call with cfg == NULL, with the persistent
- * flag cleared (a launch strategy, not arithmetic); for an FFT whose tuned
+ * flag cleared (a launch strategy, not arithmetic); for a job that runs as
+ * its own call (PPX_MIXED_DIRECT_ELEMS), that configuration unchanged and its
+ * problems per workgroup; for an FFT whose tuned
  * shape is not radix = P in {8, 16} (or 4 with n <= 1024), the radix = P
  * shape used instead.  A single call with that configuration gives the same
  * bits as the job in a mixed launch.  Needs no GPU when the configuration

@@ -88,6 +88,16 @@ int mix_plan(const ppx_job &j, MixPlan &m) {
     if (int rc = job_config(j, c)) return rc;
     const int log2n = ilog2(j.n);
     m.flags = 0;
+    const int pipe = j.op == PPX_OP_FFT ? PPX_FFT_LDS_PIPE : j.op == PPX_OP_SCAN ? PPX_SCAN_KS_PIPE : PPX_TRI_PIPE;
+    if ((c.algo & pipe) && j.n * j.batch >= PPX_MIXED_DIRECT_ELEMS) {
+        m.direct = true;
+        m.family = m.shape = -1;
+        m.per_tile = c.problems_per_block;
+        m.ntiles = 0;
+        m.cfg = c;
+        return PPX_OK;
+    }
+    m.direct = false;
     if (j.op == PPX_OP_FFT) {
         c.algo &= ~PPX_FFT_LDS_PIPE;  // the launch is persistent itself
         if (!fft_mix_shape(c.radix, c.elems_per_thread, j.n)) {
@@ -196,18 +206,24 @@ int64_t mixed_tile_count(const ppx_job *jobs, int njobs) {
 // Plans every job and writes the header and job records into `buf` (at
 // least mix_table_bytes(njobs, 0) bytes).  Returns the family mask, or a
 // negative error.  ntiles_out receives the total tile count.
-int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_out) {
+int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_out, int *direct, int *ndirect) {
     if (!jobs || njobs < 1) return fail(PPX_EINVAL, "no jobs");
     if (njobs > kMixMaxJobs) return fail(PPX_EINVAL, "too many jobs for one mixed launch");
     auto *h = reinterpret_cast<MixHeader *>(buf);
     auto *rec = reinterpret_cast<MixJob *>(buf + kMixHeaderBytes);
     std::memset(h, 0, kMixHeaderBytes);
     int64_t fam_tiles[kMixFamilies] = {};
+    int nrec = 0;
+    *ndirect = 0;
     for (int i = 0; i < njobs; ++i) {
         MixPlan m;
         if (int rc = check_job(jobs[i], &m)) return rc;
+        if (m.direct) {
+            direct[(*ndirect)++] = i;
+            continue;
+        }
         const ppx_job &j = jobs[i];
-        MixJob &r = rec[i];
+        MixJob &r = rec[nrec];
         r.shape = m.shape;
         r.flags = m.flags;
         r.log2n = ilog2(j.n);
@@ -221,6 +237,7 @@ int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_
         r.p[3] = j.d;
         r.out = j.out;
         fam_tiles[m.family] += m.ntiles;
+        ++nrec;
     }
     int64_t total = 0;
     int mask = 0;
@@ -231,8 +248,8 @@ int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_
         if (fam_tiles[f]) mask |= 1 << f;
     }
     if (total > kMixMaxTiles) return fail(PPX_EINVAL, "too many tiles for one mixed launch");
-    h->njobs = (unsigned)njobs;
-    h->tiles_off = (unsigned)((kMixHeaderBytes + (int64_t)njobs * sizeof(MixJob) + 15) & ~int64_t(15));
+    h->njobs = (unsigned)nrec;
+    h->tiles_off = (unsigned)((kMixHeaderBytes + (int64_t)nrec * sizeof(MixJob) + 15) & ~int64_t(15));
     *ntiles_out = total;
     return mask;
 }
@@ -362,18 +379,41 @@ int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEve
     Slot &s = m->slots[m->next];
     if (s.used && hipEventSynchronize(s.done) != hipSuccess) return fail(PPX_EHIP, "slot wait failed");
     int64_t ntiles = 0;
-    const int mask = mix_build_tables(jobs, njobs, s.h_stage, &ntiles);
+    std::vector<int> direct(njobs);
+    int ndirect = 0;
+    const int mask = mix_build_tables(jobs, njobs, s.h_stage, &ntiles, direct.data(), &ndirect);
     if (mask < 0) return mask;
-    m->next = (m->next + 1) % kSlots;
-    hipGraphExec_t exec = nullptr;
-    if (int rc = slot_graph(m, s, mask, &exec)) return rc;
-    hipError_t e = hipMemcpyAsync(s.d_tables, s.h_stage, kMixHeaderBytes + (size_t)njobs * sizeof(MixJob),
-                                  hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipGraphLaunch(exec, stream);
-    if (e == hipSuccess) e = hipEventRecord(s.done, stream);
-    if (e == hipSuccess && done_event) e = hipEventRecord(done_event, stream);
-    s.used = true;
+    direct.resize(ndirect);
+    hipError_t e = hipSuccess;
+    if (mask) {  // the tiled jobs: one table copy and the slot's graph
+        m->next = (m->next + 1) % kSlots;
+        hipGraphExec_t exec = nullptr;
+        if (int rc = slot_graph(m, s, mask, &exec)) return rc;
+        const size_t nrec = reinterpret_cast<const MixHeader *>(s.h_stage)->njobs;
+        e = hipMemcpyAsync(s.d_tables, s.h_stage, kMixHeaderBytes + nrec * sizeof(MixJob), hipMemcpyHostToDevice,
+                           stream);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, stream);
+        if (e == hipSuccess) e = hipEventRecord(s.done, stream);
+        s.used = true;
+        if (e != hipSuccess) return fail_hip(e, "mixed launch");
+    }
+    for (int i : direct) {  // jobs that fill the GPU alone: their tuned single calls, after the tiles
+        MixPlan p;
+        (void)mix_plan(jobs[i], p);  // planned once already: cannot fail now
+        if (int rc = mix_launch_direct(jobs[i], p.cfg, stream)) return rc;
+    }
+    if (done_event) e = hipEventRecord(done_event, stream);
     return fail_hip(e, "mixed launch");
+}
+
+int mix_launch_direct(const ppx_job &j, const ppx_config &c, hipStream_t s) {
+    switch (j.op) {
+        case PPX_OP_FFT: return fft_batched(j.in, j.out, j.n, j.batch, j.direction, &c, s);
+        case PPX_OP_SCAN:
+            return j.algo == PPX_JOB_SCAN_EXCLUSIVE ? scan_exclusive_batched(j.in, j.out, j.n, j.batch, j.dtype, &c, s)
+                                                    : scan_batched(j.in, j.out, j.n, j.batch, j.dtype, &c, s);
+        default: return tridiag_batched(j.in, j.b, j.c, j.d, j.out, j.n, j.batch, j.dtype, &c, s);
+    }
 }
 
 // ------------------------------------------------ the allocation-free launch
@@ -435,25 +475,35 @@ int launch_mixed_noalloc_impl(const ppx_job *jobs, int njobs, hipStream_t stream
     // header and job records, built on the stack
     alignas(16) char table[kMixHeaderBytes + sizeof(MixJob) * kNoAllocJobs];
     int64_t ntiles = 0;
-    const int mask = mix_build_tables(jobs, njobs, table, &ntiles);
+    int direct[kNoAllocJobs], ndirect = 0;
+    const int mask = mix_build_tables(jobs, njobs, table, &ntiles, direct, &ndirect);
     if (mask < 0) return mask;
     if (ntiles > kNoAllocTiles)
         return fail(PPX_EINVAL, "launch_mixed_noalloc takes at most PPX_NOALLOC_MAX_TILES (262144) tiles");
     char *d = noalloc_scratch();
     if (!d) return PPX_EDEVICE;
-    const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
-    const unsigned bytes = (unsigned)(kMixHeaderBytes + sizeof(MixJob) * (size_t)njobs);
-    TableChunk c;
-    for (unsigned off = 0; off < bytes; off += kTableChunk) {
-        c.offset = off;
-        c.bytes = std::min<unsigned>(kTableChunk, bytes - off);
-        std::memcpy(c.data, table + off, c.bytes);
-        hipLaunchKernelGGL(k_mix_table_copy, dim3(1), dim3(256), 0, stream, d, c);
-        if (int rc = fail_hip(hipGetLastError(), "table copy")) return rc;
+    if (mask) {
+        const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
+        const unsigned bytes = (unsigned)(kMixHeaderBytes + sizeof(MixJob) * (size_t)h->njobs);
+        TableChunk c;
+        for (unsigned off = 0; off < bytes; off += kTableChunk) {
+            c.offset = off;
+            c.bytes = std::min<unsigned>(kTableChunk, bytes - off);
+            std::memcpy(c.data, table + off, c.bytes);
+            hipLaunchKernelGGL(k_mix_table_copy, dim3(1), dim3(256), 0, stream, d, c);
+            if (int rc = fail_hip(hipGetLastError(), "table copy")) return rc;
+        }
+        int64_t fam_tiles[kMixFamilies];
+        for (int f = 0; f < kMixFamilies; ++f) fam_tiles[f] = h->ntiles[f];
+        if (int rc = mix_enqueue(d, mask, fam_tiles, static_cast<const float2 *>(device_info()->twiddles), stream))
+            return rc;
     }
-    int64_t fam_tiles[kMixFamilies];
-    for (int f = 0; f < kMixFamilies; ++f) fam_tiles[f] = h->ntiles[f];
-    return mix_enqueue(d, mask, fam_tiles, static_cast<const float2 *>(device_info()->twiddles), stream);
+    for (int k = 0; k < ndirect; ++k) {  // jobs that fill the GPU alone: their tuned single calls
+        MixPlan p;
+        (void)mix_plan(jobs[direct[k]], p);
+        if (int rc = mix_launch_direct(jobs[direct[k]], p.cfg, stream)) return rc;
+    }
+    return PPX_OK;
 }
 
 }  // namespace ppx

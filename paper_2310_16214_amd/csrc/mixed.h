@@ -135,10 +135,15 @@ constexpr int kMixExpandThreads = 256;
 // arithmetic the tiles follow (the tuned one with the persistent flag
 // cleared; a radix = P substitute where the tuned FFT shape is not one the
 // families hold).
+// A job that by itself fills the GPU and whose tuned configuration is a
+// persistent variant (which prefetches the next group while computing the
+// current one, something a tile of the shared loop cannot do) runs as its
+// own single call with that configuration instead (direct = true, no tiles).
 struct MixPlan {
     int family, shape, per_tile, flags;
     int64_t ntiles;
     ppx_config cfg;
+    bool direct;
 };
 // The single-call configuration of a job with cfg == NULL (tridiagonal: the
 // job's family).
@@ -146,7 +151,11 @@ int job_config(const ppx_job &j, ppx_config &c);
 int mix_plan(const ppx_job &j, MixPlan &m);
 // Plans every job and writes the header and job records into buf; returns
 // the mask of families with tiles or a negative error.
-int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_out);
+// Direct jobs get no record; their indices go to direct[0 .. *ndirect)
+// (room for njobs entries).
+int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_out, int *direct, int *ndirect);
+// Launches job j alone with configuration c (a direct job).
+int mix_launch_direct(const ppx_job &j, const ppx_config &c, hipStream_t s);
 // Occupancy of every family kernel on the current device (once).
 int mix_prepare_kernels();
 // Expansion plus the family kernels of `mask`, on stream s.

@@ -574,6 +574,14 @@ def launch_mixed(jobs, stream=None):
 
 
 NOALLOC_MAX_JOBS, NOALLOC_MAX_TILES = 256, 262144
+MIXED_DIRECT_ELEMS = 1 << 22  # a persistent-configured job this large runs as its own call
+PIPE_FLAG = {0: 2, 1: 2, 2: 8}  # the persistent flag of each op's algo codes (FFT, scan, tridiagonal)
+
+
+def mixed_job_is_direct(op, n, batch, cfg):
+    """Whether launch_mixed runs a job with resolved configuration cfg as its
+    own single call (see PPX_MIXED_DIRECT_ELEMS in include/ppx.h)."""
+    return bool(cfg.algo & PIPE_FLAG[op]) and n * batch >= MIXED_DIRECT_ELEMS
 
 
 def launch_mixed_noalloc(jobs, stream=None):

@@ -30,7 +30,10 @@ MIX = ([("fft", ppx.C64, 1 << k, b, d) for k, b, d in
            (ppx.F32, 10, 23, ppx.TRI_PCR), (ppx.F64, 6, 300, ppx.TRI_WM), (ppx.F64, 9, 41, ppx.TRI_LF),
            (ppx.F64, 10, 17, ppx.TRI_CR), (ppx.F32, 8, 61, ppx.TRI_LF), (ppx.F32, 12, 3, ppx.TRI_CR),
            (ppx.F64, 11, 5, ppx.TRI_PCR), (ppx.F32, 13, 3, ppx.TRI_CR_PCR), (ppx.F64, 12, 3, ppx.TRI_CR_PCR),
-           (ppx.F32, 10, 37, ppx.TRI_CR_PCR), (ppx.F32, 14, 2, ppx.TRI_CR_PCR)]])
+           (ppx.F32, 10, 37, ppx.TRI_CR_PCR), (ppx.F32, 14, 2, ppx.TRI_CR_PCR)]]
+       # jobs of at least 2^22 elements with persistent tuned configurations:
+       # their own tuned calls inside the launch
+       + [("fft", ppx.C64, 1 << 14, 300, -1), ("scan", ppx.F32, 1 << 13, 600, 0)])
 
 
 @pytest.fixture(scope="module")
@@ -110,6 +113,8 @@ def test_each_job_runs_its_tuned_configuration(cuda, tuned):
         ref = ppx.tuned_config(op, dt, n, extra) if kind == "tri" else ppx.resolve_config(op, dt, n, batch)
         if ref is None:  # no tuned entry (n > 1024): the family's analytical choice
             assert ppx.tri_family(cfg.algo) == ppx.tri_family(extra), (rec[:5], cfg)
+        elif ppx.mixed_job_is_direct(op, n, batch, ref):  # runs as its own tuned call
+            assert cfg.as_tuple() == ref.as_tuple(), (rec[:5], cfg, ref)
         else:
             assert cfg.as_tuple() == ref.as_tuple()[:5] + (ref.algo & ~PIPE[op],), (rec[:5], cfg, ref)
         print(f"{rec[:5]}: tile = {per} problems, config {cfg}")
@@ -129,7 +134,7 @@ def test_each_job_runs_its_tuned_configuration(cuda, tuned):
         if tuned_cfg is None:
             continue
         null = _single(rec, None, z)
-        if not tuned_cfg.algo & PIPE[op]:
+        if not tuned_cfg.algo & PIPE[op] or ppx.mixed_job_is_direct(op, rec[2], rec[3], tuned_cfg):
             assert np.array_equal(null, out), f"{rec[:5]}: mixed != NULL-config single call"
         else:
             assert _oracle_ok(rec, null), rec[:5]

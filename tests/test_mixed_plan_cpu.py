@@ -52,14 +52,17 @@ def test_tiles_follow_the_tuned_configuration(tuned, op, dtype, n, algo):
         ref = ppx.resolve_config(op, ppx.C64 if op == ppx.OP_FFT else dtype, n, batch)
     if ref is None:  # no tuned entry: the family's analytical choice
         assert op == ppx.OP_TRIDIAG and ppx.tri_family(cfg.algo) == algo
+    elif ppx.mixed_job_is_direct(op, n, batch, ref):  # its own single call
+        assert cfg.as_tuple() == ref.as_tuple() and per == ref.problems_per_block
+        return
     else:
         want = ref.as_tuple()[:5] + (ref.algo & ~PIPE[op],)
         assert cfg.as_tuple() == want, (cfg, ref)
     assert ppx.config_valid(op, ppx.C64 if op == ppx.OP_FFT else dtype, n, cfg)
     # problems per tile: the tuned workgroup's share scaled to the family's
-    # block (256 or 1024 threads)
+    # block (256 or 1024 threads; 512 for the float64 hybrid with P = 16)
     T = n // cfg.elems_per_thread
-    block = 256 if T <= 256 else 1024
+    block = 256 if T <= 256 else 512 if (op == ppx.OP_TRIDIAG and dtype == ppx.F64 and cfg.elems_per_thread == 16) else 1024
     assert per == block // T
 
 
@@ -104,9 +107,12 @@ def test_noalloc_refuses_oversize_calls_before_any_gpu_work():
     with pytest.raises(ppx.PpxError) as e:
         ppx.launch_mixed_noalloc(many, stream=0)
     assert e.value.code == ppx.EINVAL and "PPX_NOALLOC_MAX_JOBS" in str(e.value)
-    job = ppx.make_job(ppx.OP_SCAN, ppx.F32, 16384, 1, p, p)
-    per, _ = ppx.mixed_tile_config(job)
-    big = ppx.make_job(ppx.OP_SCAN, ppx.F32, 16384, (ppx.NOALLOC_MAX_TILES + 1) * per, p, p)
+    # tiled (not a persistent configuration, which would run as its own call)
+    job = ppx.make_job(ppx.OP_TRIDIAG, ppx.F32, 16384, 1, p, p, algo=ppx.TRI_CR_PCR, b=p, c=p, d=p)
+    per, cfg = ppx.mixed_tile_config(job)
+    assert not cfg.algo & ppx.TRI_PIPE
+    big = ppx.make_job(ppx.OP_TRIDIAG, ppx.F32, 16384, (ppx.NOALLOC_MAX_TILES + 1) * per, p, p,
+                       algo=ppx.TRI_CR_PCR, b=p, c=p, d=p)
     with pytest.raises(ppx.PpxError) as e:
         ppx.launch_mixed_noalloc([big], stream=0)
     assert e.value.code == ppx.EINVAL and "PPX_NOALLOC_MAX_TILES" in str(e.value)

@@ -17,7 +17,8 @@ FIRST = [("fft", ppx.C64, 1024, 40, -1), ("fft", ppx.C64, 16384, 3, 1), ("fft", 
          ("scan", ppx.F32, 4096, 17, 0), ("scan", ppx.I32, 128, 500, 1), ("scan", ppx.F64, 8192, 5, 0),
          ("tri", ppx.F32, 256, 90, ppx.TRI_CR), ("tri", ppx.F64, 1024, 9, ppx.TRI_PCR),
          ("tri", ppx.F32, 4096, 3, ppx.TRI_CR), ("tri", ppx.F32, 64, 200, ppx.TRI_WM),
-         ("tri", ppx.F32, 8192, 2, ppx.TRI_CR_PCR), ("tri", ppx.F64, 2048, 3, ppx.TRI_CR_PCR)]
+         ("tri", ppx.F32, 8192, 2, ppx.TRI_CR_PCR), ("tri", ppx.F64, 2048, 3, ppx.TRI_CR_PCR),
+         ("fft", ppx.C64, 16384, 300, -1)]  # a job that runs as its own tuned call
 SECOND = [("scan", ppx.F32, 256, 7, 1), ("fft", ppx.C64, 32, 11, 1), ("tri", ppx.F64, 32, 5, ppx.TRI_LF)]
 
 
