@@ -308,18 +308,21 @@ typedef struct ppx_job {
 
 /*
  * launch_mixed -- Sec. IV-A's batched invocation extended to a batch of
- * uneven jobs (different operations, sizes and batch counts) in one launch
- * of persistent kernels.  Each job is cut into tiles of the shape its
- * single call uses with cfg == NULL (the tuned configuration, else the
- * analytical one; tridiagonal: of the job's family): the same radix, values
- * per thread and solver, so each job's output equals that single call's and
- * does not depend on what else shares the launch.  The tiles run in
- * persistent kernels, one per family of tile shapes (FFT, scan and
- * tridiagonal by block size and register demand), replayed as one hipGraph.
- * Asynchronous and stream-ordered; allocates nothing after a device's first
- * mixed launch, which creates the launch tables (4 ring slots) and captures
- * graphs as new family sets appear.  At most 16384 jobs and 2^20 tiles per
- * launch (PPX_EINVAL beyond).
+ * uneven jobs (different operations, sizes and batch counts) in one launch.
+ * Each job is cut into tiles of the shape its single call uses with
+ * cfg == NULL (the tuned configuration, else the analytical one;
+ * tridiagonal: of the job's family): the same radix, values per thread and
+ * solver, so each job's output equals that single call's and does not
+ * depend on what else shares the launch.  The tiles run in one kernel per
+ * family of tile shapes (FFT, scan and tridiagonal by block size and
+ * register demand).  A launch with at most PPX_MIXED_ARG_JOBS jobs in every
+ * family passes the job records in the kernel arguments, one workgroup per
+ * tile: one kernel launch per family and nothing else.  A larger launch
+ * copies its tables to the device (one of 4 ring slots), expands the tile
+ * lists and runs persistent kernels that claim tiles from per-family
+ * counters.  Asynchronous and stream-ordered; allocates nothing after a
+ * device's first mixed launch, which creates the ring slots.  At most 16384
+ * jobs and 2^20 tiles per launch (PPX_EINVAL beyond).
  */
 int launch_mixed(const ppx_job *jobs, int njobs, void *stream);
 /* A job of at least this many elements (n * batch) whose configuration with
@@ -341,8 +344,10 @@ int launch_mixed(const ppx_job *jobs, int njobs, void *stream);
  * a job is its batch over ppx_mixed_tile_config's problems per tile).  The
  * caller passes the inputs and outputs.  The first call on a device sets it
  * up (device state, occupancy queries, the array's address) without
- * allocating; later calls only plan on the host and enqueue: a few table
- * copy kernels, the tile-list expansion and the family kernels, on `stream`.
+ * allocating; later calls only plan on the host and enqueue, on `stream`,
+ * what launch_mixed does: the argument kernels for a launch with few jobs
+ * per family (the array unused), else a few table copy kernels, the
+ * tile-list expansion and the persistent family kernels.
  * Every call on a device shares that device's array, so calls whose work
  * overlaps on one device (different streams, or host threads) race and must
  * be ordered by the caller.  Asynchronous and stream-ordered.
@@ -365,6 +370,17 @@ int launch_mixed_noalloc(const ppx_job *jobs, int njobs, void *stream);
  * comes from the tune cache or the static resource table.
  */
 int ppx_mixed_tile_config(const ppx_job *job, ppx_config *cfg);
+
+/* Most jobs of one family that a launch passes in kernel arguments. */
+#define PPX_MIXED_ARG_JOBS 32
+/*
+ * ppx_mixed_argument_launch -- 1 if launch_mixed would pass these jobs'
+ * records in the kernel arguments (no tiled job, or at most
+ * PPX_MIXED_ARG_JOBS per family), 0 if it would use the device tables and
+ * persistent kernels, or a negative PPX_E* code for jobs it would refuse.
+ * Planning only (needs no GPU where ppx_mixed_tile_config needs none).
+ */
+int ppx_mixed_argument_launch(const ppx_job *jobs, int njobs);
 
 /* ---------------------------------------------------------------------- */
 /* Helpers                                                                 */

@@ -1,18 +1,19 @@
 // Mixed batched launch, host side: planning each job's tiles from its tuned
-// configuration, the launch tables, and the per-slot hipGraphs that replay
-// the table expansion and the family kernels (see mixed.h).
+// configuration, the launch tables, and the launches of the family kernels
+// (see mixed.h).
 //
-// A launch copies one table (header and job records) from pinned memory to
-// the device and replays a graph captured for the set of families that have
-// tiles: [expand the tile lists] -> [family kernel] -> [family kernel] ...
-// Each family kernel is persistent (as many workgroups as are resident) and
-// drains its family's tiles, so every workgroup exits once they are done.
-// Graphs are captured on first use of a (ring slot, family set) and kept.
+// A launch with at most kMixArgJobs jobs in every family passes each
+// family's job records in the kernel arguments: one kernel launch per
+// family, a workgroup per tile, nothing else.  Any other
+// launch copies one table (header and job records) from pinned memory to the
+// device and enqueues [expand the tile lists] -> [family kernel] -> ...,
+// each family kernel persistent (at most as many workgroups as are resident,
+// and no more than its tiles), draining its family's tiles, so every
+// workgroup exits once they are done.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
-#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -42,11 +43,12 @@ int64_t mix_lds_bytes(int fam) {
     }
 }
 
-// The family's kernel, from whichever translation unit instantiates it.
-static const void *mix_kernel(int fam) {
-    if (const void *k = mix_fft_kernel(fam)) return k;
-    if (const void *k = mix_scan_kernel(fam)) return k;
-    return mix_tri_kernel(fam);
+// The family's kernel (persistent, or taking its records in the arguments),
+// from whichever translation unit instantiates it.
+static const void *mix_kernel(int fam, bool args) {
+    if (const void *k = mix_fft_kernel(fam, args)) return k;
+    if (const void *k = mix_scan_kernel(fam, args)) return k;
+    return mix_tri_kernel(fam, args);
 }
 
 // Writes each job's run of its family's tile list: entry first_tile + k of
@@ -261,13 +263,12 @@ struct Slot {
     char *h_stage = nullptr;  // pinned: header | jobs
     hipEvent_t done = nullptr;
     bool used = false;
-    std::map<int, hipGraphExec_t> graphs;  // by family mask
 };
 struct MixedCtx {
     int device = -1;
-    hipStream_t capture = nullptr;
     Slot slots[kSlots];
     int next = 0;
+    std::vector<char> plan;  // host tables of the launch being planned
 };
 std::mutex g_mixed_mu;
 std::vector<MixedCtx *> g_mixed;  // per device ordinal, never freed
@@ -277,13 +278,13 @@ constexpr size_t kStageBytes = (size_t)mix_table_bytes(kMixMaxJobs, 0);
 
 int init_ctx(MixedCtx *m) {
     if (int rc = mix_prepare_kernels()) return rc;
-    if (hipStreamCreate(&m->capture) != hipSuccess) return fail(PPX_EHIP, "stream creation failed");
     for (auto &s : m->slots) {
         if (hipMalloc(&s.d_tables, kTableBytes) != hipSuccess ||
             hipHostMalloc(&s.h_stage, kStageBytes, hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
             return fail(PPX_ENOMEM, "could not allocate the mixed-launch tables");
     }
+    m->plan.resize(kStageBytes);
     return PPX_OK;
 }
 
@@ -299,31 +300,6 @@ MixedCtx *mixed_ctx() {
     }
     return g_mixed[di->device];
 }
-
-// The graph of a slot for a family mask: expansion, then each family's
-// persistent kernel, in family order.
-int slot_graph(MixedCtx *m, Slot &s, int mask, hipGraphExec_t *out) {
-    auto it = s.graphs.find(mask);
-    if (it != s.graphs.end()) {
-        *out = it->second;
-        return PPX_OK;
-    }
-    const DeviceInfo *di = device_info();
-    hipGraph_t g;
-    if (hipStreamBeginCapture(m->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return fail(PPX_EHIP, "graph capture failed");
-    int rc = mix_enqueue(s.d_tables, mask, nullptr, static_cast<const float2 *>(di->twiddles), m->capture);
-    const hipError_t ce = hipStreamEndCapture(m->capture, &g);
-    if (rc) return rc;
-    if (ce != hipSuccess) return fail(PPX_EHIP, "graph capture failed");
-    hipGraphExec_t exec = nullptr;
-    const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ie != hipSuccess) return fail(PPX_EHIP, "graph instantiation failed");
-    s.graphs[mask] = exec;
-    *out = exec;
-    return PPX_OK;
-}
 }  // namespace
 
 // Resident workgroups of each family's kernel on the current device (from
@@ -338,33 +314,66 @@ int mix_prepare_kernels() {
     const DeviceInfo *di = device_info();
     if (!di) return PPX_EDEVICE;
     for (int f = 0; f < kMixFamilies; ++f) {
-        const void *k = mix_kernel(f);
-        if (!k) return fail(PPX_EHIP, "mixed launch: no kernel for family " + std::to_string(f));
-        const int64_t lds = mix_lds_bytes(f);
-        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, mix_block(f), (size_t)lds) != hipSuccess ||
-            per_cu < 1)
-            return fail(PPX_EHIP, "mixed launch: the kernel of family " + std::to_string(f) + " cannot be resident");
-        g_resident[f] = per_cu * di->cus;
+        for (int args = 0; args < 2; ++args) {
+            const void *k = mix_kernel(f, args != 0);
+            if (!k) return fail(PPX_EHIP, "mixed launch: no kernel for family " + std::to_string(f));
+            const int64_t lds = mix_lds_bytes(f);
+            (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, mix_block(f), (size_t)lds) != hipSuccess ||
+                per_cu < 1)
+                return fail(PPX_EHIP,
+                            "mixed launch: the kernel of family " + std::to_string(f) + " cannot be resident");
+            if (!args) g_resident[f] = per_cu * di->cus;
+        }
     }
     g_prepared = true;
     return PPX_OK;
 }
 
 // Enqueues the expansion and the kernels of the families in `mask` on
-// stream s, reading the tables at d_tables.  ntiles (per family, may be
-// NULL) caps each grid at the family's tile count; NULL launches the
-// resident count (a captured graph serves any tile count).
+// stream s, reading the tables at d_tables; each family's grid is its
+// resident count capped at its tile count ntiles[f].
 int mix_enqueue(char *d_tables, int mask, const int64_t *ntiles, const float2 *tw, hipStream_t s) {
     hipLaunchKernelGGL(k_mix_expand, dim3(kMixExpandBlocks), dim3(kMixExpandThreads), 0, s, d_tables);
     hipError_t e = hipGetLastError();
+    MixArgs a;
+    a.tables = d_tables;
+    a.ntiles = a.njobs = 0;
     for (int f = 0; f < kMixFamilies && e == hipSuccess; ++f) {
         if (!(mask & (1 << f))) continue;
-        int64_t grid = g_resident[f];
-        if (ntiles) grid = std::min<int64_t>(grid, std::max<int64_t>(1, ntiles[f]));
-        hipLaunchKernelGGL(reinterpret_cast<mix_kernel_t>(const_cast<void *>(mix_kernel(f))), dim3((unsigned)grid),
-                           dim3(mix_block(f)), (size_t)mix_lds_bytes(f), s, static_cast<const char *>(d_tables), tw);
+        const int64_t grid = std::min<int64_t>(g_resident[f], std::max<int64_t>(1, ntiles[f]));
+        hipLaunchKernelGGL(reinterpret_cast<mix_kernel_t>(const_cast<void *>(mix_kernel(f, false))), dim3((unsigned)grid),
+                           dim3(mix_block(f)), (size_t)mix_lds_bytes(f), s, a, tw);
+        e = hipGetLastError();
+    }
+    return fail_hip(e, "mixed launch");
+}
+
+bool mix_args_fit(const char *table, int mask) {
+    const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
+    const MixJob *rec = reinterpret_cast<const MixJob *>(table + kMixHeaderBytes);
+    int per_family[kMixFamilies] = {};
+    for (unsigned i = 0; i < h->njobs; ++i) ++per_family[rec[i].family];
+    for (int f = 0; f < kMixFamilies; ++f)
+        if ((mask & (1 << f)) && per_family[f] > kMixArgJobs) return false;
+    return true;
+}
+
+int mix_enqueue_args(const char *table, int mask, const float2 *tw, hipStream_t s) {
+    const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
+    const MixJob *rec = reinterpret_cast<const MixJob *>(table + kMixHeaderBytes);
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < kMixFamilies && e == hipSuccess; ++f) {
+        if (!(mask & (1 << f))) continue;
+        MixArgs a;
+        a.tables = nullptr;
+        a.ntiles = h->ntiles[f];
+        a.njobs = 0;
+        for (unsigned i = 0; i < h->njobs; ++i)
+            if (rec[i].family == f) a.jobs[a.njobs++] = rec[i];  // first_tile ascending, as the kernel scans them
+        hipLaunchKernelGGL(reinterpret_cast<mix_kernel_t>(const_cast<void *>(mix_kernel(f, true))), dim3(a.ntiles),
+                           dim3(mix_block(f)), (size_t)mix_lds_bytes(f), s, a, tw);
         e = hipGetLastError();
     }
     return fail_hip(e, "mixed launch");
@@ -376,24 +385,30 @@ int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEve
     std::unique_lock<std::mutex> lk(g_mixed_mu);
     MixedCtx *m = mixed_ctx();
     if (!m) return PPX_EHIP;
-    Slot &s = m->slots[m->next];
-    if (s.used && hipEventSynchronize(s.done) != hipSuccess) return fail(PPX_EHIP, "slot wait failed");
     int64_t ntiles = 0;
     std::vector<int> direct(njobs);
     int ndirect = 0;
-    const int mask = mix_build_tables(jobs, njobs, s.h_stage, &ntiles, direct.data(), &ndirect);
+    char *table = m->plan.data();
+    const int mask = mix_build_tables(jobs, njobs, table, &ntiles, direct.data(), &ndirect);
     if (mask < 0) return mask;
     direct.resize(ndirect);
+    const float2 *tw = static_cast<const float2 *>(device_info()->twiddles);
     hipError_t e = hipSuccess;
-    if (mask) {  // the tiled jobs: one table copy and the slot's graph
+    if (mask && mix_args_fit(table, mask)) {  // a small launch: the records go in the kernel arguments
+        if (int rc = mix_enqueue_args(table, mask, tw, stream)) return rc;
+    } else if (mask) {  // the tiled jobs: one table copy, the expansion and the family kernels
+        Slot &s = m->slots[m->next];
+        if (s.used && hipEventSynchronize(s.done) != hipSuccess) return fail(PPX_EHIP, "slot wait failed");
         m->next = (m->next + 1) % kSlots;
-        hipGraphExec_t exec = nullptr;
-        if (int rc = slot_graph(m, s, mask, &exec)) return rc;
-        const size_t nrec = reinterpret_cast<const MixHeader *>(s.h_stage)->njobs;
-        e = hipMemcpyAsync(s.d_tables, s.h_stage, kMixHeaderBytes + nrec * sizeof(MixJob), hipMemcpyHostToDevice,
-                           stream);
-        if (e == hipSuccess) e = hipGraphLaunch(exec, stream);
-        if (e == hipSuccess) e = hipEventRecord(s.done, stream);
+        const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
+        const size_t bytes = kMixHeaderBytes + (size_t)h->njobs * sizeof(MixJob);
+        std::memcpy(s.h_stage, table, bytes);
+        int64_t fam_tiles[kMixFamilies];
+        for (int f = 0; f < kMixFamilies; ++f) fam_tiles[f] = h->ntiles[f];
+        e = hipMemcpyAsync(s.d_tables, s.h_stage, bytes, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return fail_hip(e, "mixed launch");
+        if (int rc = mix_enqueue(s.d_tables, mask, fam_tiles, tw, stream)) return rc;
+        e = hipEventRecord(s.done, stream);
         s.used = true;
         if (e != hipSuccess) return fail_hip(e, "mixed launch");
     }
@@ -418,7 +433,8 @@ int mix_launch_direct(const ppx_job &j, const ppx_config &c, hipStream_t s) {
 
 // ------------------------------------------------ the allocation-free launch
 // The same launch for callers that cannot allocate (code under graph capture,
-// tight serving loops): its tables live in `scratch`, a file-scope device
+// tight serving loops).  A small launch passes its records in the kernel
+// arguments as launch_mixed does; any other keeps its tables in `scratch`, a file-scope device
 // array holding at most kNoAllocJobs jobs and kNoAllocTiles tiles, whose
 // address on each device is taken once at set-up (hipGetSymbolAddress; in
 // host code the array's name is not a device address).  The table reaches the
@@ -482,7 +498,10 @@ int launch_mixed_noalloc_impl(const ppx_job *jobs, int njobs, hipStream_t stream
         return fail(PPX_EINVAL, "launch_mixed_noalloc takes at most PPX_NOALLOC_MAX_TILES (262144) tiles");
     char *d = noalloc_scratch();
     if (!d) return PPX_EDEVICE;
-    if (mask) {
+    const float2 *tw = static_cast<const float2 *>(device_info()->twiddles);
+    if (mask && mix_args_fit(table, mask)) {  // a small launch: the records go in the kernel arguments
+        if (int rc = mix_enqueue_args(table, mask, tw, stream)) return rc;
+    } else if (mask) {
         const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
         const unsigned bytes = (unsigned)(kMixHeaderBytes + sizeof(MixJob) * (size_t)h->njobs);
         TableChunk c;
@@ -495,8 +514,7 @@ int launch_mixed_noalloc_impl(const ppx_job *jobs, int njobs, hipStream_t stream
         }
         int64_t fam_tiles[kMixFamilies];
         for (int f = 0; f < kMixFamilies; ++f) fam_tiles[f] = h->ntiles[f];
-        if (int rc = mix_enqueue(d, mask, fam_tiles, static_cast<const float2 *>(device_info()->twiddles), stream))
-            return rc;
+        if (int rc = mix_enqueue(d, mask, fam_tiles, tw, stream)) return rc;
     }
     for (int k = 0; k < ndirect; ++k) {  // jobs that fill the GPU alone: their tuned single calls
         MixPlan p;
@@ -520,8 +538,21 @@ extern "C" int launch_mixed(const ppx_job *jobs, int njobs, void *stream) {
 
 extern "C" int ppx_mixed_families_complete(void) {
     for (int f = 0; f < ppx::kMixFamilies; ++f)
-        if (!ppx::mix_kernel(f)) return ppx::fail(PPX_EINVAL, "mixed launch: no kernel for family " + std::to_string(f));
+        if (!ppx::mix_kernel(f, false) || !ppx::mix_kernel(f, true)) return ppx::fail(PPX_EINVAL, "mixed launch: no kernel for family " + std::to_string(f));
     return PPX_OK;
+}
+
+extern "C" int ppx_mixed_argument_launch(const ppx_job *jobs, int njobs) {
+    ppx::fail(PPX_OK, "");
+    if (!jobs || njobs < 1) return ppx::fail(PPX_EINVAL, "no jobs");
+    if (njobs > ppx::kMixMaxJobs) return ppx::fail(PPX_EINVAL, "too many jobs for one mixed launch");
+    std::vector<char> table((size_t)ppx::mix_table_bytes(njobs, 0));
+    std::vector<int> direct(njobs);
+    int64_t ntiles = 0;
+    int ndirect = 0;
+    const int mask = ppx::mix_build_tables(jobs, njobs, table.data(), &ntiles, direct.data(), &ndirect);
+    if (mask < 0) return mask;
+    return ppx::mix_args_fit(table.data(), mask) ? 1 : 0;
 }
 
 extern "C" int ppx_mixed_tile_config(const ppx_job *job, ppx_config *cfg) {

@@ -20,13 +20,16 @@
 //   light and a heavy register tier (mix_triw_family);
 //   tridiagonal through LDS (CR and PCR of larger systems);
 //   the CR -> PCR hybrid of systems spanning several waves.
-// One persistent kernel per family pulls tile indices from the family's
-// counter until its tiles are drained.  A launch runs, in one stream, the
-// table expansion and then the kernels of the families that have tiles.
+// Each family has two kernels running its tiles: one whose jobs come in the
+// kernel arguments, a workgroup per tile, for launches with few jobs per
+// family; and a persistent one pulling tile indices from the family's
+// counter until its tiles are drained, after a table expansion on the same
+// stream.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 
 #include "ppx_internal.h"
@@ -118,12 +121,27 @@ constexpr int mix_block(int fam) {
 constexpr int kMixTriLdsBudget = 128 * 1024;
 int64_t mix_lds_bytes(int fam);
 
-// Kernel of a family (signature mix_kernel_t), from the translation unit
-// that instantiates it.
-typedef void (*mix_kernel_t)(const char *tables, const float2 *tw);
-const void *mix_fft_kernel(int fam);
-const void *mix_scan_kernel(int fam);
-const void *mix_tri_kernel(int fam);
+// What a family kernel is launched with.  A launch in which every family
+// has at most kMixArgJobs jobs passes each family's job records here
+// (first_tile counted within the family) to the family's argument kernel,
+// whose workgroup b runs tile b: no table in device memory, no expansion, no
+// counter, one launch per family.  Any other launch passes the device tables
+// (tables) to the persistent kernels, which claim tiles from the counters.
+constexpr int kMixArgJobs = PPX_MIXED_ARG_JOBS;
+struct MixArgs {
+    const char *tables;  // persistent kernels: the device tables
+    unsigned ntiles;     // argument kernels: the family's tiles
+    unsigned njobs;      // argument kernels: records in jobs[]
+    MixJob jobs[kMixArgJobs];
+};
+static_assert(sizeof(MixArgs) <= 4096 - 64, "kernel arguments are limited to 4 KiB");
+
+// Kernel of a family (signature mix_kernel_t), persistent or taking its
+// records in the arguments, from the translation unit that instantiates it.
+typedef void (*mix_kernel_t)(MixArgs a, const float2 *tw);
+const void *mix_fft_kernel(int fam, bool args);
+const void *mix_scan_kernel(int fam, bool args);
+const void *mix_tri_kernel(int fam, bool args);
 // Writes every family's tile list from the job records (one launch).
 const void *mix_expand_kernel();
 constexpr int kMixExpandBlocks = 512;
@@ -158,42 +176,84 @@ int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_
 int mix_launch_direct(const ppx_job &j, const ppx_config &c, hipStream_t s);
 // Occupancy of every family kernel on the current device (once).
 int mix_prepare_kernels();
-// Expansion plus the family kernels of `mask`, on stream s.
+// Expansion plus the family kernels of `mask`, on stream s, each grid
+// capped at the family's tile count ntiles[f].
 int mix_enqueue(char *d_tables, int mask, const int64_t *ntiles, const float2 *tw, hipStream_t s);
+// Whether the launch planned in `table` (header and records) can pass its
+// jobs as kernel arguments (at most kMixArgJobs per family), and if so its
+// launches: one argument kernel per family in mask, a workgroup per tile.
+bool mix_args_fit(const char *table, int mask);
+int mix_enqueue_args(const char *table, int mask, const float2 *tw, hipStream_t s);
 
-// ---- the persistent tile loop shared by the families
-// Claims tile indices of family FAM from its counter until they run out and
-// calls body(job, first problem, problem count, tx) for each, tx being the
-// thread's index in the workgroup passed through an empty asm that claims
-// to change it: without it the compiler hoists every address derived from
-// the thread index out of the loop, for every shape a family holds, and
-// keeps them all live (the FFT families then spilled).  The next index is
-// claimed while the current tile is processed.  Every thread of the
+// ---- the tile loop shared by the families
+// ARGS: the records come in the kernel arguments and workgroup b runs tile b
+// (the grid is the family's tile count), its job found by a scan of the
+// family's few records, read through the constant address space (the
+// launch's explicit arguments start the kernarg segment, MixArgs first).
+// Otherwise the kernel is persistent: it claims tile indices of family FAM
+// from its counter in the device tables until they run out, the next index
+// being claimed while the current tile is processed, and looks the job up
+// in the family's tile list.
+// Either way body(job, first problem, problem count, tx) runs each tile, tx
+// being the thread's index in the workgroup passed through an empty asm that
+// claims to change it: without it the compiler hoists every address derived
+// from the thread index out of the loop, for every shape a family holds, and
+// keeps them all live (the FFT families then spilled).  Every thread of the
 // workgroup runs the same iterations, so all reach every barrier.
-template <int FAM, typename Body>
-__device__ __forceinline__ void mix_tile_loop(const char *tables, Body &&body) {
-    __shared__ unsigned s_tile;
-    const MixHeader *h = reinterpret_cast<const MixHeader *>(tables);
-    const MixJob *jobs = reinterpret_cast<const MixJob *>(tables + kMixHeaderBytes);
-    const unsigned *tiles = reinterpret_cast<const unsigned *>(tables + h->tiles_off) + h->tile_base[FAM];
-    unsigned *ctr = const_cast<unsigned *>(&h->next[FAM]);
-    const unsigned ntiles = h->ntiles[FAM];
-    if (threadIdx.x == 0) s_tile = atomicAdd(ctr, 1u);
-    __syncthreads();
-    unsigned t = __builtin_amdgcn_readfirstlane(s_tile);
-    while (t < ntiles) {
-        unsigned next = 0;
-        if (threadIdx.x == 0) next = atomicAdd(ctr, 1u);
-        const MixJob j = jobs[__builtin_amdgcn_readfirstlane(tiles[t])];
-        const long long first = (long long)(t - j.first_tile) * j.per_tile;
-        const int count = (int)min((long long)j.per_tile, j.batch - first);
-        int tx = threadIdx.x;
-        asm volatile("" : "+v"(tx));
-        body(j, first, count, tx);
-        __syncthreads();  // every thread is done with s_tile and the tile's LDS
-        if (threadIdx.x == 0) s_tile = next;
+typedef const __attribute__((address_space(4))) MixJob *mix_arg_job_ptr;
+
+__device__ __forceinline__ MixJob mix_load_job(mix_arg_job_ptr r) {
+    MixJob j;
+    j.shape = r->shape;
+    j.flags = r->flags;
+    j.log2n = r->log2n;
+    j.per_tile = r->per_tile;
+    j.batch = r->batch;
+    j.first_tile = r->first_tile;
+    j.family = r->family;
+    for (int i = 0; i < 4; ++i) j.p[i] = r->p[i];
+    j.out = r->out;
+    return j;
+}
+
+template <typename Body>
+__device__ __forceinline__ void mix_run_tile(const MixJob &j, unsigned t, Body &body) {
+    const long long first = (long long)(t - j.first_tile) * j.per_tile;
+    const int count = (int)min((long long)j.per_tile, j.batch - first);
+    int tx = threadIdx.x;
+    asm volatile("" : "+v"(tx));
+    body(j, first, count, tx);
+}
+
+template <int FAM, bool ARGS, typename Body>
+__device__ __forceinline__ void mix_tile_loop(const MixArgs &a, Body &&body) {
+    if constexpr (ARGS) {
+        const mix_arg_job_ptr recs = reinterpret_cast<mix_arg_job_ptr>(
+            (const __attribute__((address_space(4))) char *)__builtin_amdgcn_kernarg_segment_ptr() +
+            offsetof(MixArgs, jobs));
+        const unsigned t = blockIdx.x;
+        unsigned k = 0;
+        while (k + 1 < a.njobs && recs[k + 1].first_tile <= t) ++k;
+        mix_run_tile(mix_load_job(recs + k), t, body);
+    } else {
+        __shared__ unsigned s_tile;
+        const MixHeader *h = reinterpret_cast<const MixHeader *>(a.tables);
+        const MixJob *jobs = reinterpret_cast<const MixJob *>(a.tables + kMixHeaderBytes);
+        const unsigned *tiles = reinterpret_cast<const unsigned *>(a.tables + h->tiles_off) + h->tile_base[FAM];
+        unsigned *ctr = const_cast<unsigned *>(&h->next[FAM]);
+        const unsigned ntiles = h->ntiles[FAM];
+        if (threadIdx.x == 0) s_tile = atomicAdd(ctr, 1u);
         __syncthreads();
-        t = __builtin_amdgcn_readfirstlane(s_tile);
+        unsigned t = __builtin_amdgcn_readfirstlane(s_tile);
+        while (t < ntiles) {
+            unsigned next = 0;
+            if (threadIdx.x == 0) next = atomicAdd(ctr, 1u);
+            mix_run_tile(jobs[__builtin_amdgcn_readfirstlane(tiles[t])], t, body);
+            __syncthreads();  // every thread is done with s_tile and the tile's LDS
+            if (threadIdx.x == 0) s_tile = next;
+            __syncthreads();
+            t = __builtin_amdgcn_readfirstlane(s_tile);
+        }
     }
 }
 

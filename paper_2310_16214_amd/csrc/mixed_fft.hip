@@ -44,19 +44,24 @@ __device__ __forceinline__ void mix_fft_dispatch(const MixJob &j, long long firs
     }
 }
 
-template <int FAM>
-__global__ __launch_bounds__(mix_block(FAM)) void k_mix_fft(const char *tables, const float2 *tw) {
+template <int FAM, bool ARGS>
+__global__ __launch_bounds__(mix_block(FAM)) void k_mix_fft(MixArgs a, const float2 *tw) {
     extern __shared__ float4 lds[];
-    mix_tile_loop<FAM>(tables, [&](const MixJob &j, long long first, int count, int tx) {
+    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx) {
         mix_fft_dispatch<FAM, 0>(j, first, count, tw, lds, tx);
     });
 }
 
-const void *mix_fft_kernel(int fam) {
-    if (fam == kFamFft256) return reinterpret_cast<const void *>(&k_mix_fft<kFamFft256>);
-    if (fam == kFamFft1024) return reinterpret_cast<const void *>(&k_mix_fft<kFamFft1024>);
-    if (fam == kFamFft1024P8) return reinterpret_cast<const void *>(&k_mix_fft<kFamFft1024P8>);
+template <bool ARGS>
+static const void *fft_kernel(int fam) {
+    if (fam == kFamFft256) return reinterpret_cast<const void *>(&k_mix_fft<kFamFft256, ARGS>);
+    if (fam == kFamFft1024) return reinterpret_cast<const void *>(&k_mix_fft<kFamFft1024, ARGS>);
+    if (fam == kFamFft1024P8) return reinterpret_cast<const void *>(&k_mix_fft<kFamFft1024P8, ARGS>);
     return nullptr;
+}
+
+const void *mix_fft_kernel(int fam, bool args) {
+    return args ? fft_kernel<true>(fam) : fft_kernel<false>(fam);
 }
 
 }  // namespace ppx

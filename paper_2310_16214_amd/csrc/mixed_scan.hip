@@ -30,18 +30,23 @@ __device__ __forceinline__ void mix_scan_dispatch(const MixJob &j, long long fir
     }
 }
 
-template <int FAM>
-__global__ __launch_bounds__(mix_block(FAM)) void k_mix_scan(const char *tables, const float2 *) {
+template <int FAM, bool ARGS>
+__global__ __launch_bounds__(mix_block(FAM)) void k_mix_scan(MixArgs a, const float2 *) {
     __shared__ double wave_tot[mix_block(FAM) / kWave];  // int and float totals use its start
-    mix_tile_loop<FAM>(tables, [&](const MixJob &j, long long first, int count, int tx) {
+    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx) {
         mix_scan_dispatch<0>(j, first, count, wave_tot, tx);
     });
 }
 
-const void *mix_scan_kernel(int fam) {
-    if (fam == kFamScan256) return reinterpret_cast<const void *>(&k_mix_scan<kFamScan256>);
-    if (fam == kFamScan1024) return reinterpret_cast<const void *>(&k_mix_scan<kFamScan1024>);
+template <bool ARGS>
+static const void *scan_kernel(int fam) {
+    if (fam == kFamScan256) return reinterpret_cast<const void *>(&k_mix_scan<kFamScan256, ARGS>);
+    if (fam == kFamScan1024) return reinterpret_cast<const void *>(&k_mix_scan<kFamScan1024, ARGS>);
     return nullptr;
+}
+
+const void *mix_scan_kernel(int fam, bool args) {
+    return args ? scan_kernel<true>(fam) : scan_kernel<false>(fam);
 }
 
 }  // namespace ppx

@@ -48,17 +48,18 @@ __device__ __forceinline__ void mix_triw_dispatch(const MixJob &j, long long fir
 template <int FAM>
 constexpr int triw_min_waves() { return FAM == kFamTriW64H ? 3 : 1; }
 
-template <int FAM>
-__global__ __launch_bounds__(256, triw_min_waves<FAM>()) void k_mix_triw(const char *tables, const float2 *) {
+template <int FAM, bool ARGS>
+__global__ __launch_bounds__(256, triw_min_waves<FAM>()) void k_mix_triw(MixArgs a, const float2 *) {
     extern __shared__ float4 smem[];  // PPX_TRI_PCR_REG exchange buffers, one per wave
-    mix_tile_loop<FAM>(tables, [&](const MixJob &j, long long first, int count, int tx) {
+    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx) {
         mix_triw_dispatch<FAM, 0>(j, first, count, smem, tx);
     });
 }
 
-__global__ __launch_bounds__(1024) void k_mix_tril(const char *tables, const float2 *) {
+template <bool ARGS>
+__global__ __launch_bounds__(1024) void k_mix_tril(MixArgs a, const float2 *) {
     extern __shared__ float4 smem[];
-    mix_tile_loop<kFamTriLds>(tables, [&](const MixJob &j, long long first, int count, int tx) {
+    mix_tile_loop<kFamTriLds, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx) {
         switch (j.shape) {
             case mix_tril_shape(false, false):
                 tridiag_block<float, PPX_TRI_CR>(static_cast<const float *>(j.p[0]), static_cast<const float *>(j.p[1]),
@@ -108,27 +109,30 @@ __device__ __forceinline__ void mix_trib_dispatch(const MixJob &j, long long fir
     }
 }
 
-template <int FAM>
-__global__ __launch_bounds__(mix_block(FAM)) void k_mix_trib(const char *tables, const float2 *) {
+template <int FAM, bool ARGS>
+__global__ __launch_bounds__(mix_block(FAM)) void k_mix_trib(MixArgs a, const float2 *) {
     extern __shared__ float4 smem[];
-    mix_tile_loop<FAM>(tables, [&](const MixJob &j, long long first, int count, int tx) {
+    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx) {
         mix_trib_dispatch<FAM, 1>(j, first, count, smem, tx);
     });
 }
 
-const void *mix_tri_kernel(int fam) {
+template <bool ARGS>
+static const void *tri_kernel(int fam) {
     switch (fam) {
-        case kFamTriW32: return reinterpret_cast<const void *>(&k_mix_triw<kFamTriW32>);
-        case kFamTriW32H: return reinterpret_cast<const void *>(&k_mix_triw<kFamTriW32H>);
-        case kFamTriW64: return reinterpret_cast<const void *>(&k_mix_triw<kFamTriW64>);
-        case kFamTriW64H: return reinterpret_cast<const void *>(&k_mix_triw<kFamTriW64H>);
-        case kFamTriLds: return reinterpret_cast<const void *>(&k_mix_tril);
-        case kFamTriBlk32: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk32>);
-        case kFamTriBlk32H: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk32H>);
-        case kFamTriBlk64: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk64>);
-        case kFamTriBlk64H: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk64H>);
+        case kFamTriW32: return reinterpret_cast<const void *>(&k_mix_triw<kFamTriW32, ARGS>);
+        case kFamTriW32H: return reinterpret_cast<const void *>(&k_mix_triw<kFamTriW32H, ARGS>);
+        case kFamTriW64: return reinterpret_cast<const void *>(&k_mix_triw<kFamTriW64, ARGS>);
+        case kFamTriW64H: return reinterpret_cast<const void *>(&k_mix_triw<kFamTriW64H, ARGS>);
+        case kFamTriLds: return reinterpret_cast<const void *>(&k_mix_tril<ARGS>);
+        case kFamTriBlk32: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk32, ARGS>);
+        case kFamTriBlk32H: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk32H, ARGS>);
+        case kFamTriBlk64: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk64, ARGS>);
+        case kFamTriBlk64H: return reinterpret_cast<const void *>(&k_mix_trib<kFamTriBlk64H, ARGS>);
         default: return nullptr;
     }
 }
+
+const void *mix_tri_kernel(int fam, bool args) { return args ? tri_kernel<true>(fam) : tri_kernel<false>(fam); }
 
 }  // namespace ppx

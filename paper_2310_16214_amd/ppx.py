@@ -557,7 +557,7 @@ def make_job(op, dtype, n, batch, inp, out, direction=-1, algo=0, b=None, c=None
 
 
 def launch_mixed(jobs, stream=None):
-    """One persistent fused launch over a list of Job (see include/ppx.h)."""
+    """One fused launch over a list of Job (see include/ppx.h)."""
     L = lib()
     f = L.launch_mixed
     if not getattr(f, "_ppx_typed", False):
@@ -599,6 +599,21 @@ def launch_mixed_noalloc(jobs, stream=None):
     elif hasattr(stream, "cuda_stream"):
         stream = stream.cuda_stream
     _check(f(arr, len(jobs), stream))
+
+
+MIXED_ARG_JOBS = 32  # most jobs of one family a launch passes in kernel arguments
+
+
+def mixed_argument_launch(jobs):
+    """Whether launch_mixed passes these jobs' records in the kernel
+    arguments (True) or uses the device tables and persistent kernels."""
+    f = lib().ppx_mixed_argument_launch
+    if not getattr(f, "_ppx_typed", False):
+        f.argtypes = [ctypes.POINTER(Job), ctypes.c_int]
+        f.restype = ctypes.c_int
+        f._ppx_typed = True
+    arr = (Job * len(jobs))(*jobs)
+    return _check(f(arr, len(jobs))) == 1
 
 
 def mixed_tile_config(job):

@@ -1,7 +1,8 @@
-"""GPU tests of the mixed persistent launch: every job of a mix of
-operations, sizes and batch counts against the oracle (each operation's
-tolerance), bit-identical to the same job launched alone, and stable across
-repeated graph replays with other work in between."""
+"""GPU tests of the mixed launch: every job of a mix of operations, sizes and
+batch counts against the oracle (each operation's tolerance), bit-identical
+to the same job launched alone, stable across repeated launches with other
+work in between, and the same whether the records travel in the kernel
+arguments or in the device tables (persistent kernels)."""
 import numpy as np
 import pytest
 
@@ -132,3 +133,32 @@ def test_mixed_rejects_bad_jobs(cuda):
         ppx.launch_mixed([ppx.make_job(ppx.OP_FFT, ppx.C64, 100, 1, x, x)])
     with pytest.raises(ppx.PpxError):  # scan form must be inclusive or exclusive
         ppx.launch_mixed([ppx.make_job(ppx.OP_SCAN, ppx.F64, 64, 1, x, x, algo=2)])
+
+
+def test_table_launch_equals_argument_launch(cuda):
+    import torch
+    jobs, checks = _build(cuda, seed=7)
+    assert ppx.mixed_argument_launch(jobs)
+    banner("mixed launch, records in the kernel arguments")
+    ppx.launch_mixed(jobs)
+    outs = [to_host(c[5]).copy() for c in checks]
+    # more than PPX_MIXED_ARG_JOBS jobs of one family: the whole launch goes
+    # through the device tables and the persistent kernels
+    fill_in, fill_out, fill_host = [], [], []
+    for k in range(ppx.MIXED_ARG_JOBS + 1):
+        x = inputs.scan_input(32, 1 + 7 * k, np.int32, seed=700 + k)
+        xd = to_dev(x, cuda)
+        y = torch.full_like(xd, -5)
+        fill_in.append(ppx.make_job(ppx.OP_SCAN, ppx.I32, 32, x.shape[0], xd, y, algo=k % 2))
+        fill_out.append(y)
+        fill_host.append((x, xd))
+    mix = jobs[:5] + fill_in + jobs[5:]
+    assert not ppx.mixed_argument_launch(mix)
+    for c in checks:
+        c[5].fill_(float("nan") if c[5].dtype.is_floating_point or c[5].is_complex() else -7)
+    banner("mixed launch, device tables")
+    ppx.launch_mixed(mix)
+    for c, o, m in zip(checks, outs, MIX):
+        assert np.array_equal(to_host(c[5]), o), m
+    for k, (y, (x, _)) in enumerate(zip(fill_out, fill_host)):
+        assert np.array_equal(to_host(y), oracle.scan(x, exclusive=k % 2 == 1)), k

@@ -116,3 +116,21 @@ def test_noalloc_refuses_oversize_calls_before_any_gpu_work():
     with pytest.raises(ppx.PpxError) as e:
         ppx.launch_mixed_noalloc([big], stream=0)
     assert e.value.code == ppx.EINVAL and "PPX_NOALLOC_MAX_TILES" in str(e.value)
+
+
+def test_argument_launch_rule(tuned):
+    # at most PPX_MIXED_ARG_JOBS jobs in every family: records in the kernel
+    # arguments; one more job in a family: the device tables
+    small = [_job(ppx.OP_SCAN, ppx.I32, 32, 1 + k) for k in range(ppx.MIXED_ARG_JOBS)]
+    assert ppx.mixed_argument_launch(small)
+    assert not ppx.mixed_argument_launch(small + [_job(ppx.OP_SCAN, ppx.F32, 64, 5)])
+    # other families do not count against it, nor do jobs that run as their own call
+    others = [_job(ppx.OP_FFT, ppx.C64, 1 << (4 + k % 11), 3) for k in range(8)]
+    assert ppx.mixed_argument_launch(small + others)
+    big = _job(ppx.OP_FFT, ppx.C64, 1 << 14, 300)
+    _, cfg = ppx.mixed_tile_config(big)
+    if ppx.mixed_job_is_direct(ppx.OP_FFT, 1 << 14, 300, cfg):
+        assert ppx.mixed_argument_launch([big])
+        assert ppx.mixed_argument_launch(small + [big])
+    with pytest.raises(ppx.PpxError):
+        ppx.mixed_argument_launch([ppx.make_job(ppx.OP_SCAN, ppx.F32, 100, 1, 1 << 12, 1 << 12)])

@@ -2,7 +2,9 @@
 library's static device array): through the C ABI, its outputs are
 bit-identical to launch_mixed's on the same jobs, on two calls in a row, the
 second with fewer and smaller jobs (so any state the first call left in the
-shared array must not leak into the second).  The refusal of calls larger
+shared array must not leak into the second).  The first call has too many
+jobs of one family for the kernel arguments, so its tables go through the
+array; the second passes its records in the kernel arguments.  The refusal of calls larger
 than the array is tested on the CPU (tests/test_mixed_plan_cpu.py)."""
 import numpy as np
 import pytest
@@ -19,6 +21,10 @@ FIRST = [("fft", ppx.C64, 1024, 40, -1), ("fft", ppx.C64, 16384, 3, 1), ("fft", 
          ("tri", ppx.F32, 4096, 3, ppx.TRI_CR), ("tri", ppx.F32, 64, 200, ppx.TRI_WM),
          ("tri", ppx.F32, 8192, 2, ppx.TRI_CR_PCR), ("tri", ppx.F64, 2048, 3, ppx.TRI_CR_PCR),
          ("fft", ppx.C64, 16384, 300, -1)]  # a job that runs as its own tuned call
+# more than PPX_MIXED_ARG_JOBS jobs of one family: the first call keeps its
+# tables in the static array; the second passes its few records in the
+# kernel arguments
+FIRST += [("scan", ppx.I32, 32, 1 + 5 * k, k % 2) for k in range(ppx.MIXED_ARG_JOBS + 2)]
 SECOND = [("scan", ppx.F32, 256, 7, 1), ("fft", ppx.C64, 32, 11, 1), ("tri", ppx.F64, 32, 5, ppx.TRI_LF)]
 
 
@@ -47,11 +53,12 @@ def _jobs(cuda, mix, seed):
     return jobs, outs
 
 
-def _run_both(cuda, mix, seed):
+def _run_both(cuda, mix, seed, argument_launch):
     import torch
     make, alloc = _jobs(cuda, mix, seed)
     ya = [a() for a in alloc]
     yb = [a() for a in alloc]
+    assert ppx.mixed_argument_launch([m(y) for m, y in zip(make, ya)]) == argument_launch
     for y in yb:  # stale values in the no-alloc outputs: every element must be written
         y.fill_(float("nan") if y.dtype.is_floating_point or y.is_complex() else -9)
     banner(f"launch_mixed, {len(mix)} jobs (seed {seed})")
@@ -64,5 +71,5 @@ def _run_both(cuda, mix, seed):
 
 
 def test_noalloc_matches_launch_mixed_twice(cuda):
-    _run_both(cuda, FIRST, seed=1)
-    _run_both(cuda, SECOND, seed=2)
+    _run_both(cuda, FIRST, seed=1, argument_launch=False)
+    _run_both(cuda, SECOND, seed=2, argument_launch=True)
