@@ -4,15 +4,17 @@
 //
 // A launch with at most kMixArgJobs jobs in every family passes each
 // family's job records in the kernel arguments: one kernel launch per
-// family, a workgroup per tile, nothing else.  Any other
-// launch copies one table (header and job records) from pinned memory to the
-// device and enqueues [expand the tile lists] -> [family kernel] -> ...,
-// each family kernel persistent (at most as many workgroups as are resident,
-// and no more than its tiles), draining its family's tiles, so every
-// workgroup exits once they are done.
+// family, a workgroup per tile, nothing else.  Any other launch copies one
+// table (header and job records) from pinned memory to the device and
+// enqueues [expand the tile lists] -> [family kernel] -> ..., each family
+// kernel persistent (at most as many workgroups as are resident, and no more
+// than its tiles), draining its family's tiles, so every workgroup exits
+// once they are done.  Either way the families go in ascending order of
+// their jobs' elements, and the jobs that run as their own calls last.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -95,6 +97,8 @@ int mix_plan(const ppx_job &j, MixPlan &m) {
         m.direct = true;
         m.family = m.shape = -1;
         m.per_tile = c.problems_per_block;
+        m.tpp = 0;
+        m.block = c.threads_per_block;
         m.ntiles = 0;
         m.cfg = c;
         return PPX_OK;
@@ -120,7 +124,7 @@ int mix_plan(const ppx_job &j, MixPlan &m) {
         m.family = T <= 256 ? kFamFft256 : P == 8 ? kFamFft1024P8 : kFamFft1024;
         const bool split = (c.algo & PPX_FFT_LDS_SPLIT) != 0;
         m.shape = mix_fft_shape(log2n, P, split);
-        m.per_tile = (int)(mix_block(m.family) / T);
+        m.tpp = (int)T;
         m.flags = j.direction == 1 ? 1 : 0;
     } else if (j.op == PPX_OP_SCAN) {
         c.algo &= PPX_SCAN_LF;  // KS or LF; the persistent flag cleared
@@ -128,7 +132,7 @@ int mix_plan(const ppx_job &j, MixPlan &m) {
         const int64_t T = j.n / P;
         m.family = T <= 256 ? kFamScan256 : kFamScan1024;
         m.shape = mix_scan_shape(j.dtype, ilog2(P), c.algo == PPX_SCAN_LF);
-        m.per_tile = (int)(mix_block(m.family) / T);
+        m.tpp = (int)T;
         m.flags = j.algo == PPX_JOB_SCAN_EXCLUSIVE ? 1 : 0;
     } else {
         c.algo = tri_base(c.algo);
@@ -137,12 +141,12 @@ int mix_plan(const ppx_job &j, MixPlan &m) {
             const int P = c.elems_per_thread;
             m.family = !f64 ? (P == 16 ? kFamTriBlk32H : kFamTriBlk32) : P == 16 ? kFamTriBlk64H : kFamTriBlk64;
             m.shape = ilog2(P) - 1;
-            m.per_tile = (int)(mix_block(m.family) / (j.n / P));
+            m.tpp = (int)(j.n / P);
         } else if (tri_in_wave(c.algo)) {
             const int P = c.elems_per_thread;
             m.family = mix_triw_family(f64, c.algo, P);
             m.shape = mix_triw_shape(c.algo, ilog2(P));
-            m.per_tile = (int)(256 * P / j.n);
+            m.tpp = (int)(j.n / P);
         } else {
             const int64_t per_sys = tri_lds_arrays(c.algo) * (f64 ? 8 : 4) * j.n;
             if (per_sys > kMixTriLdsBudget)
@@ -151,9 +155,14 @@ int mix_plan(const ppx_job &j, MixPlan &m) {
             m.family = kFamTriLds;
             m.shape = mix_tril_shape(f64, c.algo == PPX_TRI_PCR);
             m.per_tile = (int)std::max<int64_t>(1, std::min<int64_t>(scaled, kMixTriLdsBudget / per_sys));
+            m.tpp = 0;  // its tiles are sized by LDS, in 1024-thread workgroups
         }
     }
     m.cfg = c;
+    // the tuned workgroup size, within what the family's kernel allows and
+    // at least a wave and a problem's threads
+    m.block = m.tpp ? std::min(mix_block(m.family), std::max({c.threads_per_block, m.tpp, kWave})) : mix_block(m.family);
+    if (m.tpp) m.per_tile = m.block / m.tpp;
     m.ntiles = (j.batch + m.per_tile - 1) / m.per_tile;
     return PPX_OK;
 }
@@ -208,15 +217,18 @@ int64_t mixed_tile_count(const ppx_job *jobs, int njobs) {
 // Plans every job and writes the header and job records into `buf` (at
 // least mix_table_bytes(njobs, 0) bytes).  Returns the family mask, or a
 // negative error.  ntiles_out receives the total tile count.
-int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_out, int *direct, int *ndirect) {
+int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_out, int *direct, int *ndirect,
+                     int *rec_job) {
     if (!jobs || njobs < 1) return fail(PPX_EINVAL, "no jobs");
     if (njobs > kMixMaxJobs) return fail(PPX_EINVAL, "too many jobs for one mixed launch");
     auto *h = reinterpret_cast<MixHeader *>(buf);
     auto *rec = reinterpret_cast<MixJob *>(buf + kMixHeaderBytes);
     std::memset(h, 0, kMixHeaderBytes);
-    int64_t fam_tiles[kMixFamilies] = {};
     int nrec = 0;
     *ndirect = 0;
+    // pass 1: plan every job; a record's per_tile holds its problem's
+    // threads until the family's workgroup size is known (the largest of its
+    // jobs' tuned sizes)
     for (int i = 0; i < njobs; ++i) {
         MixPlan m;
         if (int rc = check_job(jobs[i], &m)) return rc;
@@ -229,17 +241,27 @@ int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_
         r.shape = m.shape;
         r.flags = m.flags;
         r.log2n = ilog2(j.n);
-        r.per_tile = m.per_tile;
+        r.per_tile = m.tpp ? m.tpp : m.per_tile;
         r.batch = j.batch;
-        r.first_tile = (unsigned)fam_tiles[m.family];
+        r.first_tile = 0;
         r.family = m.family;
         r.p[0] = j.in;
         r.p[1] = j.b;
         r.p[2] = j.c;
         r.p[3] = j.d;
         r.out = j.out;
-        fam_tiles[m.family] += m.ntiles;
+        h->block[m.family] = std::max<unsigned>(h->block[m.family], (unsigned)m.block);
+        if (rec_job) rec_job[nrec] = i;
         ++nrec;
+    }
+    // pass 2: problems per tile at the family's workgroup size, tile ranges
+    int64_t fam_tiles[kMixFamilies] = {};
+    for (int k = 0; k < nrec; ++k) {
+        MixJob &r = rec[k];
+        if (r.family != kFamTriLds) r.per_tile = (int)h->block[r.family] / r.per_tile;
+        r.first_tile = (unsigned)fam_tiles[r.family];
+        fam_tiles[r.family] += (r.batch + r.per_tile - 1) / r.per_tile;
+        if (fam_tiles[r.family] > kMixMaxTiles) return fail(PPX_EINVAL, "too many tiles for one mixed launch");
     }
     int64_t total = 0;
     int mask = 0;
@@ -302,9 +324,17 @@ MixedCtx *mixed_ctx() {
 }
 }  // namespace
 
-// Resident workgroups of each family's kernel on the current device (from
-// the occupancy query at its block size and LDS), set up once per process.
-static int g_resident[kMixFamilies];
+// Resident workgroups of each family's persistent kernel on the current
+// device at each workgroup size 64 << k up to the family's (from the
+// occupancy query at that size and its LDS), set up once per process.
+constexpr int kMixBlockSizes = 5;  // 64 .. 1024
+static int g_resident[kMixFamilies][kMixBlockSizes];
+
+// LDS bytes of family fam's kernel at workgroup size block: the tiles'
+// buffers scale with it, except the LDS-exchange tridiagonal family's.
+static size_t mix_lds_at(int fam, int block) {
+    return fam == kFamTriLds ? (size_t)mix_lds_bytes(fam) : (size_t)(mix_lds_bytes(fam) * block / mix_block(fam));
+}
 static bool g_prepared = false;
 static std::mutex g_prep_mu;
 
@@ -317,14 +347,17 @@ int mix_prepare_kernels() {
         for (int args = 0; args < 2; ++args) {
             const void *k = mix_kernel(f, args != 0);
             if (!k) return fail(PPX_EHIP, "mixed launch: no kernel for family " + std::to_string(f));
-            const int64_t lds = mix_lds_bytes(f);
-            (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, mix_block(f), (size_t)lds) != hipSuccess ||
-                per_cu < 1)
-                return fail(PPX_EHIP,
-                            "mixed launch: the kernel of family " + std::to_string(f) + " cannot be resident");
-            if (!args) g_resident[f] = per_cu * di->cus;
+            (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mix_lds_bytes(f));
+            for (int b = 0; b < kMixBlockSizes && (kWave << b) <= mix_block(f); ++b) {
+                const int block = kWave << b;
+                int per_cu = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, mix_lds_at(f, block)) !=
+                        hipSuccess ||
+                    per_cu < 1)
+                    return fail(PPX_EHIP,
+                                "mixed launch: the kernel of family " + std::to_string(f) + " cannot be resident");
+                if (!args) g_resident[f][b] = per_cu * di->cus;
+            }
         }
     }
     g_prepared = true;
@@ -334,20 +367,37 @@ int mix_prepare_kernels() {
 // Enqueues the expansion and the kernels of the families in `mask` on
 // stream s, reading the tables at d_tables; each family's grid is its
 // resident count capped at its tile count ntiles[f].
-int mix_enqueue(char *d_tables, int mask, const int64_t *ntiles, const float2 *tw, hipStream_t s) {
+int mix_enqueue(char *d_tables, int mask, const int64_t *ntiles, const unsigned *blocks, const int *order, int norder,
+                const float2 *tw, hipStream_t s, mix_after_family_t after, void *arg) {
     hipLaunchKernelGGL(k_mix_expand, dim3(kMixExpandBlocks), dim3(kMixExpandThreads), 0, s, d_tables);
     hipError_t e = hipGetLastError();
     MixArgs a;
     a.tables = d_tables;
     a.ntiles = a.njobs = 0;
-    for (int f = 0; f < kMixFamilies && e == hipSuccess; ++f) {
+    for (int k = 0; k < norder && e == hipSuccess; ++k) {
+        const int f = order[k];
         if (!(mask & (1 << f))) continue;
-        const int64_t grid = std::min<int64_t>(g_resident[f], std::max<int64_t>(1, ntiles[f]));
+        const int block = (int)blocks[f];
+        const int64_t grid = std::min<int64_t>(g_resident[f][ilog2(block / kWave)], std::max<int64_t>(1, ntiles[f]));
         hipLaunchKernelGGL(reinterpret_cast<mix_kernel_t>(const_cast<void *>(mix_kernel(f, false))), dim3((unsigned)grid),
-                           dim3(mix_block(f)), (size_t)mix_lds_bytes(f), s, a, tw);
+                           dim3(block), mix_lds_at(f, block), s, a, tw);
         e = hipGetLastError();
+        if (e == hipSuccess && after)
+            if (int rc = after(arg, f, s)) return rc;
     }
     return fail_hip(e, "mixed launch");
+}
+
+int mix_family_order(const char *table, int mask, int *order) {
+    const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
+    const MixJob *rec = reinterpret_cast<const MixJob *>(table + kMixHeaderBytes);
+    double work[kMixFamilies] = {};
+    for (unsigned i = 0; i < h->njobs; ++i) work[rec[i].family] += std::ldexp(double(rec[i].batch), rec[i].log2n);
+    int n = 0;
+    for (int f = 0; f < kMixFamilies; ++f)
+        if (mask & (1 << f)) order[n++] = f;
+    std::stable_sort(order, order + n, [&](int x, int y) { return work[x] < work[y]; });
+    return n;
 }
 
 bool mix_args_fit(const char *table, int mask) {
@@ -360,54 +410,111 @@ bool mix_args_fit(const char *table, int mask) {
     return true;
 }
 
-int mix_enqueue_args(const char *table, int mask, const float2 *tw, hipStream_t s) {
+// Workgroups an argument launch aims for at least before it shrinks tiles:
+// four per CU (one per SIMD).
+constexpr int kMixFillPerCu = 4;
+
+int mix_enqueue_args(const char *table, int mask, const int *order, int norder, const float2 *tw, hipStream_t s,
+                     mix_after_family_t after, void *arg) {
     const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
     const MixJob *rec = reinterpret_cast<const MixJob *>(table + kMixHeaderBytes);
+    // A launch with fewer full tiles than it takes to fill the GPU runs its
+    // families in smaller workgroups (a problem's threads and arithmetic
+    // unchanged, fewer problems per tile), which spreads small batches over
+    // more CUs; the LDS-exchange tridiagonal family keeps its shape.
+    int64_t total = 0;
+    for (int f = 0; f < kMixFamilies; ++f)
+        if (mask & (1 << f)) total += h->ntiles[f];
+    const int64_t fill = (int64_t)kMixFillPerCu * device_info()->cus;
+    int shrink = 1;
+    while (shrink < 1024 && total * shrink * 2 <= fill) shrink *= 2;
     hipError_t e = hipSuccess;
-    for (int f = 0; f < kMixFamilies && e == hipSuccess; ++f) {
+    for (int o = 0; o < norder && e == hipSuccess; ++o) {
+        const int f = order[o];
         if (!(mask & (1 << f))) continue;
+        const int full = (int)h->block[f];
+        int block = full;
+        if (shrink > 1 && f != kFamTriLds) {
+            int need = kWave;  // threads of the widest problem among the family's jobs
+            for (unsigned i = 0; i < h->njobs; ++i)
+                if (rec[i].family == f) need = std::max(need, full / rec[i].per_tile);
+            block = std::max(full / shrink, need);
+        }
         MixArgs a;
         a.tables = nullptr;
-        a.ntiles = h->ntiles[f];
+        a.ntiles = 0;
         a.njobs = 0;
-        for (unsigned i = 0; i < h->njobs; ++i)
-            if (rec[i].family == f) a.jobs[a.njobs++] = rec[i];  // first_tile ascending, as the kernel scans them
+        for (unsigned i = 0; i < h->njobs; ++i) {
+            if (rec[i].family != f) continue;
+            MixJob r = rec[i];  // first_tile ascending, as the kernel scans them
+            r.per_tile = (int)((int64_t)r.per_tile * block / full);
+            r.first_tile = a.ntiles;
+            a.ntiles += (unsigned)((r.batch + r.per_tile - 1) / r.per_tile);
+            a.jobs[a.njobs++] = r;
+        }
+        const size_t lds = mix_lds_at(f, block);
         hipLaunchKernelGGL(reinterpret_cast<mix_kernel_t>(const_cast<void *>(mix_kernel(f, true))), dim3(a.ntiles),
-                           dim3(mix_block(f)), (size_t)mix_lds_bytes(f), s, a, tw);
+                           dim3(block), lds, s, a, tw);
         e = hipGetLastError();
+        if (e == hipSuccess && after)
+            if (int rc = after(arg, f, s)) return rc;
     }
     return fail_hip(e, "mixed launch");
 }
 
-int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEvent_t done_event) {
+namespace {
+// Stage bookkeeping of one launch: which records each family completes.
+struct StageCtx {
+    const MixStageHook *hook;
+    const MixJob *rec;
+    const int *rec_job;
+    unsigned nrec;
+    int next;
+};
+int after_family(void *arg, int fam, hipStream_t s) {
+    auto *c = static_cast<StageCtx *>(arg);
+    for (unsigned r = 0; r < c->nrec; ++r)
+        if (c->rec[r].family == fam) c->hook->job_stage[c->rec_job[r]] = c->next;
+    ++c->next;
+    return c->hook->stage(c->hook->arg, s);
+}
+}  // namespace
+
+int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEvent_t done_event,
+                      const MixStageHook *hook) {
     if (!jobs || njobs < 1) return fail(PPX_EINVAL, "no jobs");
     if (njobs > kMixMaxJobs) return fail(PPX_EINVAL, "too many jobs for one mixed launch");
     std::unique_lock<std::mutex> lk(g_mixed_mu);
     MixedCtx *m = mixed_ctx();
     if (!m) return PPX_EHIP;
     int64_t ntiles = 0;
-    std::vector<int> direct(njobs);
+    std::vector<int> direct(njobs), rec_job(njobs);
     int ndirect = 0;
     char *table = m->plan.data();
-    const int mask = mix_build_tables(jobs, njobs, table, &ntiles, direct.data(), &ndirect);
+    const int mask = mix_build_tables(jobs, njobs, table, &ntiles, direct.data(), &ndirect, rec_job.data());
     if (mask < 0) return mask;
     direct.resize(ndirect);
+    const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
+    StageCtx sc{hook, reinterpret_cast<const MixJob *>(table + kMixHeaderBytes), rec_job.data(), h->njobs, 0};
+    const mix_after_family_t after = hook ? after_family : nullptr;
+    int order[kMixFamilies];
+    const int norder = mix_family_order(table, mask, order);
     const float2 *tw = static_cast<const float2 *>(device_info()->twiddles);
     hipError_t e = hipSuccess;
-    if (mask && mix_args_fit(table, mask)) {  // a small launch: the records go in the kernel arguments
-        if (int rc = mix_enqueue_args(table, mask, tw, stream)) return rc;
+    if (mask && mix_args_fit(table, mask)) {  // the records go in the kernel arguments
+        if (int rc = mix_enqueue_args(table, mask, order, norder, tw, stream, after, &sc)) return rc;
     } else if (mask) {  // the tiled jobs: one table copy, the expansion and the family kernels
         Slot &s = m->slots[m->next];
         if (s.used && hipEventSynchronize(s.done) != hipSuccess) return fail(PPX_EHIP, "slot wait failed");
         m->next = (m->next + 1) % kSlots;
-        const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
         const size_t bytes = kMixHeaderBytes + (size_t)h->njobs * sizeof(MixJob);
         std::memcpy(s.h_stage, table, bytes);
         int64_t fam_tiles[kMixFamilies];
         for (int f = 0; f < kMixFamilies; ++f) fam_tiles[f] = h->ntiles[f];
         e = hipMemcpyAsync(s.d_tables, s.h_stage, bytes, hipMemcpyHostToDevice, stream);
         if (e != hipSuccess) return fail_hip(e, "mixed launch");
-        if (int rc = mix_enqueue(s.d_tables, mask, fam_tiles, tw, stream)) return rc;
+        if (int rc = mix_enqueue(s.d_tables, mask, fam_tiles, h->block, order, norder, tw, stream, after, &sc))
+            return rc;
         e = hipEventRecord(s.done, stream);
         s.used = true;
         if (e != hipSuccess) return fail_hip(e, "mixed launch");
@@ -416,6 +523,10 @@ int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEve
         MixPlan p;
         (void)mix_plan(jobs[i], p);  // planned once already: cannot fail now
         if (int rc = mix_launch_direct(jobs[i], p.cfg, stream)) return rc;
+        if (hook) {
+            hook->job_stage[i] = sc.next++;
+            if (int rc = hook->stage(hook->arg, stream)) return rc;
+        }
     }
     if (done_event) e = hipEventRecord(done_event, stream);
     return fail_hip(e, "mixed launch");
@@ -499,8 +610,10 @@ int launch_mixed_noalloc_impl(const ppx_job *jobs, int njobs, hipStream_t stream
     char *d = noalloc_scratch();
     if (!d) return PPX_EDEVICE;
     const float2 *tw = static_cast<const float2 *>(device_info()->twiddles);
+    int order[kMixFamilies];
+    const int norder = mix_family_order(table, mask, order);
     if (mask && mix_args_fit(table, mask)) {  // a small launch: the records go in the kernel arguments
-        if (int rc = mix_enqueue_args(table, mask, tw, stream)) return rc;
+        if (int rc = mix_enqueue_args(table, mask, order, norder, tw, stream)) return rc;
     } else if (mask) {
         const MixHeader *h = reinterpret_cast<const MixHeader *>(table);
         const unsigned bytes = (unsigned)(kMixHeaderBytes + sizeof(MixJob) * (size_t)h->njobs);
@@ -514,7 +627,7 @@ int launch_mixed_noalloc_impl(const ppx_job *jobs, int njobs, hipStream_t stream
         }
         int64_t fam_tiles[kMixFamilies];
         for (int f = 0; f < kMixFamilies; ++f) fam_tiles[f] = h->ntiles[f];
-        if (int rc = mix_enqueue(d, mask, fam_tiles, tw, stream)) return rc;
+        if (int rc = mix_enqueue(d, mask, fam_tiles, h->block, order, norder, tw, stream)) return rc;
     }
     for (int k = 0; k < ndirect; ++k) {  // jobs that fill the GPU alone: their tuned single calls
         MixPlan p;

@@ -75,6 +75,7 @@ struct MixHeader {
     unsigned next[kMixFamilies];      // tile counters (0 at launch)
     unsigned ntiles[kMixFamilies];    // tiles per family
     unsigned tile_base[kMixFamilies]; // first entry of each family's list
+    unsigned block[kMixFamilies];     // workgroup size of each family's tiles (host use)
     unsigned njobs;
     unsigned tiles_off;               // byte offset of the tile lists
 };
@@ -157,8 +158,15 @@ constexpr int kMixExpandThreads = 256;
 // persistent variant (which prefetches the next group while computing the
 // current one, something a tile of the shared loop cannot do) runs as its
 // own single call with that configuration instead (direct = true, no tiles).
+// A tile's workgroup size (block) is the tuned one (threads_per_block), kept
+// within what the family's kernel allows (mix_block) and at least a wave and
+// a problem's threads (tpp); the problems per tile are block / tpp, so a job
+// alone runs tiles of exactly its tuned shape (G_b problems of P values per
+// thread in L threads).  A launch runs each family at the largest block of
+// its jobs.  LDS-exchange tridiagonal tiles (tpp = 0) are sized by LDS.
 struct MixPlan {
     int family, shape, per_tile, flags;
+    int tpp, block;
     int64_t ntiles;
     ppx_config cfg;
     bool direct;
@@ -170,20 +178,33 @@ int mix_plan(const ppx_job &j, MixPlan &m);
 // Plans every job and writes the header and job records into buf; returns
 // the mask of families with tiles or a negative error.
 // Direct jobs get no record; their indices go to direct[0 .. *ndirect)
-// (room for njobs entries).
-int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_out, int *direct, int *ndirect);
+// (room for njobs entries).  rec_job (optional, njobs entries) receives the
+// job index of each record.
+int mix_build_tables(const ppx_job *jobs, int njobs, char *buf, int64_t *ntiles_out, int *direct, int *ndirect,
+                     int *rec_job = nullptr);
+// The families of `mask` in launch order: ascending total elements of
+// their jobs, so that the families of small jobs finish first.  Returns
+// their count.
+int mix_family_order(const char *table, int mask, int *order);
+// Called after each family kernel is enqueued (may be empty).
+typedef int (*mix_after_family_t)(void *arg, int fam, hipStream_t s);
 // Launches job j alone with configuration c (a direct job).
 int mix_launch_direct(const ppx_job &j, const ppx_config &c, hipStream_t s);
 // Occupancy of every family kernel on the current device (once).
 int mix_prepare_kernels();
-// Expansion plus the family kernels of `mask`, on stream s, each grid
-// capped at the family's tile count ntiles[f].
-int mix_enqueue(char *d_tables, int mask, const int64_t *ntiles, const float2 *tw, hipStream_t s);
+// Expansion plus the family kernels of `mask` in the given order, on stream
+// s, in workgroups of blocks[f] threads, each grid capped at the family's
+// tile count ntiles[f].
+int mix_enqueue(char *d_tables, int mask, const int64_t *ntiles, const unsigned *blocks, const int *order, int norder,
+                const float2 *tw, hipStream_t s, mix_after_family_t after = nullptr, void *arg = nullptr);
 // Whether the launch planned in `table` (header and records) can pass its
 // jobs as kernel arguments (at most kMixArgJobs per family), and if so its
 // launches: one argument kernel per family in mask, a workgroup per tile.
+// A launch too small to fill the GPU runs smaller workgroups (fewer
+// problems per tile, never fewer threads than a problem or a wave needs).
 bool mix_args_fit(const char *table, int mask);
-int mix_enqueue_args(const char *table, int mask, const float2 *tw, hipStream_t s);
+int mix_enqueue_args(const char *table, int mask, const int *order, int norder, const float2 *tw, hipStream_t s,
+                     mix_after_family_t after = nullptr, void *arg = nullptr);
 
 // ---- the tile loop shared by the families
 // ARGS: the records come in the kernel arguments and workgroup b runs tile b
@@ -194,8 +215,10 @@ int mix_enqueue_args(const char *table, int mask, const float2 *tw, hipStream_t 
 // from its counter in the device tables until they run out, the next index
 // being claimed while the current tile is processed, and looks the job up
 // in the family's tile list.
-// Either way body(job, first problem, problem count, tx) runs each tile, tx
-// being the thread's index in the workgroup passed through an empty asm that
+// Either way body(job, first problem, problem count, tx, nt) runs each tile,
+// nt being the workgroup's size (the tuned one, at most mix_block(FAM); see
+// MixPlan) and tx the thread's
+// index in the workgroup passed through an empty asm that
 // claims to change it: without it the compiler hoists every address derived
 // from the thread index out of the loop, for every shape a family holds, and
 // keeps them all live (the FFT families then spilled).  Every thread of the
@@ -217,12 +240,12 @@ __device__ __forceinline__ MixJob mix_load_job(mix_arg_job_ptr r) {
 }
 
 template <typename Body>
-__device__ __forceinline__ void mix_run_tile(const MixJob &j, unsigned t, Body &body) {
+__device__ __forceinline__ void mix_run_tile(const MixJob &j, unsigned t, int nt, Body &body) {
     const long long first = (long long)(t - j.first_tile) * j.per_tile;
     const int count = (int)min((long long)j.per_tile, j.batch - first);
     int tx = threadIdx.x;
     asm volatile("" : "+v"(tx));
-    body(j, first, count, tx);
+    body(j, first, count, tx, nt);
 }
 
 template <int FAM, bool ARGS, typename Body>
@@ -234,7 +257,7 @@ __device__ __forceinline__ void mix_tile_loop(const MixArgs &a, Body &&body) {
         const unsigned t = blockIdx.x;
         unsigned k = 0;
         while (k + 1 < a.njobs && recs[k + 1].first_tile <= t) ++k;
-        mix_run_tile(mix_load_job(recs + k), t, body);
+        mix_run_tile(mix_load_job(recs + k), t, (int)blockDim.x, body);
     } else {
         __shared__ unsigned s_tile;
         const MixHeader *h = reinterpret_cast<const MixHeader *>(a.tables);
@@ -248,7 +271,7 @@ __device__ __forceinline__ void mix_tile_loop(const MixArgs &a, Body &&body) {
         while (t < ntiles) {
             unsigned next = 0;
             if (threadIdx.x == 0) next = atomicAdd(ctr, 1u);
-            mix_run_tile(jobs[__builtin_amdgcn_readfirstlane(tiles[t])], t, body);
+            mix_run_tile(jobs[__builtin_amdgcn_readfirstlane(tiles[t])], t, (int)blockDim.x, body);
             __syncthreads();  // every thread is done with s_tile and the tile's LDS
             if (threadIdx.x == 0) s_tile = next;
             __syncthreads();

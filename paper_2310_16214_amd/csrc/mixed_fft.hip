@@ -26,7 +26,7 @@ constexpr bool mix_fft_member(int log2n, int P, bool) {
 
 template <int FAM, int ID>
 __device__ __forceinline__ void mix_fft_dispatch(const MixJob &j, long long first, int count,
-                                                 const float2 *__restrict__ tw, void *lds, int tx) {
+                                                 const float2 *__restrict__ tw, void *lds, int tx, int nt) {
     if constexpr (ID < kMixFftShapes) {
         constexpr int LOG2N = ID / 6;
         constexpr int P = 4 << ((ID / 2) % 3);
@@ -35,20 +35,19 @@ __device__ __forceinline__ void mix_fft_dispatch(const MixJob &j, long long firs
             static_assert(mix_fft_shape(LOG2N, P, SPLIT) == ID, "shape code");
             if (j.shape == ID) {
                 fft_group_ct<P, P, SPLIT, LOG2N>(static_cast<const float2 *>(j.p[0]), static_cast<float2 *>(j.out),
-                                                 tw, first, count, (j.flags & 1) ? -1.0f : 1.0f, lds, tx,
-                                                 mix_block(FAM));
+                                                 tw, first, count, (j.flags & 1) ? -1.0f : 1.0f, lds, tx, nt);
                 return;
             }
         }
-        mix_fft_dispatch<FAM, ID + 1>(j, first, count, tw, lds, tx);
+        mix_fft_dispatch<FAM, ID + 1>(j, first, count, tw, lds, tx, nt);
     }
 }
 
 template <int FAM, bool ARGS>
 __global__ __launch_bounds__(mix_block(FAM)) void k_mix_fft(MixArgs a, const float2 *tw) {
     extern __shared__ float4 lds[];
-    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx) {
-        mix_fft_dispatch<FAM, 0>(j, first, count, tw, lds, tx);
+    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx, int nt) {
+        mix_fft_dispatch<FAM, 0>(j, first, count, tw, lds, tx, nt);
     });
 }
 

@@ -33,7 +33,7 @@ __device__ __forceinline__ void mix_scan_dispatch(const MixJob &j, long long fir
 template <int FAM, bool ARGS>
 __global__ __launch_bounds__(mix_block(FAM)) void k_mix_scan(MixArgs a, const float2 *) {
     __shared__ double wave_tot[mix_block(FAM) / kWave];  // int and float totals use its start
-    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx) {
+    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx, int nt) {
         mix_scan_dispatch<0>(j, first, count, wave_tot, tx);
     });
 }

@@ -51,7 +51,7 @@ constexpr int triw_min_waves() { return FAM == kFamTriW64H ? 3 : 1; }
 template <int FAM, bool ARGS>
 __global__ __launch_bounds__(256, triw_min_waves<FAM>()) void k_mix_triw(MixArgs a, const float2 *) {
     extern __shared__ float4 smem[];  // PPX_TRI_PCR_REG exchange buffers, one per wave
-    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx) {
+    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx, int nt) {
         mix_triw_dispatch<FAM, 0>(j, first, count, smem, tx);
     });
 }
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256, triw_min_waves<FAM>()) void k_mix_triw(MixArgs
 template <bool ARGS>
 __global__ __launch_bounds__(1024) void k_mix_tril(MixArgs a, const float2 *) {
     extern __shared__ float4 smem[];
-    mix_tile_loop<kFamTriLds, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx) {
+    mix_tile_loop<kFamTriLds, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx, int nt) {
         switch (j.shape) {
             case mix_tril_shape(false, false):
                 tridiag_block<float, PPX_TRI_CR>(static_cast<const float *>(j.p[0]), static_cast<const float *>(j.p[1]),
@@ -89,10 +89,12 @@ __global__ __launch_bounds__(1024) void k_mix_tril(MixArgs a, const float2 *) {
     });
 }
 
-// The hybrid across waves: a tile is mix_block(FAM) / (n / P) systems, the
-// lanes exchanging through LDS slots (two sets of a, c, d per thread).
+// The hybrid across waves: a tile is nt / (n / P) systems (nt the workgroup
+// size), the lanes exchanging through LDS slots (two sets of a, c, d per
+// thread).
 template <int FAM, int LP>
-__device__ __forceinline__ void mix_trib_dispatch(const MixJob &j, long long first, int count, void *smem, int tx) {
+__device__ __forceinline__ void mix_trib_dispatch(const MixJob &j, long long first, int count, void *smem, int tx,
+                                                  int nt) {
     if constexpr (LP <= 4) {
         using T = typename std::conditional<FAM == kFamTriBlk32 || FAM == kFamTriBlk32H, float, double>::type;
         constexpr int P = 1 << LP;
@@ -101,19 +103,19 @@ __device__ __forceinline__ void mix_trib_dispatch(const MixJob &j, long long fir
                 tridiag_blk_block<T, P>(static_cast<const T *>(j.p[0]), static_cast<const T *>(j.p[1]),
                                         static_cast<const T *>(j.p[2]), static_cast<const T *>(j.p[3]),
                                         static_cast<T *>(j.out), j.log2n, first, count, static_cast<T *>(smem), tx,
-                                        mix_block(FAM));
+                                        nt);
                 return;
             }
         }
-        mix_trib_dispatch<FAM, LP + 1>(j, first, count, smem, tx);
+        mix_trib_dispatch<FAM, LP + 1>(j, first, count, smem, tx, nt);
     }
 }
 
 template <int FAM, bool ARGS>
 __global__ __launch_bounds__(mix_block(FAM)) void k_mix_trib(MixArgs a, const float2 *) {
     extern __shared__ float4 smem[];
-    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx) {
-        mix_trib_dispatch<FAM, 1>(j, first, count, smem, tx);
+    mix_tile_loop<FAM, ARGS>(a, [&](const MixJob &j, long long first, int count, int tx, int nt) {
+        mix_trib_dispatch<FAM, 1>(j, first, count, smem, tx, nt);
     });
 }
 

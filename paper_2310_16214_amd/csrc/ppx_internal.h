@@ -163,8 +163,20 @@ struct MixPlan;
 int check_job(const ppx_job &j, MixPlan *plan = nullptr);
 // Tiles of the jobs' mixed launch, or -1 if a job cannot be planned.
 int64_t mixed_tile_count(const ppx_job *jobs, int njobs);
-// launch_mixed with an optional extra event recorded after the launch.
-int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEvent_t done_event);
+// Completion stages of a mixed launch, for callers that retire jobs as
+// their kernels finish: right after enqueuing each kernel that completes
+// jobs (a family kernel, or a direct job's call) the launch calls
+// stage(arg, stream), and writes that stage's index (from 0, in launch
+// order) to job_stage[i] for each job i it completes.
+struct MixStageHook {
+    int (*stage)(void *arg, hipStream_t s);
+    void *arg;
+    int *job_stage;  // one entry per job
+};
+// launch_mixed with an optional extra event recorded after the launch and
+// optional completion stages.
+int launch_mixed_impl(const ppx_job *jobs, int njobs, hipStream_t stream, hipEvent_t done_event,
+                      const MixStageHook *hook = nullptr);
 
 // ---- configuration logic (config.cpp) ----
 int validate_config(int op, int dtype, int64_t n, const ppx_config &c);

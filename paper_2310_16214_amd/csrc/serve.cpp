@@ -81,6 +81,11 @@ struct Launch {
     std::vector<int64_t> ids;
     hipEvent_t done = nullptr;
     int stream = 0;
+    // a fused launch retires its jobs by stage: stage k's jobs are complete
+    // once stage_ev[k] has fired (stages finish in order on the stream)
+    std::vector<hipEvent_t> stage_ev;
+    std::vector<std::vector<int64_t>> stage_ids;
+    size_t stages_done = 0;
     // an online-tuning evaluation: timed by start -> done (both with timing)
     ppx_online *session = nullptr;
     hipEvent_t start = nullptr;
@@ -158,11 +163,26 @@ int launch_single(const ppx_job &j, hipStream_t st, const ppx_config *cfg) {
     }
 }
 
+void complete_job(ppx_server *s, int64_t id, double t) {
+    Job &j = s->jobs[id];
+    j.completed = true;
+    j.complete_us = t;
+    s->completed.push_back(id);
+    ++s->ncompleted;
+}
+
 // Retires launches whose completion event has fired (all of them, in the
-// null-device mode).
+// null-device mode), and the finished stages of fused launches still
+// running.
 void retire(ppx_server *s) {
     const double t = s->now_us();
     for (auto it = s->inflight.begin(); it != s->inflight.end();) {
+        while (!s->null_device() && it->stages_done < it->stage_ev.size() &&
+               hipEventQuery(it->stage_ev[it->stages_done]) == hipSuccess) {
+            for (int64_t id : it->stage_ids[it->stages_done]) complete_job(s, id, t);
+            s->free_events.push_back(it->stage_ev[it->stages_done]);
+            ++it->stages_done;
+        }
         bool done = s->null_device() || hipEventQuery(it->done) == hipSuccess;
         if (!done) {
             ++it;
@@ -176,12 +196,13 @@ void retire(ppx_server *s) {
             (void)hipEventDestroy(it->done);
             it->done = nullptr;
         }
-        for (int64_t id : it->ids) {
-            Job &j = s->jobs[id];
-            j.completed = true;
-            j.complete_us = t;
-            s->completed.push_back(id);
-            ++s->ncompleted;
+        if (it->stage_ev.empty()) {
+            for (int64_t id : it->ids) complete_job(s, id, t);
+        } else {  // the stages not seen yet (all fired with the final event)
+            for (; it->stages_done < it->stage_ev.size(); ++it->stages_done) {
+                for (int64_t id : it->stage_ids[it->stages_done]) complete_job(s, id, t);
+                s->free_events.push_back(it->stage_ev[it->stages_done]);
+            }
         }
         if (it->done) s->free_events.push_back(it->done);
         it = s->inflight.erase(it);
@@ -257,6 +278,9 @@ void unadmit(ppx_server *s, const std::vector<int64_t> &ids, Launch &l) {
         s->pending.push_front(*it);
         --s->admitted;
     }
+    for (hipEvent_t e : l.stage_ev) s->free_events.push_back(e);
+    l.stage_ev.clear();
+    l.stage_ids.clear();
     if (l.start) (void)hipEventDestroy(l.start);
     if (l.session) {  // a timed evaluation: its events were its own
         if (l.done) (void)hipEventDestroy(l.done);
@@ -267,6 +291,19 @@ void unadmit(ppx_server *s, const std::vector<int64_t> &ids, Launch &l) {
     }
     l.done = l.start = nullptr;
     l.session = nullptr;
+}
+
+// Records the completion event of a fused launch's next stage.
+struct StageArg {
+    ppx_server *s;
+    Launch *l;
+};
+int record_stage(void *arg, hipStream_t st) {
+    auto *a = static_cast<StageArg *>(arg);
+    hipEvent_t e = take_event(a->s);
+    if (!e) return fail(PPX_EHIP, "event creation failed");
+    a->l->stage_ev.push_back(e);
+    return fail_hip(hipEventRecord(e, st), "event record");
 }
 
 // Launches the admitted jobs `ids` as l (one job alone in the per-request
@@ -305,17 +342,36 @@ int launch_admitted(ppx_server *s, const std::vector<int64_t> &ids, Launch &l) {
         std::vector<ppx_job> batch;
         batch.reserve(ids.size());
         for (int64_t id : ids) batch.push_back(s->jobs[id].job);
-        rc = launch_mixed_impl(batch.data(), (int)batch.size(), st, l.done);
+        std::vector<int> job_stage(ids.size(), -1);
+        StageArg sa{s, &l};
+        const MixStageHook hook{record_stage, &sa, job_stage.data()};
+        rc = launch_mixed_impl(batch.data(), (int)batch.size(), st, l.done, &hook);
+        if (rc == PPX_OK) {
+            l.stage_ids.resize(l.stage_ev.size());
+            for (size_t k = 0; k < ids.size(); ++k) {
+                if (job_stage[k] < 0 || job_stage[k] >= (int)l.stage_ids.size())
+                    return fail(PPX_EHIP, "mixed launch: a job without a completion stage");
+                l.stage_ids[job_stage[k]].push_back(ids[k]);
+            }
+        }
     }
     return rc;
 }
 
+// Retires what has completed, then fills the free launch slots.  In the
+// fused mode the pending jobs are spread over the free slots (each launch
+// takes its share of them, at least one): at light load, when jobs arrive
+// one by one, each goes out alone at once as it would per request, and it
+// takes a backlog for launches to batch.
 int progress(ppx_server *s, int *launched) {
     if (launched) *launched = 0;
     retire(s);
     while ((int)s->inflight.size() < s->max_inflight && !s->pending.empty()) {
         const bool single = s->per_request();
-        std::vector<int64_t> ids = admit(s, kMixLaunchTiles, single ? 1 : kMixLaunchJobs);
+        const int64_t free_slots = s->max_inflight - (int64_t)s->inflight.size();
+        const int64_t share = ((int64_t)s->pending.size() + free_slots - 1) / free_slots;
+        const int job_cap = single ? 1 : (int)std::min<int64_t>(kMixLaunchJobs, share);
+        std::vector<int64_t> ids = admit(s, kMixLaunchTiles, job_cap);
         if (ids.empty()) break;
         Launch l;
         l.ids = ids;

@@ -59,11 +59,21 @@ def test_tiles_follow_the_tuned_configuration(tuned, op, dtype, n, algo):
         want = ref.as_tuple()[:5] + (ref.algo & ~PIPE[op],)
         assert cfg.as_tuple() == want, (cfg, ref)
     assert ppx.config_valid(op, ppx.C64 if op == ppx.OP_FFT else dtype, n, cfg)
-    # problems per tile: the tuned workgroup's share scaled to the family's
-    # block (256 or 1024 threads; 512 for the float64 hybrid with P = 16)
+    # problems per tile: the tuned workgroup size within the family's limit
+    # (256 or 1024 threads; 512 for the float64 hybrid with P = 16) and at
+    # least a wave, over the problem's threads -- the tuned G_b where the
+    # tuned workgroup is within those bounds
     T = n // cfg.elems_per_thread
-    block = 256 if T <= 256 else 512 if (op == ppx.OP_TRIDIAG and dtype == ppx.F64 and cfg.elems_per_thread == 16) else 1024
+    if op == ppx.OP_TRIDIAG and cfg.algo & 7 in (ppx.TRI_CR, ppx.TRI_PCR):
+        return  # LDS-exchange tiles: sized by LDS
+    if op == ppx.OP_TRIDIAG:  # in-wave (T <= 64) or the hybrid across waves
+        limit = 256 if T <= 64 else 512 if (dtype == ppx.F64 and cfg.elems_per_thread == 16) else 1024
+    else:
+        limit = 256 if T <= 256 else 1024
+    block = min(limit, max(cfg.threads_per_block, T, 64))
     assert per == block // T
+    if 64 <= cfg.threads_per_block <= limit:
+        assert per == cfg.problems_per_block
 
 
 def test_untuned_fft_shape_gets_a_radix_equal_p_substitute(tmp_path):
@@ -81,7 +91,7 @@ def test_untuned_fft_shape_gets_a_radix_equal_p_substitute(tmp_path):
         per, cfg = ppx.mixed_tile_config(_job(ppx.OP_FFT, ppx.C64, 1024, 100))
         assert cfg.radix == cfg.elems_per_thread and cfg.radix in (8, 16)
         assert ppx.config_valid(ppx.OP_FFT, ppx.C64, 1024, cfg)
-        assert per == 256 // (1024 // cfg.elems_per_thread)
+        assert per == cfg.problems_per_block == max(1, 64 // (1024 // cfg.elems_per_thread))
     finally:
         ppx.clear_tune_cache()
 

@@ -84,11 +84,17 @@ def test_continuous_batching_and_inflight_cap():
     s = ppx.Server(1 << 30, max_inflight=2, flags=ppx.SERVE_NULL_DEVICE)
     for _ in range(4):
         s.submit(_job(64, 8))
-    assert s.progress() == 4                      # all pending jobs go in one launch
-    for _ in range(3):
-        s.submit(_job(64, 8))
-    assert s.progress() == 3                      # the next step's arrivals: a second launch
+    assert s.progress() == 4                      # spread over the two free slots
     assert s.stats()["launches"] == 2
+    for _ in range(5):
+        s.submit(_job(64, 8))
+    assert s.progress() == 5                      # the next step's arrivals: 3 + 2
+    assert s.stats()["launches"] == 4
+    one = ppx.Server(1 << 30, max_inflight=1, flags=ppx.SERVE_NULL_DEVICE)
+    for _ in range(7):
+        one.submit(_job(64, 8))
+    assert one.progress() == 7                    # one slot: every pending job in one launch
+    assert one.stats()["launches"] == 1
     per = ppx.Server(1 << 30, max_inflight=2, flags=ppx.SERVE_NULL_DEVICE | ppx.SERVE_PER_REQUEST)
     for _ in range(4):
         per.submit(_job(64, 8))
