@@ -37,6 +37,21 @@ constexpr int kNMax = 1 << kFftLog2NMax;
 __device__ __forceinline__ int swz_c(int p) { return p ^ ((p >> 4) & 15); }  // float2 words
 __device__ __forceinline__ int swz_f(int p) { return p ^ ((p >> 5) & 31); }  // float words
 
+// The same swizzles with the block index shifted left by sigma before the
+// XOR: p ^ (((p >> 4) << sigma) & 15) (float2), p ^ (((p >> 5) << sigma) & 31)
+// (float).  A radix-RS stage with span 2^lns writes, per group of lanes served
+// together (16 lanes of 8-byte words, 32 of 4-byte words), addresses whose
+// low bits come partly from the lane index directly and partly from the
+// block index (the lane bits at and above lns land log2 RS positions higher).
+// sigma = min(lns, 4 - log2 RS) (float2) or min(lns, 5 - log2 RS) (float)
+// moves those block-index bits onto exactly the low positions the lanes leave
+// free, so every group's writes hit distinct banks; the reads of the same
+// exchange (consecutive lanes on consecutive words) are conflict-free under
+// any such swizzle.  sigma = 0 is the plain swizzle above (radix 16 with
+// float2 words); radix 8 needs sigma = 1 after its first stage.
+__device__ __forceinline__ int swz_cs(int p, int sigma) { return p ^ ((p >> (4 - sigma)) & ((15 << sigma) & 15)); }
+__device__ __forceinline__ int swz_fs(int p, int sigma) { return p ^ ((p >> (5 - sigma)) & ((31 << sigma) & 31)); }
+
 // Twiddles w[q] = w_{Ns*RS}^{q*k}, q = 1..RS-1, from the table of w_NMAX^m:
 // w^k, w^{4k} and w^{8k} are read (as the radix needs them) and the other
 // powers are products of at most three of them, so a butterfly issues at most
@@ -115,41 +130,46 @@ __device__ __forceinline__ int stage_out_pos(int t, int lns, int q) {
     return ((t >> lns) << (lns + LRS)) + k + (q << lns);
 }
 
-// `lds` is the workgroup's buffer and `poff` the problem's offset in it.
+// `lds` is the workgroup's buffer and `poff` the problem's offset in it.  The
+// stage's swizzle (swz_cs / swz_fs with its sigma) is used for both the
+// writes and the reads of the exchange.
 template <int RS, int P, bool SPLIT>
 __device__ __forceinline__ void stage_exchange(float2 (&v)[P], void *lds, int poff, int tid, int T,
                                                int lns) {
     constexpr int NB = P / RS;
+    constexpr int LRS = RS == 2 ? 1 : RS == 4 ? 2 : RS == 8 ? 3 : 4;
     if constexpr (!SPLIT) {
         float2 *buf = static_cast<float2 *>(lds);
+        const int sg = min(lns, 4 - LRS);
 #pragma unroll
         for (int i = 0; i < NB; ++i)
 #pragma unroll
             for (int q = 0; q < RS; ++q)
-                buf[swz_c(poff + stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB];
+                buf[swz_cs(poff + stage_out_pos<RS>(tid + i * T, lns, q), sg)] = v[i + q * NB];
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < P; ++j) v[j] = buf[swz_c(poff + tid + j * T)];
+        for (int j = 0; j < P; ++j) v[j] = buf[swz_cs(poff + tid + j * T, sg)];
         __syncthreads();
     } else {
         float *buf = static_cast<float *>(lds);
+        const int sg = min(lns, 5 - LRS);
 #pragma unroll
         for (int i = 0; i < NB; ++i)
 #pragma unroll
             for (int q = 0; q < RS; ++q)
-                buf[swz_f(poff + stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB].x;
+                buf[swz_fs(poff + stage_out_pos<RS>(tid + i * T, lns, q), sg)] = v[i + q * NB].x;
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < P; ++j) v[j].x = buf[swz_f(poff + tid + j * T)];
+        for (int j = 0; j < P; ++j) v[j].x = buf[swz_fs(poff + tid + j * T, sg)];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NB; ++i)
 #pragma unroll
             for (int q = 0; q < RS; ++q)
-                buf[swz_f(poff + stage_out_pos<RS>(tid + i * T, lns, q))] = v[i + q * NB].y;
+                buf[swz_fs(poff + stage_out_pos<RS>(tid + i * T, lns, q), sg)] = v[i + q * NB].y;
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < P; ++j) v[j].y = buf[swz_f(poff + tid + j * T)];
+        for (int j = 0; j < P; ++j) v[j].y = buf[swz_fs(poff + tid + j * T, sg)];
         __syncthreads();
     }
 }
