@@ -50,6 +50,8 @@ def kernel_name_prefix(d):
         excl = "true" if d.get("exclusive") else "false"
         return f"{name}<{t}, {c['elems_per_thread']}, {c['algo'] & 1}, {excl}>"
     t = "double" if d["dtype"] == "float64" else "float"
+    if c["algo"] & 7 == 2 and d["n"] // c["elems_per_thread"] > 64:  # the hybrid across waves
+        return f"k_tridiag_blk<{t}, {c['elems_per_thread']}>"
     if c["algo"] & 7 >= 2:
         name = "k_tridiag_wave_pipe" if c["algo"] & 8 else "k_tridiag_wave"
         return f"{name}<{t}, {c['algo'] & 7}, {c['elems_per_thread']}>"
