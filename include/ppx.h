@@ -358,8 +358,13 @@ int launch_mixed_noalloc(const ppx_job *jobs, int njobs, void *stream);
 
 /*
  * ppx_mixed_tile_config -- how launch_mixed cuts *job: returns the problems
- * per tile (> 0) or a negative PPX_E* code, and writes to *cfg (if not
- * NULL) the single-call configuration whose arithmetic the tiles follow:
+ * per tile (> 0) of the job in a launch of its own (the configuration's
+ * problems per workgroup where its workgroup size is within the tile
+ * kernel's limit; a launch runs each family at the largest workgroup size of
+ * its jobs, so a job may get more problems per tile there, and a launch too
+ * small to fill the GPU fewer) or a negative PPX_E* code, and writes to *cfg
+ * (if not NULL) the single-call configuration whose arithmetic the tiles
+ * follow:
  * the configuration of the job's call with cfg == NULL, with the persistent
  * flag cleared (a launch strategy, not arithmetic); for a job that runs as
  * its own call (PPX_MIXED_DIRECT_ELEMS), that configuration unchanged and its
