@@ -350,7 +350,11 @@ int launch_mixed(const ppx_job *jobs, int njobs, void *stream);
  * tile-list expansion and the persistent family kernels.
  * Every call on a device shares that device's array, so calls whose work
  * overlaps on one device (different streams, or host threads) race and must
- * be ordered by the caller.  Asynchronous and stream-ordered.
+ * be ordered by the caller.  Host-side planning touches no heap for shapes
+ * whose configuration is in the tune cache or was resolved before (the
+ * analytical choice is memoised on its first use); a caller under graph
+ * capture can resolve its shapes once beforehand (ppx_mixed_tile_config).
+ * Asynchronous and stream-ordered.
  */
 #define PPX_NOALLOC_MAX_JOBS 256
 #define PPX_NOALLOC_MAX_TILES 262144
