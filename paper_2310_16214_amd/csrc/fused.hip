@@ -32,8 +32,8 @@ int64_t mix_lds_bytes(int fam) {
         case kFamFft256: return 256 * 16 * 8;    // complex exchange, P = 16
         case kFamFft1024: return 1024 * 16 * 8;  // complex exchange, P = 16
         case kFamFft1024P8: return 1024 * 8 * 8;  // complex exchange, P = 8
-        case kFamTriW32:
-        case kFamTriW32H: return 4 * 3 * 64 * 4 * 4;  // PCR LDS exchange: 4 waves, 3 * 64 * 4 floats each
+        case kFamTriW32: return 0;  // no PCR exchange, no staged stores (P <= 8)
+        case kFamTriW32H: return 4 * 64 * 16 * 4;  // per wave: PCR exchange (3 * 64 * 4) or P = 16 staging (64 * 16) floats
         case kFamTriW64:
         case kFamTriW64H: return 4 * 3 * 64 * 4 * 8;
         case kFamTriLds: return kMixTriLdsBudget;

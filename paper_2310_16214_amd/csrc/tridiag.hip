@@ -16,13 +16,15 @@ int64_t tridiag_lds_bytes(int n, const ppx_config &c, int dtype) {
     const int64_t P = c.elems_per_thread > 0 ? c.elems_per_thread
                                              : (int64_t)n * c.problems_per_block / c.threads_per_block;
     if (tri_blk(c.algo, n, P)) return 6 * (int64_t)c.threads_per_block * es;  // two sets of a, c, d slots
-    if (tri_base(c.algo) == PPX_TRI_PCR_REG) {  // exchange buffer: 3 * 64 * min(P, 4) values per wave
+    if (tri_in_wave(c.algo)) {
+        // per wave: the PCR_REG exchange buffer (3 * 64 * min(P, 4) values)
+        // and the staging buffer of 64-byte solution chunks (64 * P values,
+        // float32 with P = 16) share one region (tri_wave_lds_vals)
         const int64_t waves = (c.threads_per_block + 63) / 64;
-        const int64_t P = c.elems_per_thread > 0 ? c.elems_per_thread
-                                                 : (int64_t)n * c.problems_per_block / c.threads_per_block;
-        return waves * 3 * 64 * (P < 4 ? P : 4) * es;
+        const int64_t exch = tri_base(c.algo) == PPX_TRI_PCR_REG ? 3 * 64 * (P < 4 ? P : 4) : 0;
+        const int64_t stage = dtype == PPX_F32 && P == 16 ? 64 * P : 0;
+        return waves * (exch > stage ? exch : stage) * es;
     }
-    if (tri_in_wave(c.algo)) return 0;
     return tri_lds_arrays(c.algo) * es * (int64_t)c.problems_per_block * n;
 }
 

@@ -616,6 +616,22 @@ __device__ __forceinline__ void wave_lf(T (&a)[P], T (&c)[P], T (&d)[P], int t, 
 // Boundary zeros, unit-diagonal scaling and the solve of the equations a
 // lane holds (b is consumed; x ends in d).  tx: the thread's index in the
 // workgroup (it selects the wave's LDS exchange buffer).
+// Solutions of 64 bytes per lane (float32, P = 16) leave through a per-wave
+// LDS buffer (wave_store_staged): a non-temporal store of lane chunks that
+// size covers only part of each line per instruction and measured slower
+// than the default policy, while the staged form stores 64 consecutive
+// 16-byte words per instruction.
+template <typename T, int P>
+constexpr bool tri_staged_stores() { return sizeof(T) == 4 && P == 16; }
+// LDS values per wave of the in-wave kernels: the PCR_REG exchange buffer
+// and the staging buffer share one region per wave.
+template <typename T, int ALGO, int P>
+constexpr int tri_wave_lds_vals() {
+    constexpr int exch = ALGO == PPX_TRI_PCR_REG ? 3 * 64 * (P < 4 ? P : 4) : 0;
+    constexpr int stage = tri_staged_stores<T, P>() ? 64 * P : 0;
+    return exch > stage ? exch : stage;
+}
+
 template <typename T, int ALGO, int P>
 __device__ __forceinline__ void tridiag_wave_solve(T (&a)[P], const T (&b)[P], T (&c)[P], T (&d)[P], int t,
                                                    int lps, T *smem, int tx) {
@@ -633,7 +649,39 @@ __device__ __forceinline__ void tridiag_wave_solve(T (&a)[P], const T (&b)[P], T
     else if constexpr (ALGO == PPX_TRI_PCR_SHFL) wave_pcr<T, P>(a, c, d, lps);
     else if constexpr (ALGO == PPX_TRI_WM) wave_wm<T, P>(a, c, d, t, lps);
     else if constexpr (ALGO == PPX_TRI_LF) wave_lf<T, P>(a, c, d, t, lps);
-    else wave_pcr_reg<T, P>(a, c, d, t, lps, smem + (tx >> 6) * (3 * 64 * (P < 4 ? P : 4)));
+    else wave_pcr_reg<T, P>(a, c, d, t, lps, smem + (tx >> 6) * tri_wave_lds_vals<T, ALGO, P>());
+}
+
+// The solution of a wave whose lanes hold consecutive chunks of P values of
+// one contiguous range (dst: the wave's first value; lanes at and beyond
+// `active` store nothing): each lane writes its chunk to the wave's LDS
+// buffer `buf` (64 P values), then lane l stores 16-byte words l, l + 64,
+// ... of the range, non-temporal.  Words are XOR-swizzled within each lane's
+// four (w ^ ((w >> 2) & 3)), which spreads a write instruction's lanes over
+// the banks and leaves the reads, four consecutive words per group of four
+// lanes, conflict-free.  A wave's LDS operations run in order; the fences
+// only keep the compiler from moving them.
+template <typename T, int P>
+__device__ __forceinline__ void wave_store_staged(T *dst, const T (&v)[P], T *buf, int lane, int active) {
+    constexpr int W = P * (int)sizeof(T) / 16;  // words per lane
+    static_assert(W == 4, "staged stores are laid out for four words per lane");
+    u32x4 *bw = reinterpret_cast<u32x4 *>(buf);
+    const auto phys = [](int w) { return w ^ ((w >> 2) & 3); };
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        u32x4 x;
+        __builtin_memcpy(&x, &v[j * 16 / (int)sizeof(T)], 16);
+        bw[phys(lane * W + j)] = x;
+    }
+    wave_lds_order();
+    u32x4 *dw = reinterpret_cast<u32x4 *>(dst);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int w = lane + 64 * k;
+        const u32x4 x = bw[phys(w)];
+        if (w < active * W) store_nt(dw + w, x);
+    }
+    wave_lds_order();
 }
 
 // One workgroup's share: systems [first, first + nsys) of size n = P * lps,
@@ -663,6 +711,17 @@ __device__ __forceinline__ void tridiag_wave_block(const T *A, const T *B, const
         }
     }
     tridiag_wave_solve<T, ALGO, P>(a, b, c, d, t, lps, smem, tx);
+    if constexpr (tri_staged_stores<T, P>()) {
+        // whole waves of consecutive threads: the wave's lanes cover the
+        // contiguous range starting at its first thread's chunk
+        if (blockDim.x % 64 == 0) {
+            const int w0 = tx & ~63;
+            const int active_lanes = max(0, min(64, nsys * lps - w0));
+            wave_store_staged<T, P>(X + first * n + (long long)w0 * P, d,
+                                    smem + (tx >> 6) * tri_wave_lds_vals<T, ALGO, P>(), tx & 63, active_lanes);
+            return;
+        }
+    }
     if (active) wave_store<T, P>(X + base, d);
 }
 
