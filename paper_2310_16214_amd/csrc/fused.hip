@@ -34,8 +34,8 @@ int64_t mix_lds_bytes(int fam) {
         case kFamFft1024P8: return 1024 * 8 * 8;  // complex exchange, P = 8
         case kFamTriW32: return 0;  // no PCR exchange, no staged stores (P <= 8)
         case kFamTriW32H: return 4 * 64 * 16 * 4;  // per wave: PCR exchange (3 * 64 * 4) or P = 16 staging (64 * 16) floats
-        case kFamTriW64:
-        case kFamTriW64H: return 4 * 3 * 64 * 4 * 8;
+        case kFamTriW64: return 4 * 3 * 64 * 4 * 8;  // per wave: PCR exchange (3 * 64 * 4) or P = 8 staging (64 * 8) doubles
+        case kFamTriW64H: return 4 * 64 * 16 * 8;    // per wave: P = 16 staging (64 * 16 doubles)
         case kFamTriLds: return kMixTriLdsBudget;
         case kFamTriBlk32:
         case kFamTriBlk32H: return 6 * 1024 * 4;  // two sets of a, c, d lane slots

@@ -22,7 +22,7 @@ int64_t tridiag_lds_bytes(int n, const ppx_config &c, int dtype) {
         // float32 with P = 16) share one region (tri_wave_lds_vals)
         const int64_t waves = (c.threads_per_block + 63) / 64;
         const int64_t exch = tri_base(c.algo) == PPX_TRI_PCR_REG ? 3 * 64 * (P < 4 ? P : 4) : 0;
-        const int64_t stage = dtype == PPX_F32 && P == 16 ? 64 * P : 0;
+        const int64_t stage = P * es >= 64 ? 64 * P : 0;
         return waves * (exch > stage ? exch : stage) * es;
     }
     return tri_lds_arrays(c.algo) * es * (int64_t)c.problems_per_block * n;

@@ -622,7 +622,7 @@ __device__ __forceinline__ void wave_lf(T (&a)[P], T (&c)[P], T (&d)[P], int t, 
 // than the default policy, while the staged form stores 64 consecutive
 // 16-byte words per instruction.
 template <typename T, int P>
-constexpr bool tri_staged_stores() { return sizeof(T) == 4 && P == 16; }
+constexpr bool tri_staged_stores() { return P * (int)sizeof(T) >= 64; }
 // LDS values per wave of the in-wave kernels: the PCR_REG exchange buffer
 // and the staging buffer share one region per wave.
 template <typename T, int ALGO, int P>
@@ -664,9 +664,10 @@ __device__ __forceinline__ void tridiag_wave_solve(T (&a)[P], const T (&b)[P], T
 template <typename T, int P>
 __device__ __forceinline__ void wave_store_staged(T *dst, const T (&v)[P], T *buf, int lane, int active) {
     constexpr int W = P * (int)sizeof(T) / 16;  // words per lane
-    static_assert(W == 4, "staged stores are laid out for four words per lane");
+    static_assert(W == 4 || W == 8, "staged stores are laid out for four or eight words per lane");
+    constexpr int LW = W == 4 ? 2 : 3;
     u32x4 *bw = reinterpret_cast<u32x4 *>(buf);
-    const auto phys = [](int w) { return w ^ ((w >> 2) & 3); };
+    const auto phys = [](int w) { return w ^ ((w >> LW) & (W - 1)); };
 #pragma unroll
     for (int j = 0; j < W; ++j) {
         u32x4 x;
