@@ -2,10 +2,12 @@
 
 Each counter CSV is one pass of ``rocprofv3 --pmc ... --output-format csv``
 over the same ``one_call`` command; rows are per (dispatch, counter).  The
-dispatches of the library's kernels are grouped by (kernel, grid, workgroup)
-in the order they first run, which is the order of the shapes in the calls
-file that ``one_call --out`` wrote, and each counter is averaged over a
-group's dispatches.  FETCH_SIZE / WRITE_SIZE (KiB) are scaled to bytes by
+library's dispatches, in dispatch order, are assigned to the calls of the
+calls file that ``one_call --out`` wrote: each call ran its ``reps`` times,
+launching ``kernels`` kernels each time (a two-pass FFT call: pass A then
+pass B, one table row per pass, each with the call's algorithmic bytes, since
+both passes read and write every value once).  Each counter is averaged over
+a row's dispatches.  FETCH_SIZE / WRITE_SIZE (KiB) are scaled to bytes by
 what they read for the 256 MiB reference copy (``one_call --copy-ref``).
 
 Derived columns, per call:
@@ -38,36 +40,62 @@ def _short(name):
     return name.replace("HIP_vector_type<float, 2u>", "float2")
 
 
-def load(paths):
-    """{(kernel, grid, wg): {counter: [values per dispatch]}} in first-run
-    order, and the reference copy's readings."""
+def _rows(calls):
+    """The (call index, kernel index) of each library dispatch, in order."""
+    out = []
+    for ci, call in enumerate(calls):
+        for _ in range(call.get("reps", 5)):
+            out += [(ci, k) for k in range(call.get("kernels", 1))]
+    return out
+
+
+def _dispatches(path, value_of):
+    """{dispatch id: (key, name, row value)} of one CSV."""
+    per = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            name = r["Kernel_Name"]
+            key = (_short(name), int(r.get("Grid_Size") or r["Grid_Size_X"]),
+                   int(r.get("Workgroup_Size") or r["Workgroup_Size_X"]))
+            per.setdefault(int(r["Dispatch_Id"]), (key, name, []))[2].append(value_of(r))
+    return per
+
+
+def load(paths, calls):
+    """({(call, kernel): (key, {counter: [values per dispatch]})}, the
+    reference copy's readings)."""
+    rows = _rows(calls)
     groups = OrderedDict()
     copy = {}
     for p in paths:
-        with open(p) as f:
-            for r in csv.DictReader(f):
-                name, val = r["Kernel_Name"], float(r["Counter_Value"])
-                key = (_short(name), int(r["Grid_Size"]), int(r["Workgroup_Size"]))
-                if "copyBuffer" in name:
-                    big = copy.setdefault(r["Counter_Name"], [0.0])
-                    big[0] = max(big[0], val)
-                    continue
-                if not name.startswith("ppx::") and "ppx::" not in name:
-                    continue
-                groups.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(val)
+        per = _dispatches(p, lambda r: (r["Counter_Name"], float(r["Counter_Value"])))
+        lib = [d for d in sorted(per) if "ppx::" in per[d][1]]
+        if len(lib) != len(rows):
+            raise SystemExit(f"{p}: {len(lib)} library dispatches for {len(rows)} expected (calls x reps x kernels)")
+        for d in sorted(per):
+            key, name, vals = per[d]
+            if "copyBuffer" in name:
+                for cn, v in vals:
+                    big = copy.setdefault(cn, [0.0])
+                    big[0] = max(big[0], v)
+        for row, d in zip(rows, lib):
+            key, _, vals = per[d]
+            g = groups.setdefault(row, (key, {}))[1]
+            for cn, v in vals:
+                g.setdefault(cn, []).append(v)
     return groups, copy
 
 
-def trace_means(path):
-    """Mean kernel duration (us) per (kernel, grid, wg) from a kernel trace."""
+def trace_means(path, calls):
+    """Mean kernel duration (us) per (call, kernel) from a kernel trace."""
+    rows = _rows(calls)
+    per = _dispatches(path, lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lib = [d for d in sorted(per) if "ppx::" in per[d][1]]
+    if len(lib) != len(rows):
+        raise SystemExit(f"{path}: {len(lib)} library dispatches for {len(rows)} expected")
     acc = OrderedDict()
-    with open(path) as f:
-        for r in csv.DictReader(f):
-            key = (_short(r["Kernel_Name"]), int(r.get("Grid_Size") or r["Grid_Size_X"]),
-                   int(r.get("Workgroup_Size") or r["Workgroup_Size_X"]))
-            if "ppx::" not in key[0]:
-                continue
-            acc.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    for row, d in zip(rows, lib):
+        acc.setdefault(row, []).append(per[d][2][0])
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
@@ -79,13 +107,10 @@ def main():
     ap.add_argument("--command", default="")
     args = ap.parse_args()
     calls = [json.loads(x) for x in open(args.calls) if x.strip()]
-    groups, copy = load(args.passes)
-    durs = trace_means(args.trace) if args.trace else {}
+    groups, copy = load(args.passes, calls)
+    durs = trace_means(args.trace, calls) if args.trace else {}
     fs = COPY_BYTES / (copy["FETCH_SIZE"][0] * 1024) if "FETCH_SIZE" in copy else None
     ws = COPY_BYTES / (copy["WRITE_SIZE"][0] * 1024) if "WRITE_SIZE" in copy else None
-    keys = list(groups)
-    if len(keys) != len(calls):
-        raise SystemExit(f"{len(keys)} kernel groups for {len(calls)} calls: run one kernel per shape")
     if args.command:
         print(f"command: `{args.command}`\n")
     if fs:
@@ -94,9 +119,11 @@ def main():
           " of which transcendental | VALU floor us | LDS insts per wave | wait LDS / wave cycles |"
           " wait any / wave cycles | LDS bank conflicts per LDS inst |")
     print("|---|---|---|---|---|---|---|---|---|---|---|---|---|---|")
-    for call, key in zip(calls, keys):
-        c = {k: sum(v) / len(v) for k, v in groups[key].items()}
-        us = durs.get(key)
+    for row, (key, vals) in groups.items():
+        call = calls[row[0]]
+        tag = "" if call.get("kernels", 1) == 1 else f" pass {'AB'[row[1]]}"
+        c = {k: sum(v) / len(v) for k, v in vals.items()}
+        us = durs.get(row)
         alg = call["algorithmic_bytes"]
         gbs = f"{alg / us / 1e3:.0f} ({alg / us / 8e6:.3f})" if us else "-"
         traffic = "-"
@@ -115,6 +142,10 @@ def main():
         label = f"{call['op']} {call['dtype']} n={call['n']} x {call['batch']}"
         if call["op"] == "tridiag":
             label += f" {call['shape'].split(':')[3] if call['shape'].count(':') >= 3 else 'cr'} (algo {cfg.get('algo')})"
+        if "plan" in call:
+            pl = call["plan"]
+            label += (f" (n1 = 2^{pl['log2_n1']}, A r{pl['radix_a']}/t{pl['tile_a']},"
+                      f" B r{pl['radix_b']}/t{pl['tile_b']}){tag}")
         print(f"| {label} | `{key[0]}` | {key[1] // key[2]} | {key[2]} | {us:.2f} |" if us else
               f"| {label} | `{key[0]}` | {key[1] // key[2]} | {key[2]} | - |", end="")
         print(f" {gbs} | {traffic} | {per_wave('SQ_INSTS_VALU')} | {per_wave('SQ_INSTS_VALU_TRANS_F')} | {floor} |"

@@ -293,7 +293,11 @@ __global__ __launch_bounds__(fft_max_threads(P)) void k_fft(const float2 *in, fl
 constexpr int clog2(int x) { return x <= 1 ? 0 : 1 + clog2(x / 2); }
 
 // With STAGED the last stage leaves its results in the LDS buffer, at their
-// output positions, instead of storing them (see k_fft_n).  After the
+// output positions (XORed with pxor, then swizzled), instead of storing them
+// (see k_fft_n).  A nonzero pxor needs pxor < 64 <= T and a last stage whose
+// span is at least 64: the XOR is then applied to the thread index, where it
+// changes the same low bits of the position.  With a last span of at least 64
+// and one butterfly per thread, poff must be a multiple of 256.  After the
 // exchange that follows stage s (0-based), hook.template at<s>() runs: a
 // caller's work to place between the stages (none by default).
 struct NoStageHook {
@@ -303,7 +307,7 @@ struct NoStageHook {
 template <int R, int P, bool SPLIT, int LOG2N, int LNS, bool STAGED = false, typename Hook = NoStageHook>
 __device__ __forceinline__ void fft_stages_ct(float2 (&v)[P], void *lds, int poff, float2 *dst, int tid,
                                               bool active, float sgn, const float2 *__restrict__ tw,
-                                              const Hook &hook = Hook{}) {
+                                              const Hook &hook = Hook{}, int pxor = 0) {
     constexpr int REM = LOG2N % clog2(R);
     constexpr int RS = (LNS == 0 && REM != 0) ? (1 << REM) : R;  // mixed-radix first stage
     constexpr int LRS = clog2(RS);
@@ -313,10 +317,21 @@ __device__ __forceinline__ void fft_stages_ct(float2 (&v)[P], void *lds, int pof
         if constexpr (STAGED) {
             constexpr int NB = P / RS;
             float2 *buf = static_cast<float2 *>(lds);
+            if constexpr (NB == 1 && LNS >= 6) {
+                // position t + q 2^LNS (t = tid ^ pxor < 2^LNS); with poff a
+                // multiple of 256, its swizzle is that of poff + t XORed with
+                // the swizzle term of q 2^LNS (bits 4..7 moved to 0..3), plus
+                // q 2^LNS: one base, constant offsets
+                const int b = swz_c(poff + (tid ^ pxor));
 #pragma unroll
-            for (int i = 0; i < NB; ++i)
+                for (int q = 0; q < RS; ++q) buf[(b ^ (((q << LNS) >> 4) & 15)) + (q << LNS)] = v[q];
+            } else {
 #pragma unroll
-                for (int q = 0; q < RS; ++q) buf[swz_c(poff + stage_out_pos<RS>(tid + i * T, LNS, q))] = v[i + q * NB];
+                for (int i = 0; i < NB; ++i)
+#pragma unroll
+                    for (int q = 0; q < RS; ++q)
+                        buf[swz_c(poff + stage_out_pos<RS>((tid ^ pxor) + i * T, LNS, q))] = v[i + q * NB];
+            }
         } else {
             if (active) stage_store<RS, P>(v, dst, tid, T, LNS, sgn);
         }
@@ -325,7 +340,8 @@ __device__ __forceinline__ void fft_stages_ct(float2 (&v)[P], void *lds, int pof
         // index of the stage just done: the first spans REM or log2 R bits
         constexpr int S = LNS == 0 ? 0 : 1 + (LNS - (REM ? REM : clog2(R))) / clog2(R);
         hook.template at<S>();
-        fft_stages_ct<R, P, SPLIT, LOG2N, LNS + LRS, STAGED, Hook>(v, lds, poff, dst, tid, active, sgn, tw, hook);
+        fft_stages_ct<R, P, SPLIT, LOG2N, LNS + LRS, STAGED, Hook>(v, lds, poff, dst, tid, active, sgn, tw, hook,
+                                                                   pxor);
     }
 }
 

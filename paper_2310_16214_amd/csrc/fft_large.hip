@@ -16,8 +16,8 @@
 // LDS, transforms the TC columns with the single-pass stage code (radix
 // R = P, T = len/P threads per column, exchanges in LDS), and writes the tile
 // back the same way (pass B) or row by row (pass A, 512-byte runs per wave).
-// The LDS tile pads each column to len + 1 values, so that the TC values a
-// row read or write touches fall on different banks.  Tiles of 16, 32 or 64
+// The LDS layout (TileLayout) spreads a row access over the banks and keeps
+// the exchanges of long columns aligned to the stage swizzles.  Tiles of 16, 32 or 64
 // columns read and write runs of 128 to 512 bytes; tiles of 2, 4 or 8 (runs
 // of 16 to 64 bytes) are the only ones that fit LDS for columns of 2048 to
 // 8192 values (pass A, with its tables, up to 4096), and are also valid for
@@ -39,7 +39,39 @@
 
 namespace ppx {
 
-__device__ __forceinline__ int tile_slot(int c, int e, int len) { return swz_c(c * (len + 1) + e); }
+// LDS layout of a tile: element e of column c at swz_c(poff(c) + (e ^ px(c))).
+// The row accesses (the tile's loads, pass B's stores) put TC columns x
+// 64 / TC consecutive rows in a wave; the stage exchanges put T = len / R
+// consecutive threads of a column in a wave.
+// * T >= 64 (one column per wave in the exchanges): columns at multiples of
+//   len, so each column is aligned to the 256-value blocks of the stage
+//   swizzles and its exchanges are as conflict-free as a single-pass
+//   transform's.  The LDS serves 16 lanes of 8-byte words together; in a row
+//   access those are 16 / TC consecutive rows of each of TC columns (TC <=
+//   16) or one row of 16 columns.  px(c) = c * max(1, 16 / TC) (mod 16) puts
+//   each column's run on its own banks, so the 16 words fall on 16 banks.
+//   It is below 16 and the index constants of the accesses are multiples of
+//   64, so the XOR commutes with them and they stay instruction offsets.
+// * T < 64 (several columns per wave): columns padded to len + 1 values, so
+//   that the columns of a wave fall on different banks; px = 0.
+template <int R, int LOG2LEN, int TC>
+struct TileLayout {
+    static constexpr int len = 1 << LOG2LEN;
+    static constexpr bool kAligned = LOG2LEN - clog2(R) >= 6;
+    __device__ __forceinline__ static int poff(int c) { return kAligned ? c * len : c * (len + 1); }
+    __device__ __forceinline__ static int px(int c) { return kAligned ? (c * (TC < 16 ? 16 / TC : 1)) & 15 : 0; }
+    __device__ __forceinline__ static int slot(int c, int e) { return swz_c(poff(c) + (e ^ px(c))); }
+    // slot(c, e + k) for e < 2^m and k a multiple of 2^m, m >= 6 (with
+    // T < 64: any e, k).  e + k then has k's bits and e's bits apart, and so
+    // have poff(c) (a multiple of len) and e ^ px(c): the swizzle of the sum is
+    // that of poff(c) + (e ^ px(c)), XORed with k's swizzle term (bits 4..7 of
+    // k, moved to 0..3), plus k.  Written this way, one base per thread serves
+    // every k, and constant k become instruction offsets.
+    __device__ __forceinline__ static int slot_k(int c, int e, int k) {
+        if constexpr (kAligned) return (swz_c(poff(c) + (e ^ px(c))) ^ ((k >> 4) & 15)) + k;
+        else return swz_c(poff(c) + e + k);
+    }
+};
 
 __device__ __forceinline__ int tw_swz(int j) { return j ^ ((j >> 5) & 31); }
 
@@ -99,10 +131,12 @@ __device__ __forceinline__ void tile_tables_to_lds(float2 *tlo, float2 *thi, flo
 // read, issued after the next tile's loads, waits for those loads too
 // (vector memory operations complete in issue order).  Radix R = P: one
 // butterfly per thread and stage after a first stage of the remaining bits.
-// The last stage leaves its results in LDS at their output positions.
+// The last stage leaves its results in LDS at their output positions (XORed
+// with pxor, then swizzled: pxor < 64 <= T, and the last stage's span is at
+// least 64, so XORing the thread index does the same).
 template <int R, int LOG2LEN, int LNS, int IDX, typename Hook>
-__device__ __forceinline__ void tile_stages_twl(float2 (&v)[R], float2 *buf, int poff, int tid, const float2 *twl,
-                                                const Hook &hook) {
+__device__ __forceinline__ void tile_stages_twl(float2 (&v)[R], float2 *buf, int poff, int pxor, int tid,
+                                                const float2 *twl, const Hook &hook) {
     constexpr int P = R;
     constexpr int REM = LOG2LEN % clog2(R);
     constexpr int RS = (LNS == 0 && REM != 0) ? (1 << REM) : R;
@@ -124,16 +158,22 @@ __device__ __forceinline__ void tile_stages_twl(float2 (&v)[R], float2 *buf, int
         RegDFT<RS>::run(v);
     }
     if constexpr (LNS + LRS == LOG2LEN) {
-        constexpr int NB = P / RS;
+        static_assert(P == RS, "the last stage is a full radix-R stage, one butterfly per thread");
+        if constexpr (LNS >= 6) {
+            // aligned layout (T = 2^LNS >= 64): output position (tid ^ pxor) + q T,
+            // swizzled as in TileLayout::slot_k
+            const int b = swz_c(poff + (tid ^ pxor));
 #pragma unroll
-        for (int i = 0; i < NB; ++i)
+            for (int q = 0; q < RS; ++q) buf[(b ^ (((q << LNS) >> 4) & 15)) + (q << LNS)] = v[q];
+        } else {
 #pragma unroll
-            for (int q = 0; q < RS; ++q) buf[swz_c(poff + stage_out_pos<RS>(tid + i * T, LNS, q))] = v[i + q * NB];
+            for (int q = 0; q < RS; ++q) buf[swz_c(poff + stage_out_pos<RS>(tid ^ pxor, LNS, q))] = v[q];
+        }
     } else {
         stage_exchange<RS, P, false>(v, buf, poff, tid, T, LNS);
         constexpr int S = LNS == 0 ? 0 : 1 + (LNS - (REM ? REM : clog2(R))) / clog2(R);
         hook.template at<S>();
-        tile_stages_twl<R, LOG2LEN, LNS + LRS, LNS == 0 ? IDX : IDX + 1, Hook>(v, buf, poff, tid, twl, hook);
+        tile_stages_twl<R, LOG2LEN, LNS + LRS, LNS == 0 ? IDX : IDX + 1, Hook>(v, buf, poff, pxor, tid, twl, hook);
     }
 }
 
@@ -153,6 +193,7 @@ __device__ __forceinline__ void tile_transform_store(float2 *buf, const float2 *
     constexpr int T = 1 << lT;
     constexpr int LTC = clog2(TC);
     constexpr int NT = len * TC / R;
+    using Lay = TileLayout<R, LOG2LEN, TC>;
     // the problem's n values of the output (offsets below 2^26 bytes)
     const __amdgpu_buffer_rsrc_t orsrc = __builtin_amdgcn_make_buffer_rsrc(
         out + base, (short)0, (int)((1LL << log2n) * (long long)sizeof(float2)), kBufferFlags);
@@ -161,13 +202,18 @@ __device__ __forceinline__ void tile_transform_store(float2 *buf, const float2 *
     const int tid = tx & (T - 1);
     float2 v[P];
 #pragma unroll
-    for (int j = 0; j < P; ++j) v[j] = buf[tile_slot(lp, tid + j * T, len)];
+    for (int j = 0; j < P; ++j) v[j] = buf[Lay::slot_k(lp, tid, j * T)];
     __syncthreads();
     if constexpr (PASS_A) fft_conj<P>(v, sgn);  // the inverse: conjugated in pass A, out in pass B
+    // the last stage's writes recompute their base from an opaque copy of
+    // px, rather than keep the gather's bases live through the stages
+    int pxl = Lay::px(lp);
+    if constexpr (Lay::kAligned) asm volatile("" : "+v"(pxl));
     if constexpr (PERSIST)  // tw: the stage twiddle bases in LDS
-        tile_stages_twl<R, LOG2LEN, 0, 0, Hook>(v, buf, lp * (len + 1), tid, tw, hook);
+        tile_stages_twl<R, LOG2LEN, 0, 0, Hook>(v, buf, Lay::poff(lp), pxl, tid, tw, hook);
     else
-        fft_stages_ct<R, P, false, LOG2LEN, 0, true, Hook>(v, buf, lp * (len + 1), nullptr, tid, true, sgn, tw, hook);
+        fft_stages_ct<R, P, false, LOG2LEN, 0, true, Hook>(v, buf, Lay::poff(lp), nullptr, tid, true, sgn, tw, hook,
+                                                           pxl);
     __syncthreads();
     if constexpr (PASS_A) {
         // Element (c, e) of the tile is stored at row c0 + c, position e, of
@@ -192,7 +238,7 @@ __device__ __forceinline__ void tile_transform_store(float2 *buf, const float2 *
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const int c = ct + k * CS;
-                const float2 y = cmul(buf[tile_slot(c, e, len)], w);
+                const float2 y = cmul(buf[Lay::slot(c, e)], w);
                 if constexpr (PERSIST)  // one vector offset, the column step in the scalar operand
                     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, y), orsrc,
                                                           ((c0 + ct) * len + e) * (int)sizeof(float2),
@@ -209,7 +255,7 @@ __device__ __forceinline__ void tile_transform_store(float2 *buf, const float2 *
                 const float2 step = table_tw((unsigned)e);
 #pragma unroll
                 for (int c = 0; c < TC; ++c) {
-                    const float2 y = cmul(buf[tile_slot(c, e, len)], w);
+                    const float2 y = cmul(buf[Lay::slot_k(c, tx, r * NT)], w);
                     if constexpr (PERSIST)
                         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, y), orsrc,
                                                               (c0 * len + tx) * (int)sizeof(float2),
@@ -223,7 +269,7 @@ __device__ __forceinline__ void tile_transform_store(float2 *buf, const float2 *
     } else {
         for (int i = tx; i < len * TC; i += NT) {
             const int c = i & (TC - 1), e = i >> LTC;
-            const float2 y = buf[tile_slot(c, e, len)];
+            const float2 y = buf[Lay::slot(c, e)];
             if constexpr (TC * (int)sizeof(float2) >= kTileNtRun)
                 store_nt_any(out + base + e * cols + c0 + c, make_float2(y.x, sgn * y.y));
             else
@@ -254,10 +300,11 @@ __global__ __launch_bounds__(1024) void k_fft_tile(const float2 *in, float2 *out
     const long long base = prob << log2n;
     const long long cols = 1LL << log2cols;
     float2 *tlo = buf + tile_vals(LOG2LEN, TC), *thi = tlo + 1024, *tht = thi + 1024;
+    using Lay = TileLayout<R, LOG2LEN, TC>;
     if constexpr (PASS_A) tile_tables_to_lds(tlo, thi, tht, tw_lo, tw_hi);
     for (int i = threadIdx.x; i < len * TC; i += NT) {
         const int c = i & (TC - 1), e = i >> LTC;
-        buf[tile_slot(c, e, len)] = in[base + e * cols + c0 + c];
+        buf[Lay::slot(c, e)] = in[base + e * cols + c0 + c];
     }
     tile_transform_store<R, LOG2LEN, PASS_A, TC, false>(buf, tlo, thi, tht, out, base, c0, cols, log2n, sgn, tw,
                                                         (int)threadIdx.x);
@@ -363,7 +410,7 @@ __global__ __launch_bounds__(1024) void k_fft_tile_p(const float2 *in, float2 *o
         __syncthreads();  // the previous tile's LDS reads (or the tables' writes) are done
         const int c = tx & (TC - 1), e0 = tx >> LTC;
 #pragma unroll
-        for (int k = 0; k < R; ++k) buf[tile_slot(c, e0 + k * (len / R), len)] = pre[k];
+        for (int k = 0; k < R; ++k) buf[TileLayout<R, LOG2LEN, TC>::slot_k(c, e0, k * (len / R))] = pre[k];
         const TilePrefetch<R, LOG2LEN, TC> nxt{pre, tile_rsrc(in, cur + step, end, tiles, TC, log2n), (int)cols, tx};
         tile_load_rows<R, LOG2LEN, TC, 0, TilePrefetch<R, LOG2LEN, TC>::NC>(pre, nxt.r, nxt.cols, tx);
         const long long prob = cur / tiles;

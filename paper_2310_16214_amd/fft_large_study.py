@@ -46,9 +46,37 @@ def stream_gbs(ppx, torch, nbytes, dev, reps=10):
     return 2 * nbytes / ts[len(ts) // 2] / 1e3
 
 
-def report(study_json, stats_csv=""):
-    """Markdown summary of a study JSON (and of a rocprofv3 kernel-stats CSV of
-    a --replay run, when given)."""
+def traffic_table(fetch_csv, write_csv):
+    """Per-kernel HBM traffic of a --replay run from two rocprofv3 counter
+    CSVs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what it
+    reads for the replay's first dispatch, a plain 256 MiB device copy."""
+    import csv
+    from collections import OrderedDict
+    per, copy = OrderedDict(), {}
+    for path in (fetch_csv, write_csv):
+        for r in csv.DictReader(open(path)):
+            name, cn, v = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
+            if "copyBuffer" in name:
+                copy[cn] = max(copy.get(cn, 0.0), v)
+            elif "k_fft_tile" in name:
+                per.setdefault(name.split("(")[0].replace("void ", ""), {}).setdefault(cn, []).append(v)
+    mib = 256.0
+    fs, ws = mib * 1024 / copy["FETCH_SIZE"], mib * 1024 / copy["WRITE_SIZE"]
+    out = [f"Calibration: the replay's first dispatch is a plain 256 MiB device copy; it reads FETCH_SIZE "
+           f"{copy['FETCH_SIZE']:.0f} KiB and WRITE_SIZE {copy['WRITE_SIZE']:.0f} KiB, so the counters are scaled "
+           f"by x{fs:.3f} (reads) and x{ws:.3f} (writes). Each pass moves 256 MiB in each direction (algorithmic).",
+           "", "| kernel | dispatches | read MiB | write MiB | read / 256 MiB | write / 256 MiB |",
+           "|---|---|---|---|---|---|"]
+    for k, c in per.items():
+        rd = sum(c["FETCH_SIZE"]) / len(c["FETCH_SIZE"]) * fs / 1024
+        wr = sum(c["WRITE_SIZE"]) / len(c["WRITE_SIZE"]) * ws / 1024
+        out.append(f"| `{k}` | {len(c['FETCH_SIZE'])} | {rd:.1f} | {wr:.1f} | {rd / mib:.3f} | {wr / mib:.3f} |")
+    return out
+
+
+def report(study_json, stats_csv="", fetch_csv="", write_csv=""):
+    """Markdown summary of a study JSON (and of a rocprofv3 kernel-stats CSV
+    and FETCH_SIZE / WRITE_SIZE counter CSVs of a --replay run, when given)."""
     import csv
     d = json.load(open(study_json))
     plan = lambda p: f"n1=2^{p[0]} A:r{p[1]}/t{p[3]} B:r{p[2]}/t{p[4]}"  # noqa: E731
@@ -71,6 +99,8 @@ def report(study_json, stats_csv=""):
             if "k_fft_tile" in r["Name"]:
                 name = r["Name"].split("(")[0].replace("void ", "")
                 out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} |")
+    if fetch_csv and write_csv:
+        out += [""] + traffic_table(fetch_csv, write_csv)
     print("\n".join(out))
 
 
@@ -79,7 +109,8 @@ def main():
     ap.add_argument("--reps", type=int, default=30)
     ap.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"))
     ap.add_argument("--sizes", default="15,16,17,18,19,20,21,22,23")
-    ap.add_argument("--report", nargs="+", default=None, metavar=("STUDY_JSON", "KERNEL_STATS_CSV"),
+    ap.add_argument("--report", nargs="+", default=None,
+                    metavar=("STUDY_JSON", "KERNEL_STATS_CSV [FETCH_CSV WRITE_CSV]"),
                     help="print the markdown summary of a study (no GPU)")
     ap.add_argument("--plans", default="", metavar="STUDY_JSON",
                     help="print the exhaustive-best plans of a study as tune-cache lines")

@@ -4,9 +4,12 @@ rocprofv3 kernel traces and counter runs of one kernel at a time.
 Each shape is ``op:dtype:n[:family]`` (family: the tridiagonal family, cr,
 pcr, crpcr, wm or lf; FFT and scan use the configuration their call takes
 with cfg = NULL, tridiagonal the tuned one of the family), run with batch =
-elems // n.  One JSON line per shape gives its configuration and its
-algorithmic bytes per call (inputs read once, outputs written once), in the
-order the kernels run.  ``--copy-ref`` first runs a 256 MiB device-to-device
+elems // n.  FFT sizes above 16384 run the two-pass transform with its tuned
+(else default) plan: two kernels per call, pass A then pass B, each moving
+every value once in each direction.  One JSON line per shape gives its
+configuration (or plan), the kernels one call launches and the algorithmic
+bytes of each (inputs read once, outputs written once), in the order the
+kernels run.  ``--copy-ref`` first runs a 256 MiB device-to-device
 copy, whose counter readings scale FETCH_SIZE / WRITE_SIZE to bytes.
 
     python -m paper_2310_16214_amd.one_call tridiag:f32:1024:pcr tridiag:f64:1024:cr \\
@@ -41,7 +44,17 @@ def prepare(spec, elems, dev):
     op, dt, n = parts[0], parts[1], int(parts[2])
     code, npdt = DTYPES[dt]
     batch = max(1, elems // n)
-    if op == "fft":
+    kernels = 1
+    if op == "fft" and n > 16384:
+        x = torch.from_numpy(inputs.fft_input(n, batch, seed=1)).to(dev)
+        y = torch.empty_like(x)
+        plan = ppx.tuned_fft_plan(n) or ppx.default_fft_plan(n)
+        run = lambda: ppx.fft_batched_large(x, y, n, batch, -1, plan)  # noqa: E731
+        cfg = None
+        nbytes, kernels = 16 * n * batch, 2
+        rec_plan = dict(zip(("log2_n1", "radix_a", "radix_b", "tile_a", "tile_b"),
+                            (plan.log2_n1, plan.radix_a, plan.radix_b, plan.tile_a, plan.tile_b)))
+    elif op == "fft":
         x = torch.from_numpy(inputs.fft_input(n, batch, seed=1)).to(dev)
         y = torch.empty_like(x)
         cfg = ppx.resolve_config(ppx.OP_FFT, ppx.C64, n, batch)
@@ -62,7 +75,11 @@ def prepare(spec, elems, dev):
         nbytes = 5 * np.dtype(npdt).itemsize * n * batch
     else:
         raise SystemExit(f"unknown op in {spec!r}")
-    return run, dict(shape=spec, op=op, dtype=dt, n=n, batch=batch, cfg=_cfg_dict(cfg), algorithmic_bytes=nbytes)
+    rec = dict(shape=spec, op=op, dtype=dt, n=n, batch=batch, cfg=_cfg_dict(cfg), kernels=kernels,
+               algorithmic_bytes=nbytes)
+    if kernels == 2:
+        rec["plan"] = rec_plan
+    return run, rec
 
 
 def main():
@@ -88,6 +105,7 @@ def main():
     recs = []
     for spec in args.shapes:
         run, rec = prepare(spec, args.elems, dev)
+        rec["reps"] = args.reps
         for _ in range(args.reps):
             run()
         torch.cuda.synchronize()
