@@ -88,13 +88,16 @@ constexpr int kLog2NLargeMax = 23;
 // blocks (the swizzle permutes within aligned blocks of 256)
 __host__ __device__ constexpr int tile_vals(int log2len, int tc) { return (tc * ((1 << log2len) + 1) + 255) / 256 * 256; }
 
-// Pass-A workgroups whose tile and tables take more than half of the LDS run
-// one per CU; such tile shapes are launched persistent (k_fft_tile_p).  Pass
-// B keeps one workgroup per tile: its persistent form (radix 16 only, at
-// these sizes) needs more than the 128 registers of a 1024-thread workgroup
-// and spilled, and measured slower at n = 2^23.
+// Workgroups whose tile (and, in pass A, tables) take more than half of the
+// LDS run one per CU; such tile shapes are launched persistent
+// (k_fft_tile_p), so that a CU's loads overlap its own stages.  In pass B
+// only for columns of 1024 values or more (the aligned tile layout, whose
+// accesses are a base register plus offsets): the persistent pass B on
+// shorter, wider tiles needs more than the 128 registers of a 1024-thread
+// workgroup.
 __host__ __device__ constexpr bool tile_persistent(int log2len, int tc, bool pass_a) {
-    return pass_a && ((int64_t)tile_vals(log2len, tc) + kTwLargeVals) * (int64_t)sizeof(float2) > 80 * 1024;
+    return (pass_a || log2len >= 10) &&
+           ((int64_t)tile_vals(log2len, tc) + (pass_a ? kTwLargeVals : 0)) * (int64_t)sizeof(float2) > 80 * 1024;
 }
 
 // float2 entries of a column transform's stage twiddle bases (every stage but
@@ -266,6 +269,20 @@ __device__ __forceinline__ void tile_transform_store(float2 *buf, const float2 *
                 }
             }
         }
+    } else if constexpr (PERSIST) {
+        // element i = tx + k * NT: column tx mod TC, row tx div TC + k * T;
+        // one vector offset, the row step in the scalar operand, and a
+        // constant number of stores (the wait for the next tile's loads then
+        // leaves these stores in flight)
+        const int c = tx & (TC - 1), e0 = tx >> LTC;
+        const int voff = (e0 * (int)cols + c0 + c) * (int)sizeof(float2);
+        const int rstep = T * (int)cols * (int)sizeof(float2);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const float2 y = buf[Lay::slot_k(c, e0, k * T)];
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, make_float2(y.x, sgn * y.y)), orsrc, voff,
+                                                  k * rstep, TC * (int)sizeof(float2) >= kTileNtRun ? kStoreNT : 0);
+        }
     } else {
         for (int i = tx; i < len * TC; i += NT) {
             const int c = i & (TC - 1), e = i >> LTC;
@@ -378,16 +395,17 @@ __global__ __launch_bounds__(1024) void k_fft_tile_p(const float2 *in, float2 *o
                                                       const float2 *__restrict__ tw_lo,
                                                       const float2 *__restrict__ tw_hi, int log2n,
                                                       int log2cols, long long tiles, long long total, float sgn) {
-    static_assert(PASS_A, "pass A only");
     constexpr int len = 1 << LOG2LEN;
     constexpr int LTC = clog2(TC);
     extern __shared__ float4 lds_raw[];
     float2 *buf = reinterpret_cast<float2 *>(lds_raw);
     const long long cols = 1LL << log2cols;
+    // pass A: the twiddle tables after the tile; both passes: then the stage
+    // twiddle bases
     float2 *tlo = buf + tile_vals(LOG2LEN, TC), *thi = tlo + 1024, *tht = thi + 1024;
-    float2 *twl = tht + 8;  // the stage twiddle bases
+    float2 *twl = PASS_A ? tht + 8 : tlo;
     static_assert(fft_tw_entries<R, LOG2LEN>() == tile_stage_tw_vals(R, LOG2LEN), "stage base count");
-    tile_tables_to_lds(tlo, thi, tht, tw_lo, tw_hi);
+    if constexpr (PASS_A) tile_tables_to_lds(tlo, thi, tht, tw_lo, tw_hi);
     fft_tw_to_lds<R, LOG2LEN>(twl, tw);
     // this workgroup's tiles: t = first, first + step, ... < end (first < end:
     // the grid never exceeds the tiles)

@@ -35,7 +35,7 @@ int64_t mix_lds_bytes(int fam) {
         case kFamTriW32: return 0;  // no PCR exchange, no staged stores (P <= 8)
         case kFamTriW32H: return 4 * 64 * 16 * 4;  // per wave: PCR exchange (3 * 64 * 4) or P = 16 staging (64 * 16) floats
         case kFamTriW64: return 4 * 3 * 64 * 4 * 8;  // per wave: PCR exchange (3 * 64 * 4) or P = 8 staging (64 * 8) doubles
-        case kFamTriW64H: return 4 * 64 * 16 * 8;    // per wave: P = 16 staging (64 * 16 doubles)
+        case kFamTriW64H: return 4 * 64 * 16 * 8;    // per wave: P = 16 staging (64 * 16 doubles) or PCR exchange (3 * 64 * 4)
         case kFamTriLds: return kMixTriLdsBudget;
         case kFamTriBlk32:
         case kFamTriBlk32H: return 6 * 1024 * 4;  // two sets of a, c, d lane slots

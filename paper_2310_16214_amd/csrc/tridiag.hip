@@ -18,11 +18,13 @@ int64_t tridiag_lds_bytes(int n, const ppx_config &c, int dtype) {
     if (tri_blk(c.algo, n, P)) return 6 * (int64_t)c.threads_per_block * es;  // two sets of a, c, d slots
     if (tri_in_wave(c.algo)) {
         // per wave: the PCR_REG exchange buffer (3 * 64 * min(P, 4) values)
-        // and the staging buffer of 64-byte solution chunks (64 * P values,
-        // float32 with P = 16) share one region (tri_wave_lds_vals)
+        // and the staging buffer of solution chunks of 64 bytes or more
+        // (64 * P values) share one region (tri_wave_lds_vals,
+        // tri_staged_stores)
         const int64_t waves = (c.threads_per_block + 63) / 64;
-        const int64_t exch = tri_base(c.algo) == PPX_TRI_PCR_REG ? 3 * 64 * (P < 4 ? P : 4) : 0;
-        const int64_t stage = P * es >= 64 ? 64 * P : 0;
+        const bool pcr_reg = tri_base(c.algo) == PPX_TRI_PCR_REG;
+        const int64_t exch = pcr_reg ? 3 * 64 * (P < 4 ? P : 4) : 0;
+        const int64_t stage = P * es >= 64 && !(pcr_reg && es == 8 && P == 16) ? 64 * P : 0;
         return waves * (exch > stage ? exch : stage) * es;
     }
     return tri_lds_arrays(c.algo) * es * (int64_t)c.problems_per_block * n;

@@ -616,19 +616,22 @@ __device__ __forceinline__ void wave_lf(T (&a)[P], T (&c)[P], T (&d)[P], int t, 
 // Boundary zeros, unit-diagonal scaling and the solve of the equations a
 // lane holds (b is consumed; x ends in d).  tx: the thread's index in the
 // workgroup (it selects the wave's LDS exchange buffer).
-// Solutions of 64 bytes per lane (float32, P = 16) leave through a per-wave
-// LDS buffer (wave_store_staged): a non-temporal store of lane chunks that
-// size covers only part of each line per instruction and measured slower
-// than the default policy, while the staged form stores 64 consecutive
-// 16-byte words per instruction.
-template <typename T, int P>
-constexpr bool tri_staged_stores() { return P * (int)sizeof(T) >= 64; }
+// Solutions of 64 bytes or more per lane leave through a per-wave LDS buffer
+// (wave_store_staged): a non-temporal store of lane chunks that size covers
+// only part of each line per instruction and measured slower than the
+// default policy, while the staged form stores 64 consecutive 16-byte words
+// per instruction.  Float64 PCR with 16 equations per lane keeps direct
+// stores: staged, it measured 3-4% slower (alone and inside whole steps).
+template <typename T, int ALGO, int P>
+constexpr bool tri_staged_stores() {
+    return P * (int)sizeof(T) >= 64 && !(ALGO == PPX_TRI_PCR_REG && sizeof(T) == 8 && P == 16);
+}
 // LDS values per wave of the in-wave kernels: the PCR_REG exchange buffer
 // and the staging buffer share one region per wave.
 template <typename T, int ALGO, int P>
 constexpr int tri_wave_lds_vals() {
     constexpr int exch = ALGO == PPX_TRI_PCR_REG ? 3 * 64 * (P < 4 ? P : 4) : 0;
-    constexpr int stage = tri_staged_stores<T, P>() ? 64 * P : 0;
+    constexpr int stage = tri_staged_stores<T, ALGO, P>() ? 64 * P : 0;
     return exch > stage ? exch : stage;
 }
 
@@ -712,7 +715,7 @@ __device__ __forceinline__ void tridiag_wave_block(const T *A, const T *B, const
         }
     }
     tridiag_wave_solve<T, ALGO, P>(a, b, c, d, t, lps, smem, tx);
-    if constexpr (tri_staged_stores<T, P>()) {
+    if constexpr (tri_staged_stores<T, ALGO, P>()) {
         // whole waves of consecutive threads: the wave's lanes cover the
         // contiguous range starting at its first thread's chunk
         if (blockDim.x % 64 == 0) {
