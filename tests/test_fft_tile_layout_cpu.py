@@ -99,3 +99,24 @@ def test_tile_slot_offset_form(r, ll, tc):
         base = swz_c(c * ln + (tid ^ px(c, tc)))
         for q in range(r):
             assert (base ^ (((q * t) >> 4) & 15)) + q * t == slot(c, tid + q * t, ln, tc)
+
+
+def tile_order(b, tc):
+    lg = 16 // tc if tc < 16 else 1
+    x, w = b & 7, b >> 3
+    return (w // lg) * (8 * lg) + lg * x + (w % lg)
+
+
+@pytest.mark.parametrize("tc", [2, 4, 8, 16, 32, 64])
+def test_tile_order(tc):
+    """tile_order (csrc/fft_large.hip) permutes each run of 8 * LG
+    workgroups onto as many consecutive tiles, and the LG tiles that share a
+    row's 128-byte lines land on one XCD (workgroup index mod 8)."""
+    lg = 16 // tc if tc < 16 else 1
+    g = 8 * lg * 5
+    order = [tile_order(b, tc) for b in range(g)]
+    assert sorted(order) == list(range(g))
+    for run in range(0, g, 8 * lg):
+        assert sorted(order[run:run + 8 * lg]) == list(range(run, run + 8 * lg))
+    for b, t in enumerate(order):
+        assert (t // lg) % 8 == b % 8
