@@ -164,8 +164,10 @@ int fft_batched(const void *in, void *out, int64_t n, int64_t batch,
  *              up to 1024 values, 2, 4 or 8 for longer ones
  * A pass's workgroup transforms tile adjacent columns of length len with
  * tile * len / radix threads (64..1024) and tile * (len + 1) complex values
- * of LDS (<= 160 KiB, with 2056 more for pass A's twiddle tables); the tile
- * must divide the pass's column count (n1 for pass A, n2 for pass B).  Tuning the plan (tune_fft_large) is the
+ * of LDS (<= 160 KiB, with 2056 more for pass A's twiddle tables, and the
+ * stage twiddle bases where a tile leaves room for one workgroup per CU and
+ * runs persistent); the tile must divide the pass's column count (n1 for
+ * pass A, n2 for pass B).  Tuning the plan (tune_fft_large) is the
  * interdependent per-kernel search of the paper's learned tuner.
  */
 #define PPX_MAX_N_LARGE 8388608
