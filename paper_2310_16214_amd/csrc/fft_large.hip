@@ -107,8 +107,8 @@ __host__ __device__ constexpr bool tile_persistent(int log2len, int tc, bool pas
 // fetched into one L2 and served from there to all of them; and each run of
 // 8 * LG consecutive workgroups takes 8 * LG consecutive tiles, so the
 // workgroups in flight together cover whole stretches of every row they
-// read (rather than each XCD walking its own eighth of the tiles: 5% faster
-// calls from 2^20 to 2^23).  A permutation of [0, 8 * LG * k).
+// read (rather than each XCD walking its own eighth of the tiles: 4-10%
+// faster calls from 2^19 to 2^23).  A permutation of [0, 8 * LG * k).
 template <int TC>
 __device__ __forceinline__ long long tile_order(long long b) {
     constexpr int LG = TC < 16 ? 16 / TC : 1;
@@ -118,7 +118,7 @@ __device__ __forceinline__ long long tile_order(long long b) {
 
 // float2 entries of a column transform's stage twiddle bases (every stage but
 // the first: w^k, w^{4k} and, radix 16, w^{8k} for k below the stage's span),
-// which the persistent pass A keeps in LDS after the tables.
+// which the persistent tiles keep in LDS (after the tables in pass A).
 __host__ __device__ constexpr int tile_stage_tw_vals(int radix, int log2len) {
     const int lr = radix == 16 ? 4 : 3;
     const int nst = (log2len + lr - 1) / lr;
