@@ -48,3 +48,46 @@ def test_names_are_kernels_of_the_library():
     out = subprocess.run(["nm", "-C", ppx.LIB_PATH], capture_output=True, text=True, check=True).stdout
     for _, name in CASES:
         assert f"ppx::{name}(" in out, name
+
+
+def test_counter_table_assigns_dispatches_to_calls_in_order(tmp_path):
+    """counter_table maps the library's dispatches, in dispatch order, onto
+    the calls file's calls x reps x kernels (a two-pass FFT call gives two
+    rows, even where two calls share a kernel instantiation and grid); other
+    kernels (the reference copy, torch's fills) are skipped, the copy's
+    readings calibrate FETCH_SIZE."""
+    import csv
+
+    from paper_2310_16214_amd import counter_table
+    calls = [dict(shape="fft:c64:4194304", op="fft", dtype="c64", n=1 << 22, batch=8, cfg=None, kernels=2,
+                  reps=2, algorithmic_bytes=1 << 29),
+             dict(shape="fft:c64:8388608", op="fft", dtype="c64", n=1 << 23, batch=4, cfg=None, kernels=2,
+                  reps=2, algorithmic_bytes=1 << 29)]
+    fields = ["Dispatch_Id", "Kernel_Name", "Grid_Size", "Workgroup_Size", "Counter_Name", "Counter_Value",
+              "Start_Timestamp", "End_Timestamp"]
+    rows, did = [], 0
+
+    def disp(name, grid, value):
+        nonlocal did
+        did += 1
+        rows.append(dict(Dispatch_Id=did, Kernel_Name=name, Grid_Size=grid, Workgroup_Size=1024,
+                         Counter_Name="FETCH_SIZE", Counter_Value=value, Start_Timestamp=0, End_Timestamp=1000))
+
+    disp("__amd_rocclr_copyBuffer", 4096, 131072.0)
+    disp("void at::native::fill", 256, 5.0)
+    shared = "void ppx::k_fft_tile_p<16, 12, true, 4>(float2 const*)"
+    for ci, (b_name, vals) in enumerate((("void ppx::k_fft_tile_p<16, 10, false, 16>(float2 const*)", (10.0, 20.0)),
+                                         ("void ppx::k_fft_tile_p<16, 11, false, 8>(float2 const*)", (30.0, 40.0)))):
+        for _ in range(2):
+            disp(shared, 262144, vals[0])
+            disp(b_name, 262144, vals[1])
+    path = tmp_path / "pass.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        w.writerows(rows)
+    groups, copy = counter_table.load([str(path)], calls)
+    assert copy["FETCH_SIZE"] == [131072.0]
+    assert list(groups) == [(0, 0), (0, 1), (1, 0), (1, 1)]
+    assert [groups[k][1]["FETCH_SIZE"] for k in groups] == [[10.0, 10.0], [20.0, 20.0], [30.0, 30.0], [40.0, 40.0]]
+    assert groups[(0, 0)][0][0] == groups[(1, 0)][0][0]  # one kernel instantiation, two calls
