@@ -116,6 +116,36 @@ __device__ __forceinline__ long long tile_order(long long b) {
     return (w / LG) * (8 * LG) + LG * x + (w % LG);
 }
 
+// Step order of the persistent tiles.  At each step the grid (G workgroups)
+// covers G consecutive positions of its walk; where a problem's row holds
+// m = tiles / G >= 2 times that many tiles (long rows), consecutive steps
+// would each read one m-th of every row, in one stretch.  Instead, the m
+// steps over a row's tiles take its line groups (the LG = 16 / TC tiles
+// sharing 128-byte lines) in turn, step h the groups h, h + m, h + 2m, ...,
+// so every step reads lines spread over whole rows (4.4% faster calls at
+// 2^23, where both passes' rows hold 2 G tiles).  A workgroup whose walk
+// starts at position t0 < G (group g0 = t0 / LG, lane i0 = t0 mod LG) then
+// takes tiles (g0 m + h) LG + i0 of row r at step r m + h: from one tile to
+// the next it adds LG, or LG + tiles - m LG where h wraps; no division in
+// the loop.
+// The walk is a separate instantiation (WALK), launched where a row holds
+// 2 G tiles or more (tile_walk_reorders); elsewhere the identity walk keeps
+// the kernel's code as it was (the walk's state, carried through the loop,
+// measured 3.6% slower at 2^22 even where it changes no tile).
+__host__ __device__ constexpr int tile_line_group(int tc) { return tc < 16 ? 16 / tc : 1; }
+inline bool tile_walk_reorders(long long G, long long tiles, int tc) {
+    return tiles >= 2 * G && tiles % G == 0 && G % tile_line_group(tc) == 0;
+}
+template <int TC>
+struct TileWalk {
+    static constexpr int LG = tile_line_group(TC);
+    long long m, wrap;
+    __device__ __forceinline__ TileWalk(long long G, long long tiles) : m(tiles / G), wrap(tiles - (tiles / G - 1) * LG) {}
+    __device__ __forceinline__ long long first(long long t0) const { return (t0 / LG) * m * LG + t0 % LG; }
+    __device__ __forceinline__ long long next(long long tile, int h) const { return tile + (h + 1 < m ? LG : wrap); }
+    __device__ __forceinline__ int next_h(int h) const { return h + 1 < m ? h + 1 : 0; }
+};
+
 // float2 entries of a column transform's stage twiddle bases (every stage but
 // the first: w^k, w^{4k} and, radix 16, w^{8k} for k below the stage's span),
 // which the persistent tiles keep in LDS (after the tables in pass A).
@@ -399,13 +429,13 @@ struct TilePrefetch {
 // them; the first tile is peeled, so the loop is entered only after a whole
 // tile (loads, then stores), the same history as its back edge, and the
 // compiler's wait before the LDS writes covers the prefetch only, not the
-// stores issued after it.  Workgroup b takes tiles tile_order(b) + k * G
+// stores issued after it.  Workgroup b walks positions tile_order(b) + k * G
 // (G the grid; where G is a multiple of 8 * 16 / TC and divides the tile
-// count, else b + k * G): at each step the grid covers G consecutive tiles,
-// and the tiles sharing a row's cache lines are in flight on one XCD
-// together.  Every thread of a workgroup runs the same iterations, so all
-// reach every barrier.
-template <int R, int LOG2LEN, bool PASS_A, int TC>
+// count, else b + k * G): at each step the grid covers G consecutive
+// positions, and the tiles sharing a row's cache lines are in flight on one
+// XCD together; TileWalk maps positions to tiles.  Every thread of a
+// workgroup runs the same iterations, so all reach every barrier.
+template <int R, int LOG2LEN, bool PASS_A, int TC, bool WALK = false>
 __global__ __launch_bounds__(1024) void k_fft_tile_p(const float2 *in, float2 *out, const float2 *__restrict__ tw,
                                                       const float2 *__restrict__ tw_lo,
                                                       const float2 *__restrict__ tw_hi, int log2n,
@@ -428,8 +458,11 @@ __global__ __launch_bounds__(1024) void k_fft_tile_p(const float2 *in, float2 *o
     long long t = b;
     const long long step = G, end = total;
     if (G % (8 * (TC < 16 ? 16 / TC : 1)) == 0 && total % G == 0) t = tile_order<TC>(b);
+    const TileWalk<TC> walk(G, tiles);
+    long long tile = WALK ? walk.first(t) : t;  // the tile at walk position t
+    int h = 0;
     float2 pre[R];
-    tile_load_rows<R, LOG2LEN, TC>(pre, tile_rsrc(in, t, end, tiles, TC, log2n), (int)cols, (int)threadIdx.x);
+    tile_load_rows<R, LOG2LEN, TC>(pre, tile_rsrc(in, tile, end, tiles, TC, log2n), (int)cols, (int)threadIdx.x);
     auto one_tile = [&](long long cur) {
         // an empty asm that claims to change tx keeps the compiler from
         // hoisting every tx-derived address out of the tile loop and keeping
@@ -440,10 +473,17 @@ __global__ __launch_bounds__(1024) void k_fft_tile_p(const float2 *in, float2 *o
         const int c = tx & (TC - 1), e0 = tx >> LTC;
 #pragma unroll
         for (int k = 0; k < R; ++k) buf[TileLayout<R, LOG2LEN, TC>::slot_k(c, e0, k * (len / R))] = pre[k];
-        const TilePrefetch<R, LOG2LEN, TC> nxt{pre, tile_rsrc(in, cur + step, end, tiles, TC, log2n), (int)cols, tx};
+        long long cur_tile = cur, next_tile = cur + step;
+        if constexpr (WALK) {
+            cur_tile = tile;
+            tile = walk.next(tile, h);  // the walk's next step
+            h = walk.next_h(h);
+            next_tile = cur + step < end ? tile : end;
+        }
+        const TilePrefetch<R, LOG2LEN, TC> nxt{pre, tile_rsrc(in, next_tile, end, tiles, TC, log2n), (int)cols, tx};
         tile_load_rows<R, LOG2LEN, TC, 0, TilePrefetch<R, LOG2LEN, TC>::NC>(pre, nxt.r, nxt.cols, tx);
-        const long long prob = cur / tiles;
-        const int c0 = (int)(cur % tiles) * TC;
+        const long long prob = cur_tile / tiles;
+        const int c0 = (int)(cur_tile % tiles) * TC;
         tile_transform_store<R, LOG2LEN, PASS_A, TC, true>(buf, tlo, thi, tht, out, prob << log2n, c0, cols, log2n,
                                                            sgn, twl, tx, nxt);
     };
@@ -469,43 +509,46 @@ constexpr bool tile_ok(int radix, int log2len, int tc, bool pass_a) {
            tc * ((1 << log2len) / radix) <= 1024 && tile_lds(radix, log2len, tc, pass_a) <= kTileLdsMax;
 }
 
+// walk: the persistent kernel with the whole-row step order (TileWalk), for
+// launches where it reorders; shapes that are not persistent ignore it.
 template <int R, int L, bool A, int TC>
-static TileKernel tile_entry() {
+static TileKernel tile_entry(bool walk) {
     if constexpr (!tile_ok(R, L, TC, A)) return nullptr;
-    else if constexpr (tile_persistent(L, TC, A)) return &k_fft_tile_p<R, L, A, TC>;
+    else if constexpr (tile_persistent(L, TC, A))
+        return walk ? &k_fft_tile_p<R, L, A, TC, true> : &k_fft_tile_p<R, L, A, TC>;
     else return &k_fft_tile<R, L, A, TC>;
 }
 template <int R, bool A, int TC>
-static TileKernel tile_len(int log2len) {
+static TileKernel tile_len(int log2len, bool walk) {
     switch (log2len) {
-        case 5: return tile_entry<R, 5, A, TC>();
-        case 6: return tile_entry<R, 6, A, TC>();
-        case 7: return tile_entry<R, 7, A, TC>();
-        case 8: return tile_entry<R, 8, A, TC>();
-        case 9: return tile_entry<R, 9, A, TC>();
-        case 10: return tile_entry<R, 10, A, TC>();
-        case 11: return tile_entry<R, 11, A, TC>();
-        case 12: return tile_entry<R, 12, A, TC>();
-        case 13: return tile_entry<R, 13, A, TC>();
+        case 5: return tile_entry<R, 5, A, TC>(walk);
+        case 6: return tile_entry<R, 6, A, TC>(walk);
+        case 7: return tile_entry<R, 7, A, TC>(walk);
+        case 8: return tile_entry<R, 8, A, TC>(walk);
+        case 9: return tile_entry<R, 9, A, TC>(walk);
+        case 10: return tile_entry<R, 10, A, TC>(walk);
+        case 11: return tile_entry<R, 11, A, TC>(walk);
+        case 12: return tile_entry<R, 12, A, TC>(walk);
+        case 13: return tile_entry<R, 13, A, TC>(walk);
         default: return nullptr;
     }
 }
 template <int R, bool A>
-static TileKernel tile_tc(int log2len, int tc) {
+static TileKernel tile_tc(int log2len, int tc, bool walk) {
     switch (tc) {
-        case 2: return tile_len<R, A, 2>(log2len);
-        case 4: return tile_len<R, A, 4>(log2len);
-        case 8: return tile_len<R, A, 8>(log2len);
-        case 16: return tile_len<R, A, 16>(log2len);
-        case 32: return tile_len<R, A, 32>(log2len);
-        case 64: return tile_len<R, A, 64>(log2len);
+        case 2: return tile_len<R, A, 2>(log2len, walk);
+        case 4: return tile_len<R, A, 4>(log2len, walk);
+        case 8: return tile_len<R, A, 8>(log2len, walk);
+        case 16: return tile_len<R, A, 16>(log2len, walk);
+        case 32: return tile_len<R, A, 32>(log2len, walk);
+        case 64: return tile_len<R, A, 64>(log2len, walk);
         default: return nullptr;
     }
 }
 template <bool A>
-static TileKernel tile_lookup(int radix, int log2len, int tc) {
-    if (radix == 16) return tile_tc<16, A>(log2len, tc);
-    if (radix == 8) return tile_tc<8, A>(log2len, tc);
+static TileKernel tile_lookup(int radix, int log2len, int tc, bool walk = false) {
+    if (radix == 16) return tile_tc<16, A>(log2len, tc, walk);
+    if (radix == 8) return tile_tc<8, A>(log2len, tc, walk);
     return nullptr;
 }
 
@@ -628,8 +671,6 @@ int launch_fft_large(const void *in, void *out, int log2n, int64_t batch, const 
     const DeviceInfo *di = device_info();
     if (!di) return PPX_EDEVICE;
     const int l1 = p.log2_n1, l2 = log2n - l1;
-    TileKernel ka = tile_lookup<true>(p.radix_a, l2, p.tile_a), kb = tile_lookup<false>(p.radix_b, l1, p.tile_b);
-    if (!ka || !kb) return fail(PPX_ECONFIG, "no tile kernel for this plan");
     const float sgn = inverse ? -1.0f : 1.0f;
     const float2 *tw = static_cast<const float2 *>(di->twiddles);
     const float2 *lo = static_cast<const float2 *>(di->twiddles_large_lo);
@@ -641,6 +682,11 @@ int launch_fft_large(const void *in, void *out, int log2n, int64_t batch, const 
     auto grid = [&](long long total, int log2len, int tc, bool pass_a) {
         return tile_persistent(log2len, tc, pass_a) ? std::min<long long>(total, std::max(di->cus, 1)) : total;
     };
+    const bool walk_a = tile_walk_reorders(grid(total_a, l2, p.tile_a, true), tiles_a, p.tile_a);
+    const bool walk_b = tile_walk_reorders(grid(total_b, l1, p.tile_b, false), tiles_b, p.tile_b);
+    TileKernel ka = tile_lookup<true>(p.radix_a, l2, p.tile_a, walk_a);
+    TileKernel kb = tile_lookup<false>(p.radix_b, l1, p.tile_b, walk_b);
+    if (!ka || !kb) return fail(PPX_ECONFIG, "no tile kernel for this plan");
     hipLaunchKernelGGL(ka, dim3((unsigned)grid(total_a, l2, p.tile_a, true)), dim3(p.tile_a * ((1 << l2) / p.radix_a)),
                        (size_t)tile_lds(p.radix_a, l2, p.tile_a, true), s, static_cast<const float2 *>(in), static_cast<float2 *>(out),
                        tw, lo, hi, log2n, l1, tiles_a, total_a, sgn);

@@ -120,3 +120,46 @@ def test_tile_order(tc):
         assert sorted(order[run:run + 8 * lg]) == list(range(run, run + 8 * lg))
     for b, t in enumerate(order):
         assert (t // lg) % 8 == b % 8
+
+
+def tile_step_order(u, g, tiles, tc):
+    lg = 16 // tc if tc < 16 else 1
+    m = tiles // g
+    if m < 2 or tiles % g or g % lg:
+        return u
+    row, p = divmod(u, tiles)
+    grp, i = divmod(p, lg)
+    ng = g // lg
+    return row * tiles + ((grp % ng) * m + grp // ng) * lg + i
+
+
+@pytest.mark.parametrize("tc,tiles", [(4, 512), (8, 512), (2, 1024), (4, 1024), (16, 512), (4, 256), (8, 128)])
+def test_tile_step_order(tc, tiles):
+    """The step order of the persistent tiles (TileWalk in
+    csrc/fft_large.hip) permutes each problem's tiles, keeps the 16 / TC
+    tiles of a line group together, and, where a row holds m >= 2 steps of
+    the grid's G tiles, gives every step line groups spread over the whole
+    row (step h: groups h, h + m, ...).  The kernel walks it incrementally
+    (+LG, or +tiles - (m - 1) LG where h wraps, from the first tile
+    (t0 div LG) m LG + t0 mod LG): checked against the definition here."""
+    g = 256
+    lg = 16 // tc if tc < 16 else 1
+    total = 3 * tiles
+    order = [tile_step_order(u, g, tiles, tc) for u in range(total)]
+    assert sorted(order) == list(range(total))
+    for u in range(0, total, lg):
+        assert order[u:u + lg] == list(range(order[u], order[u] + lg))
+    m = tiles // g
+    if m >= 2:
+        groups = sorted({order[u] // lg for u in range(g)})  # the first step
+        assert groups == list(range(0, tiles // lg, m))
+    reorder = tiles >= 2 * g and tiles % g == 0 and g % lg == 0
+    mm = tiles // g if reorder else 1
+    wrap = tiles - (mm - 1) * lg
+    for t0 in range(g):
+        tile = (t0 // lg) * mm * lg + t0 % lg if reorder else t0
+        h = 0
+        for t in range(t0, total, g):
+            assert tile == order[t]
+            tile += (lg if h + 1 < mm else wrap) if reorder else g
+            h = h + 1 if h + 1 < mm else 0
