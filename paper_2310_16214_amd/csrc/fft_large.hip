@@ -122,7 +122,7 @@ __device__ __forceinline__ long long tile_order(long long b) {
 // would each read one m-th of every row, in one stretch.  Instead, the m
 // steps over a row's tiles take its line groups (the LG = 16 / TC tiles
 // sharing 128-byte lines) in turn, step h the groups h, h + m, h + 2m, ...,
-// so every step reads lines spread over whole rows (4.4% faster calls at
+// so every step reads lines spread over whole rows (6% faster calls at
 // 2^23, where both passes' rows hold 2 G tiles).  A workgroup whose walk
 // starts at position t0 < G (group g0 = t0 / LG, lane i0 = t0 mod LG) then
 // takes tiles (g0 m + h) LG + i0 of row r at step r m + h: from one tile to
