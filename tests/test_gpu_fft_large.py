@@ -2,9 +2,12 @@
 oracle: every plan at N = 2^15 and 2^16 on whole problems (every bin by its
 definition), the tuned and the default plan on one whole problem at 2^17 and
 2^18, every plan at 2^20 .. 2^23 (narrow pass-B tiles for columns of
-more than 1024 values) and the default plan at full size up to 2^23 on
-sampled bins (each bin by its definition) plus Parseval, forward and
-inverse.  Bar: per-problem relative L2 <= 1e-5 * log2 N."""
+more than 1024 values), the default plan at full size up to 2^23 and the
+shipped tuned plans at 2^22 and 2^23 on one and three problems, on sampled
+bins (each bin by its definition) plus Parseval, forward and inverse.  Bar:
+per-problem relative L2 <= 1e-5 * log2 N."""
+import os
+
 import numpy as np
 import pytest
 
@@ -13,6 +16,8 @@ from paper_2310_16214_amd import inputs, ppx
 from tests.gpu_util import banner, fft_tol, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
+
+CACHE = os.path.join(os.path.dirname(ppx.__file__), "tuned", "mi355x.txt")
 
 
 def _run(x, n, batch, plan=None, direction=-1):
@@ -109,6 +114,34 @@ def test_default_plan_sampled_bins(cuda, ln):
     y = _run(x, n, batch)
     _sampled_bins(x, y, n, np.random.default_rng(ln), (0, batch // 2, batch - 1))
     _parseval(x, y, n)  # every problem: sum |X|^2 = N sum |x|^2
+
+
+@pytest.fixture
+def shipped_plans():
+    ppx.clear_tune_cache()
+    ppx.load_tune_cache(CACHE)
+    yield
+    ppx.clear_tune_cache()
+
+
+@pytest.mark.parametrize("ln,batch", [(22, 1), (22, 3), (23, 1), (23, 3)])
+def test_shipped_plan_few_problems(cuda, shipped_plans, ln, batch):
+    """The shipped tuned plans at 2^22 and 2^23 on one and three problems,
+    forward and inverse.  Their persistent passes run one workgroup per CU;
+    where a row holds two grid-steps of tiles or more (both passes at 2^23),
+    the steps take the row's line groups in turn, and with one or three rows
+    the walk wraps from row to row at every problem boundary.  48 bins per
+    problem by definition, every bin through Parseval."""
+    n = 1 << ln
+    plan = ppx.tuned_fft_plan(n)
+    assert plan is not None
+    x = inputs.fft_input(n, batch, seed=10 * ln + batch)
+    rng = np.random.default_rng(10 * ln + batch)
+    for direction in (-1, +1):
+        banner(f"fft large n={n} batch={batch} shipped plan {plan} dir={direction}")
+        y = _run(x, n, batch, plan, direction)
+        _sampled_bins(x, y, n, rng, range(batch), inverse=direction > 0)
+        _parseval(x, y, n)
 
 
 def test_inverse_roundtrip_and_forwarding(cuda):
